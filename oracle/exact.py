@@ -1,0 +1,60 @@
+"""Exact-rational brute force of the same scheme on tiny grids.
+
+TEST INFRASTRUCTURE ONLY.  Every FP64 input (field values, dx, dt, model
+parameters) is taken as the exact binary value it represents and every
+operation is done in Fraction arithmetic, so the result is the scheme's
+exact value; the FP64 oracle must agree with it to rounding error.  Pure
+Python loops: use grids of a few dozen sites and a handful of steps.
+"""
+from fractions import Fraction
+
+from .weights import second_derivative_weights_exact
+
+
+def _lap(u, shape, ndim, dx, w):
+    nz, ny, nx = shape
+    inv = 1 / (dx * dx)
+    out = {}
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                acc = Fraction(0)
+                for a in range(ndim):
+                    for j in range(1, len(w)):
+                        d = [0, 0, 0]
+                        d[a] = j
+                        up = u[((z + d[2]) % nz, (y + d[1]) % ny, (x + d[0]) % nx)]
+                        um = u[((z - d[2]) % nz, (y - d[1]) % ny, (x - d[0]) % nx)]
+                        acc += w[j] * inv * (up + um - 2 * u[(z, y, x)])
+                out[(z, y, x)] = acc
+    return out
+
+
+def run_exact(kind, fields, ndim, dx, dt, order, params, nsteps):
+    """Exact forward-Euler run.  fields: list of nested lists/arrays (nz, ny, nx)."""
+    w = second_derivative_weights_exact(order)
+    shape = (len(fields[0]), len(fields[0][0]), len(fields[0][0][0]))
+    nz, ny, nx = shape
+    keys = [(z, y, x) for z in range(nz) for y in range(ny) for x in range(nx)]
+    F = [{k: Fraction(float(f[k[0]][k[1]][k[2]])) for k in keys} for f in fields]
+    dx, dt = Fraction(dx), Fraction(dt)
+    P = [Fraction(p) for p in params]
+    for _ in range(nsteps):
+        if kind == 1:
+            c1, c2 = P[0], P[1]
+            L = _lap(F[0], shape, ndim, dx, w)
+            F = [{k: F[0][k] + dt * (L[k] + c1 * F[0][k] - c2 * F[0][k] ** 3) for k in keys}]
+        elif kind == 2:
+            c1, c2 = P[0], P[1]
+            L = _lap(F[0], shape, ndim, dx, w)
+            mu = {k: c2 * F[0][k] ** 3 - c1 * F[0][k] - L[k] for k in keys}
+            Lm = _lap(mu, shape, ndim, dx, w)
+            F = [{k: F[0][k] + dt * Lm[k] for k in keys}]
+        else:
+            Du, Dv, Fr, kr = P[0], P[1], P[2], P[3]
+            u, v = F
+            Lu = _lap(u, shape, ndim, dx, w)
+            Lv = _lap(v, shape, ndim, dx, w)
+            F = [{k: u[k] + dt * (Du * Lu[k] - u[k] * v[k] ** 2 + Fr * (1 - u[k])) for k in keys},
+                 {k: v[k] + dt * (Dv * Lv[k] + u[k] * v[k] ** 2 - (Fr + kr) * v[k]) for k in keys}]
+    return [[[[f[(z, y, x)] for x in range(nx)] for y in range(ny)] for z in range(nz)] for f in F]

@@ -1,0 +1,53 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a copy of oracle/oracle.c (a flipped sign, a
+dropped term, a wrong index or stride, a transposed operand), builds it, and
+runs the pin suite against the copy in a subprocess: the suite must fail.
+Mistakes are planted in the oracle, on the CPU, never in GPU code.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTANTS = {
+    "ac_c1_sign": ("rhs[i] = (lap[i] + c1 * p) - c2 * (p * p * p);", "rhs[i] = (lap[i] - c1 * p) - c2 * (p * p * p);"),
+    "ac_drop_cubic": ("rhs[i] = (lap[i] + c1 * p) - c2 * (p * p * p);", "rhs[i] = (lap[i] + c1 * p);"),
+    "ch_lap_sign": ("mu[i] = (c2 * (c * c * c) - c1 * c) - lap[i];", "mu[i] = (c2 * (c * c * c) - c1 * c) + lap[i];"),
+    "ch_square_not_cube": ("mu[i] = (c2 * (c * c * c) - c1 * c) - lap[i];", "mu[i] = (c2 * (c * c) - c1 * c) - lap[i];"),
+    "gs_reaction_sign": ("rhs[i] = (Du * lap[i] - uvv) + F * (1.0 - u[i]);", "rhs[i] = (Du * lap[i] + uvv) + F * (1.0 - u[i]);"),
+    "gs_drop_k": ("rhs[N + i] = (Dv * lapv[i] + uvv) - (F + k) * v[i];", "rhs[N + i] = (Dv * lapv[i] + uvv) - F * v[i];"),
+    "gs_feed_wrong_field": ("F * (1.0 - u[i])", "F * (1.0 - v[i])"),
+    "gs_v_uses_u_laplacian": ("(Dv * lapv[i] + uvv)", "(Dv * lap[i] + uvv)"),
+    "lap_wrong_minus_index": ("u[site(n, x - dp[0], y - dp[1], z - dp[2])]", "u[site(n, x - dp[0], y + dp[1], z - dp[2])]"),
+    "lap_dx_not_squared": ("1.0 / (dx * dx)", "1.0 / dx"),
+    "lap_transposed_stride": ("wrap(x, n[0]) + n[0] * (wrap(y, n[1]) + n[1] * wrap(z, n[2]))",
+                              "wrap(x, n[0]) + n[1] * (wrap(y, n[1]) + n[0] * wrap(z, n[2]))"),
+    "lap_skip_last_j": ("for (int j = 1; j <= r; ++j) {\n                        int64_t dp",
+                        "for (int j = 1; j < r; ++j) {\n                        int64_t dp"),
+    "euler_sign": ("fields[i] = fields[i] + dt * rhs[i];", "fields[i] = fields[i] - dt * rhs[i];"),
+    "energy_quartic_coeff": ("(0.25 * c2)", "(0.5 * c2)"),
+    "energy_drop_gradient": ("((-0.5 * v) * lap[i] + (0.25 * c2)", "((-0.0 * v) * lap[i] + (0.25 * c2)"),
+    "exact_sum_drop_error": ("if (lo != 0.0) part[k++] = lo;", "(void)lo;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, "mutation anchor not found: " + name
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared", "-o",
+                    str(lib), str(mut), "-lm"], check=True)
+    env = dict(os.environ, PF_ORACLE_MUTANT_LIB=str(lib), OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, "pin suite passed with planted mistake " + name

@@ -1,0 +1,418 @@
+"""Pins of the CPU FP64 oracle against what the paper and mathematics fix.
+
+Every part of the oracle is checked against something other than itself:
+closed forms, exact discrete eigenvalues, invariants, special cases, the
+paper's printed table, exact-rational brute force and convergence rates.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import AC, CH, GS
+from oracle.exact import run_exact
+from oracle.weights import second_derivative_weights_exact
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- weights --
+
+def _closed_form(order):
+    """w_j = 2 (-1)^(j+1) (r!)^2 / (j^2 (r-j)! (r+j)!), w_0 = -2 sum w_j."""
+    r = order // 2
+    w = [Fraction(0)] * (r + 1)
+    for j in range(1, r + 1):
+        w[j] = Fraction(2 * (-1) ** (j + 1) * math.factorial(r) ** 2,
+                        j * j * math.factorial(r - j) * math.factorial(r + j))
+    w[0] = -2 * sum(w[1:])
+    return w
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_weights_polynomial_exactness(order):
+    w = second_derivative_weights_exact(order)
+    r = order // 2
+    full = {j: w[abs(j)] for j in range(-r, r + 1)}
+    for k in range(0, 2 * r + 2):
+        moment = sum(wj * Fraction(j) ** k for j, wj in full.items())
+        assert moment == (2 if k == 2 else 0), (order, k)
+    # accuracy is exactly p, not more: the next even moment is non-zero
+    k = 2 * r + 2
+    assert sum(wj * Fraction(j) ** k for j, wj in full.items()) != 0
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_weights_closed_form(order):
+    assert second_derivative_weights_exact(order) == _closed_form(order)
+
+
+def test_weights_golden_table():
+    with open(os.path.join(GOLDEN, "centered_d2_weights.txt")) as f:
+        rows = [l for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 4
+    for line in rows:
+        p, vals = line.split(":")
+        expect = [Fraction(v) for v in vals.split()]
+        assert second_derivative_weights_exact(int(p)) == expect
+
+
+def test_weights_fp64_correctly_rounded():
+    for order in (2, 4, 6, 8, 12, 16):
+        exact = second_derivative_weights_exact(order)
+        for e, f in zip(exact, oracle.second_derivative_weights(order)):
+            err = abs(Fraction(f) - e)
+            assert err <= Fraction(math.ulp(f)) / 2
+
+
+# ------------------------------------------------------- Fourier eigenpins --
+
+def _eig(order, thetas, dx):
+    w = [float(v) for v in _closed_form(order)]
+    lam = 0.0
+    for th in thetas:
+        lam += (w[0] + 2 * sum(w[j] * math.cos(j * th) for j in range(1, len(w)))) / dx ** 2
+    return lam
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8])
+@pytest.mark.parametrize("shape,ndim,modes", [
+    ((1, 18, 24), 2, (0, 2, 5)),
+    ((1, 18, 24), 2, (0, 7, 0)),
+    ((1, 18, 24), 2, (0, 0, 11)),
+    ((8, 10, 12), 3, (3, 1, 4)),
+    ((8, 10, 12), 3, (4, 0, 0)),
+])
+def test_laplacian_fourier_eigenvalue(order, shape, ndim, modes):
+    nz, ny, nx = shape
+    dx = 0.7
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    thetas = [2 * math.pi * modes[2] / nx, 2 * math.pi * modes[1] / ny]
+    if ndim == 3:
+        thetas.append(2 * math.pi * modes[0] / nz)
+    phase = thetas[0] * x + thetas[1] * y + (thetas[2] * z if ndim == 3 else 0)
+    for u in (np.cos(phase + 0.3), np.sin(phase)):
+        lu = oracle.laplacian(u, ndim, dx, order)
+        lam = _eig(order, thetas, dx)
+        scale = sum(abs(float(v)) for v in _closed_form(order)) * 2 * ndim / dx ** 2
+        assert np.max(np.abs(lu - lam * u)) <= 4e-16 * scale * 8
+
+
+def test_laplacian_dimension_reduction():
+    """A 2D grid with ny = 1 gives exactly the 1D result; constants are exact zeros."""
+    rng = np.random.default_rng(1)
+    u = rng.uniform(-1, 1, size=(1, 1, 37))
+    for order in (2, 4, 6):
+        a = oracle.laplacian(u, 1, 0.5, order)
+        b = oracle.laplacian(u, 2, 0.5, order)
+        c = oracle.laplacian(np.broadcast_to(u, (5, 1, 37)), 3, 0.5, order)
+        assert np.array_equal(a, b)
+        assert np.array_equal(np.broadcast_to(a, (5, 1, 37)), c)
+        k = oracle.laplacian(np.full((3, 4, 5), 0.123456789), 3, 0.3, order)
+        assert np.all(k == 0.0)
+
+
+def test_laplacian_stencil_wider_than_grid():
+    """Periodic wrap with a true modulo: a radius-4 stencil on a 3-site axis."""
+    u = np.array([[[1.0, 2.0, 4.0]]])
+    w = second_derivative_weights_exact(8)
+    expect = []
+    for i in range(3):
+        acc = Fraction(0)
+        for j in range(1, 5):
+            acc += w[j] * (Fraction(u[0, 0, (i + j) % 3]) + Fraction(u[0, 0, (i - j) % 3]) - 2 * Fraction(u[0, 0, i]))
+        expect.append(float(acc))
+    got = oracle.laplacian(u, 1, 1.0, 8)[0, 0]
+    assert np.allclose(got, expect, rtol=0, atol=1e-14)
+
+
+# -------------------------------------------------- single-mode decay pins --
+
+def _mode(shape, ndim, modes):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    th = [2 * math.pi * modes[2] / nx, 2 * math.pi * modes[1] / ny, 2 * math.pi * modes[0] / nz]
+    phase = th[0] * x + th[1] * y + (th[2] * z if ndim == 3 else 0)
+    return np.cos(phase), th[:ndim]
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("shape,ndim,modes", [((1, 16, 20), 2, (0, 3, 2)), ((6, 8, 10), 3, (1, 2, 3))])
+def test_single_mode_decay_all_models(order, shape, ndim, modes):
+    dx, n = 1.0, 25
+    m, th = _mode(shape, ndim, modes)
+    lam = _eig(order, th, dx)
+    A0 = 0.01
+    cases = [
+        (AC, [0.0, 0.0], 0.02, 1 + 0.02 * lam),
+        (AC, [0.7, 0.0], 0.02, 1 + 0.02 * (lam + 0.7)),
+        (CH, [0.0, 0.0], 0.002, 1 - 0.002 * lam * lam),
+        (CH, [0.7, 0.0], 0.002, 1 + 0.002 * (-0.7 * lam - lam * lam)),
+    ]
+    for kind, params, dt, g in cases:
+        out = oracle.run(kind, [A0 * m], ndim, dx, dt, order, params, n)[0]
+        assert np.max(np.abs(out - A0 * g ** n * m)) <= 1e-15 * n * 4, (kind, params)
+    # Gray-Scott with v = 0: u = 1 + A mode decays with 1 + dt (Du lam - F)
+    Du, Dv, F, k, dt = 0.2, 0.1, 0.04, 0.06, 0.3
+    u0, v0 = 1.0 + A0 * m, np.zeros(shape)
+    u, v = oracle.run(GS, [u0, v0], ndim, dx, dt, order, [Du, Dv, F, k], n)
+    g = 1 + dt * (Du * lam - F)
+    assert np.max(np.abs(u - (1 + A0 * g ** n * m))) <= 1e-15 * n * 4
+    assert np.all(v == 0.0)
+
+
+# -------------------------------------------------------------- invariants --
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("shape,ndim", [((1, 24, 30), 2), ((8, 9, 10), 3)])
+def test_cahn_hilliard_mass_conservation(order, shape, ndim):
+    rng = np.random.default_rng(7)
+    c = rng.uniform(-0.05, 0.05, size=shape)
+    nsteps = 40
+    m0 = oracle.exact_sum(c)
+    drift = []
+    for _ in range(4):
+        c = oracle.run(CH, [c], ndim, 1.0, 0.005, order, [1.0, 1.0], nsteps // 4)[0]
+        drift.append(abs(oracle.exact_sum(c) - m0))
+    N = c.size
+    bound = nsteps * N * 2.2e-16 * 0.1
+    assert max(drift) <= bound
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8])
+@pytest.mark.parametrize("shape,ndim", [((1, 12, 14), 2), ((5, 6, 7), 3)])
+def test_gray_scott_trivial_fixed_point_bitwise(order, shape, ndim):
+    u, v = np.ones(shape), np.zeros(shape)
+    u2, v2 = oracle.run(GS, [u, v], ndim, 1.0, 0.5, order, [0.2, 0.1, 0.04, 0.06], 20)
+    assert np.array_equal(u2, u) and np.array_equal(v2, v)
+
+
+def _gs_fixed_points(F, k):
+    """Homogeneous fixed points with v != 0: u v = F + k, (F+k) v^2 - F v + F (F+k) = 0."""
+    a, b, c = F + k, -F, F * (F + k)
+    disc = b * b - 4 * a * c
+    if disc < 0:
+        return []
+    vs = [(-b + s * math.sqrt(max(disc, 0.0))) / (2 * a) for s in (1, -1)]
+    return [((F + k) / v, v) for v in vs]
+
+
+@pytest.mark.parametrize("F,k", [(0.04, 0.06), (0.03, 0.05), (0.02, 0.05)])
+def test_gray_scott_nontrivial_fixed_point(F, k):
+    """Every reaction term takes part; a wrong sign or a dropped term moves the state."""
+    shape = (3, 4, 5)
+    for u_s, v_s in _gs_fixed_points(F, k):
+        u, v = np.full(shape, u_s), np.full(shape, v_s)
+        u2, v2 = oracle.run(GS, [u, v], 3, 1.0, 0.1, 2, [0.2, 0.1, F, k], 10)
+        assert np.max(np.abs(u2 - u_s)) < 1e-13
+        assert np.max(np.abs(v2 - v_s)) < 1e-13
+        # a perturbed state does move (the pin is not vacuous)
+        u3, v3 = oracle.run(GS, [u * 1.01, v], 3, 1.0, 0.1, 2, [0.2, 0.1, F, k], 1)
+        assert np.max(np.abs(u3 - u * 1.01)) > 1e-6
+
+
+def test_gray_scott_homogeneous_reaction_euler():
+    """Spatially constant state: L = 0 exactly, so one step is the ODE's Euler step.
+
+    Checked against the rate functions written as a polynomial in (u, v) with
+    the constants of the reaction network A: u + 2v -> 3v (rate uv^2), feed
+    F(1-u), removal (F+k) v, evaluated in exact rationals.
+    """
+    Du, Dv, F, k, dt = 0.2, 0.1, 0.04, 0.06, 0.25
+    u_s, v_s = 0.37, 0.61
+    u, v = oracle.run(GS, [np.full((1, 3, 3), u_s), np.full((1, 3, 3), v_s)], 2, 1.0, dt, 4,
+                      [Du, Dv, F, k], 1)
+    U, V, Fq, Kq, T = (Fraction(x) for x in (u_s, v_s, F, k, dt))
+    react = U * V * V
+    assert abs(u[0, 0, 0] - float(U + T * (Fq * (1 - U) - react))) < 1e-16
+    assert abs(v[0, 0, 0] - float(V + T * (react - (Fq + Kq) * V))) < 1e-16
+
+
+# ------------------------------------------------------ tanh profile pins --
+
+def _kinks(n, h, L):
+    x = np.arange(n) * h
+    s = 1 / math.sqrt(2)
+    return np.tanh((x - L / 4) * s) * np.tanh((3 * L / 4 - x) * s)
+
+
+@pytest.mark.parametrize("kind,order", [(AC, 2), (AC, 4), (CH, 2), (CH, 4)])
+def test_tanh_profile_convergence_rate(kind, order):
+    """phi* = tanh(x / sqrt 2) is stationary for c1 = c2 = 1; the scheme keeps it to O(h^p)."""
+    L = 40.0
+    errs = []
+    for n in (80, 160):
+        h = L / n
+        phi = _kinks(n, h, L)[None, None, :]
+        if kind == AC:
+            dt, T = 0.1 * h * h, 2.0
+        else:
+            dt, T = 0.02 * h ** 4, 0.25
+        nsteps = int(round(T / dt))
+        out = oracle.run(kind, [phi], 1, h, dt, order, [1.0, 1.0], nsteps)[0]
+        errs.append(np.max(np.abs(out - phi)))
+    rate = math.log2(errs[0] / errs[1])
+    assert order - 0.6 < rate < order + 0.6, (errs, rate)
+
+
+def test_tanh_profile_sign_pins():
+    """A wrong sign on c1 or c2 destroys the kink: the profile stays put only with the paper's signs."""
+    L, n = 40.0, 160
+    h = L / n
+    phi = _kinks(n, h, L)[None, None, :]
+    good = oracle.run(AC, [phi], 1, h, 0.1 * h * h, 4, [1.0, 1.0], 200)[0]
+    bad = oracle.run(AC, [phi], 1, h, 0.1 * h * h, 4, [-1.0, -1.0], 200)[0]
+    assert np.max(np.abs(good - phi)) < 1e-4
+    assert np.max(np.abs(bad - phi)) > 1e-2
+
+
+# ---------------------------------------------------- exact-rational brute --
+
+@pytest.mark.parametrize("kind,shape,ndim,order,params,dt", [
+    (AC, (1, 4, 4), 2, 2, [1.0, 1.0], 0.05),
+    (AC, (1, 4, 4), 2, 4, [0.9, 1.3], 0.05),
+    (CH, (1, 4, 4), 2, 4, [1.0, 1.0], 0.01),
+    (CH, (3, 3, 3), 3, 2, [1.1, 0.8], 0.01),
+    (GS, (3, 3, 3), 3, 2, [0.2, 0.1, 0.04, 0.06], 0.5),
+    (GS, (1, 4, 4), 2, 6, [0.2, 0.1, 0.04, 0.06], 0.3),
+])
+def test_exact_rational_brute_force(kind, shape, ndim, order, params, dt):
+    rng = np.random.default_rng(11)
+    nf = 2 if kind == GS else 1
+    fields = [rng.uniform(0.0, 1.0, size=shape) for _ in range(nf)]
+    nsteps = 4
+    got = oracle.run(kind, fields, ndim, 1.0, dt, order, params, nsteps)
+    ex = run_exact(kind, fields, ndim, 1.0, dt, order, params, nsteps)
+    for g, e in zip(got, ex):
+        e = np.array([[[float(v) for v in row] for row in pl] for pl in e])
+        assert np.max(np.abs(g - e)) < 5e-15
+
+
+# ----------------------------------------------------------- energy pins --
+
+def test_energy_constant_field_closed_form():
+    a, c1, c2, dx = 0.3, 1.2, 0.7, 0.5
+    x = np.full((4, 5, 6), a)
+    m, e, bad = oracle.reduce(AC, [x], 3, dx, 4, [c1, c2])
+    N = x.size
+    assert bad == 0
+    assert math.isclose(m[0], N * a * dx ** 3, rel_tol=1e-15)
+    assert math.isclose(e, N * dx ** 3 * (-c1 * a * a / 2 + c2 * a ** 4 / 4), rel_tol=1e-14)
+
+
+def test_energy_p2_summation_by_parts():
+    """For p = 2 the gradient term -1/2 sum x L x equals 1/2 sum |forward difference|^2."""
+    rng = np.random.default_rng(3)
+    dx = 0.8
+    for shape, ndim in (((1, 9, 11), 2), ((5, 6, 7), 3)):
+        x = rng.uniform(-1, 1, size=shape)
+        _, e, _ = oracle.reduce(AC, [x], ndim, dx, 2, [0.0, 0.0])
+        g = 0.0
+        for ax in range(ndim):
+            d = (np.roll(x, -1, axis=2 - ax) - x) / dx
+            g += 0.5 * float(np.sum(d * d))
+        assert math.isclose(e, g * dx ** ndim, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_allen_cahn_is_gradient_flow_of_energy(order):
+    """AC rhs_i = -(1/dx^d) dF/dx_i, by central differences of the oracle energy."""
+    rng = np.random.default_rng(5)
+    shape, ndim, dx, params = (1, 5, 6), 2, 0.9, [1.1, 0.8]
+    x = rng.uniform(-0.8, 0.8, size=shape)
+    r = oracle.rhs(AC, [x], ndim, dx, order, params)[0]
+    eps = 1e-5
+    for (zi, yi, xi) in [(0, 0, 0), (0, 2, 3), (0, 4, 5)]:
+        xp, xm = x.copy(), x.copy()
+        xp[zi, yi, xi] += eps
+        xm[zi, yi, xi] -= eps
+        Fp = oracle.reduce(AC, [xp], ndim, dx, order, params)[1]
+        Fm = oracle.reduce(AC, [xm], ndim, dx, order, params)[1]
+        grad = (Fp - Fm) / (2 * eps) / dx ** ndim
+        assert abs(grad + r[zi, yi, xi]) < 1e-7
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_cahn_hilliard_is_laplacian_of_chemical_potential(order):
+    """CH rhs = L(dF/dc / dx^d) = L(-AC rhs): conserved dynamics of the same functional."""
+    rng = np.random.default_rng(9)
+    shape, ndim, dx, params = (4, 5, 6), 3, 1.0, [1.0, 1.0]
+    c = rng.uniform(-0.5, 0.5, size=shape)
+    ac = oracle.rhs(AC, [c], ndim, dx, order, params)[0]
+    ch = oracle.rhs(CH, [c], ndim, dx, order, params)[0]
+    expect = oracle.laplacian(-ac, ndim, dx, order)
+    assert np.max(np.abs(ch - expect)) < 1e-13
+
+
+def test_cahn_hilliard_energy_decreases():
+    rng = np.random.default_rng(2)
+    c = rng.uniform(-0.5, 0.5, size=(1, 32, 32))
+    E = []
+    for _ in range(6):
+        E.append(oracle.reduce(CH, [c], 2, 1.0, 4, [1.0, 1.0])[1])
+        c = oracle.run(CH, [c], 2, 1.0, 0.01, 4, [1.0, 1.0], 20)[0]
+    assert all(b < a for a, b in zip(E, E[1:]))
+
+
+# ------------------------------------------------------------- exact sums --
+
+def test_exact_sum_matches_fsum():
+    rng = np.random.default_rng(4)
+    cases = [
+        rng.uniform(-1, 1, 10000),
+        np.array([1e100, 1.0, -1e100, 1e-100, 3.0]),
+        np.array([1.0, 1e-16, 1e-16, -1.0]),
+        np.concatenate([rng.uniform(-1, 1, 1000) * 10.0 ** rng.integers(-30, 30, 1000)]),
+        np.array([0.1] * 10),
+        np.array([2.0 ** 53, 1.0, 1e-300]),
+        np.array([]),
+    ]
+    for x in cases:
+        assert oracle.exact_sum(x) == math.fsum(x)
+
+
+def test_reduce_counts_nonfinite():
+    x = np.zeros((1, 4, 4))
+    x[0, 1, 2] = np.nan
+    x[0, 3, 3] = np.inf
+    assert oracle.reduce(AC, [x], 2, 1.0, 2, [1.0, 1.0])[2] == 2
+
+
+# ---------------------------------------------------------- stability pins --
+
+@pytest.mark.parametrize("kind,params,order,ndim", [
+    (AC, [0.0, 0.0], 2, 2), (AC, [0.0, 0.0], 4, 3),
+    (CH, [0.0, 0.0], 2, 2), (CH, [0.0, 0.0], 6, 3),
+])
+def test_dt_max_separates_growth_from_decay(kind, params, order, ndim):
+    """The Nyquist (checkerboard) mode grows just above dt_max and decays just below it."""
+    shape = (1, 8, 8) if ndim == 2 else (4, 4, 4)
+    z, y, x = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    cb = ((-1.0) ** (x + y + (z if ndim == 3 else 0))) * 1e-3
+    lim = oracle.dt_max(kind, ndim, 1.0, order, params)
+    up = oracle.run(kind, [cb], ndim, 1.0, lim * 1.02, order, params, 200)[0]
+    dn = oracle.run(kind, [cb], ndim, 1.0, lim * 0.98, order, params, 200)[0]
+    assert np.max(np.abs(up)) > 1e-3 and np.max(np.abs(dn)) < 1e-3
+
+
+def test_dt_max_config_values():
+    """Reading of the explicit-stability limit at the workloads' settings."""
+    assert math.isclose(oracle.dt_max(AC, 2, 1.0, 2, [1.0, 1.0]), 0.2, rel_tol=1e-12)
+    assert oracle.dt_max(CH, 2, 1.0, 4, [1.0, 1.0]) > 0.01
+    assert oracle.dt_max(CH, 3, 1.0, 6, [1.0, 1.0]) > 0.005
+    # 3D Gray-Scott with the 7-point stencil: dt = 1 is beyond the limit
+    assert oracle.dt_max(GS, 3, 1.0, 2, [0.2, 0.1, 0.04, 0.06]) < 1.0
+
+
+def test_gray_scott_3d_dt1_is_unstable():
+    """The Nyquist u-mode amplification at dt = 1 is 1 - dt (12 Du + F) = -1.44."""
+    shape = (8, 8, 8)
+    z, y, x = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    cb = (-1.0) ** (x + y + z)
+    u0, v0 = 1.0 + 1e-6 * cb, np.zeros(shape)
+    u, v = oracle.run(GS, [u0, v0], 3, 1.0, 1.0, 2, [0.2, 0.1, 0.04, 0.06], 10)
+    amp = np.max(np.abs(u - 1.0)) / 1e-6
+    assert math.isclose(amp, 1.44 ** 10, rel_tol=1e-6)
