@@ -1,0 +1,321 @@
+/*
+ * pfmi — explicit finite-difference phase-field / reaction-diffusion steps
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libpfmi.so.  Plain pointers and sizes only; no C++ exceptions
+ * cross this boundary.  Every call returns a pf_status (or a plain value
+ * where noted); on failure pf_last_error() gives a thread-local message.
+ *
+ * Method (SymPhas 2.0, arXiv 2511.10508):
+ *   Model A, Allen-Cahn, Eq. (model-a):  dphi/dt = lap phi + c1 phi - c2 phi^3
+ *   Model B, Cahn-Hilliard, Eq. (model-b): drho/dt = lap(-lap rho - c1 rho + c2 rho^3)
+ *   Gray-Scott (named in the paper's Introduction as a reaction-diffusion
+ *   model; standard two-species form):
+ *       du/dt = Du lap u - u v^2 + F (1 - u)
+ *       dv/dt = Dv lap v + u v^2 - (F + k) v
+ * on a uniform periodic 2D or 3D grid.  lap is the star-shaped sum of 1D
+ * centred second-derivative stencils of any even accuracy order p
+ * (Sec. "Compile-Time Stencil Generation": weights from polynomial
+ * interpolation, symmetric unknowns); the Cahn-Hilliard biharmonic is that
+ * Laplacian applied twice.  Time stepping is forward Euler with every
+ * right-hand side taken from the state at the start of the step.  All fields
+ * stay resident on the device; data reaches the host only through
+ * pf_get_field / pf_reduce (Sec. "CUDA Implementation": device residency).
+ *
+ * Memory layout on the device: one array per field and per ping-pong
+ * buffer, x fastest, rows of `pitch` elements (pitch >= nx, a multiple of
+ * 16 bytes), planes of pitch * ny elements.  Storage is FP64 or FP32.
+ */
+#ifndef PFMI_H
+#define PFMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_ABI_VERSION 1
+
+typedef enum {
+    PF_OK = 0,
+    PF_ERR_ARG = 1,          /* invalid argument or descriptor */
+    PF_ERR_UNSTABLE = 2,     /* dt above the explicit-stability limit */
+    PF_ERR_NOMEM = 3,        /* device or host allocation failed / over budget */
+    PF_ERR_DEVICE = 4,       /* a HIP call failed */
+    PF_ERR_STATE = 5,        /* call not valid in the object's current state */
+    PF_ERR_UNSUPPORTED = 6,  /* combination not supported (e.g. energy of Gray-Scott) */
+    PF_ERR_BUSY = 7,         /* resource busy (server queue full) */
+    PF_ERR_NOTFOUND = 8      /* unknown ticket */
+} pf_status;
+
+/* Model kinds. */
+enum { PF_AC = 1, PF_CH = 2, PF_GS = 3 };
+/* Storage / arithmetic precision of the bulk step. */
+enum { PF_FP64 = 0, PF_FP32 = 1 };
+/* Descriptor flags. */
+enum {
+    PF_ALLOW_UNSTABLE = 1u,    /* accept dt above the stability limit */
+    PF_USE_GRAPH = 2u,         /* pf_step replays captured HIP graphs of steps */
+    PF_REDUCE_EACH_STEP = 4u,  /* fuse the reductions into every step (history) */
+    PF_FORCE_GENERIC = 8u      /* use the simple per-site kernels (testing) */
+};
+/* Initial conditions for pf_init (counter-based SplitMix64 generator). */
+enum { PF_IC_UNIFORM = 1, PF_IC_GS_CUBES = 2, PF_IC_CONST = 3 };
+/* Reduction selectors for pf_reduce. */
+enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE = 3 };
+
+/*
+ * Model descriptor.  struct_size must be sizeof(pf_desc) (ABI check).
+ *   kind      PF_AC, PF_CH or PF_GS
+ *   nfields   1 for AC and CH, 2 for GS (u, v); anything else -> PF_ERR_ARG
+ *   ndim      2 or 3; n[ndim..2] must be 1.  A 1D problem is a 2D grid with
+ *             n[1] = 1 (the y stencil of a length-1 periodic axis is exactly 0)
+ *   n         grid extents (x, y, z), each >= 1, N = n0 n1 n2 < 2^40
+ *   dx        uniform spacing (> 0); dt time step (> 0)
+ *   order     accuracy order p of the Laplacian stencil, even, 2..16
+ *   precision PF_FP64 or PF_FP32 (FP32: storage, weights, parameters, the
+ *             stencil, the nonlinear terms and the update in FP32; the
+ *             reductions stay FP64 with compensation)
+ *   params    AC, CH: {c1, c2};  GS: {Du, Dv, F, k};  nparams must match
+ *   flags     PF_* flags above
+ */
+typedef struct pf_desc {
+    uint32_t struct_size;
+    int32_t kind;
+    int32_t nfields;
+    int32_t ndim;
+    int64_t n[3];
+    double dx;
+    double dt;
+    int32_t order;
+    int32_t precision;
+    int32_t nparams;
+    uint32_t flags;
+    double params[8];
+} pf_desc;
+
+typedef struct pf_model pf_model;
+
+/* Library information. */
+int32_t pf_abi_version(void);
+const char *pf_last_error(void);            /* thread-local, never NULL */
+const char *pf_status_str(pf_status s);
+
+/*
+ * Host FP64 stencil weights: the centred second-derivative weights
+ * w[0..order/2] (w_{-j} = w_j) for accuracy `order`, computed by Fornberg's
+ * recursion (Math. Comp. 51, 1988) on the nodes 0, +-1, .., +-r at unit
+ * spacing.  `w` must hold order/2 + 1 doubles (caller-owned).
+ */
+pf_status pf_weights(int32_t order, double *w);
+
+/*
+ * Explicit-stability limit of the descriptor's model: the largest dt for
+ * which the linearised forward-Euler step keeps every Fourier mode bounded
+ * (Nyquist-mode symbol of the stencil; AC linearised for phi^2 <= c1/c2,
+ * CH for rho^2 <= c1/c2, GS for u, v in [0, 1]).
+ */
+pf_status pf_stability(const pf_desc *desc, double *dt_max);
+
+/* Device bytes a model of this descriptor holds (2 buffers per field, padded
+ * pitch, plus reduction scratch).  0 for an invalid descriptor. */
+uint64_t pf_footprint_bytes(const pf_desc *desc);
+
+/* Elements of one device field buffer (pitch * n1 * n2).  -1 if invalid. */
+int64_t pf_buffer_elems(const pf_desc *desc);
+
+/*
+ * Create a model.  The library allocates and owns 2 * nfields device
+ * buffers (ping-pong) plus reduction scratch; fields start at zero.
+ * hip_stream: a hipStream_t owned by the caller, or NULL for a stream owned
+ * by the model.  Errors: PF_ERR_ARG (bad descriptor), PF_ERR_UNSTABLE (dt >
+ * dt_max without PF_ALLOW_UNSTABLE), PF_ERR_NOMEM, PF_ERR_DEVICE.
+ */
+pf_status pf_create(const pf_desc *desc, void *hip_stream, pf_model **out);
+
+/*
+ * Create a model on caller-owned device memory (e.g. torch tensors):
+ * dev_bufs holds nbufs = 2 * nfields pointers, in the order field 0 buffer
+ * A, field 0 buffer B, field 1 buffer A, field 1 buffer B; each of
+ * pf_buffer_elems(desc) elements of the storage type, 16-byte aligned.  The
+ * caller keeps them alive until pf_destroy; the library never frees them.
+ */
+pf_status pf_create_on(const pf_desc *desc, void *hip_stream, void *const *dev_bufs,
+                       int32_t nbufs, pf_model **out);
+
+/* Release the model (syncs its stream first).  NULL is a no-op. */
+void pf_destroy(pf_model *m);
+
+/*
+ * Initialise the fields on the device from the counter-based generator:
+ * every value is a pure function of (seed, stream, site index), site index
+ * x + n0 (y + n1 z), so any sub-window can be reproduced on the host.
+ *   PF_IC_UNIFORM  ic_params {lo, hi}: field f = lo + (hi - lo) U_f
+ *   PF_IC_GS_CUBES ic_params {ncubes, side, noise}: u = 1, v = 0 except
+ *                  ncubes cubes (periodic) with u = 0.5, v = 0.25, then
+ *                  U[-noise, noise] added to u and v
+ *   PF_IC_CONST    ic_params {value_0, value_1}
+ * Asynchronous on the model's stream.  Resets pf_steps_done to 0.
+ */
+pf_status pf_init(pf_model *m, int32_t ic, uint64_t seed, const double *ic_params,
+                  int32_t n_ic_params);
+
+/* Copy a field between host FP64 memory (count = N doubles, x fastest,
+ * caller-owned, used only during the call) and the device.  FP32 storage
+ * rounds to nearest on set and widens exactly on get.  Both synchronise the
+ * model's stream.  count != N -> PF_ERR_ARG. */
+pf_status pf_set_field(pf_model *m, int32_t field, const double *host, int64_t count);
+pf_status pf_get_field(pf_model *m, int32_t field, double *host, int64_t count);
+
+/* Copy a box of a field to host FP64 memory: origin (x, y, z) (periodic,
+ * wrapped) and extent w (wx, wy, wz); host holds wx*wy*wz doubles, x
+ * fastest.  Synchronises the model's stream. */
+pf_status pf_get_window(pf_model *m, int32_t field, const int64_t *origin, const int64_t *w,
+                        double *host);
+
+/* Zero-copy view of the current buffer of a field; valid until the next
+ * pf_step / pf_init / pf_destroy. */
+pf_status pf_field_device(pf_model *m, int32_t field, void **ptr, int64_t *pitch_elems,
+                          int32_t *elem_bytes);
+
+/*
+ * Enqueue nsteps forward-Euler steps on the model's stream and return
+ * (asynchronous).  With PF_REDUCE_EACH_STEP the reductions of the state at
+ * the start of every step are fused into the step kernel and kept in a
+ * device history (pf_reduce_history).  With PF_USE_GRAPH the launches are
+ * replayed from captured HIP graphs.
+ */
+pf_status pf_step(pf_model *m, int64_t nsteps);
+
+/*
+ * Reductions of the current state, compensated in FP64 on the device and
+ * combined in a fixed order: value = hi + lo (double-double).
+ *   PF_RED_MASS0 / PF_RED_MASS1: dx^d sum of field 0 / 1
+ *   PF_RED_ENERGY: dx^d sum of -(1/2) x L x + (c2/4) x^4 - (c1/2) x^2 (AC, CH
+ *                  only; GS -> PF_ERR_UNSUPPORTED)
+ *   PF_RED_NONFINITE: number of NaN / Inf values (hi = count, lo = 0)
+ * Synchronises the stream.
+ */
+pf_status pf_reduce(pf_model *m, int32_t which, double *hi, double *lo);
+
+/* Per-step reductions recorded by the last pf_step under PF_REDUCE_EACH_STEP:
+ * entry k is the state at the start of step k of that call.  hi/lo hold
+ * `count` doubles each (caller-owned); count must not exceed that call's
+ * nsteps.  Synchronises the stream. */
+pf_status pf_reduce_history(pf_model *m, int32_t which, double *hi, double *lo, int64_t count);
+
+/* Wait for all work enqueued on the model's stream. */
+pf_status pf_sync(pf_model *m);
+
+/* Steps advanced since creation or the last pf_init / pf_set_steps_done. */
+int64_t pf_steps_done(const pf_model *m);
+pf_status pf_set_steps_done(pf_model *m, int64_t steps);
+
+/* The hipStream_t the model enqueues on. */
+pf_status pf_stream(pf_model *m, void **hip_stream);
+
+/*
+ * Tile shape of the step kernels: chunk = sites marched per work item along
+ * the slowest axis (y in 2D, z in 3D), 0 = the library's choice.  Results
+ * do not depend on it (bitwise).  pf_get_tile reports the current one and
+ * the kernel family in use (0 fused marching, 1 per-site generic).
+ */
+pf_status pf_set_tile(pf_model *m, int32_t chunk);
+pf_status pf_get_tile(pf_model *m, int32_t *chunk, int32_t *family);
+
+/*
+ * Autotuner: times each candidate tile on the model's own buffers (the
+ * state is saved and restored), keeps the fastest and records it in an
+ * in-process cache keyed by (kind, ndim, order, precision, size class) that
+ * later models of the same class reuse.  trials = timed steps per candidate.
+ */
+pf_status pf_autotune(pf_model *m, int32_t trials);
+
+/*
+ * Kernel timing on the model's stream: while enabled, pf_step records a HIP
+ * event pair around every step-kernel launch; pf_timing_read synchronises
+ * and returns the summed kernel milliseconds and the number of launches
+ * since the last enable.
+ */
+pf_status pf_timing_enable(pf_model *m, int32_t on);
+pf_status pf_timing_read(pf_model *m, double *total_ms, int64_t *launches);
+
+/*
+ * Measurement helper: stream `bytes` from src to dst (device pointers,
+ * 16-byte aligned, bytes a multiple of 16) with the library's plain copy
+ * kernel on hip_stream (NULL = the null stream) and return the kernel time
+ * in milliseconds measured with HIP events (synchronises).  Calibrates
+ * attainable HBM bandwidth and hardware byte counters.
+ */
+pf_status pf_copy_probe(void *dst, const void *src, uint64_t bytes, void *hip_stream,
+                        int32_t reps, double *ms_per_rep);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent simulation requests.
+ *
+ * A server owns one device and a stream.  Requests (a descriptor, an initial
+ * condition and a step count) are admitted while their footprint fits the
+ * HBM budget and a slot is free; every scheduler tick runs a block of steps
+ * for all admitted requests in batched launches (one per kernel class and
+ * step) replayed from a captured HIP graph.  Requests that arrive while
+ * others run are admitted at the next tick.  Each request's result is
+ * bitwise the same as a model stepped alone with the same tile.
+ * ---------------------------------------------------------------------- */
+typedef struct pf_server pf_server;
+
+typedef struct pf_result {
+    uint64_t ticket;
+    int32_t status;          /* PF_OK, or the request's failure */
+    int32_t _pad;
+    double t_submit;         /* seconds on the server's monotonic clock */
+    double t_admit;
+    double t_done;           /* device completion observed by the scheduler */
+    double mass[2];          /* reductions of the final state (hi + lo folded) */
+    double energy;           /* AC / CH */
+    int64_t nonfinite;
+    int64_t steps_done;
+} pf_result;
+
+/*
+ * hbm_budget: bytes of device memory the server may hold for requests
+ * (0 = 90 % of free memory at creation); max_slots: most requests resident
+ * at once; steps_per_tick: steps per request per tick (0 = 64).
+ */
+pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t max_slots,
+                           int32_t steps_per_tick, pf_server **out);
+
+/* Thread-safe, non-blocking.  Footprint above the budget -> PF_ERR_NOMEM;
+ * an invalid or unstable descriptor -> PF_ERR_ARG / PF_ERR_UNSTABLE. */
+pf_status pf_server_submit(pf_server *s, const pf_desc *desc, int32_t ic, uint64_t seed,
+                           const double *ic_params, int32_t n_ic_params, int64_t nsteps,
+                           uint64_t *ticket);
+
+/* Up to max finished requests not yet reported (non-blocking). */
+pf_status pf_server_poll(pf_server *s, pf_result *out, int32_t max, int32_t *n);
+
+/* Copy a finished request's field to host FP64 memory (count = N). */
+pf_status pf_server_fetch(pf_server *s, uint64_t ticket, int32_t field, double *host,
+                          int64_t count);
+
+/* Free a finished request's device memory. */
+pf_status pf_server_release(pf_server *s, uint64_t ticket);
+
+/* Cancel a queued or running request (it finishes with PF_ERR_STATE). */
+pf_status pf_server_cancel(pf_server *s, uint64_t ticket);
+
+/* Block until every submitted request has finished or timeout_s passed
+ * (PF_ERR_BUSY on timeout). */
+pf_status pf_server_drain(pf_server *s, double timeout_s);
+
+/* Server statistics: ticks run, batched launches, graph captures, graph replays. */
+pf_status pf_server_stats(pf_server *s, int64_t *ticks, int64_t *launches, int64_t *captures,
+                          int64_t *replays);
+
+/* Stop the scheduler and free everything (pending requests are dropped). */
+void pf_server_destroy(pf_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFMI_H */

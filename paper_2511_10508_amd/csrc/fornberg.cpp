@@ -1,0 +1,64 @@
+// Host FP64 finite-difference weights by Fornberg's recursion.
+//
+// B. Fornberg, "Generation of finite difference formulas on arbitrarily
+// spaced grids", Math. Comp. 51 (1988) 699-706.  The recursion builds, node
+// by node, the weights of every derivative order m <= M on the first n+1
+// nodes from those on the first n nodes; it is the numerically stable way to
+// obtain the polynomial-interpolation stencils the paper derives at compile
+// time (Sec. "Compile-Time Stencil Generation").
+#include <cmath>
+#include <vector>
+
+namespace pf {
+
+// Weights delta[m][k] of the m-th derivative at x0 on nodes alpha[0..n-1],
+// for m = 0..M.
+std::vector<std::vector<double>> fornberg(double x0, const std::vector<double> &alpha, int M)
+{
+    const int n = (int)alpha.size();
+    std::vector<std::vector<double>> cur(M + 1, std::vector<double>(n, 0.0));
+    std::vector<std::vector<double>> prev = cur;
+    cur[0][0] = 1.0;
+    double c1 = 1.0;
+    for (int i = 1; i < n; ++i) {
+        prev = cur;
+        double c2 = 1.0;
+        const int mmax = i < M ? i : M;
+        for (int k = 0; k < i; ++k) {
+            const double c3 = alpha[i] - alpha[k];
+            c2 *= c3;
+            for (int m = mmax; m >= 0; --m) {
+                const double lower = m > 0 ? prev[m - 1][k] : 0.0;
+                cur[m][k] = ((alpha[i] - x0) * prev[m][k] - m * lower) / c3;
+            }
+        }
+        for (int m = mmax; m >= 0; --m) {
+            const double lower = m > 0 ? prev[m - 1][i - 1] : 0.0;
+            cur[m][i] = c1 / c2 * (m * lower - (alpha[i - 1] - x0) * prev[m][i - 1]);
+        }
+        c1 = c2;
+    }
+    return cur;
+}
+
+// Centred second-derivative weights w[0..r] (w_{-j} = w_j) for accuracy
+// order p = 2r at unit spacing.  Nodes are taken in the order 0, 1, -1, 2,
+// -2, .. so every partial stencil is centred; the two weights of +j and -j
+// are averaged (they agree to rounding).
+bool centered_d2_weights(int order, double *w)
+{
+    if (order < 2 || order % 2 != 0 || order > 16) return false;
+    const int r = order / 2;
+    std::vector<double> alpha;
+    alpha.push_back(0.0);
+    for (int j = 1; j <= r; ++j) {
+        alpha.push_back((double)j);
+        alpha.push_back((double)-j);
+    }
+    const auto d = fornberg(0.0, alpha, 2);
+    w[0] = d[2][0];
+    for (int j = 1; j <= r; ++j) w[j] = 0.5 * (d[2][2 * j - 1] + d[2][2 * j]);
+    return true;
+}
+
+}  // namespace pf

@@ -1,0 +1,76 @@
+// Instantiations and launchers of the 2D fused marching kernels.
+#include "pf_device.h"
+#include "pf_dispatch.h"
+
+namespace pf {
+
+using Fused2DRadii = RList<1, 2, 3, 4>;
+
+bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int32_t *strips,
+                  int32_t *ow, int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads)
+{
+    bool ok = false;
+    dispatch_prec(L.fp32, [&](auto tz) {
+        using T = decltype(tz);
+        dispatch_kind(L.kind, [&](auto kc) {
+            constexpr int KIND = decltype(kc)::value;
+            ok = dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
+                constexpr int R = decltype(rc)::value;
+                using S = Shape<T, KIND, R>;
+                const int64_t st = cdiv(nx, S::OWMAX);
+                int64_t w = cdiv(cdiv(nx, st), S::V) * S::V;
+                *strips = (int32_t)st;
+                *ow = (int32_t)w;
+                *chunks = (int32_t)cdiv(ny, clen);
+                const int64_t it = st * *chunks;
+                *items = (int32_t)it;
+                *blocks = (int32_t)cdiv(it, kWaves2D);
+                *threads = 64 * kWaves2D;
+            });
+        });
+    });
+    return ok;
+}
+
+hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
+                          int red, hipStream_t s)
+{
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_prec(L.fp32, [&](auto tz) {
+        using T = decltype(tz);
+        const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
+        dispatch_kind(L.kind, [&](auto kc) {
+            constexpr int KIND = decltype(kc)::value;
+            dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
+                constexpr int R = decltype(rc)::value;
+                if (red)
+                    hipLaunchKernelGGL((k_step2d<T, KIND, R, true>), dim3(blocks), dim3(threads), 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_step2d<T, KIND, R, false>), dim3(blocks), dim3(threads), 0, s, a);
+                err = hipGetLastError();
+            });
+        });
+    });
+    return err;
+}
+
+hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
+                                  hipStream_t s)
+{
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_prec(L.fp32, [&](auto tz) {
+        using T = decltype(tz);
+        const BatchTable<T> &tb = *static_cast<const BatchTable<T> *>(table);
+        dispatch_kind(L.kind, [&](auto kc) {
+            constexpr int KIND = decltype(kc)::value;
+            dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
+                constexpr int R = decltype(rc)::value;
+                hipLaunchKernelGGL((k_step2d_batched<T, KIND, R>), dim3(blocks), dim3(64 * kWaves2D), 0, s, tb, k);
+                err = hipGetLastError();
+            });
+        });
+    });
+    return err;
+}
+
+}  // namespace pf

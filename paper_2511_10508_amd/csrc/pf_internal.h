@@ -1,0 +1,112 @@
+// Internal interface between the host runtime and the HIP kernels of libpfmi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pf {
+
+constexpr int kAC = 1, kCH = 2, kGS = 3;
+constexpr int kMaxR = 8;            // stencil radius r = order / 2 (order <= 16)
+constexpr int kNumQ = 3;            // reduction quantities per partial slot
+constexpr int kWaves2D = 4;         // waves per workgroup, 2D kernels
+constexpr int kWaves3D = 16;        // waves (= tile rows) per workgroup, 3D kernels
+
+// Reduction quantities of one partial slot:
+//   q0 = sum of field 0, q1 = sum of field 1 (GS) or of the energy density
+//   (AC, CH), q2 = number of non-finite values.  Each is an FP64 (hi, lo)
+//   pair; the runtime scales the sums by dx^d.
+
+// Arguments of one model's step, shared by the single-model and batched
+// launches.  All sizes in elements.  Weights and constants are in the storage
+// precision T (rounded once from FP64 on the host).
+template <typename T>
+struct StepArgs {
+    T *buf[2][2];            // [field][parity]
+    int64_t nx, ny, nz;      // grid extents (nz = 1 in 2D)
+    int64_t pitch;           // row stride
+    int64_t plane;           // plane stride = pitch * ny
+    int32_t parity;          // input buffer of this launch (output = 1 - parity)
+    int32_t strips;          // x strips
+    int32_t ow;              // outputs per strip
+    int32_t ytiles;          // 3D: tiles along y
+    int32_t chunks;          // chunks along the marching axis
+    int32_t clen;            // chunk length
+    int32_t items;           // work items (2D: waves, 3D: workgroups)
+    int32_t red;             // fuse reductions into this launch
+    T wi[kMaxR];             // w_j / dx^2 (inner Laplacian: CH chemical potential)
+    T wu[kMaxR];             // update weights of field 0 (dt-scaled)
+    T wv[kMaxR];             // update weights of field 1 (GS)
+    T k0, k1, k2, k3;        // model constants (see kernels)
+    double w64[kMaxR];       // w_j / dx^2 in FP64 (energy)
+    double c1, c2;           // FP64 Landau constants (energy)
+    double2 *part;           // partial sums [q][slot]
+    int64_t pstride;         // slots per quantity
+};
+
+// Batched (serving) launch: a table of StepArgs, one per request of one
+// kernel class, with work-item prefix sums; a launch processes step `k` of the
+// current tick for every request whose `steps[i]` exceeds k.
+template <typename T>
+struct BatchTable {
+    StepArgs<T> *args;       // device array [n]
+    int32_t *item_start;     // device array [n + 1]
+    int32_t *steps;          // device array [n]: steps of this tick
+    int32_t n;
+};
+
+// Kernel-family launchers (defined in kernels.hip).  Every launcher returns
+// the hipError_t of the launch.
+//   family 0: fused marching kernels; family 1: per-site generic kernels.
+struct Launch {
+    int kind, ndim, r, fp32;
+};
+
+// Fused marching family.  plan_* fills the decomposition for a chunk length
+// and returns false when the family does not cover this (kind, ndim, r).
+bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int32_t *strips,
+                  int32_t *ow, int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads);
+bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen,
+                  int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items,
+                  int32_t *blocks, int32_t *threads);
+hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
+                          int red, hipStream_t s);
+hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
+                          int red, hipStream_t s);
+hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
+                                  hipStream_t s);
+hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
+                                  hipStream_t s);
+
+// Generic per-site family (any r <= kMaxR, 2D and 3D).  CH runs two passes
+// through `scratch` (one field-sized buffer of T, same pitch as the fields).
+hipError_t launch_generic(const Launch &L, const void *args, void *scratch, hipStream_t s);
+
+// Standalone reductions of the state buf[.][parity] (no step).
+hipError_t launch_reduce_state(const Launch &L, const void *args, hipStream_t s);
+int64_t reduce_partial_slots(int64_t nsites);
+
+// Fixed-order compensated combination of `slots` partials per quantity into
+// out[q] (double2 hi, lo), q = 0..kNumQ-1.
+hipError_t launch_finalize(const double2 *part, int64_t pstride, int64_t slots, double2 *out,
+                           hipStream_t s);
+
+// Counter-based initial conditions.
+struct InitArgs {
+    void *f0, *f1;            // field buffers
+    int64_t nx, ny, nz, pitch, plane;
+    int32_t fp32, nfields;
+    int32_t ic;               // 1 uniform, 2 GS cubes, 3 const
+    uint64_t key0, key1;      // per-stream keys (SplitMix64 of seed, stream)
+    double lo, span;          // x = lo + span * u01 (span = hi - lo rounded on the host)
+    double v0, v1;            // const values / (cubes) outside values
+    double in0, in1;          // (cubes) inside values
+    int32_t ncubes, side;
+    int32_t cube[64][3];      // cube corners (x, y, z)
+};
+hipError_t launch_init(const InitArgs &a, hipStream_t s);
+
+// Plain streaming copy (16-byte vectors), for bandwidth calibration.
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
+
+}  // namespace pf

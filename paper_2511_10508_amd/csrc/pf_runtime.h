@@ -1,0 +1,79 @@
+// Host-side model object shared by the runtime and the serving engine.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/pfmi.h"
+#include "pf_internal.h"
+
+namespace pf {
+
+constexpr int kGraphSteps = 32;  // steps per captured graph (pf_step with PF_USE_GRAPH)
+
+struct Model {
+    pf_desc desc{};
+    int nf = 1;
+    bool fp32 = false;
+    Launch L{};
+    int64_t pitch = 0, elems = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false, own_bufs = true;
+    void *buf[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int parity = 0;
+    int64_t steps_done = 0;
+
+    // decomposition of the fused family (family 0) or per-site (family 1)
+    int family = 1;
+    int32_t clen = 0, strips = 0, ow = 0, ytiles = 1, chunks = 0, items = 0, blocks = 0,
+            threads = 0;
+    int64_t fused_slots = 0;
+    StepArgs<double> a64{};
+    StepArgs<float> a32{};
+
+    double2 *part = nullptr;     // partial sums [kNumQ][pstride]
+    int64_t pstride = 0;
+    double2 *res = nullptr;      // finalised reductions [kNumQ]
+    double2 *hist = nullptr;     // per-step reductions [hist_cap][kNumQ]
+    int64_t hist_cap = 0, hist_len = 0;
+    double2 *stage = nullptr;    // graph staging rows [kGraphSteps][kNumQ]
+    void *scratch = nullptr;     // CH mu buffer of the per-site family
+
+    struct Graph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        int par = 0, steps = 0;
+        bool red = false;
+    };
+    std::vector<Graph> graphs;
+    bool graphs_valid = false;
+    int64_t captures = 0, replays = 0, launches = 0;
+
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    size_t ev_used = 0;
+
+    ~Model();
+};
+
+pf_status fail(pf_status s, const std::string &msg);
+pf_status hip_fail(hipError_t e, const char *what);
+pf_status check_desc(const pf_desc *d);
+double stability_limit(const pf_desc *d);
+int nfields_of(int kind);
+int64_t pitch_of(const pf_desc *d);
+int64_t buffer_elems(const pf_desc *d);
+int elem_bytes(const pf_desc *d);
+double volume(const pf_desc &d);
+
+pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int32_t nbufs,
+                       Model **out);
+void pf_destroy_model(Model *m);
+pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int32_t np);
+pf_status set_chunk(Model *m, int32_t chunk);
+pf_status do_steps(Model *m, int64_t nsteps);
+pf_status reduce_now(Model *m, double2 *host_out);
+pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double *hi, double *lo);
+int32_t default_chunk(const pf_desc *d);
+
+}  // namespace pf

@@ -1,0 +1,1026 @@
+// Host runtime and C ABI of libpfmi: model objects, device buffers, the step
+// loop (eager or replayed HIP graphs), reductions, initial conditions,
+// kernel timing and the tile autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pfmi.h"
+#include "pf_internal.h"
+#include "pf_runtime.h"
+
+namespace pf {
+
+bool centered_d2_weights(int order, double *w);
+
+static thread_local std::string g_err;
+
+pf_status fail(pf_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+pf_status hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return PF_ERR_DEVICE;
+}
+
+#define PF_HIP(call, what)                                  \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, what);    \
+    } while (0)
+
+// ------------------------------------------------------------------ desc --
+int nfields_of(int kind) { return kind == kGS ? 2 : 1; }
+
+pf_status check_desc(const pf_desc *d)
+{
+    if (!d) return fail(PF_ERR_ARG, "descriptor is NULL");
+    if (d->struct_size != sizeof(pf_desc))
+        return fail(PF_ERR_ARG, "pf_desc.struct_size does not match this library");
+    if (d->kind != kAC && d->kind != kCH && d->kind != kGS)
+        return fail(PF_ERR_ARG, "unknown model kind");
+    if (d->nfields != nfields_of(d->kind))
+        return fail(PF_ERR_ARG, "nfields does not match the model (AC, CH: 1; GS: 2)");
+    if (d->ndim != 2 && d->ndim != 3) return fail(PF_ERR_ARG, "ndim must be 2 or 3");
+    for (int a = 0; a < 3; ++a)
+        if (d->n[a] < 1) return fail(PF_ERR_ARG, "grid extents must be >= 1");
+    if (d->ndim == 2 && d->n[2] != 1) return fail(PF_ERR_ARG, "2D grids need n[2] == 1");
+    const double N = (double)d->n[0] * (double)d->n[1] * (double)d->n[2];
+    if (N > (double)(1ll << 40)) return fail(PF_ERR_ARG, "grid too large");
+    if (d->n[0] > (1ll << 30) || d->n[1] > (1ll << 30) || d->n[2] > (1ll << 30))
+        return fail(PF_ERR_ARG, "grid extent too large");
+    if (!(d->dx > 0.0) || !std::isfinite(d->dx)) return fail(PF_ERR_ARG, "dx must be > 0");
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(PF_ERR_ARG, "dt must be > 0");
+    if (d->order < 2 || d->order > 16 || d->order % 2)
+        return fail(PF_ERR_ARG, "order must be even, 2..16");
+    if (d->precision != PF_FP64 && d->precision != PF_FP32)
+        return fail(PF_ERR_ARG, "precision must be PF_FP64 or PF_FP32");
+    const int np = d->kind == kGS ? 4 : 2;
+    if (d->nparams != np) return fail(PF_ERR_ARG, "nparams must be 2 (AC, CH) or 4 (GS)");
+    for (int i = 0; i < np; ++i)
+        if (!std::isfinite(d->params[i])) return fail(PF_ERR_ARG, "parameters must be finite");
+    if (d->kind == kGS)
+        for (int i = 0; i < np; ++i)
+            if (d->params[i] < 0.0) return fail(PF_ERR_ARG, "Gray-Scott parameters must be >= 0");
+    return PF_OK;
+}
+
+double stability_limit(const pf_desc *d)
+{
+    double w[kMaxR + 1];
+    centered_d2_weights(d->order, w);
+    double sigma = w[0];
+    for (int j = 1; j <= d->order / 2; ++j) sigma += 2.0 * w[j] * ((j & 1) ? -1.0 : 1.0);
+    const double lam = std::fabs(sigma) * d->ndim / (d->dx * d->dx);
+    double rho;
+    if (d->kind == kAC)
+        rho = lam + 2.0 * std::fabs(d->params[0]);
+    else if (d->kind == kCH)
+        rho = lam * lam + 2.0 * std::fabs(d->params[0]) * lam;
+    else
+        rho = std::max(d->params[0], d->params[1]) * lam + d->params[2] + d->params[3] + 1.0;
+    return 2.0 / rho;
+}
+
+int64_t pitch_of(const pf_desc *d)
+{
+    const int64_t v = d->precision == PF_FP32 ? 4 : 2;  // 16 bytes
+    return (d->n[0] + v - 1) / v * v;
+}
+
+int64_t buffer_elems(const pf_desc *d) { return pitch_of(d) * d->n[1] * d->n[2]; }
+
+int elem_bytes(const pf_desc *d) { return d->precision == PF_FP32 ? 4 : 8; }
+
+// ------------------------------------------------------------ SplitMix64 --
+static uint64_t mix64(uint64_t z)
+{
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static const uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+static uint64_t stream_key(uint64_t seed, uint64_t stream) { return mix64(seed + (stream + 1) * kGolden); }
+static double u01_host(uint64_t key, uint64_t idx)
+{
+    return (double)(mix64(key + (idx + 1) * kGolden) >> 11) * 0x1.0p-53;
+}
+
+// ----------------------------------------------------------------- model --
+Model::~Model() {}
+
+static size_t tsize(const Model *m) { return m->fp32 ? 4 : 8; }
+
+template <typename T>
+static void fill_args(Model *m, StepArgs<T> &a)
+{
+    const pf_desc &d = m->desc;
+    std::memset(&a, 0, sizeof(a));
+    for (int f = 0; f < 2; ++f)
+        for (int p = 0; p < 2; ++p)
+            a.buf[f][p] = static_cast<T *>(m->buf[f < m->nf ? f : 0][p]);
+    a.nx = d.n[0];
+    a.ny = d.n[1];
+    a.nz = d.n[2];
+    a.pitch = m->pitch;
+    a.plane = m->pitch * d.n[1];
+    const int r = d.order / 2;
+    double w[kMaxR + 1];
+    centered_d2_weights(d.order, w);
+    const double idx2 = 1.0 / (d.dx * d.dx);
+    for (int j = 1; j <= r; ++j) {
+        const double wl = w[j] * idx2;
+        a.w64[j - 1] = wl;
+        a.wi[j - 1] = (T)wl;
+        if (d.kind == kGS) {
+            a.wu[j - 1] = (T)(d.dt * d.params[0] * wl);
+            a.wv[j - 1] = (T)(d.dt * d.params[1] * wl);
+        } else {
+            a.wu[j - 1] = (T)(d.dt * wl);
+        }
+    }
+    if (d.kind == kAC) {
+        a.k0 = (T)(d.dt * d.params[0]);
+        a.k1 = (T)(d.dt * d.params[1]);
+    } else if (d.kind == kCH) {
+        a.k0 = (T)d.params[0];
+        a.k1 = (T)d.params[1];
+    } else {
+        a.k0 = (T)(d.dt * d.params[2]);
+        a.k1 = (T)(d.dt * (d.params[2] + d.params[3]));
+        a.k2 = (T)d.dt;
+    }
+    a.c1 = d.kind == kGS ? 0.0 : d.params[0];
+    a.c2 = d.kind == kGS ? 0.0 : d.params[1];
+    a.part = m->part;
+    a.pstride = m->pstride;
+}
+
+// Plan the fused decomposition for the model's chunk length.
+static bool plan(Model *m)
+{
+    Launch L = m->L;
+    const pf_desc &d = m->desc;
+    m->family = 1;
+    if (d.flags & PF_FORCE_GENERIC) return true;
+    int32_t strips, ow, ytiles = 1, chunks, items, blocks, threads;
+    bool ok;
+    if (d.ndim == 2)
+        ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, &strips, &ow, &chunks, &items, &blocks,
+                          &threads);
+    else
+        ok = plan_fused3d(L, d.n[0], d.n[1], d.n[2], m->clen, &strips, &ow, &ytiles, &chunks,
+                          &items, &blocks, &threads);
+    if (!ok) return true;
+    m->family = 0;
+    m->strips = strips;
+    m->ow = ow;
+    m->ytiles = ytiles;
+    m->chunks = chunks;
+    m->items = items;
+    m->blocks = blocks;
+    m->threads = threads;
+    m->fused_slots = d.ndim == 2 ? (int64_t)items : (int64_t)items * kWaves3D;
+    return true;
+}
+
+int32_t default_chunk(const pf_desc *d)
+{
+    const int64_t march = d->ndim == 2 ? d->n[1] : d->n[2];
+    int64_t c = d->ndim == 2 ? 512 : 64;
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(c, march));
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int, int, int>, int32_t> g_tune_cache;
+
+static std::tuple<int, int, int, int, int, int, int> tune_key(const pf_desc &d)
+{
+    auto lg = [](int64_t v) { int b = 0; while ((1ll << (b + 1)) <= v) ++b; return b; };
+    return std::make_tuple(d.kind, d.ndim, d.order, d.precision, lg(d.n[0]), lg(d.n[1]),
+                           lg(d.n[2]));
+}
+
+static pf_status ensure_partials(Model *m)
+{
+    const int64_t N = m->desc.n[0] * m->desc.n[1] * m->desc.n[2];
+    int64_t need = std::max<int64_t>(reduce_partial_slots(N), m->family == 0 ? m->fused_slots : 0);
+    need = std::max<int64_t>(need, 1);
+    if (need <= m->pstride && m->part) return PF_OK;
+    if (m->part) {
+        PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        PF_HIP(hipFree(m->part), "hipFree(partials)");
+        m->part = nullptr;
+    }
+    PF_HIP(hipMalloc((void **)&m->part, sizeof(double2) * kNumQ * need), "hipMalloc(partials)");
+    m->pstride = need;
+    return PF_OK;
+}
+
+// Cache the launch arguments of the model's current plan.
+static void refresh_args(Model *m)
+{
+    auto setp = [&](auto &a) {
+        a.strips = m->strips;
+        a.ow = m->ow;
+        a.ytiles = m->ytiles;
+        a.chunks = m->chunks;
+        a.clen = m->clen;
+        a.items = m->items;
+    };
+    if (m->fp32) {
+        fill_args<float>(m, m->a32);
+        setp(m->a32);
+    } else {
+        fill_args<double>(m, m->a64);
+        setp(m->a64);
+    }
+}
+
+pf_status set_chunk(Model *m, int32_t chunk)
+{
+    m->clen = chunk > 0 ? chunk : default_chunk(&m->desc);
+    plan(m);
+    m->graphs_valid = false;
+    pf_status st = ensure_partials(m);
+    refresh_args(m);
+    return st;
+}
+
+static pf_status ensure_scratch(Model *m)
+{
+    if (m->family == 0 || m->desc.kind != kCH || m->scratch) return PF_OK;
+    PF_HIP(hipMalloc(&m->scratch, tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
+    return PF_OK;
+}
+
+// Launch one step from parity `par` (writes 1 - par).  red: fuse the
+// reductions of the input state; their finalised result goes to `res`.
+static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool timed)
+{
+    const pf_desc &d = m->desc;
+    union {
+        StepArgs<double> d64;
+        StepArgs<float> d32;
+    } u;
+    void *ap;
+    if (m->fp32) {
+        u.d32 = m->a32;
+        u.d32.parity = par;
+        u.d32.red = red;
+        ap = &u.d32;
+    } else {
+        u.d64 = m->a64;
+        u.d64.parity = par;
+        u.d64.red = red;
+        ap = &u.d64;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        if (m->ev_used + 2 > m->events.size()) {
+            hipEvent_t a, b;
+            PF_HIP(hipEventCreate(&a), "hipEventCreate");
+            PF_HIP(hipEventCreate(&b), "hipEventCreate");
+            m->events.push_back(a);
+            m->events.push_back(b);
+        }
+        e0 = m->events[m->ev_used];
+        e1 = m->events[m->ev_used + 1];
+        m->ev_used += 2;
+    }
+    if (m->family == 0) {
+        if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
+        hipError_t e = d.ndim == 2 ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, m->stream)
+                                   : launch_fused3d(m->L, ap, m->blocks, m->threads, red, m->stream);
+        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
+        if (red) {
+            hipError_t f = launch_finalize(m->part, m->pstride, m->fused_slots, res, m->stream);
+            if (f != hipSuccess) return hip_fail(f, "finalize launch");
+        }
+    } else {
+        if (red) {
+            hipError_t e = launch_reduce_state(m->L, ap, m->stream);
+            if (e != hipSuccess) return hip_fail(e, "reduce launch");
+            const int64_t N = d.n[0] * d.n[1] * d.n[2];
+            e = launch_finalize(m->part, m->pstride, reduce_partial_slots(N), res, m->stream);
+            if (e != hipSuccess) return hip_fail(e, "finalize launch");
+        }
+        pf_status st = ensure_scratch(m);
+        if (st != PF_OK) return st;
+        if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
+        hipError_t e = launch_generic(m->L, ap, m->scratch, m->stream);
+        if (e != hipSuccess) return hip_fail(e, "generic step launch");
+        if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
+    }
+    m->launches++;
+    return PF_OK;
+}
+
+static pf_status ensure_history(Model *m, int64_t n)
+{
+    if (n <= m->hist_cap) return PF_OK;
+    if (m->hist) {
+        PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        PF_HIP(hipFree(m->hist), "hipFree(history)");
+        m->hist = nullptr;
+    }
+    const int64_t cap = std::max<int64_t>(n, 1024);
+    PF_HIP(hipMalloc((void **)&m->hist, sizeof(double2) * kNumQ * cap), "hipMalloc(history)");
+    m->hist_cap = cap;
+    return PF_OK;
+}
+
+static void destroy_graphs(Model *m)
+{
+    for (auto &g : m->graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        if (g.graph) hipGraphDestroy(g.graph);
+    }
+    m->graphs.clear();
+    m->graphs_valid = false;
+}
+
+// Capture `k` steps starting at parity `par` (reductions into the staging
+// history rows 0..k-1 when red) as one graph.
+static pf_status capture_graph(Model *m, int par, int k, bool red, Model::Graph &g)
+{
+    g.par = par;
+    g.steps = k;
+    g.red = red;
+    PF_HIP(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    pf_status st = PF_OK;
+    int p = par;
+    for (int i = 0; i < k && st == PF_OK; ++i) {
+        st = launch_step(m, p, red, m->stage + kNumQ * i, false);
+        p ^= 1;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(m->stream, &graph);
+    if (st != PF_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    g.graph = graph;
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    m->captures++;
+    return PF_OK;
+}
+
+pf_status do_steps(Model *m, int64_t nsteps)
+{
+    if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
+    const bool each = (m->desc.flags & PF_REDUCE_EACH_STEP) != 0;
+    if (each) {
+        pf_status st = ensure_history(m, nsteps);
+        if (st != PF_OK) return st;
+        m->hist_len = nsteps;
+    }
+    const bool use_graph = (m->desc.flags & PF_USE_GRAPH) != 0 && !m->timing;
+    int64_t done = 0;
+    if (use_graph && nsteps >= 2 * kGraphSteps) {
+        if (!m->stage) PF_HIP(hipMalloc((void **)&m->stage, sizeof(double2) * kNumQ * kGraphSteps),
+                              "hipMalloc(stage)");
+        if (!m->graphs_valid) {
+            destroy_graphs(m);
+            m->graphs.resize(2);
+            for (int p = 0; p < 2; ++p) {
+                pf_status st = capture_graph(m, p, kGraphSteps, each, m->graphs[p]);
+                if (st != PF_OK) {
+                    destroy_graphs(m);
+                    return st;
+                }
+            }
+            m->graphs_valid = true;
+        }
+        while (nsteps - done >= kGraphSteps) {
+            Model::Graph &g = m->graphs[m->parity];
+            PF_HIP(hipGraphLaunch(g.exec, m->stream), "hipGraphLaunch");
+            m->replays++;
+            if (each)
+                PF_HIP(hipMemcpyAsync(m->hist + kNumQ * done, m->stage,
+                                      sizeof(double2) * kNumQ * kGraphSteps,
+                                      hipMemcpyDeviceToDevice, m->stream),
+                       "hipMemcpyAsync(history)");
+            m->parity ^= (kGraphSteps & 1);
+            done += kGraphSteps;
+            m->steps_done += kGraphSteps;
+        }
+    }
+    for (; done < nsteps; ++done) {
+        pf_status st = launch_step(m, m->parity, each, each ? m->hist + kNumQ * done : nullptr,
+                                   m->timing);
+        if (st != PF_OK) return st;
+        m->parity ^= 1;
+        m->steps_done++;
+    }
+    return PF_OK;
+}
+
+pf_status reduce_now(Model *m, double2 *host_out)
+{
+    union {
+        StepArgs<double> d64;
+        StepArgs<float> d32;
+    } u;
+    void *ap;
+    if (m->fp32) {
+        u.d32 = m->a32;
+        u.d32.parity = m->parity;
+        ap = &u.d32;
+    } else {
+        u.d64 = m->a64;
+        u.d64.parity = m->parity;
+        ap = &u.d64;
+    }
+    const int64_t N = m->desc.n[0] * m->desc.n[1] * m->desc.n[2];
+    hipError_t e = launch_reduce_state(m->L, ap, m->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    e = launch_finalize(m->part, m->pstride, reduce_partial_slots(N), m->res, m->stream);
+    if (e != hipSuccess) return hip_fail(e, "finalize launch");
+    PF_HIP(hipMemcpyAsync(host_out, m->res, sizeof(double2) * kNumQ, hipMemcpyDeviceToHost, m->stream),
+           "hipMemcpyAsync(reductions)");
+    PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    return PF_OK;
+}
+
+double volume(const pf_desc &d)
+{
+    double v = 1.0;
+    for (int a = 0; a < d.ndim; ++a) v *= d.dx;
+    return v;
+}
+
+pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double *hi, double *lo)
+{
+    const pf_desc &d = m->desc;
+    const double vol = volume(d);
+    switch (which) {
+    case PF_RED_MASS0:
+        *hi = q[0].x * vol;
+        *lo = q[0].y * vol;
+        return PF_OK;
+    case PF_RED_MASS1:
+        if (d.kind != kGS) return fail(PF_ERR_UNSUPPORTED, "mass of field 1 needs Gray-Scott");
+        *hi = q[1].x * vol;
+        *lo = q[1].y * vol;
+        return PF_OK;
+    case PF_RED_ENERGY:
+        if (d.kind == kGS) return fail(PF_ERR_UNSUPPORTED, "no free energy for Gray-Scott");
+        *hi = q[1].x * vol;
+        *lo = q[1].y * vol;
+        return PF_OK;
+    case PF_RED_NONFINITE:
+        *hi = q[2].x;
+        *lo = 0.0;
+        return PF_OK;
+    default:
+        return fail(PF_ERR_ARG, "unknown reduction");
+    }
+}
+
+pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int32_t nbufs,
+                       Model **out)
+{
+    pf_status st = check_desc(desc);
+    if (st != PF_OK) return st;
+    if (!out) return fail(PF_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!(desc->flags & PF_ALLOW_UNSTABLE)) {
+        const double lim = stability_limit(desc);
+        if (desc->dt > lim) {
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "dt = %g exceeds the explicit-stability limit %g", desc->dt, lim);
+            return fail(PF_ERR_UNSTABLE, msg);
+        }
+    }
+    Model *m = new Model();
+    m->desc = *desc;
+    m->nf = desc->nfields;
+    m->fp32 = desc->precision == PF_FP32;
+    m->L = Launch{desc->kind, desc->ndim, desc->order / 2, m->fp32 ? 1 : 0};
+    m->pitch = pitch_of(desc);
+    m->elems = buffer_elems(desc);
+    hipError_t e;
+    if (stream) {
+        m->stream = static_cast<hipStream_t>(stream);
+    } else {
+        e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete m;
+            return hip_fail(e, "hipStreamCreate");
+        }
+        m->own_stream = true;
+    }
+    const size_t bytes = tsize(m) * (size_t)m->elems;
+    if (bufs) {
+        if (nbufs != 2 * m->nf) {
+            pf_destroy_model(m);
+            return fail(PF_ERR_ARG, "nbufs must be 2 * nfields");
+        }
+        for (int f = 0; f < m->nf; ++f)
+            for (int p = 0; p < 2; ++p) {
+                void *b = bufs[2 * f + p];
+                if (!b || (reinterpret_cast<uintptr_t>(b) & 15)) {
+                    pf_destroy_model(m);
+                    return fail(PF_ERR_ARG, "device buffers must be non-NULL and 16-byte aligned");
+                }
+                m->buf[f][p] = b;
+            }
+        m->own_bufs = false;
+    } else {
+        for (int f = 0; f < m->nf; ++f)
+            for (int p = 0; p < 2; ++p) {
+                e = hipMalloc(&m->buf[f][p], bytes);
+                if (e != hipSuccess) {
+                    pf_destroy_model(m);
+                    hip_fail(e, "hipMalloc(field)");
+                    return PF_ERR_NOMEM;
+                }
+                e = hipMemsetAsync(m->buf[f][p], 0, bytes, m->stream);
+                if (e != hipSuccess) {
+                    pf_destroy_model(m);
+                    return hip_fail(e, "hipMemsetAsync(field)");
+                }
+            }
+        m->own_bufs = true;
+    }
+    e = hipMalloc((void **)&m->res, sizeof(double2) * kNumQ);
+    if (e != hipSuccess) {
+        pf_destroy_model(m);
+        return hip_fail(e, "hipMalloc(result)");
+    }
+    int32_t chunk = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(tune_key(*desc));
+        if (it != g_tune_cache.end()) chunk = it->second;
+    }
+    st = set_chunk(m, chunk);
+    if (st != PF_OK) {
+        pf_destroy_model(m);
+        return st;
+    }
+    e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+        pf_destroy_model(m);
+        return hip_fail(e, "hipStreamSynchronize");
+    }
+    *out = m;
+    return PF_OK;
+}
+
+void pf_destroy_model(Model *m)
+{
+    if (!m) return;
+    if (m->stream) hipStreamSynchronize(m->stream);
+    destroy_graphs(m);
+    if (m->own_bufs)
+        for (int f = 0; f < 2; ++f)
+            for (int p = 0; p < 2; ++p)
+                if (m->buf[f][p]) hipFree(m->buf[f][p]);
+    if (m->part) hipFree(m->part);
+    if (m->res) hipFree(m->res);
+    if (m->hist) hipFree(m->hist);
+    if (m->stage) hipFree(m->stage);
+    if (m->scratch) hipFree(m->scratch);
+    for (auto ev : m->events) hipEventDestroy(ev);
+    if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
+    delete m;
+}
+
+pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int32_t np)
+{
+    const pf_desc &d = m->desc;
+    InitArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.f0 = m->buf[0][m->parity];
+    a.f1 = m->nf > 1 ? m->buf[1][m->parity] : nullptr;
+    a.nx = d.n[0];
+    a.ny = d.n[1];
+    a.nz = d.n[2];
+    a.pitch = m->pitch;
+    a.plane = m->pitch * d.n[1];
+    a.fp32 = m->fp32;
+    a.nfields = m->nf;
+    a.ic = ic;
+    a.key0 = stream_key(seed, 0);
+    a.key1 = stream_key(seed, 1);
+    if (ic == PF_IC_UNIFORM) {
+        if (np < 2 || !p) return fail(PF_ERR_ARG, "uniform IC needs {lo, hi}");
+        a.lo = p[0];
+        a.span = p[1] - p[0];
+    } else if (ic == PF_IC_GS_CUBES) {
+        if (d.kind != kGS) return fail(PF_ERR_ARG, "cube IC is for Gray-Scott");
+        if (np < 3 || !p) return fail(PF_ERR_ARG, "cube IC needs {ncubes, side, noise}");
+        const int nc = (int)p[0];
+        if (nc < 0 || nc > 64) return fail(PF_ERR_ARG, "ncubes must be 0..64");
+        if (p[1] < 1) return fail(PF_ERR_ARG, "cube side must be >= 1");
+        a.ncubes = nc;
+        a.side = (int32_t)p[1];
+        a.lo = -p[2];
+        a.span = p[2] - (-p[2]);
+        a.v0 = 1.0;
+        a.v1 = 0.0;
+        a.in0 = 0.5;
+        a.in1 = 0.25;
+        const uint64_t k2 = stream_key(seed, 2);
+        const int64_t ext[3] = {d.n[0], d.n[1], d.n[2]};
+        for (int c = 0; c < nc; ++c)
+            for (int ax = 0; ax < 3; ++ax) {
+                const double u = u01_host(k2, (uint64_t)(3 * c + ax));
+                int64_t v = (int64_t)std::floor(u * (double)ext[ax]);
+                a.cube[c][ax] = (int32_t)std::min<int64_t>(v, ext[ax] - 1);
+            }
+    } else if (ic == PF_IC_CONST) {
+        if (np < m->nf || !p) return fail(PF_ERR_ARG, "const IC needs one value per field");
+        a.v0 = p[0];
+        a.v1 = m->nf > 1 ? p[1] : 0.0;
+    } else {
+        return fail(PF_ERR_ARG, "unknown initial condition");
+    }
+    hipError_t e = launch_init(a, m->stream);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    m->steps_done = 0;
+    return PF_OK;
+}
+
+pf_status autotune(Model *m, int32_t trials)
+{
+    if (m->family != 0) return PF_OK;
+    const pf_desc &d = m->desc;
+    const int64_t march = d.ndim == 2 ? d.n[1] : d.n[2];
+    std::vector<int32_t> cand;
+    const int32_t base[] = {16, 32, 64, 128, 256, 512, 1024, 2048};
+    for (int32_t c : base)
+        if (c <= march * 2 || cand.empty()) cand.push_back((int32_t)std::min<int64_t>(c, march));
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    if (trials < 1) trials = 3;
+    const int32_t keep = m->clen;
+    hipEvent_t a, b;
+    PF_HIP(hipEventCreate(&a), "hipEventCreate");
+    PF_HIP(hipEventCreate(&b), "hipEventCreate");
+    float best = 1e30f;
+    int32_t best_c = keep;
+    for (int32_t c : cand) {
+        pf_status st = set_chunk(m, c);
+        if (st != PF_OK) break;
+        // Re-run the step from the current parity: the input buffer is never
+        // written, so the state is untouched.
+        st = launch_step(m, m->parity, false, nullptr, false);
+        if (st != PF_OK) break;
+        (void)hipEventRecord(a, m->stream);
+        for (int t = 0; t < trials && st == PF_OK; ++t) st = launch_step(m, m->parity, false, nullptr, false);
+        (void)hipEventRecord(b, m->stream);
+        (void)hipEventSynchronize(b);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (st == PF_OK && ms < best) {
+            best = ms;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    pf_status st = set_chunk(m, best_c);
+    if (st != PF_OK) return st;
+    m->launches = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[tune_key(d)] = best_c;
+    }
+    return PF_OK;
+}
+
+}  // namespace pf
+
+// ===================================================================== ABI
+using namespace pf;
+
+#define PF_API extern "C" __attribute__((visibility("default")))
+
+PF_API int32_t pf_abi_version(void) { return PF_ABI_VERSION; }
+
+PF_API const char *pf_last_error(void) { return g_err.c_str(); }
+
+PF_API const char *pf_status_str(pf_status s)
+{
+    switch (s) {
+    case PF_OK: return "ok";
+    case PF_ERR_ARG: return "invalid argument";
+    case PF_ERR_UNSTABLE: return "time step above the stability limit";
+    case PF_ERR_NOMEM: return "out of memory";
+    case PF_ERR_DEVICE: return "device error";
+    case PF_ERR_STATE: return "invalid state";
+    case PF_ERR_UNSUPPORTED: return "unsupported";
+    case PF_ERR_BUSY: return "busy";
+    case PF_ERR_NOTFOUND: return "not found";
+    }
+    return "unknown status";
+}
+
+PF_API pf_status pf_weights(int32_t order, double *w)
+{
+    if (!w) return fail(PF_ERR_ARG, "w is NULL");
+    if (!centered_d2_weights(order, w)) return fail(PF_ERR_ARG, "order must be even, 2..16");
+    return PF_OK;
+}
+
+PF_API pf_status pf_stability(const pf_desc *desc, double *dt_max)
+{
+    pf_status st = check_desc(desc);
+    if (st != PF_OK) return st;
+    if (!dt_max) return fail(PF_ERR_ARG, "dt_max is NULL");
+    *dt_max = stability_limit(desc);
+    return PF_OK;
+}
+
+PF_API int64_t pf_buffer_elems(const pf_desc *desc)
+{
+    if (check_desc(desc) != PF_OK) return -1;
+    return buffer_elems(desc);
+}
+
+PF_API uint64_t pf_footprint_bytes(const pf_desc *desc)
+{
+    if (check_desc(desc) != PF_OK) return 0;
+    const uint64_t P = (uint64_t)elem_bytes(desc);
+    const uint64_t N = (uint64_t)(desc->n[0] * desc->n[1] * desc->n[2]);
+    uint64_t bytes = 2ull * desc->nfields * (uint64_t)buffer_elems(desc) * P;
+    // reduction partials (per-wave pairs) and the result block
+    bytes += sizeof(double2) * kNumQ * (uint64_t)std::max<int64_t>(reduce_partial_slots((int64_t)N), N / 64 + 1);
+    bytes += sizeof(double2) * kNumQ;
+    return bytes;
+}
+
+PF_API pf_status pf_create(const pf_desc *desc, void *hip_stream, pf_model **out)
+{
+    Model *m = nullptr;
+    pf_status st = model_create(desc, hip_stream, nullptr, 0, &m);
+    if (out) *out = reinterpret_cast<pf_model *>(m);
+    return st;
+}
+
+PF_API pf_status pf_create_on(const pf_desc *desc, void *hip_stream, void *const *dev_bufs,
+                              int32_t nbufs, pf_model **out)
+{
+    if (!dev_bufs) return fail(PF_ERR_ARG, "dev_bufs is NULL");
+    Model *m = nullptr;
+    pf_status st = model_create(desc, hip_stream, dev_bufs, nbufs, &m);
+    if (out) *out = reinterpret_cast<pf_model *>(m);
+    return st;
+}
+
+PF_API void pf_destroy(pf_model *m) { pf_destroy_model(reinterpret_cast<Model *>(m)); }
+
+static Model *M(pf_model *m) { return reinterpret_cast<Model *>(m); }
+
+PF_API pf_status pf_init(pf_model *m, int32_t ic, uint64_t seed, const double *ic_params,
+                         int32_t n_ic_params)
+{
+    if (!m) return fail(PF_ERR_ARG, "model is NULL");
+    return init_fields(M(m), ic, seed, ic_params, n_ic_params);
+}
+
+PF_API pf_status pf_set_field(pf_model *mm, int32_t field, const double *host, int64_t count)
+{
+    Model *m = M(mm);
+    if (!m || !host) return fail(PF_ERR_ARG, "NULL argument");
+    if (field < 0 || field >= m->nf) return fail(PF_ERR_ARG, "field index out of range");
+    const pf_desc &d = m->desc;
+    const int64_t N = d.n[0] * d.n[1] * d.n[2];
+    if (count != N) return fail(PF_ERR_ARG, "count must equal the number of sites");
+    const size_t ts = tsize(m);
+    std::vector<unsigned char> stage;
+    const void *src = host;
+    if (m->fp32) {
+        stage.resize(ts * (size_t)N);
+        float *s = reinterpret_cast<float *>(stage.data());
+        for (int64_t i = 0; i < N; ++i) s[i] = (float)host[i];
+        src = s;
+    }
+    PF_HIP(hipMemcpy2DAsync(m->buf[field][m->parity], ts * m->pitch, src, ts * d.n[0], ts * d.n[0],
+                            d.n[1] * d.n[2], hipMemcpyHostToDevice, m->stream),
+           "hipMemcpy2DAsync(set_field)");
+    PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    return PF_OK;
+}
+
+PF_API pf_status pf_get_field(pf_model *mm, int32_t field, double *host, int64_t count)
+{
+    Model *m = M(mm);
+    if (!m || !host) return fail(PF_ERR_ARG, "NULL argument");
+    if (field < 0 || field >= m->nf) return fail(PF_ERR_ARG, "field index out of range");
+    const pf_desc &d = m->desc;
+    const int64_t N = d.n[0] * d.n[1] * d.n[2];
+    if (count != N) return fail(PF_ERR_ARG, "count must equal the number of sites");
+    const size_t ts = tsize(m);
+    if (m->fp32) {
+        std::vector<float> stage((size_t)N);
+        PF_HIP(hipMemcpy2DAsync(stage.data(), ts * d.n[0], m->buf[field][m->parity], ts * m->pitch,
+                                ts * d.n[0], d.n[1] * d.n[2], hipMemcpyDeviceToHost, m->stream),
+               "hipMemcpy2DAsync(get_field)");
+        PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        for (int64_t i = 0; i < N; ++i) host[i] = (double)stage[i];
+    } else {
+        PF_HIP(hipMemcpy2DAsync(host, ts * d.n[0], m->buf[field][m->parity], ts * m->pitch,
+                                ts * d.n[0], d.n[1] * d.n[2], hipMemcpyDeviceToHost, m->stream),
+               "hipMemcpy2DAsync(get_field)");
+        PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    }
+    return PF_OK;
+}
+
+PF_API pf_status pf_get_window(pf_model *mm, int32_t field, const int64_t *origin, const int64_t *w,
+                               double *host)
+{
+    Model *m = M(mm);
+    if (!m || !origin || !w || !host) return fail(PF_ERR_ARG, "NULL argument");
+    if (field < 0 || field >= m->nf) return fail(PF_ERR_ARG, "field index out of range");
+    const pf_desc &d = m->desc;
+    for (int a = 0; a < 3; ++a)
+        if (w[a] < 1 || w[a] > d.n[a]) return fail(PF_ERR_ARG, "window extent must be 1..n");
+    const size_t ts = tsize(m);
+    std::vector<unsigned char> row(ts * (size_t)d.n[0]);
+    PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    int64_t k = 0;
+    for (int64_t z = 0; z < w[2]; ++z)
+        for (int64_t y = 0; y < w[1]; ++y) {
+            const int64_t zz = ((origin[2] + z) % d.n[2] + d.n[2]) % d.n[2];
+            const int64_t yy = ((origin[1] + y) % d.n[1] + d.n[1]) % d.n[1];
+            const unsigned char *src = static_cast<const unsigned char *>(m->buf[field][m->parity]) +
+                                       ts * (size_t)(zz * m->pitch * d.n[1] + yy * m->pitch);
+            PF_HIP(hipMemcpy(row.data(), src, ts * (size_t)d.n[0], hipMemcpyDeviceToHost),
+                   "hipMemcpy(window row)");
+            for (int64_t x = 0; x < w[0]; ++x) {
+                const int64_t xx = ((origin[0] + x) % d.n[0] + d.n[0]) % d.n[0];
+                host[k++] = m->fp32 ? (double)reinterpret_cast<const float *>(row.data())[xx]
+                                    : reinterpret_cast<const double *>(row.data())[xx];
+            }
+        }
+    return PF_OK;
+}
+
+PF_API pf_status pf_field_device(pf_model *mm, int32_t field, void **ptr, int64_t *pitch_elems,
+                                 int32_t *eb)
+{
+    Model *m = M(mm);
+    if (!m) return fail(PF_ERR_ARG, "model is NULL");
+    if (field < 0 || field >= m->nf) return fail(PF_ERR_ARG, "field index out of range");
+    if (ptr) *ptr = m->buf[field][m->parity];
+    if (pitch_elems) *pitch_elems = m->pitch;
+    if (eb) *eb = (int32_t)tsize(m);
+    return PF_OK;
+}
+
+PF_API pf_status pf_step(pf_model *m, int64_t nsteps)
+{
+    if (!m) return fail(PF_ERR_ARG, "model is NULL");
+    return do_steps(M(m), nsteps);
+}
+
+PF_API pf_status pf_reduce(pf_model *mm, int32_t which, double *hi, double *lo)
+{
+    Model *m = M(mm);
+    if (!m || !hi || !lo) return fail(PF_ERR_ARG, "NULL argument");
+    double2 q[kNumQ];
+    pf_status st = reduce_now(m, q);
+    if (st != PF_OK) return st;
+    return pick_quantity(m, which, q, hi, lo);
+}
+
+PF_API pf_status pf_reduce_history(pf_model *mm, int32_t which, double *hi, double *lo,
+                                   int64_t count)
+{
+    Model *m = M(mm);
+    if (!m || !hi || !lo) return fail(PF_ERR_ARG, "NULL argument");
+    if (!(m->desc.flags & PF_REDUCE_EACH_STEP)) return fail(PF_ERR_STATE, "PF_REDUCE_EACH_STEP not set");
+    if (count < 0 || count > m->hist_len) return fail(PF_ERR_ARG, "count exceeds the recorded steps");
+    std::vector<double2> h((size_t)count * kNumQ);
+    if (count) {
+        PF_HIP(hipMemcpyAsync(h.data(), m->hist, sizeof(double2) * kNumQ * count, hipMemcpyDeviceToHost,
+                              m->stream),
+               "hipMemcpyAsync(history)");
+    }
+    PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    for (int64_t k = 0; k < count; ++k) {
+        pf_status st = pick_quantity(m, which, &h[(size_t)k * kNumQ], &hi[k], &lo[k]);
+        if (st != PF_OK) return st;
+    }
+    return PF_OK;
+}
+
+PF_API pf_status pf_sync(pf_model *mm)
+{
+    Model *m = M(mm);
+    if (!m) return fail(PF_ERR_ARG, "model is NULL");
+    PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    return PF_OK;
+}
+
+PF_API int64_t pf_steps_done(const pf_model *m)
+{
+    return m ? reinterpret_cast<const Model *>(m)->steps_done : -1;
+}
+
+PF_API pf_status pf_set_steps_done(pf_model *m, int64_t steps)
+{
+    if (!m || steps < 0) return fail(PF_ERR_ARG, "bad argument");
+    M(m)->steps_done = steps;
+    return PF_OK;
+}
+
+PF_API pf_status pf_stream(pf_model *m, void **s)
+{
+    if (!m || !s) return fail(PF_ERR_ARG, "NULL argument");
+    *s = M(m)->stream;
+    return PF_OK;
+}
+
+PF_API pf_status pf_set_tile(pf_model *m, int32_t chunk)
+{
+    if (!m || chunk < 0) return fail(PF_ERR_ARG, "bad argument");
+    PF_HIP(hipStreamSynchronize(M(m)->stream), "hipStreamSynchronize");
+    return set_chunk(M(m), chunk);
+}
+
+PF_API pf_status pf_get_tile(pf_model *m, int32_t *chunk, int32_t *family)
+{
+    if (!m) return fail(PF_ERR_ARG, "model is NULL");
+    if (chunk) *chunk = M(m)->clen;
+    if (family) *family = M(m)->family;
+    return PF_OK;
+}
+
+PF_API pf_status pf_autotune(pf_model *m, int32_t trials)
+{
+    if (!m) return fail(PF_ERR_ARG, "model is NULL");
+    return autotune(M(m), trials);
+}
+
+PF_API pf_status pf_timing_enable(pf_model *mm, int32_t on)
+{
+    Model *m = M(mm);
+    if (!m) return fail(PF_ERR_ARG, "model is NULL");
+    PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    m->timing = on != 0;
+    m->ev_used = 0;
+    return PF_OK;
+}
+
+PF_API pf_status pf_timing_read(pf_model *mm, double *total_ms, int64_t *launches)
+{
+    Model *m = M(mm);
+    if (!m) return fail(PF_ERR_ARG, "model is NULL");
+    PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < m->ev_used; i += 2) {
+        float ms = 0;
+        PF_HIP(hipEventElapsedTime(&ms, m->events[i], m->events[i + 1]), "hipEventElapsedTime");
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)(m->ev_used / 2);
+    return PF_OK;
+}
+
+PF_API pf_status pf_copy_probe(void *dst, const void *src, uint64_t bytes, void *hip_stream,
+                               int32_t reps, double *ms_per_rep)
+{
+    if (!dst || !src || (bytes & 15) || (reinterpret_cast<uintptr_t>(dst) & 15) ||
+        (reinterpret_cast<uintptr_t>(src) & 15))
+        return fail(PF_ERR_ARG, "copy probe needs 16-byte aligned pointers and size");
+    if (reps < 1) reps = 1;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t a, b;
+    PF_HIP(hipEventCreate(&a), "hipEventCreate");
+    PF_HIP(hipEventCreate(&b), "hipEventCreate");
+    hipError_t e = launch_copy(dst, src, bytes, s);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_copy(dst, src, bytes, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "copy probe");
+    if (ms_per_rep) *ms_per_rep = ms / reps;
+    return PF_OK;
+}

@@ -1,0 +1,117 @@
+"""Host-side checks of libpfmi: it loads, exports every declared symbol, and
+its host logic (weights, stability limit, footprint, descriptor validation)
+agrees with the oracle and the paper's table.  No device calls."""
+import ctypes
+import math
+import os
+import re
+from fractions import Fraction
+
+import pytest
+
+import oracle
+import paper_2511_10508_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pfmi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = _declared()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(P.SIGNATURES), set(names) ^ set(P.SIGNATURES)
+
+
+def test_single_hip_runtime_and_version():
+    P.lib()
+    assert len(P.hip_runtimes_mapped()) == 1
+    assert P.lib().pf_abi_version() == 1
+    assert P.lib().pf_status_str(2) == b"time step above the stability limit"
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_fornberg_matches_exact_weights(order):
+    w = P.weights(order)
+    exact = oracle.second_derivative_weights_exact(order)
+    for a, e in zip(w, exact):
+        assert abs(Fraction(float(a)) - e) <= 8 * Fraction(math.ulp(float(e)) or 2.0 ** -1074) + Fraction(1, 10 ** 14) * abs(e)
+
+
+def test_weights_reject_bad_order():
+    with pytest.raises(P.PfError):
+        P.weights(3)
+    with pytest.raises(P.PfError):
+        P.weights(18)
+
+
+@pytest.mark.parametrize("kind,ndim,order,params", [
+    (P.PF_AC, 2, 2, [1.0, 1.0]), (P.PF_CH, 2, 4, [1.0, 1.0]), (P.PF_CH, 3, 6, [1.0, 1.0]),
+    (P.PF_GS, 3, 2, [0.2, 0.1, 0.04, 0.06]), (P.PF_AC, 3, 8, [0.7, 1.3]),
+])
+def test_stability_matches_oracle(kind, ndim, order, params):
+    n = (16,) * ndim
+    d = P.make_desc(kind, n, dx=0.9, order=order, params=params)
+    assert math.isclose(P.stability(d), oracle.dt_max(kind, ndim, 0.9, order, params), rel_tol=1e-12)
+
+
+def test_footprint_against_paper_table():
+    """Paper Table memory-footprint: m = 2f + f0.  The fused kernels keep no
+    temporary (f0 = 0), so Model A stays m = 2 and Model B drops from 3 to 2."""
+    rows = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "memory_footprint.txt")):
+        if line.strip() and not line.startswith("#"):
+            name, f, f0, m = line.split()
+            rows[name] = (int(f), int(f0), int(m))
+    assert rows["A"] == (1, 0, 2) and rows["B"] == (1, 1, 3)
+    for kind, name, P_ in ((P.PF_AC, "A", 8), (P.PF_CH, "B", 8), (P.PF_AC, "A", 4)):
+        prec = P.PF_FP64 if P_ == 8 else P.PF_FP32
+        d = P.make_desc(kind, (1024, 1024), precision=prec)
+        f, f0, m = rows[name]
+        per_site = P.footprint_bytes(d) / (1024 * 1024 * P_)
+        assert 2 * f <= per_site < 2 * f + 0.2
+    d = P.make_desc(P.PF_GS, (256, 256, 256))
+    assert 4 <= P.footprint_bytes(d) / (256 ** 3 * 8) < 4.2
+
+
+def test_padded_pitch_and_buffer_elems():
+    d = P.make_desc(P.PF_AC, (13, 7), precision=P.PF_FP64)
+    assert P.buffer_elems(d) == 14 * 7
+    d = P.make_desc(P.PF_AC, (13, 7), precision=P.PF_FP32)
+    assert P.buffer_elems(d) == 16 * 7
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda d: setattr(d, "kind", 9), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "nfields", 2), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "order", 3), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "order", 18), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "dt", -1.0), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "dx", 0.0), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "ndim", 4), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "nparams", 3), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "struct_size", 8), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "precision", 7), P.PF_ERR_ARG),
+    (lambda d: setattr(d, "dt", 1.0), P.PF_ERR_UNSTABLE),
+])
+def test_create_rejects_bad_descriptors_before_touching_the_device(mutate, status):
+    d = P.make_desc(P.PF_CH, (64, 64), dt=0.01, order=4)
+    mutate(d)
+    h = ctypes.c_void_p()
+    assert P.lib().pf_create(ctypes.byref(d), None, ctypes.byref(h)) == status
+    assert not h.value
+    assert P.lib().pf_last_error()
+
+
+def test_gray_scott_dt1_in_3d_is_refused():
+    d = P.make_desc(P.PF_GS, (512, 512, 512), dt=1.0)
+    h = ctypes.c_void_p()
+    assert P.lib().pf_create(ctypes.byref(d), None, ctypes.byref(h)) == P.PF_ERR_UNSTABLE
+    assert P.stability(d) > 0.5  # the proposed dt = 0.5 is accepted
