@@ -1,0 +1,185 @@
+"""Benchmark of the explicit FD phase-field step on one MI355X.
+
+Workload (the headline one): 2D Cahn-Hilliard dc/dt = lap(c^3 - c - lap c) on
+a 32768^2 periodic grid, dx = 1, dt = 0.01, 4th-order Laplacian applied
+twice, c0 = U[-0.05, 0.05] (seed 202), synthetic data.  One step = one
+forward-Euler update of every site with the mass / free-energy reductions of
+the state fused into the same kernel (the whole hot path).  `value` is FP64
+site-updates/s; the FP32-storage run is reported beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu] [--skip-fp32]
+                    [--serving N]
+
+Prints one JSON line.  The roofline object covers the dominant kernel (the
+fused step): achieved = algorithmic bytes per launch (2 * fields * bytes per
+value * sites: every field read once and written once) / mean kernel time,
+timed with HIP events on the model's stream.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2511_10508_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tag, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % tag)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(P, torch, nbytes=2 ** 31, reps=10):
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    ms = ctypes.c_double()
+    P.check(P.lib().pf_copy_probe(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                  nbytes, None, reps, ctypes.byref(ms)))
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms.value * 1e-3) / 1e9
+
+
+def run_ch(P, n, prec, steps, warmup, seed=202):
+    d = P.make_desc(P.PF_CH, (n, n), dx=1.0, dt=0.01, order=4, precision=prec,
+                    params=[1.0, 1.0], flags=P.PF_REDUCE_EACH_STEP)
+    m = P.Model(d)
+    m.init(P.PF_IC_UNIFORM, seed, (-0.05, 0.05))
+    m.autotune(2)
+    m.step(warmup)
+    m.sync()
+    m.timing(True)
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.sync()
+    t1 = time.perf_counter()
+    kernel_ms, launches = m.timing_read()
+    hi, lo = m.reduce_history(P.PF_RED_MASS0, steps)
+    mass = hi + lo
+    drift = float(abs(mass - mass[0]).max())
+    chunk, family = m.tile()
+    m.close()
+    sites = float(n) * n
+    wall = t1 - t0
+    per_launch = kernel_ms / launches
+    alg_bytes = 2 * 1 * (8 if prec == P.PF_FP64 else 4) * sites
+    return dict(sites=sites, wall=wall, su_s=sites * steps / wall, ms_per_step=wall / steps * 1e3,
+                kernel_ms=per_launch, alg_bytes=alg_bytes,
+                achieved_gbs=alg_bytes / (per_launch * 1e-3) / 1e9, mass_drift=drift,
+                chunk=chunk, family=family)
+
+
+def cpu_baseline(n=2048, steps=3):
+    """The oracle as it stands on the host cores: CH 2D p4 FP64 on an n^2 sample."""
+    import numpy as np
+    import oracle
+    import synth
+    oracle.build()
+    f0 = synth.initial_fields(2, (1, n, n), 202, synth.IC_UNIFORM, (-0.05, 0.05))
+    oracle.run(2, f0, 2, 1.0, 0.01, 4, [1.0, 1.0], 1)  # warm
+    t0 = time.perf_counter()
+    oracle.run(2, f0, 2, 1.0, 0.01, 4, [1.0, 1.0], steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0) or os.cpu_count() or 1)
+    return dict(value=n * n * steps / dt, unit="site-updates/s", cores=cores, kind="oracle",
+                sample="2D Cahn-Hilliard %d^2 p4 FP64, %d steps (%.1f s)" % (n, steps, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="also run the serving comparison with this many requests")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(requests shard per GPU, the solver by slabs; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2511_10508_amd as P
+    P.lib()
+    assert torch.cuda.is_available(), "no GPU visible"
+
+    attain = copy_probe(P, torch)
+    src = source_hash()
+    fp64 = run_ch(P, args.n, P.PF_FP64, args.steps, args.warmup)
+    extra = {"copy_probe_gbs": round(attain, 1), "source_hash": src}
+    if not args.skip_fp32:
+        fp32 = run_ch(P, args.n, P.PF_FP32, args.steps, args.warmup)
+        extra["fp32"] = {
+            "value": fp32["su_s"], "ms_per_step": round(fp32["ms_per_step"], 4),
+            "kernel_ms": round(fp32["kernel_ms"], 4), "achieved_gbs": round(fp32["achieved_gbs"], 1),
+            "frac_of_peak": round(fp32["achieved_gbs"] / PEAK_GBS, 4),
+            "mass_drift": fp32["mass_drift"], "chunk": fp32["chunk"]}
+    extra["fp64_mass_drift"] = fp64["mass_drift"]
+    extra["fp64_chunk"] = fp64["chunk"]
+    if args.serving:
+        from paper_2511_10508_amd import serving
+        extra["serving"] = serving.compare(args.serving)
+
+    traffic = measured_traffic("ch2d_%d_fp64" % args.n, src)
+    out = {
+        "metric": "site-updates/s & % HBM peak (FP64 vs FP32); serving p50/p99 vs serial",
+        "value": fp64["su_s"],
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fp64["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D Cahn-Hilliard %d^2 periodic, dx=1, dt=0.01, 4th-order "
+                               "Laplacian applied twice, c0=U[-0.05,0.05] seed 202, fused "
+                               "mass/energy reductions every step" % args.n,
+                   "grid": [args.n, args.n], "order": 4, "fields": 1, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(fp64["achieved_gbs"], 1),
+                     "peak": PEAK_GBS, "unit": "GB/s",
+                     "frac": round(fp64["achieved_gbs"] / PEAK_GBS, 4),
+                     "traffic": traffic},
+        "extra": extra,
+    }
+    if not args.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -121,39 +121,68 @@ __global__ void __launch_bounds__(256) k_reduce_state(StepArgs<T> a, int ndim)
     red_flush(red, a.part, a.pstride, slot, threadIdx.x & 63);
 }
 
-// One workgroup combines every partial: thread t takes slots t, t + 1024, ..
-// in order, then a fixed binary tree in LDS.  The result is renormalised.
-__global__ void __launch_bounds__(1024) k_finalize(const double2 *part, int64_t pstride,
-                                                   int64_t slots, double2 *out)
+// Fixed-order combination of the partials in two levels: block b of the
+// first level takes a contiguous range of slots (thread t: slots t, t + 256,
+// .. of the range, compensated), reduces it with a fixed binary tree in LDS
+// and writes one pair per quantity; one block then combines those pairs the
+// same way.  The result depends only on the slot count, never on timing.
+constexpr int kFin = 256;
+
+__device__ __forceinline__ Acc block_tree(Acc a, double *sh, double *sl)
 {
-    __shared__ double sh[1024], sl[1024];
     const int t = threadIdx.x;
+    sh[t] = a.hi;
+    sl[t] = a.lo;
+    __syncthreads();
+    for (int w = kFin / 2; w >= 1; w >>= 1) {
+        if (t < w) {
+            Acc x{sh[t], sl[t]};
+            const Acc y{sh[t + w], sl[t + w]};
+            acc_merge(x, y);
+            sh[t] = x.hi;
+            sl[t] = x.lo;
+        }
+        __syncthreads();
+    }
+    Acc r{sh[0], sl[0]};
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kFin) k_finalize1(const double2 *part, int64_t pstride,
+                                                    int64_t slots, double2 *part2)
+{
+    __shared__ double sh[kFin], sl[kFin];
+    const int64_t per = (slots + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = min(slots, lo + per);
     for (int q = 0; q < kNumQ; ++q) {
         Acc a{0.0, 0.0};
-        for (int64_t i = t; i < slots; i += 1024) {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kFin) {
             const double2 p = part[q * pstride + i];
             acc_add(a, p.x);
             a.lo += p.y;
         }
-        sh[t] = a.hi;
-        sl[t] = a.lo;
-        __syncthreads();
-        for (int w = 512; w >= 1; w >>= 1) {
-            if (t < w) {
-                Acc x{sh[t], sl[t]};
-                const Acc y{sh[t + w], sl[t + w]};
-                acc_merge(x, y);
-                sh[t] = x.hi;
-                sl[t] = x.lo;
-            }
-            __syncthreads();
+        const Acc r = block_tree(a, sh, sl);
+        if (threadIdx.x == 0) part2[q * kFin + blockIdx.x] = make_double2(r.hi, r.lo);
+    }
+}
+
+__global__ void __launch_bounds__(kFin) k_finalize2(const double2 *part2, int nb, double2 *out)
+{
+    __shared__ double sh[kFin], sl[kFin];
+    for (int q = 0; q < kNumQ; ++q) {
+        Acc a{0.0, 0.0};
+        if ((int)threadIdx.x < nb) {
+            const double2 p = part2[q * kFin + threadIdx.x];
+            a.hi = p.x;
+            a.lo = p.y;
         }
-        if (t == 0) {
-            const double s = sh[0] + sl[0];
-            const double e = sl[0] - (s - sh[0]);
-            out[q] = make_double2(s, e);
+        const Acc r = block_tree(a, sh, sl);
+        if (threadIdx.x == 0) {
+            const double s = r.hi + r.lo;
+            out[q] = make_double2(s, r.lo - (s - r.hi));
         }
-        __syncthreads();
     }
 }
 
@@ -276,10 +305,14 @@ hipError_t launch_reduce_state(const Launch &L, const void *args, hipStream_t s)
     return err;
 }
 
-hipError_t launch_finalize(const double2 *part, int64_t pstride, int64_t slots, double2 *out,
-                           hipStream_t s)
+hipError_t launch_finalize(const double2 *part, int64_t pstride, int64_t slots, double2 *part2,
+                           double2 *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, part, pstride, slots, out);
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kFin, cdiv(slots, kFin)));
+    hipLaunchKernelGGL(k_finalize1, dim3(nb), dim3(kFin), 0, s, part, pstride, slots, part2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kFin), 0, s, part2, nb, out);
     return hipGetLastError();
 }
 

@@ -48,13 +48,20 @@ __device__ __forceinline__ void vload(const float *p, float (&o)[4])
     o[2] = q.z;
     o[3] = q.w;
 }
+// Field stores are streaming: nothing in the same step reads them back, so
+// they are written non-temporally (they do not displace the input rows and
+// halos that neighbouring strips still read from the caches).
+typedef double pf_d2v __attribute__((ext_vector_type(2)));
+typedef float pf_f4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void vstore(double *p, const double (&o)[2])
 {
-    *reinterpret_cast<double2 *>(p) = make_double2(o[0], o[1]);
+    const pf_d2v v = {o[0], o[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<pf_d2v *>(p));
 }
 __device__ __forceinline__ void vstore(float *p, const float (&o)[4])
 {
-    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+    const pf_f4v v = {o[0], o[1], o[2], o[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<pf_f4v *>(p));
 }
 
 // ---------------------------------------------------------------------------
@@ -197,22 +204,25 @@ __device__ __forceinline__ int32_t xcd_item(int32_t b, int32_t nwg)
     return x * per + (x < rem ? x : rem) + q;
 }
 
-// Gather the x-neighbourhood of a lane's V values: e[(d + D) V + v] holds
-// element v of lane (lane + d), d = -D..D.  Edge lanes receive values from
-// the other end of the wave; their results are masked as halo.
-template <typename T, int V, int D>
-__device__ __forceinline__ void gather_x(const T (&c)[V], T (&e)[(2 * D + 1) * V])
+// Gather the x-neighbourhood a radius-R stencil needs around a lane's V
+// values: e[k + R] is the value at column offset k (k = -R .. V-1+R) from the
+// lane's first column, taken from lane floor(k / V) away by a lane shuffle.
+// Edge lanes receive values from the other end of the wave; their results
+// are masked as halo.
+template <typename T, int V, int R>
+__device__ __forceinline__ void gather_x(const T (&c)[V], T (&e)[V + 2 * R])
 {
-#pragma unroll
-    for (int v = 0; v < V; ++v) e[D * V + v] = c[v];
-#pragma unroll
-    for (int d = 1; d <= D; ++d) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            e[(D + d) * V + v] = __shfl_down(c[v], d);
-            e[(D - d) * V + v] = __shfl_up(c[v], d);
-        }
-    }
+    static_for<0, V + 2 * R>([&](auto kc) {
+        constexpr int k = decltype(kc)::value - R;
+        constexpr int d = k >= 0 ? k / V : -((-k + V - 1) / V);
+        constexpr int el = k - d * V;
+        if constexpr (d == 0)
+            e[k + R] = c[el];
+        else if constexpr (d > 0)
+            e[k + R] = __shfl_down(c[el], d);
+        else
+            e[k + R] = __shfl_up(c[el], -d);
+    });
 }
 
 template <typename T, int KIND, int R>
@@ -222,36 +232,62 @@ struct Shape {
     static constexpr int HV = (H + V - 1) / V * V;     // halo rounded to whole lanes
     static constexpr int SW = 64 * V;                  // strip width (loaded columns)
     static constexpr int OWMAX = SW - 2 * HV;          // most outputs per strip
-    static constexpr int D = (R + V - 1) / V;          // neighbour lanes per side
-    static constexpr int NE = (2 * D + 1) * V;
+    static constexpr int NE = V + 2 * R;               // gathered x-neighbourhood
     static constexpr int K = 2 * R + 1;                // ring length (rows or planes)
     static constexpr int NF = KIND == kGS ? 2 : 1;
 };
 
-// Load the lane's V values of one row (x from xl, wrapped per element unless
-// the whole strip lies inside the row).
-template <typename T, int V>
-__device__ __forceinline__ void load_row(const T *__restrict__ row, int64_t xl, int64_t nx,
-                                         bool fast, T (&o)[V])
-{
-    if (fast) {
-        vload(row + xl, o);
-    } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) o[v] = row[wrap_any(xl + v, nx)];
-    }
-}
+// Row access of one lane.  FAST strips lie inside the row: the row pointer
+// plus the strip start is wave-uniform and the lane adds a constant offset,
+// so loads and stores are plain 16-byte vector accesses with no per-row
+// vector address arithmetic.  Edge strips wrap each column once, up front.
+template <typename T, int V, bool FAST>
+struct RowIO;
 
 template <typename T, int V>
-__device__ __forceinline__ void store_row(T *__restrict__ row, int64_t xl, bool all,
-                                          const bool (&ov)[V], const T (&o)[V])
+struct RowIO<T, V, true> {
+    int64_t xb;  // first column of the strip (uniform)
+    int lo;      // lane * V
+    __device__ __forceinline__ RowIO(int64_t xb_, int lane, int64_t) : xb(xb_), lo(lane * V) {}
+    __device__ __forceinline__ void load(const T *__restrict__ row, T (&o)[V]) const
+    {
+        vload(row + xb + lo, o);
+    }
+};
+
+template <typename T, int V>
+struct RowIO<T, V, false> {
+    int64_t col[V];
+    __device__ __forceinline__ RowIO(int64_t xb, int lane, int64_t nx)
+    {
+#pragma unroll
+        for (int v = 0; v < V; ++v) col[v] = wrap_any(xb + lane * V + v, nx);
+    }
+    __device__ __forceinline__ void load(const T *__restrict__ row, T (&o)[V]) const
+    {
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = row[col[v]];
+    }
+};
+
+// Output mask of a lane: which of its V columns are written, and whether all
+// are (then one vector store).
+template <int V>
+struct OutMask {
+    bool ov[V];
+    bool all;
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void store_row(T *__restrict__ row, int64_t xl, const OutMask<V> &m,
+                                          const T (&o)[V])
 {
-    if (all) {
+    if (m.all) {
         vstore(row + xl, o);
     } else {
 #pragma unroll
         for (int v = 0; v < V; ++v)
-            if (ov[v]) row[xl + v] = o[v];
+            if (m.ov[v]) row[xl + v] = o[v];
     }
 }
 
@@ -262,30 +298,23 @@ __device__ __forceinline__ void store_row(T *__restrict__ row, int64_t xl, bool 
 // (and for CH of mu) in registers.  Loads run K rows ahead (prefetch ring).
 // CH computes mu = c2 c^3 - c1 c - L c for row t - r and the update for row
 // t - 2r in the same sweep: the biharmonic never touches memory.
-template <typename T, int KIND, int R, bool RED>
-__device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32_t item,
-                                            int lane, int64_t pslot)
+template <typename T, int KIND, int R, bool RED, bool FAST>
+__device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t xb, int64_t y0,
+                                        int64_t y1, int lane, int64_t pslot)
 {
     using S = Shape<T, KIND, R>;
-    constexpr int V = S::V, H = S::H, HV = S::HV, SW = S::SW, D = S::D, NE = S::NE, K = S::K,
-                  NF = S::NF;
-    const int32_t strip = item % a.strips;
-    const int32_t chunk = item / a.strips;
+    constexpr int V = S::V, H = S::H, HV = S::HV, NE = S::NE, K = S::K, NF = S::NF;
     const int64_t nx = a.nx, ny = a.ny, pitch = a.pitch;
-    const int64_t x0 = (int64_t)strip * a.ow;
-    const int64_t xb = x0 - HV;
     const int64_t xl = xb + lane * V;
-    const bool fast = (xb >= 0) && (xb + SW <= nx);
-    const int64_t y0 = (int64_t)chunk * a.clen;
-    const int64_t y1 = min(y0 + (int64_t)a.clen, ny);
     const int pl = lane * V;
-    bool ov[V];
-    bool allv = true;
+    OutMask<V> om;
+    om.all = true;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        ov[v] = (pl + v >= HV) && (pl + v < HV + a.ow) && (xl + v < nx);
-        allv = allv && ov[v];
+        om.ov[v] = (pl + v >= HV) && (pl + v < HV + a.ow) && (xl + v < nx);
+        om.all = om.all && om.ov[v];
     }
+    const RowIO<T, V, FAST> io(xb, lane, nx);
     const T *in[2] = {a.buf[0][par], a.buf[NF - 1][par]};
     T *out[2] = {a.buf[0][par ^ 1], a.buf[NF - 1][par ^ 1]};
 
@@ -301,7 +330,7 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
         if (t < tend) {
             const int64_t off = wrap_any(t, ny) * pitch;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) load_row<T, V>(in[f] + off, xl, nx, fast, pre[f][ph]);
+            for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
         }
     });
 
@@ -317,8 +346,7 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
                 if (t + K < tend) {
                     const int64_t off = wrap_any(t + K, ny) * pitch;
 #pragma unroll
-                    for (int f = 0; f < NF; ++f)
-                        load_row<T, V>(in[f] + off, xl, nx, fast, pre[f][ph]);
+                    for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
                 }
                 if constexpr (KIND != kCH) {
                     constexpr int co = (ph - R + K) % K;
@@ -326,8 +354,9 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
                     if (o >= y0) {
                         T e[NF][NE];
 #pragma unroll
-                        for (int f = 0; f < NF; ++f) gather_x<T, V, D>(ring[f][co], e[f]);
+                        for (int f = 0; f < NF; ++f) gather_x<T, V, R>(ring[f][co], e[f]);
                         T res[NF][V];
+                        double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             T Sf[NF][R];
@@ -336,7 +365,7 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
                                 constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
 #pragma unroll
                                 for (int f = 0; f < NF; ++f)
-                                    Sf[f][j - 1] = (e[f][D * V + v + j] + e[f][D * V + v - j]) +
+                                    Sf[f][j - 1] = (e[f][R + v + j] + e[f][R + v - j]) +
                                                    (ring[f][sp][v] + ring[f][sm][v]);
                             });
                             const T u0 = ring[0][co][v];
@@ -348,33 +377,37 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
                                                 v0 * T(4), res[0][v], res[NF - 1][v]);
                             }
                             if constexpr (RED) {
-                                if (ov[v]) {
+                                if (om.ov[v]) {
                                     const double x = (double)u0;
-                                    acc_add(red.q0, x);
-                                    red.bad += finite_val(x) ? 0.0 : 1.0;
+                                    rs0 += x;
+                                    rbad += finite_val(x) ? 0.0 : 1.0;
                                     if constexpr (KIND == kAC) {
                                         double S64[R];
                                         static_for<1, R + 1>([&](auto jc) {
                                             constexpr int j = decltype(jc)::value;
                                             constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
-                                            S64[j - 1] = ((double)e[0][D * V + v + j] +
-                                                          (double)e[0][D * V + v - j]) +
+                                            S64[j - 1] = ((double)e[0][R + v + j] +
+                                                          (double)e[0][R + v - j]) +
                                                          ((double)ring[0][sp][v] +
                                                           (double)ring[0][sm][v]);
                                         });
-                                        acc_add(red.q1, energy_density<R>(a.c1, a.c2, a.w64, x,
-                                                                          S64, x * 4.0));
+                                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
                                     } else {
                                         const double y = (double)ring[NF - 1][co][v];
-                                        acc_add(red.q1, y);
-                                        red.bad += finite_val(y) ? 0.0 : 1.0;
+                                        rs1 += y;
+                                        rbad += finite_val(y) ? 0.0 : 1.0;
                                     }
                                 }
                             }
                         }
+                        if constexpr (RED) {
+                            acc_add(red.q0, rs0);
+                            acc_add(red.q1, rs1);
+                            red.bad += rbad;
+                        }
                         const int64_t ooff = wrap_any(o, ny) * pitch;
 #pragma unroll
-                        for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, allv, ov, res[f]);
+                        for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
                     }
                 } else {
                     // chemical potential of row m = t - r
@@ -382,35 +415,42 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
                     const int64_t m = t - R;
                     if (m >= y0 - R) {
                         T e[NE];
-                        gather_x<T, V, D>(ring[0][cm], e);
+                        gather_x<T, V, R>(ring[0][cm], e);
+                        double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+                        const bool red_row = RED && m >= y0 && m < y1;
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             T Sc[R];
                             static_for<1, R + 1>([&](auto jc) {
                                 constexpr int j = decltype(jc)::value;
                                 constexpr int sp = (cm + j) % K, sm = (cm - j + K) % K;
-                                Sc[j - 1] = (e[D * V + v + j] + e[D * V + v - j]) +
+                                Sc[j - 1] = (e[R + v + j] + e[R + v - j]) +
                                             (ring[0][sp][v] + ring[0][sm][v]);
                             });
                             const T c0 = ring[0][cm][v];
                             mring[cm][v] = ch_mu<T, R>(a, c0, Sc, c0 * T(4));
                             if constexpr (RED) {
-                                if (ov[v] && m >= y0 && m < y1) {
+                                if (red_row && om.ov[v]) {
                                     const double x = (double)c0;
                                     double S64[R];
                                     static_for<1, R + 1>([&](auto jc) {
                                         constexpr int j = decltype(jc)::value;
                                         constexpr int sp = (cm + j) % K, sm = (cm - j + K) % K;
-                                        S64[j - 1] = ((double)e[D * V + v + j] +
-                                                      (double)e[D * V + v - j]) +
+                                        S64[j - 1] = ((double)e[R + v + j] + (double)e[R + v - j]) +
                                                      ((double)ring[0][sp][v] +
                                                       (double)ring[0][sm][v]);
                                     });
-                                    acc_add(red.q0, x);
-                                    acc_add(red.q1,
-                                            energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0));
-                                    red.bad += finite_val(x) ? 0.0 : 1.0;
+                                    rs0 += x;
+                                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                                    rbad += finite_val(x) ? 0.0 : 1.0;
                                 }
+                            }
+                        }
+                        if constexpr (RED) {
+                            if (red_row) {
+                                acc_add(red.q0, rs0);
+                                acc_add(red.q1, rs1);
+                                red.bad += rbad;
                             }
                         }
                     }
@@ -419,7 +459,7 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
                     const int64_t o = t - 2 * R;
                     if (o >= y0) {
                         T em[NE];
-                        gather_x<T, V, D>(mring[co], em);
+                        gather_x<T, V, R>(mring[co], em);
                         T res[V];
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
@@ -427,18 +467,34 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
                             static_for<1, R + 1>([&](auto jc) {
                                 constexpr int j = decltype(jc)::value;
                                 constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
-                                Sm[j - 1] = (em[D * V + v + j] + em[D * V + v - j]) +
+                                Sm[j - 1] = (em[R + v + j] + em[R + v - j]) +
                                             (mring[sp][v] + mring[sm][v]);
                             });
                             res[v] = ch_update<T, R>(a, ring[0][co][v], Sm, mring[co][v] * T(4));
                         }
-                        store_row<T, V>(out[0] + wrap_any(o, ny) * pitch, xl, allv, ov, res);
+                        store_row<T, V>(out[0] + wrap_any(o, ny) * pitch, xl, om, res);
                     }
                 }
             }
         });
     }
     if constexpr (RED) red_flush(red, a.part, a.pstride, pslot, lane);
+}
+
+template <typename T, int KIND, int R, bool RED>
+__device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32_t item,
+                                            int lane, int64_t pslot)
+{
+    using S = Shape<T, KIND, R>;
+    const int32_t strip = item % a.strips;
+    const int32_t chunk = item / a.strips;
+    const int64_t xb = (int64_t)strip * a.ow - S::HV;
+    const int64_t y0 = (int64_t)chunk * a.clen;
+    const int64_t y1 = min(y0 + (int64_t)a.clen, a.ny);
+    if (xb >= 0 && xb + S::SW <= a.nx)
+        march2d<T, KIND, R, RED, true>(a, par, xb, y0, y1, lane, pslot);
+    else
+        march2d<T, KIND, R, RED, false>(a, par, xb, y0, y1, lane, pslot);
 }
 
 template <typename T, int KIND, int R, bool RED>
@@ -451,21 +507,35 @@ __global__ void __launch_bounds__(64 * kWaves2D) k_step2d(StepArgs<T> a)
     step2d_item<T, KIND, R, RED>(a, a.parity, item, threadIdx.x & 63, item);
 }
 
-template <typename T, int KIND, int R>
-__global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> tb, int32_t k)
+// Request of global work item g in a batch table (binary search over the
+// item prefix sums).
+template <typename T>
+__device__ __forceinline__ int batch_request(const BatchTable<T> &tb, int32_t n, int32_t g)
 {
-    const int32_t nwg = gridDim.x;
-    const int32_t g = xcd_item(blockIdx.x, nwg) * kWaves2D + (threadIdx.x >> 6);
-    if (g >= tb.item_start[tb.n]) return;
-    int lo = 0, hi = tb.n - 1;
+    int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (tb.item_start[mid] <= g) lo = mid; else hi = mid - 1;
     }
-    if (k >= tb.steps[lo]) return;
-    const StepArgs<T> &a = tb.args[lo];
-    step2d_item<T, KIND, R, false>(a, (a.parity + k) & 1, g - tb.item_start[lo],
-                                   threadIdx.x & 63, 0);
+    return lo;
+}
+
+// Persistent batched 2D step: a fixed grid strides over the work items of
+// every request in the table (step k of the tick; requests with fewer steps
+// this tick skip).  Each request is stepped exactly as by k_step2d.
+template <typename T, int KIND, int R>
+__global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> tb, int32_t k)
+{
+    const int32_t n = *tb.count;
+    const int32_t total = tb.item_start[n];
+    const int32_t stride = gridDim.x * kWaves2D;
+    for (int32_t g = blockIdx.x * kWaves2D + (threadIdx.x >> 6); g < total; g += stride) {
+        const int i = batch_request(tb, n, g);
+        if (k >= tb.steps[i]) continue;
+        const StepArgs<T> &a = tb.args[i];
+        step2d_item<T, KIND, R, false>(a, (a.parity + k) & 1, g - tb.item_start[i],
+                                       threadIdx.x & 63, 0);
+    }
 }
 
 // ===========================================================================
@@ -475,49 +545,47 @@ __global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> 
 // from lane shuffles and y-neighbours from the other waves' rows through a
 // double-buffered LDS plane (one barrier per plane).  Rows within H of the
 // tile edge are halo: only rows [H, NW - H) are written.
-template <typename T, int KIND, int R, bool RED>
-__device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32_t item,
-                                            int64_t pslot_base)
+template <typename T, int KIND, int R>
+struct Lds3D {
+    using S = Shape<T, KIND, R>;
+    static constexpr int NL = KIND == kCH ? 2 : S::NF;  // planes per buffer
+    using type = T[2][NL][kWaves3D][S::SW];
+};
+
+template <typename T, int KIND, int R, bool RED, bool FAST>
+__device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t xb, int64_t yrow,
+                                        bool out_row, int64_t z0, int64_t z1, int64_t pslot,
+                                        typename Lds3D<T, KIND, R>::type &lds)
 {
     using S = Shape<T, KIND, R>;
-    constexpr int V = S::V, H = S::H, HV = S::HV, SW = S::SW, D = S::D, NE = S::NE, K = S::K,
-                  NF = S::NF;
+    constexpr int V = S::V, H = S::H, HV = S::HV, NE = S::NE, K = S::K, NF = S::NF;
     constexpr int NW = kWaves3D;
-    constexpr int NL = KIND == kCH ? 2 : NF;  // LDS planes per buffer
     static_assert(2 * H < NW, "halo too wide for the 3D tile");
-    __shared__ T lds[2][NL][NW][SW];
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int32_t strip = item % a.strips;
-    const int32_t rest = item / a.strips;
-    const int32_t ytile = rest % a.ytiles;
-    const int32_t chunk = rest / a.ytiles;
     const int64_t nx = a.nx, ny = a.ny, nz = a.nz, pitch = a.pitch, plane = a.plane;
-    const int64_t x0 = (int64_t)strip * a.ow;
-    const int64_t xb = x0 - HV;
     const int64_t xl = xb + lane * V;
-    const bool fast = (xb >= 0) && (xb + SW <= nx);
-    const int64_t yo0 = (int64_t)ytile * (NW - 2 * H);      // first output row of the tile
-    const int64_t yrow = yo0 - H + w;                        // this wave's row
-    const bool out_row = (w >= H) && (w < NW - H) && (yrow < ny);
     const int64_t rowoff = wrap_any(yrow, ny) * pitch;
-    const int64_t z0 = (int64_t)chunk * a.clen;
-    const int64_t z1 = min(z0 + (int64_t)a.clen, nz);
     const int pl = lane * V;
-    bool ov[V];
-    bool allv = true;
+    OutMask<V> om;
+    om.all = true;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        ov[v] = out_row && (pl + v >= HV) && (pl + v < HV + a.ow) && (xl + v < nx);
-        allv = allv && ov[v];
+        om.ov[v] = out_row && (pl + v >= HV) && (pl + v < HV + a.ow) && (xl + v < nx);
+        om.all = om.all && om.ov[v];
     }
+    const RowIO<T, V, FAST> io(xb, lane, nx);
     const T *in[2] = {a.buf[0][par], a.buf[NF - 1][par]};
     T *out[2] = {a.buf[0][par ^ 1], a.buf[NF - 1][par ^ 1]};
 
     T ring[NF][K][V];
     T pre[NF][K][V];
     T mring[KIND == kCH ? K : 1][V];
+#pragma unroll
+    for (int i = 0; i < (KIND == kCH ? K : 1); ++i)
+#pragma unroll
+        for (int v = 0; v < V; ++v) mring[i][v] = T(0);
     RedState red;
 
     const int64_t tb0 = z0 - H, tend = z1 + H;
@@ -527,7 +595,7 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
         if (t < tend) {
             const int64_t off = wrap_any(t, nz) * plane + rowoff;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) load_row<T, V>(in[f] + off, xl, nx, fast, pre[f][ph]);
+            for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
         }
     });
 
@@ -544,8 +612,7 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
                 if (t + K < tend) {
                     const int64_t off = wrap_any(t + K, nz) * plane + rowoff;
 #pragma unroll
-                    for (int f = 0; f < NF; ++f)
-                        load_row<T, V>(in[f] + off, xl, nx, fast, pre[f][ph]);
+                    for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
                 }
                 if constexpr (KIND != kCH) {
                     constexpr int co = (ph - R + K) % K;
@@ -558,8 +625,9 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
                     if (o >= z0 && w >= R && w < NW - R) {
                         T e[NF][NE];
 #pragma unroll
-                        for (int f = 0; f < NF; ++f) gather_x<T, V, D>(ring[f][co], e[f]);
+                        for (int f = 0; f < NF; ++f) gather_x<T, V, R>(ring[f][co], e[f]);
                         T res[NF][V];
+                        double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             T Sf[NF][R];
@@ -569,7 +637,7 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
 #pragma unroll
                                 for (int f = 0; f < NF; ++f)
                                     Sf[f][j - 1] =
-                                        ((e[f][D * V + v + j] + e[f][D * V + v - j]) +
+                                        ((e[f][R + v + j] + e[f][R + v - j]) +
                                          (lds[buf][f][w + j][pl + v] + lds[buf][f][w - j][pl + v])) +
                                         (ring[f][sp][v] + ring[f][sm][v]);
                             });
@@ -582,37 +650,40 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
                                                 v0 * T(6), res[0][v], res[NF - 1][v]);
                             }
                             if constexpr (RED) {
-                                if (ov[v]) {
+                                if (om.ov[v]) {
                                     const double x = (double)u0;
-                                    acc_add(red.q0, x);
-                                    red.bad += finite_val(x) ? 0.0 : 1.0;
+                                    rs0 += x;
+                                    rbad += finite_val(x) ? 0.0 : 1.0;
                                     if constexpr (KIND == kAC) {
                                         double S64[R];
                                         static_for<1, R + 1>([&](auto jc) {
                                             constexpr int j = decltype(jc)::value;
                                             constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
                                             S64[j - 1] =
-                                                (((double)e[0][D * V + v + j] +
-                                                  (double)e[0][D * V + v - j]) +
+                                                (((double)e[0][R + v + j] +
+                                                  (double)e[0][R + v - j]) +
                                                  ((double)lds[buf][0][w + j][pl + v] +
                                                   (double)lds[buf][0][w - j][pl + v])) +
                                                 ((double)ring[0][sp][v] + (double)ring[0][sm][v]);
                                         });
-                                        acc_add(red.q1, energy_density<R>(a.c1, a.c2, a.w64, x,
-                                                                          S64, x * 6.0));
+                                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
                                     } else {
                                         const double y = (double)ring[NF - 1][co][v];
-                                        acc_add(red.q1, y);
-                                        red.bad += finite_val(y) ? 0.0 : 1.0;
+                                        rs1 += y;
+                                        rbad += finite_val(y) ? 0.0 : 1.0;
                                     }
                                 }
                             }
                         }
-                        if (o < z1) {
+                        if constexpr (RED) {
+                            acc_add(red.q0, rs0);
+                            acc_add(red.q1, rs1);
+                            red.bad += rbad;
+                        }
+                        if (out_row) {
                             const int64_t ooff = wrap_any(o, nz) * plane + rowoff;
 #pragma unroll
-                            for (int f = 0; f < NF; ++f)
-                                if (out_row) store_row<T, V>(out[f] + ooff, xl, allv, ov, res[f]);
+                            for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
                         }
                     }
                 } else {
@@ -628,43 +699,51 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
                     __syncthreads();
                     if (m >= z0 - R && w >= R && w < NW - R) {
                         T e[NE];
-                        gather_x<T, V, D>(ring[0][cm], e);
+                        gather_x<T, V, R>(ring[0][cm], e);
+                        double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+                        const bool red_row = RED && m >= z0 && m < z1;
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             T Sc[R];
                             static_for<1, R + 1>([&](auto jc) {
                                 constexpr int j = decltype(jc)::value;
                                 constexpr int sp = (cm + j) % K, sm = (cm - j + K) % K;
-                                Sc[j - 1] = ((e[D * V + v + j] + e[D * V + v - j]) +
+                                Sc[j - 1] = ((e[R + v + j] + e[R + v - j]) +
                                              (lds[buf][0][w + j][pl + v] + lds[buf][0][w - j][pl + v])) +
                                             (ring[0][sp][v] + ring[0][sm][v]);
                             });
                             const T c0 = ring[0][cm][v];
                             mring[cm][v] = ch_mu<T, R>(a, c0, Sc, c0 * T(6));
                             if constexpr (RED) {
-                                if (ov[v] && m >= z0 && m < z1) {
+                                if (red_row && om.ov[v]) {
                                     const double x = (double)c0;
                                     double S64[R];
                                     static_for<1, R + 1>([&](auto jc) {
                                         constexpr int j = decltype(jc)::value;
                                         constexpr int sp = (cm + j) % K, sm = (cm - j + K) % K;
                                         S64[j - 1] =
-                                            (((double)e[D * V + v + j] + (double)e[D * V + v - j]) +
+                                            (((double)e[R + v + j] + (double)e[R + v - j]) +
                                              ((double)lds[buf][0][w + j][pl + v] +
                                               (double)lds[buf][0][w - j][pl + v])) +
                                             ((double)ring[0][sp][v] + (double)ring[0][sm][v]);
                                     });
-                                    acc_add(red.q0, x);
-                                    acc_add(red.q1,
-                                            energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0));
-                                    red.bad += finite_val(x) ? 0.0 : 1.0;
+                                    rs0 += x;
+                                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
+                                    rbad += finite_val(x) ? 0.0 : 1.0;
                                 }
+                            }
+                        }
+                        if constexpr (RED) {
+                            if (red_row) {
+                                acc_add(red.q0, rs0);
+                                acc_add(red.q1, rs1);
+                                red.bad += rbad;
                             }
                         }
                     }
                     if (o >= z0 && o < z1 && w >= 2 * R && w < NW - 2 * R) {
                         T em[NE];
-                        gather_x<T, V, D>(mring[co], em);
+                        gather_x<T, V, R>(mring[co], em);
                         T res[V];
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
@@ -672,21 +751,44 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
                             static_for<1, R + 1>([&](auto jc) {
                                 constexpr int j = decltype(jc)::value;
                                 constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
-                                Sm[j - 1] = ((em[D * V + v + j] + em[D * V + v - j]) +
+                                Sm[j - 1] = ((em[R + v + j] + em[R + v - j]) +
                                              (lds[buf][1][w + j][pl + v] + lds[buf][1][w - j][pl + v])) +
                                             (mring[sp][v] + mring[sm][v]);
                             });
                             res[v] = ch_update<T, R>(a, ring[0][co][v], Sm, mring[co][v] * T(6));
                         }
                         if (out_row)
-                            store_row<T, V>(out[0] + wrap_any(o, nz) * plane + rowoff, xl, allv, ov,
-                                            res);
+                            store_row<T, V>(out[0] + wrap_any(o, nz) * plane + rowoff, xl, om, res);
                     }
                 }
             }
         });
     }
-    if constexpr (RED) red_flush(red, a.part, a.pstride, pslot_base + w, lane);
+    if constexpr (RED) red_flush(red, a.part, a.pstride, pslot, lane);
+}
+
+template <typename T, int KIND, int R, bool RED>
+__device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32_t item,
+                                            int64_t pslot_base)
+{
+    using S = Shape<T, KIND, R>;
+    constexpr int NW = kWaves3D;
+    const int w = threadIdx.x >> 6;
+    const int32_t strip = item % a.strips;
+    const int32_t rest = item / a.strips;
+    const int32_t ytile = rest % a.ytiles;
+    const int32_t chunk = rest / a.ytiles;
+    const int64_t xb = (int64_t)strip * a.ow - S::HV;
+    const int64_t yrow = (int64_t)ytile * (NW - 2 * S::H) - S::H + w;
+    const bool out_row = (w >= S::H) && (w < NW - S::H) && (yrow < a.ny);
+    const int64_t z0 = (int64_t)chunk * a.clen;
+    const int64_t z1 = min(z0 + (int64_t)a.clen, a.nz);
+    __shared__ typename Lds3D<T, KIND, R>::type lds;
+    // the FAST choice is uniform over the workgroup (it depends on the strip only)
+    if (xb >= 0 && xb + S::SW <= a.nx)
+        march3d<T, KIND, R, RED, true>(a, par, xb, yrow, out_row, z0, z1, pslot_base + w, lds);
+    else
+        march3d<T, KIND, R, RED, false>(a, par, xb, yrow, out_row, z0, z1, pslot_base + w, lds);
 }
 
 template <typename T, int KIND, int R, bool RED>
@@ -697,19 +799,19 @@ __global__ void __launch_bounds__(64 * kWaves3D) k_step3d(StepArgs<T> a)
     step3d_item<T, KIND, R, RED>(a, a.parity, item, (int64_t)item * kWaves3D);
 }
 
+// Persistent batched 3D step (see k_step2d_batched); the item loop is uniform
+// over the workgroup, so every wave reaches the same barriers.
 template <typename T, int KIND, int R>
 __global__ void __launch_bounds__(64 * kWaves3D) k_step3d_batched(BatchTable<T> tb, int32_t k)
 {
-    const int32_t g = xcd_item(blockIdx.x, gridDim.x);
-    if (g >= tb.item_start[tb.n]) return;
-    int lo = 0, hi = tb.n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tb.item_start[mid] <= g) lo = mid; else hi = mid - 1;
+    const int32_t n = *tb.count;
+    const int32_t total = tb.item_start[n];
+    for (int32_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const int i = batch_request(tb, n, g);
+        if (k >= tb.steps[i]) continue;
+        const StepArgs<T> &a = tb.args[i];
+        step3d_item<T, KIND, R, false>(a, (a.parity + k) & 1, g - tb.item_start[i], 0);
     }
-    if (k >= tb.steps[lo]) return;
-    const StepArgs<T> &a = tb.args[lo];
-    step3d_item<T, KIND, R, false>(a, (a.parity + k) & 1, g - tb.item_start[lo], 0);
 }
 
 }  // namespace pf

@@ -46,13 +46,15 @@ struct StepArgs {
 
 // Batched (serving) launch: a table of StepArgs, one per request of one
 // kernel class, with work-item prefix sums; a launch processes step `k` of the
-// current tick for every request whose `steps[i]` exceeds k.
+// current tick for every request whose `steps[i]` exceeds k.  Everything the
+// kernel reads lives in device memory (the struct holds only pointers), so a
+// captured graph stays valid when the table's contents change.
 template <typename T>
 struct BatchTable {
     StepArgs<T> *args;       // device array [n]
+    int32_t *count;          // device scalar n
     int32_t *item_start;     // device array [n + 1]
     int32_t *steps;          // device array [n]: steps of this tick
-    int32_t n;
 };
 
 // Kernel-family launchers (defined in kernels.hip).  Every launcher returns
@@ -87,9 +89,11 @@ hipError_t launch_reduce_state(const Launch &L, const void *args, hipStream_t s)
 int64_t reduce_partial_slots(int64_t nsites);
 
 // Fixed-order compensated combination of `slots` partials per quantity into
-// out[q] (double2 hi, lo), q = 0..kNumQ-1.
-hipError_t launch_finalize(const double2 *part, int64_t pstride, int64_t slots, double2 *out,
-                           hipStream_t s);
+// out[q] (double2 hi, lo), q = 0..kNumQ-1, through `part2` (kNumQ * kFinSlots
+// pairs of second-level scratch).
+constexpr int kFinSlots = 256;
+hipError_t launch_finalize(const double2 *part, int64_t pstride, int64_t slots, double2 *part2,
+                           double2 *out, hipStream_t s);
 
 // Counter-based initial conditions.
 struct InitArgs {

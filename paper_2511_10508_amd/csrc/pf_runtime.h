@@ -10,6 +10,7 @@
 namespace pf {
 
 constexpr int kGraphSteps = 32;  // steps per captured graph (pf_step with PF_USE_GRAPH)
+constexpr int64_t kDefaultPitchPadBytes = 0;  // row padding for rows >= 4 KiB
 
 struct Model {
     pf_desc desc{};
@@ -19,6 +20,7 @@ struct Model {
     int64_t pitch = 0, elems = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false, own_bufs = true;
+    bool async_alloc = false;     // stream-ordered allocations, no host syncs (server models)
     void *buf[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int parity = 0;
     int64_t steps_done = 0;
@@ -33,6 +35,7 @@ struct Model {
 
     double2 *part = nullptr;     // partial sums [kNumQ][pstride]
     int64_t pstride = 0;
+    double2 *part2 = nullptr;    // second-level partials [kNumQ][kFinSlots]
     double2 *res = nullptr;      // finalised reductions [kNumQ]
     double2 *hist = nullptr;     // per-step reductions [hist_cap][kNumQ]
     int64_t hist_cap = 0, hist_len = 0;
@@ -67,7 +70,8 @@ int elem_bytes(const pf_desc *d);
 double volume(const pf_desc &d);
 
 pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int32_t nbufs,
-                       Model **out);
+                       Model **out, bool async_alloc = false);
+void model_release_async(Model *m);  // free a server model's memory in stream order
 void pf_destroy_model(Model *m);
 pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int32_t np);
 pf_status set_chunk(Model *m, int32_t chunk);

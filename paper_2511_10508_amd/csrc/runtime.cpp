@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -93,10 +94,18 @@ double stability_limit(const pf_desc *d)
     return 2.0 / rho;
 }
 
+// Row pitch: nx rounded up to 16 bytes, plus a padding for rows of 4 KiB or
+// more so that consecutive rows do not start at the same large power-of-two
+// offset.  PFMI_PITCH_PAD_BYTES overrides the padding (tuning knob).
 int64_t pitch_of(const pf_desc *d)
 {
-    const int64_t v = d->precision == PF_FP32 ? 4 : 2;  // 16 bytes
-    return (d->n[0] + v - 1) / v * v;
+    const int64_t eb = d->precision == PF_FP32 ? 4 : 8;
+    const int64_t v = 16 / eb;
+    int64_t p = (d->n[0] + v - 1) / v * v;
+    int64_t pad = kDefaultPitchPadBytes;
+    if (const char *env = std::getenv("PFMI_PITCH_PAD_BYTES")) pad = std::atoll(env);
+    if (p * eb >= 4096 && pad > 0) p += (pad / eb + v - 1) / v * v;
+    return p;
 }
 
 int64_t buffer_elems(const pf_desc *d) { return pitch_of(d) * d->n[1] * d->n[2]; }
@@ -214,6 +223,20 @@ static std::tuple<int, int, int, int, int, int, int> tune_key(const pf_desc &d)
                            lg(d.n[2]));
 }
 
+static hipError_t dev_alloc(Model *m, void **p, size_t bytes)
+{
+    return m->async_alloc ? hipMallocAsync(p, bytes, m->stream) : hipMalloc(p, bytes);
+}
+
+static void dev_free(Model *m, void *p)
+{
+    if (!p) return;
+    if (m->async_alloc)
+        (void)hipFreeAsync(p, m->stream);
+    else
+        (void)hipFree(p);
+}
+
 static pf_status ensure_partials(Model *m)
 {
     const int64_t N = m->desc.n[0] * m->desc.n[1] * m->desc.n[2];
@@ -221,11 +244,11 @@ static pf_status ensure_partials(Model *m)
     need = std::max<int64_t>(need, 1);
     if (need <= m->pstride && m->part) return PF_OK;
     if (m->part) {
-        PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
-        PF_HIP(hipFree(m->part), "hipFree(partials)");
+        if (!m->async_alloc) PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        dev_free(m, m->part);
         m->part = nullptr;
     }
-    PF_HIP(hipMalloc((void **)&m->part, sizeof(double2) * kNumQ * need), "hipMalloc(partials)");
+    PF_HIP(dev_alloc(m, (void **)&m->part, sizeof(double2) * kNumQ * need), "hipMalloc(partials)");
     m->pstride = need;
     return PF_OK;
 }
@@ -263,7 +286,7 @@ pf_status set_chunk(Model *m, int32_t chunk)
 static pf_status ensure_scratch(Model *m)
 {
     if (m->family == 0 || m->desc.kind != kCH || m->scratch) return PF_OK;
-    PF_HIP(hipMalloc(&m->scratch, tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
+    PF_HIP(dev_alloc(m, &m->scratch, tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
     return PF_OK;
 }
 
@@ -308,7 +331,7 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
         if (red) {
-            hipError_t f = launch_finalize(m->part, m->pstride, m->fused_slots, res, m->stream);
+            hipError_t f = launch_finalize(m->part, m->pstride, m->fused_slots, m->part2, res, m->stream);
             if (f != hipSuccess) return hip_fail(f, "finalize launch");
         }
     } else {
@@ -316,7 +339,7 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
             hipError_t e = launch_reduce_state(m->L, ap, m->stream);
             if (e != hipSuccess) return hip_fail(e, "reduce launch");
             const int64_t N = d.n[0] * d.n[1] * d.n[2];
-            e = launch_finalize(m->part, m->pstride, reduce_partial_slots(N), res, m->stream);
+            e = launch_finalize(m->part, m->pstride, reduce_partial_slots(N), m->part2, res, m->stream);
             if (e != hipSuccess) return hip_fail(e, "finalize launch");
         }
         pf_status st = ensure_scratch(m);
@@ -451,7 +474,7 @@ pf_status reduce_now(Model *m, double2 *host_out)
     const int64_t N = m->desc.n[0] * m->desc.n[1] * m->desc.n[2];
     hipError_t e = launch_reduce_state(m->L, ap, m->stream);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
-    e = launch_finalize(m->part, m->pstride, reduce_partial_slots(N), m->res, m->stream);
+    e = launch_finalize(m->part, m->pstride, reduce_partial_slots(N), m->part2, m->res, m->stream);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
     PF_HIP(hipMemcpyAsync(host_out, m->res, sizeof(double2) * kNumQ, hipMemcpyDeviceToHost, m->stream),
            "hipMemcpyAsync(reductions)");
@@ -495,7 +518,7 @@ pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double 
 }
 
 pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int32_t nbufs,
-                       Model **out)
+                       Model **out, bool async_alloc)
 {
     pf_status st = check_desc(desc);
     if (st != PF_OK) return st;
@@ -510,6 +533,7 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
         }
     }
     Model *m = new Model();
+    m->async_alloc = async_alloc && stream != nullptr;
     m->desc = *desc;
     m->nf = desc->nfields;
     m->fp32 = desc->precision == PF_FP32;
@@ -546,12 +570,13 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
     } else {
         for (int f = 0; f < m->nf; ++f)
             for (int p = 0; p < 2; ++p) {
-                e = hipMalloc(&m->buf[f][p], bytes);
+                e = dev_alloc(m, &m->buf[f][p], bytes);
                 if (e != hipSuccess) {
                     pf_destroy_model(m);
                     hip_fail(e, "hipMalloc(field)");
                     return PF_ERR_NOMEM;
                 }
+                if (m->async_alloc) continue;  // the caller initialises the fields
                 e = hipMemsetAsync(m->buf[f][p], 0, bytes, m->stream);
                 if (e != hipSuccess) {
                     pf_destroy_model(m);
@@ -560,7 +585,8 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
             }
         m->own_bufs = true;
     }
-    e = hipMalloc((void **)&m->res, sizeof(double2) * kNumQ);
+    e = dev_alloc(m, (void **)&m->res, sizeof(double2) * kNumQ);
+    if (e == hipSuccess) e = dev_alloc(m, (void **)&m->part2, sizeof(double2) * kNumQ * kFinSlots);
     if (e != hipSuccess) {
         pf_destroy_model(m);
         return hip_fail(e, "hipMalloc(result)");
@@ -576,19 +602,45 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
         pf_destroy_model(m);
         return st;
     }
-    e = hipStreamSynchronize(m->stream);
-    if (e != hipSuccess) {
-        pf_destroy_model(m);
-        return hip_fail(e, "hipStreamSynchronize");
+    if (!m->async_alloc) {
+        e = hipStreamSynchronize(m->stream);
+        if (e != hipSuccess) {
+            pf_destroy_model(m);
+            return hip_fail(e, "hipStreamSynchronize");
+        }
     }
     *out = m;
     return PF_OK;
 }
 
+void model_release_async(Model *m)
+{
+    if (!m) return;
+    for (int f = 0; f < 2; ++f)
+        for (int p = 0; p < 2; ++p)
+            if (m->own_bufs) dev_free(m, m->buf[f][p]);
+    dev_free(m, m->part);
+    dev_free(m, m->part2);
+    dev_free(m, m->res);
+    dev_free(m, m->hist);
+    dev_free(m, m->stage);
+    dev_free(m, m->scratch);
+    destroy_graphs(m);
+    for (auto ev : m->events) (void)hipEventDestroy(ev);
+    delete m;
+}
+
 void pf_destroy_model(Model *m)
 {
     if (!m) return;
-    if (m->stream) hipStreamSynchronize(m->stream);
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    if (m->async_alloc) {
+        const bool own = m->own_stream;
+        hipStream_t st = m->stream;
+        model_release_async(m);
+        if (own && st) (void)hipStreamDestroy(st);
+        return;
+    }
     destroy_graphs(m);
     if (m->own_bufs)
         for (int f = 0; f < 2; ++f)
@@ -596,6 +648,7 @@ void pf_destroy_model(Model *m)
                 if (m->buf[f][p]) hipFree(m->buf[f][p]);
     if (m->part) hipFree(m->part);
     if (m->res) hipFree(m->res);
+    if (m->part2) hipFree(m->part2);
     if (m->hist) hipFree(m->hist);
     if (m->stage) hipFree(m->stage);
     if (m->scratch) hipFree(m->scratch);

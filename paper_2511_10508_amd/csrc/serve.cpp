@@ -1,34 +1,669 @@
-// Serving engine (continuous batching).  Placeholder until the scheduler lands.
+// Serving engine: continuous batching of independent simulation requests.
+//
+// A scheduler thread owns one HIP stream.  Every tick it
+//   1. admits queued requests in FIFO order while a slot is free and their
+//      device footprint fits the HBM budget (allocation and initial
+//      conditions are enqueued in stream order, no host synchronisation);
+//   2. groups the running requests by kernel class (model, dimension,
+//      stencil radius, precision) and uploads one work-item table per class;
+//   3. replays a captured HIP graph of `steps_per_tick` persistent batched
+//      launches per class (captured once per class set and table buffer);
+//   4. enqueues the final reductions of requests that finish in this tick.
+// Ticks are pipelined two deep: tick i+1 is enqueued before the host waits
+// for tick i, and requests that finished in tick i are retired (results
+// visible to pf_server_poll) once its event completes.  Requests submitted
+// while ticks run join at the next tick boundary.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
 #include "../../include/pfmi.h"
 #include "pf_runtime.h"
+
+namespace pf {
+
+namespace {
+
+constexpr int kPersist2D = 2048;  // workgroups of a persistent 2D batched launch
+constexpr int kPersist3D = 512;   // workgroups of a persistent 3D batched launch
+constexpr int kMaxGraphs = 64;
+
+enum ReqState { QUEUED = 0, RUNNING = 1, FINISHED = 2 };
+
+struct Req {
+    uint64_t ticket = 0;
+    pf_desc desc{};
+    int32_t ic = 0;
+    uint64_t seed = 0;
+    std::vector<double> icp;
+    int64_t nsteps = 0, done = 0;
+    Model *m = nullptr;
+    int state = QUEUED;
+    int32_t status = PF_OK;
+    bool cancel = false, released = false, reported = false;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    uint64_t footprint = 0;
+    int64_t finish_tick = -1;
+    int cls = -1;            // batched class, -1 = stepped on its own
+    double2 *pinned = nullptr;  // final reductions (host-pinned, kNumQ pairs)
+    pf_result res{};
+};
+
+struct ClassKey {
+    int kind, ndim, r, fp32;
+    bool operator<(const ClassKey &o) const
+    {
+        return std::tie(kind, ndim, r, fp32) < std::tie(o.kind, o.ndim, o.r, o.fp32);
+    }
+};
+
+// Device and pinned host buffers of one class's work-item tables, double
+// buffered across pipelined ticks.
+struct ClassTables {
+    ClassKey key{};
+    Launch L{};
+    size_t args_bytes = 0;
+    void *dev[2] = {nullptr, nullptr};   // [args | count | item_start | steps]
+    void *host[2] = {nullptr, nullptr};
+    int32_t n[2] = {0, 0};
+};
+
+}  // namespace
+
+struct Server {
+    int device = 0;
+    uint64_t budget = 0, used = 0;
+    int max_slots = 0;
+    int spt = 64;
+    hipStream_t stream = nullptr, copy_stream = nullptr;
+    std::chrono::steady_clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::deque<Req *> queue;
+    std::vector<Req *> active;
+    std::map<uint64_t, Req *> all;
+    std::vector<Req *> to_free;
+    uint64_t next_ticket = 1;
+    int64_t unfinished = 0;
+    bool stop = false;
+    std::thread worker;
+
+    std::map<ClassKey, int> class_index;
+    std::vector<ClassTables> classes;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int64_t tick = 0, launches = 0, captures = 0, replays = 0;
+    std::string fatal;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+static int class_of(Server *s, const Model *m)
+{
+    if (m->family != 0) return -1;
+    ClassKey k{m->L.kind, m->L.ndim, m->L.r, m->L.fp32};
+    auto it = s->class_index.find(k);
+    if (it != s->class_index.end()) return it->second;
+    ClassTables t;
+    t.key = k;
+    t.L = m->L;
+    const size_t argsz = m->fp32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
+    t.args_bytes = argsz * s->max_slots;
+    const size_t total = t.args_bytes + sizeof(int32_t) * (2 * s->max_slots + 2);
+    for (int b = 0; b < 2; ++b) {
+        if (hipMalloc(&t.dev[b], total) != hipSuccess) return -1;
+        if (hipHostMalloc(&t.host[b], total, hipHostMallocDefault) != hipSuccess) return -1;
+    }
+    const int idx = (int)s->classes.size();
+    s->classes.push_back(t);
+    s->class_index[k] = idx;
+    return idx;
+}
+
+static void free_req(Server *s, Req *r)
+{
+    if (r->m) {
+        model_release_async(r->m);
+        r->m = nullptr;
+    }
+    if (r->pinned) {
+        (void)hipHostFree(r->pinned);
+        r->pinned = nullptr;
+    }
+    s->used -= std::min(s->used, r->footprint);
+    r->footprint = 0;
+}
+
+// Fill the request's result from its pinned reductions.
+static void fill_result(Req *r)
+{
+    pf_result &o = r->res;
+    o.ticket = r->ticket;
+    o.status = r->status;
+    o.t_submit = r->t_submit;
+    o.t_admit = r->t_admit;
+    o.t_done = r->t_done;
+    o.steps_done = r->done;
+    if (r->status == PF_OK && r->pinned) {
+        const double vol = volume(r->desc);
+        const double2 *q = r->pinned;
+        o.mass[0] = (q[0].x + q[0].y) * vol;
+        if (r->desc.kind == kGS) {
+            o.mass[1] = (q[1].x + q[1].y) * vol;
+            o.energy = 0.0;
+        } else {
+            o.mass[1] = 0.0;
+            o.energy = (q[1].x + q[1].y) * vol;
+        }
+        o.nonfinite = (int64_t)q[2].x;
+    }
+}
+
+// Launch the batched steps of one tick for the given classes and buffer set.
+static hipError_t launch_tick(Server *s, const std::vector<int> &cls, int set, int S)
+{
+    for (int k = 0; k < S; ++k)
+        for (int c : cls) {
+            ClassTables &t = s->classes[c];
+            char *dev = static_cast<char *>(t.dev[set]);
+            hipError_t e;
+            int32_t *ints = reinterpret_cast<int32_t *>(dev + t.args_bytes);
+            if (t.L.fp32) {
+                BatchTable<float> tb{reinterpret_cast<StepArgs<float> *>(dev), ints, ints + 1,
+                                     ints + 1 + s->max_slots + 1};
+                e = t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, kPersist2D, s->stream)
+                                  : launch_fused3d_batched(t.L, &tb, k, kPersist3D, s->stream);
+            } else {
+                BatchTable<double> tb{reinterpret_cast<StepArgs<double> *>(dev), ints, ints + 1,
+                                      ints + 1 + s->max_slots + 1};
+                e = t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, kPersist2D, s->stream)
+                                  : launch_fused3d_batched(t.L, &tb, k, kPersist3D, s->stream);
+            }
+            if (e != hipSuccess) return e;
+            s->launches++;
+        }
+    return hipSuccess;
+}
+
+static hipError_t run_graph(Server *s, const std::vector<int> &cls, int set, int S)
+{
+    std::vector<int64_t> key;
+    key.push_back(set);
+    key.push_back(S);
+    for (int c : cls) key.push_back(c);
+    auto it = s->graphs.find(key);
+    if (it == s->graphs.end()) {
+        if ((int)s->graphs.size() >= kMaxGraphs) {
+            for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
+            s->graphs.clear();
+        }
+        hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        hipError_t le = launch_tick(s, cls, set, S);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s->stream, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return le;
+        }
+        if (e != hipSuccess) return e;
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return e;
+        it = s->graphs.emplace(key, ex).first;
+        s->captures++;
+    } else {
+        s->replays++;
+    }
+    return hipGraphLaunch(it->second, s->stream);
+}
+
+template <typename T>
+static void put_args(ClassTables &t, int set, int i, const StepArgs<T> &a)
+{
+    reinterpret_cast<StepArgs<T> *>(t.host[set])[i] = a;
+}
+
+// Enqueue one tick.  Returns false on a device error (recorded in fatal).
+static bool enqueue_tick(Server *s, std::vector<Req *> &run, int set)
+{
+    const int S = s->spt;
+    std::vector<std::vector<Req *>> by_class(s->classes.size());
+    std::vector<Req *> solo;
+    for (Req *r : run) {
+        if (r->cls >= 0)
+            by_class[r->cls].push_back(r);
+        else
+            solo.push_back(r);
+    }
+    std::vector<int> cls;
+    for (size_t c = 0; c < by_class.size(); ++c) {
+        ClassTables &t = s->classes[c];
+        auto &v = by_class[c];
+        t.n[set] = (int32_t)v.size();
+        if (v.empty()) continue;
+        cls.push_back((int)c);
+        char *h = static_cast<char *>(t.host[set]);
+        int32_t *ints = reinterpret_cast<int32_t *>(h + t.args_bytes);
+        ints[0] = (int32_t)v.size();
+        int32_t *start = ints + 1;
+        int32_t *steps = start + s->max_slots + 1;
+        int32_t acc = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+            Model *m = v[i]->m;
+            if (m->fp32) {
+                StepArgs<float> a = m->a32;
+                a.parity = m->parity;
+                put_args(t, set, (int)i, a);
+            } else {
+                StepArgs<double> a = m->a64;
+                a.parity = m->parity;
+                put_args(t, set, (int)i, a);
+            }
+            start[i] = acc;
+            acc += m->items;
+            steps[i] = (int32_t)std::min<int64_t>(S, v[i]->nsteps - v[i]->done);
+        }
+        start[v.size()] = acc;
+        const size_t argsz = t.L.fp32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
+        hipError_t e = hipMemcpyAsync(t.dev[set], t.host[set], argsz * v.size(), hipMemcpyHostToDevice,
+                                      s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(static_cast<char *>(t.dev[set]) + t.args_bytes, ints,
+                               sizeof(int32_t) * (2 * s->max_slots + 2), hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) {
+            s->fatal = std::string("table upload: ") + hipGetErrorString(e);
+            return false;
+        }
+    }
+    if (!cls.empty()) {
+        hipError_t e = run_graph(s, cls, set, S);
+        if (e != hipSuccess) {
+            s->fatal = std::string("batched launch: ") + hipGetErrorString(e);
+            return false;
+        }
+    }
+    for (Req *r : solo) {
+        const int64_t n = std::min<int64_t>(S, r->nsteps - r->done);
+        if (do_steps(r->m, n) != PF_OK) {
+            r->status = PF_ERR_DEVICE;
+            r->nsteps = r->done;  // stop it
+            continue;
+        }
+        r->done += n;  // do_steps advanced the model's parity and step count
+    }
+    for (auto &v : by_class)
+        for (Req *r : v) {
+            const int64_t n = std::min<int64_t>(S, r->nsteps - r->done);
+            r->m->parity ^= (int)(n & 1);
+            r->m->steps_done += n;
+            r->done += n;
+        }
+    // final reductions of requests that finish in this tick
+    for (Req *r : run) {
+        if (r->done < r->nsteps) continue;
+        Model *m = r->m;
+        union {
+            StepArgs<double> d64;
+            StepArgs<float> d32;
+        } u;
+        void *ap;
+        if (m->fp32) {
+            u.d32 = m->a32;
+            u.d32.parity = m->parity;
+            ap = &u.d32;
+        } else {
+            u.d64 = m->a64;
+            u.d64.parity = m->parity;
+            ap = &u.d64;
+        }
+        const int64_t N = m->desc.n[0] * m->desc.n[1] * m->desc.n[2];
+        hipError_t e = launch_reduce_state(m->L, ap, s->stream);
+        if (e == hipSuccess)
+            e = launch_finalize(m->part, m->pstride, reduce_partial_slots(N), m->part2, m->res, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->pinned, m->res, sizeof(double2) * kNumQ, hipMemcpyDeviceToHost, s->stream);
+        if (e != hipSuccess) r->status = PF_ERR_DEVICE;
+        r->finish_tick = s->tick;
+    }
+    return true;
+}
+
+static void retire(Server *s, int64_t tick)
+{
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double t = s->now();
+    std::vector<Req *> keep;
+    for (Req *r : s->active) {
+        if (r->finish_tick >= 0 && r->finish_tick <= tick) {
+            r->state = FINISHED;
+            r->t_done = t;
+            fill_result(r);
+            s->unfinished--;
+        } else {
+            keep.push_back(r);
+        }
+    }
+    s->active.swap(keep);
+    s->done_cv.notify_all();
+}
+
+static void worker_main(Server *s)
+{
+    (void)hipSetDevice(s->device);
+    bool pending[2] = {false, false};
+    while (true) {
+        std::vector<Req *> admitted;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (Req *r : s->to_free) free_req(s, r);
+            s->to_free.clear();
+            if (s->stop) break;
+            // FIFO admission by footprint and slots
+            while (!s->queue.empty() && (int)s->active.size() + (int)admitted.size() < s->max_slots) {
+                Req *r = s->queue.front();
+                if (s->used + r->footprint > s->budget) break;
+                s->queue.pop_front();
+                s->used += r->footprint;
+                admitted.push_back(r);
+            }
+            if (admitted.empty() && s->active.empty() && !pending[0] && !pending[1]) {
+                s->cv.wait_for(lk, std::chrono::milliseconds(50));
+                continue;
+            }
+        }
+        for (Req *r : admitted) {
+            Model *m = nullptr;
+            pf_status st = model_create(&r->desc, s->stream, nullptr, 0, &m, true);
+            if (st == PF_OK)
+                st = init_fields(m, r->ic, r->seed, r->icp.data(), (int32_t)r->icp.size());
+            if (st == PF_OK && hipHostMalloc((void **)&r->pinned, sizeof(double2) * kNumQ,
+                                             hipHostMallocDefault) != hipSuccess)
+                st = PF_ERR_NOMEM;
+            std::lock_guard<std::mutex> lk(s->mu);
+            r->m = m;
+            r->t_admit = s->now();
+            if (st != PF_OK) {
+                r->status = st;
+                r->state = FINISHED;
+                r->t_done = r->t_admit;
+                fill_result(r);
+                s->unfinished--;
+                s->done_cv.notify_all();
+                continue;
+            }
+            r->cls = class_of(s, m);
+            r->state = RUNNING;
+            s->active.push_back(r);
+        }
+        std::vector<Req *> run;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (Req *r : s->active) {
+                if (r->finish_tick >= 0) continue;  // finished, waiting for retirement
+                if (r->cancel) {
+                    r->status = PF_ERR_STATE;
+                    r->finish_tick = s->tick;
+                    continue;
+                }
+                run.push_back(r);
+            }
+        }
+        const int set = (int)(s->tick & 1);
+        if (!run.empty()) {
+            if (!enqueue_tick(s, run, set)) break;
+        }
+        (void)hipEventRecord(s->ev[set], s->stream);
+        pending[set] = true;
+        // wait for the previous tick, retire what finished in it
+        const int prev = set ^ 1;
+        if (pending[prev]) {
+            (void)hipEventSynchronize(s->ev[prev]);
+            pending[prev] = false;
+            retire(s, s->tick - 1);
+        }
+        if (run.empty()) {
+            (void)hipEventSynchronize(s->ev[set]);
+            pending[set] = false;
+            retire(s, s->tick);
+        }
+        s->tick++;
+    }
+    (void)hipStreamSynchronize(s->stream);
+}
+
+}  // namespace pf
 
 using namespace pf;
 #define PF_API extern "C" __attribute__((visibility("default")))
 
-PF_API pf_status pf_server_create(int32_t, uint64_t, int32_t, int32_t, pf_server **out)
+static Server *SV(pf_server *s) { return reinterpret_cast<Server *>(s); }
+
+PF_API pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t max_slots,
+                                  int32_t steps_per_tick, pf_server **out)
 {
-    if (out) *out = nullptr;
-    return fail(PF_ERR_UNSUPPORTED, "serving not built yet");
+    if (!out) return fail(PF_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 4096) return fail(PF_ERR_ARG, "max_slots must be 1..4096");
+    if (steps_per_tick < 0 || steps_per_tick > 4096) return fail(PF_ERR_ARG, "steps_per_tick must be 0..4096");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    Server *s = new Server();
+    s->device = device;
+    s->max_slots = max_slots;
+    s->spt = steps_per_tick ? steps_per_tick : 64;
+    s->t0 = std::chrono::steady_clock::now();
+    if (hbm_budget == 0) {
+        size_t fr = 0, tot = 0;
+        e = hipMemGetInfo(&fr, &tot);
+        if (e != hipSuccess) {
+            delete s;
+            return hip_fail(e, "hipMemGetInfo");
+        }
+        hbm_budget = (uint64_t)(0.9 * (double)fr);
+    }
+    s->budget = hbm_budget;
+    e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "server stream/event");
+    }
+    s->worker = std::thread(worker_main, s);
+    *out = reinterpret_cast<pf_server *>(s);
+    return PF_OK;
 }
-PF_API pf_status pf_server_submit(pf_server *, const pf_desc *, int32_t, uint64_t, const double *,
-                                  int32_t, int64_t, uint64_t *)
+
+PF_API pf_status pf_server_submit(pf_server *ss, const pf_desc *desc, int32_t ic, uint64_t seed,
+                                  const double *ic_params, int32_t n_ic_params, int64_t nsteps,
+                                  uint64_t *ticket)
 {
-    return fail(PF_ERR_UNSUPPORTED, "serving not built yet");
+    Server *s = SV(ss);
+    if (!s || !ticket) return fail(PF_ERR_ARG, "NULL argument");
+    pf_status st = check_desc(desc);
+    if (st != PF_OK) return st;
+    if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
+    if (!(desc->flags & PF_ALLOW_UNSTABLE) && desc->dt > stability_limit(desc))
+        return fail(PF_ERR_UNSTABLE, "dt exceeds the explicit-stability limit");
+    if (desc->flags & (PF_USE_GRAPH | PF_REDUCE_EACH_STEP))
+        return fail(PF_ERR_ARG, "served requests take no PF_USE_GRAPH / PF_REDUCE_EACH_STEP");
+    if (n_ic_params < 0 || n_ic_params > 8 || (n_ic_params && !ic_params))
+        return fail(PF_ERR_ARG, "bad initial-condition parameters");
+    const uint64_t fp = pf_footprint_bytes(desc);
+    if (fp > s->budget) return fail(PF_ERR_NOMEM, "request footprint exceeds the server's HBM budget");
+    Req *r = new Req();
+    r->desc = *desc;
+    r->ic = ic;
+    r->seed = seed;
+    r->icp.assign(ic_params, ic_params + n_ic_params);
+    r->nsteps = nsteps;
+    r->footprint = fp;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->fatal.empty()) return fail(PF_ERR_DEVICE, s->fatal);
+    r->ticket = s->next_ticket++;
+    r->t_submit = s->now();
+    s->queue.push_back(r);
+    s->all[r->ticket] = r;
+    s->unfinished++;
+    *ticket = r->ticket;
+    s->cv.notify_all();
+    return PF_OK;
 }
-PF_API pf_status pf_server_poll(pf_server *, pf_result *, int32_t, int32_t *n)
+
+PF_API pf_status pf_server_poll(pf_server *ss, pf_result *out, int32_t max, int32_t *n)
 {
-    if (n) *n = 0;
-    return fail(PF_ERR_UNSUPPORTED, "serving not built yet");
+    Server *s = SV(ss);
+    if (!s || !n || (max > 0 && !out)) return fail(PF_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t k = 0;
+    for (auto &kv : s->all) {
+        if (k >= max) break;
+        Req *r = kv.second;
+        if (r->state == FINISHED && !r->reported) {
+            out[k++] = r->res;
+            r->reported = true;
+        }
+    }
+    *n = k;
+    if (!s->fatal.empty()) return fail(PF_ERR_DEVICE, s->fatal);
+    return PF_OK;
 }
-PF_API pf_status pf_server_fetch(pf_server *, uint64_t, int32_t, double *, int64_t)
+
+PF_API pf_status pf_server_fetch(pf_server *ss, uint64_t ticket, int32_t field, double *host,
+                                 int64_t count)
 {
-    return fail(PF_ERR_UNSUPPORTED, "serving not built yet");
+    Server *s = SV(ss);
+    if (!s || !host) return fail(PF_ERR_ARG, "NULL argument");
+    Model *m;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) return fail(PF_ERR_NOTFOUND, "unknown ticket");
+        Req *r = it->second;
+        if (r->state != FINISHED || r->released || !r->m) return fail(PF_ERR_STATE, "request not finished or released");
+        m = r->m;
+    }
+    if (field < 0 || field >= m->nf) return fail(PF_ERR_ARG, "field index out of range");
+    const pf_desc &d = m->desc;
+    const int64_t N = d.n[0] * d.n[1] * d.n[2];
+    if (count != N) return fail(PF_ERR_ARG, "count must equal the number of sites");
+    const size_t ts = m->fp32 ? 4 : 8;
+    std::vector<unsigned char> stage(ts * (size_t)N);
+    hipError_t e = hipMemcpy2DAsync(stage.data(), ts * d.n[0], m->buf[field][m->parity], ts * m->pitch,
+                                    ts * d.n[0], d.n[1] * d.n[2], hipMemcpyDeviceToHost, s->copy_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->copy_stream);
+    if (e != hipSuccess) return hip_fail(e, "fetch");
+    for (int64_t i = 0; i < N; ++i)
+        host[i] = m->fp32 ? (double)reinterpret_cast<float *>(stage.data())[i]
+                          : reinterpret_cast<double *>(stage.data())[i];
+    return PF_OK;
 }
-PF_API pf_status pf_server_release(pf_server *, uint64_t) { return fail(PF_ERR_UNSUPPORTED, "serving not built yet"); }
-PF_API pf_status pf_server_cancel(pf_server *, uint64_t) { return fail(PF_ERR_UNSUPPORTED, "serving not built yet"); }
-PF_API pf_status pf_server_drain(pf_server *, double) { return fail(PF_ERR_UNSUPPORTED, "serving not built yet"); }
-PF_API pf_status pf_server_stats(pf_server *, int64_t *, int64_t *, int64_t *, int64_t *)
+
+PF_API pf_status pf_server_release(pf_server *ss, uint64_t ticket)
 {
-    return fail(PF_ERR_UNSUPPORTED, "serving not built yet");
+    Server *s = SV(ss);
+    if (!s) return fail(PF_ERR_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(PF_ERR_NOTFOUND, "unknown ticket");
+    Req *r = it->second;
+    if (r->state != FINISHED) return fail(PF_ERR_STATE, "request not finished");
+    s->all.erase(it);
+    r->released = true;
+    s->to_free.push_back(r);  // freed by the scheduler, in stream order
+    s->cv.notify_all();
+    return PF_OK;
 }
-PF_API void pf_server_destroy(pf_server *) {}
+
+PF_API pf_status pf_server_cancel(pf_server *ss, uint64_t ticket)
+{
+    Server *s = SV(ss);
+    if (!s) return fail(PF_ERR_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(PF_ERR_NOTFOUND, "unknown ticket");
+    Req *r = it->second;
+    if (r->state == QUEUED) {
+        s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), r), s->queue.end());
+        r->status = PF_ERR_STATE;
+        r->state = FINISHED;
+        r->t_done = r->t_admit = s->now();
+        fill_result(r);
+        s->unfinished--;
+        s->done_cv.notify_all();
+    } else if (r->state == RUNNING) {
+        r->cancel = true;
+    }
+    return PF_OK;
+}
+
+PF_API pf_status pf_server_drain(pf_server *ss, double timeout_s)
+{
+    Server *s = SV(ss);
+    if (!s) return fail(PF_ERR_ARG, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto until = std::chrono::steady_clock::now() +
+                       std::chrono::microseconds((int64_t)(timeout_s * 1e6));
+    while (s->unfinished > 0 && s->fatal.empty()) {
+        if (s->done_cv.wait_until(lk, until) == std::cv_status::timeout && s->unfinished > 0)
+            return fail(PF_ERR_BUSY, "drain timed out");
+    }
+    if (!s->fatal.empty()) return fail(PF_ERR_DEVICE, s->fatal);
+    return PF_OK;
+}
+
+PF_API pf_status pf_server_stats(pf_server *ss, int64_t *ticks, int64_t *launches,
+                                 int64_t *captures, int64_t *replays)
+{
+    Server *s = SV(ss);
+    if (!s) return fail(PF_ERR_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (ticks) *ticks = s->tick;
+    if (launches) *launches = s->launches;
+    if (captures) *captures = s->captures;
+    if (replays) *replays = s->replays;
+    return PF_OK;
+}
+
+PF_API void pf_server_destroy(pf_server *ss)
+{
+    Server *s = SV(ss);
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipStreamSynchronize(s->stream);
+    for (auto &kv : s->all) free_req(s, kv.second), delete kv.second;
+    for (Req *r : s->to_free) free_req(s, r), delete r;
+    for (Req *r : s->queue)
+        if (s->all.find(r->ticket) == s->all.end()) delete r;
+    (void)hipStreamSynchronize(s->stream);
+    for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &t : s->classes)
+        for (int b = 0; b < 2; ++b) {
+            (void)hipFree(t.dev[b]);
+            (void)hipHostFree(t.host[b]);
+        }
+    (void)hipEventDestroy(s->ev[0]);
+    (void)hipEventDestroy(s->ev[1]);
+    (void)hipStreamDestroy(s->stream);
+    (void)hipStreamDestroy(s->copy_stream);
+    delete s;
+}
