@@ -29,6 +29,13 @@ sys.path.insert(0, ROOT)
 PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+def log(msg):
+    print("[bench %.1fs] %s" % (time.perf_counter() - T0, msg), file=sys.stderr, flush=True)
+
+
+T0 = time.perf_counter()
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_10508_amd", "csrc")
@@ -97,20 +104,47 @@ def run_ch(P, n, prec, steps, warmup, seed=202):
                 chunk=chunk, family=family)
 
 
-def cpu_baseline(n=2048, steps=3):
-    """The oracle as it stands on the host cores: CH 2D p4 FP64 on an n^2 sample."""
-    import numpy as np
+def cpu_baseline(n=4096, seconds=10.0, batch=10):
+    """The oracle as it stands on the host cores: CH 2D p4 FP64 on an n^2
+    sample of the workload, stepped in batches until `seconds` have passed."""
     import oracle
     import synth
     oracle.build()
-    f0 = synth.initial_fields(2, (1, n, n), 202, synth.IC_UNIFORM, (-0.05, 0.05))
-    oracle.run(2, f0, 2, 1.0, 0.01, 4, [1.0, 1.0], 1)  # warm
+    f = synth.initial_fields(2, (1, n, n), 202, synth.IC_UNIFORM, (-0.05, 0.05))
+    f = oracle.run(2, f, 2, 1.0, 0.01, 4, [1.0, 1.0], 1)  # warm
+    steps = 0
     t0 = time.perf_counter()
-    oracle.run(2, f0, 2, 1.0, 0.01, 4, [1.0, 1.0], steps)
+    while time.perf_counter() - t0 < seconds:
+        f = oracle.run(2, f, 2, 1.0, 0.01, 4, [1.0, 1.0], batch)
+        steps += batch
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", 0) or os.cpu_count() or 1)
     return dict(value=n * n * steps / dt, unit="site-updates/s", cores=cores, kind="oracle",
-                sample="2D Cahn-Hilliard %d^2 p4 FP64, %d steps (%.1f s)" % (n, steps, dt))
+                sample="2D Cahn-Hilliard %d^2 p4 FP64, %d steps in %.1f s (OpenMP)" % (n, steps, dt))
+
+
+def run_gs3d(P, n, prec, steps, warmup, seed=303):
+    """3D Gray-Scott n^3, p = 2, dt = 0.5, 20 cubes of side 16 plus 1 % noise."""
+    d = P.make_desc(P.PF_GS, (n, n, n), dx=1.0, dt=0.5, order=2, precision=prec,
+                    params=[0.2, 0.1, 0.04, 0.06])
+    m = P.Model(d)
+    m.init(P.PF_IC_GS_CUBES, seed, (20, 16, 0.01))
+    m.autotune(2)
+    m.step(warmup)
+    m.sync()
+    m.timing(True)
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.sync()
+    wall = time.perf_counter() - t0
+    kernel_ms, launches = m.timing_read()
+    m.close()
+    sites = float(n) ** 3
+    per = kernel_ms / launches
+    gbs = 2 * 2 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
+    return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
+            "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
+            "frac_of_peak": round(gbs / PEAK_GBS, 4)}
 
 
 def main():
@@ -121,8 +155,9 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
-    ap.add_argument("--serving", type=int, default=0,
-                    help="also run the serving comparison with this many requests")
+    ap.add_argument("--serving", type=int, default=120,
+                    help="requests in the serving comparison (0 skips it)")
+    ap.add_argument("--skip-3d", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -136,8 +171,10 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
 
     attain = copy_probe(P, torch)
+    log("copy probe %.1f GB/s" % attain)
     src = source_hash()
     fp64 = run_ch(P, args.n, P.PF_FP64, args.steps, args.warmup)
+    log("CH FP64: %.3f ms/step" % fp64["ms_per_step"])
     extra = {"copy_probe_gbs": round(attain, 1), "source_hash": src}
     if not args.skip_fp32:
         fp32 = run_ch(P, args.n, P.PF_FP32, args.steps, args.warmup)
@@ -146,11 +183,17 @@ def main():
             "kernel_ms": round(fp32["kernel_ms"], 4), "achieved_gbs": round(fp32["achieved_gbs"], 1),
             "frac_of_peak": round(fp32["achieved_gbs"] / PEAK_GBS, 4),
             "mass_drift": fp32["mass_drift"], "chunk": fp32["chunk"]}
+        log("CH FP32: %.3f ms/step" % fp32["ms_per_step"])
+    if not args.skip_3d:
+        extra["gs3d_1024_fp64"] = run_gs3d(P, 1024, P.PF_FP64, max(10, args.steps // 4), 5)
+        extra["gs3d_1024_fp32"] = run_gs3d(P, 1024, P.PF_FP32, max(10, args.steps // 4), 5)
+        log("GS 3D done")
     extra["fp64_mass_drift"] = fp64["mass_drift"]
     extra["fp64_chunk"] = fp64["chunk"]
     if args.serving:
         from paper_2511_10508_amd import serving
-        extra["serving"] = serving.compare(args.serving)
+        extra["serving"] = serving.compare(args.serving, log=log)
+        log("serving done")
 
     traffic = measured_traffic("ch2d_%d_fp64" % args.n, src)
     out = {
@@ -178,6 +221,7 @@ def main():
     }
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline()
+        log("cpu baseline done")
     print(json.dumps(out))
 
 

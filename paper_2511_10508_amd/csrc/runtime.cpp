@@ -206,10 +206,25 @@ static bool plan(Model *m)
     return true;
 }
 
+// Default chunk length along the marching axis: long enough to amortise the
+// 2H warm-up rows, short enough that small grids still expose thousands of
+// work items (about 4096 waves in 2D, 1024 workgroups of 16 waves in 3D).
 int32_t default_chunk(const pf_desc *d)
 {
     const int64_t march = d->ndim == 2 ? d->n[1] : d->n[2];
-    int64_t c = d->ndim == 2 ? 512 : 64;
+    const int64_t lanes = d->precision == PF_FP32 ? 256 : 128;
+    const int64_t strips = std::max<int64_t>(1, (d->n[0] + lanes - 1) / lanes);
+    const int64_t cmin = 8;
+    int64_t cmax, c;
+    if (d->ndim == 2) {
+        cmax = 512;
+        c = march * strips / 4096;
+    } else {
+        cmax = 64;
+        const int64_t ytiles = std::max<int64_t>(1, (d->n[1] + 7) / 8);
+        c = march * strips * ytiles / 1024;
+    }
+    c = std::max(cmin, std::min(cmax, c));
     return (int32_t)std::max<int64_t>(1, std::min<int64_t>(c, march));
 }
 

@@ -73,6 +73,9 @@ struct ClassTables {
     void *dev[2] = {nullptr, nullptr};   // [args | count | item_start | steps]
     void *host[2] = {nullptr, nullptr};
     int32_t n[2] = {0, 0};
+    int32_t blocks[2] = {1, 1};          // persistent grid of this tick (power of two)
+    hipStream_t stream = nullptr;        // graph branch of this class
+    hipEvent_t join = nullptr;
 };
 
 }  // namespace
@@ -100,6 +103,7 @@ struct Server {
     std::vector<ClassTables> classes;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr;
     int64_t tick = 0, launches = 0, captures = 0, replays = 0;
     std::string fatal;
 
@@ -125,6 +129,8 @@ static int class_of(Server *s, const Model *m)
         if (hipMalloc(&t.dev[b], total) != hipSuccess) return -1;
         if (hipHostMalloc(&t.host[b], total, hipHostMallocDefault) != hipSuccess) return -1;
     }
+    if (hipStreamCreateWithFlags(&t.stream, hipStreamNonBlocking) != hipSuccess) return -1;
+    if (hipEventCreateWithFlags(&t.join, hipEventDisableTiming) != hipSuccess) return -1;
     const int idx = (int)s->classes.size();
     s->classes.push_back(t);
     s->class_index[k] = idx;
@@ -170,38 +176,43 @@ static void fill_result(Req *r)
     }
 }
 
-// Launch the batched steps of one tick for the given classes and buffer set.
-static hipError_t launch_tick(Server *s, const std::vector<int> &cls, int set, int S)
+// Launch the S batched steps of one class (buffer set `set`) on `st`.
+static hipError_t launch_class(Server *s, int c, int set, int S, hipStream_t st)
 {
-    for (int k = 0; k < S; ++k)
-        for (int c : cls) {
-            ClassTables &t = s->classes[c];
-            char *dev = static_cast<char *>(t.dev[set]);
-            hipError_t e;
-            int32_t *ints = reinterpret_cast<int32_t *>(dev + t.args_bytes);
-            if (t.L.fp32) {
-                BatchTable<float> tb{reinterpret_cast<StepArgs<float> *>(dev), ints, ints + 1,
-                                     ints + 1 + s->max_slots + 1};
-                e = t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, kPersist2D, s->stream)
-                                  : launch_fused3d_batched(t.L, &tb, k, kPersist3D, s->stream);
-            } else {
-                BatchTable<double> tb{reinterpret_cast<StepArgs<double> *>(dev), ints, ints + 1,
-                                      ints + 1 + s->max_slots + 1};
-                e = t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, kPersist2D, s->stream)
-                                  : launch_fused3d_batched(t.L, &tb, k, kPersist3D, s->stream);
-            }
-            if (e != hipSuccess) return e;
-            s->launches++;
+    ClassTables &t = s->classes[c];
+    char *dev = static_cast<char *>(t.dev[set]);
+    int32_t *ints = reinterpret_cast<int32_t *>(dev + t.args_bytes);
+    for (int k = 0; k < S; ++k) {
+        hipError_t e;
+        if (t.L.fp32) {
+            BatchTable<float> tb{reinterpret_cast<StepArgs<float> *>(dev), ints, ints + 1,
+                                 ints + 1 + s->max_slots + 1};
+            e = t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, t.blocks[set], st)
+                              : launch_fused3d_batched(t.L, &tb, k, t.blocks[set], st);
+        } else {
+            BatchTable<double> tb{reinterpret_cast<StepArgs<double> *>(dev), ints, ints + 1,
+                                  ints + 1 + s->max_slots + 1};
+            e = t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, t.blocks[set], st)
+                              : launch_fused3d_batched(t.L, &tb, k, t.blocks[set], st);
         }
+        if (e != hipSuccess) return e;
+        s->launches++;
+    }
     return hipSuccess;
 }
 
+// One graph per (buffer set, steps, class set with grid buckets).  Each class
+// is a branch of S chained launches on its own stream, forked from and joined
+// back into the server stream, so different classes run concurrently.
 static hipError_t run_graph(Server *s, const std::vector<int> &cls, int set, int S)
 {
     std::vector<int64_t> key;
     key.push_back(set);
     key.push_back(S);
-    for (int c : cls) key.push_back(c);
+    for (int c : cls) {
+        key.push_back(c);
+        key.push_back(s->classes[c].blocks[set]);
+    }
     auto it = s->graphs.find(key);
     if (it == s->graphs.end()) {
         if ((int)s->graphs.size() >= kMaxGraphs) {
@@ -210,7 +221,14 @@ static hipError_t run_graph(Server *s, const std::vector<int> &cls, int set, int
         }
         hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        hipError_t le = launch_tick(s, cls, set, S);
+        hipError_t le = hipEventRecord(s->fork, s->stream);
+        for (int c : cls) {
+            ClassTables &t = s->classes[c];
+            if (le == hipSuccess) le = hipStreamWaitEvent(t.stream, s->fork, 0);
+            if (le == hipSuccess) le = launch_class(s, c, set, S, t.stream);
+            if (le == hipSuccess) le = hipEventRecord(t.join, t.stream);
+            if (le == hipSuccess) le = hipStreamWaitEvent(s->stream, t.join, 0);
+        }
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(s->stream, &g);
         if (le != hipSuccess) {
@@ -277,6 +295,13 @@ static bool enqueue_tick(Server *s, std::vector<Req *> &run, int set)
             steps[i] = (int32_t)std::min<int64_t>(S, v[i]->nsteps - v[i]->done);
         }
         start[v.size()] = acc;
+        // persistent grid: enough workgroups for every item, rounded up to a
+        // power of two so that few distinct graphs are needed
+        const int64_t need = t.L.ndim == 2 ? (acc + kWaves2D - 1) / kWaves2D : acc;
+        const int32_t cap = t.L.ndim == 2 ? kPersist2D : kPersist3D;
+        int32_t b = 1;
+        while (b < need && b < cap) b <<= 1;
+        t.blocks[set] = b;
         const size_t argsz = t.L.fp32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
         hipError_t e = hipMemcpyAsync(t.dev[set], t.host[set], argsz * v.size(), hipMemcpyHostToDevice,
                                       s->stream);
@@ -479,6 +504,7 @@ PF_API pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t m
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
     if (e != hipSuccess) {
         delete s;
         return hip_fail(e, "server stream/event");
@@ -656,11 +682,15 @@ PF_API void pf_server_destroy(pf_server *ss)
         if (s->all.find(r->ticket) == s->all.end()) delete r;
     (void)hipStreamSynchronize(s->stream);
     for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
-    for (auto &t : s->classes)
+    for (auto &t : s->classes) {
         for (int b = 0; b < 2; ++b) {
             (void)hipFree(t.dev[b]);
             (void)hipHostFree(t.host[b]);
         }
+        (void)hipStreamDestroy(t.stream);
+        (void)hipEventDestroy(t.join);
+    }
+    (void)hipEventDestroy(s->fork);
     (void)hipEventDestroy(s->ev[0]);
     (void)hipEventDestroy(s->ev[1]);
     (void)hipStreamDestroy(s->stream);

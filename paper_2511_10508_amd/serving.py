@@ -162,15 +162,27 @@ def run_serial(trace):
     return dict(p50_s=_pct(lat, 50), p99_s=_pct(lat, 99), makespan_s=makespan, su_per_s=work / makespan)
 
 
-def compare(nreq, seed=505, load=0.8, steps_per_tick=64):
-    """Pilot (all requests at t = 0) sets the batched capacity; then both the
-    server and the serial loop replay the same Poisson trace at `load` x
-    capacity."""
-    pilot = synth.serving_trace(nreq, seed=seed, rate=None)
-    cap = run_batched(pilot, steps_per_tick=steps_per_tick)
-    rate = load * nreq / cap["makespan_s"]
+def compare(nreq, seed=505, load=0.8, steps_per_tick=64, log=None):
+    """Throughput: both loops on the whole trace submitted at t = 0 (capacity,
+    aggregate site-updates/s over the makespan).  Latency: both loops on the
+    same Poisson trace at `load` x the batched capacity (requests/s); p50 and
+    p99 of completion minus arrival."""
+    log = log or (lambda m: None)
+    burst = synth.serving_trace(nreq, seed=seed, rate=None)
+    cap_b = run_batched(burst, steps_per_tick=steps_per_tick)
+    log("serving batched capacity: %.2f s" % cap_b["makespan_s"])
+    cap_s = run_serial(burst)
+    log("serving serial capacity: %.2f s" % cap_s["makespan_s"])
+    rate = load * nreq / cap_b["makespan_s"]
     trace = synth.serving_trace(nreq, seed=seed, rate=rate)
-    b = run_batched(trace, steps_per_tick=steps_per_tick)
-    s = run_serial(trace)
-    return dict(requests=nreq, rate_req_per_s=rate, pilot_su_per_s=cap["su_per_s"],
-                batched=b, serial=s, speedup=b["su_per_s"] / s["su_per_s"])
+    lat_b = run_batched(trace, steps_per_tick=steps_per_tick)
+    log("serving batched at %.1f req/s: %.2f s" % (rate, lat_b["makespan_s"]))
+    lat_s = run_serial(trace)
+    log("serving serial at %.1f req/s: %.2f s" % (rate, lat_s["makespan_s"]))
+    return dict(requests=nreq, site_updates=sum(request_spec(r)[3] * r["steps"] for r in burst),
+                batched_su_per_s=cap_b["su_per_s"], serial_su_per_s=cap_s["su_per_s"],
+                throughput_speedup=cap_b["su_per_s"] / cap_s["su_per_s"],
+                load=load, rate_req_per_s=rate,
+                batched_p50_s=lat_b["p50_s"], batched_p99_s=lat_b["p99_s"],
+                serial_p50_s=lat_s["p50_s"], serial_p99_s=lat_s["p99_s"],
+                batched_capacity=cap_b, serial_capacity=cap_s, batched_load=lat_b, serial_load=lat_s)

@@ -57,7 +57,11 @@ def _serve(reqs, steps_per_tick=16, budget=0, max_slots=64, late=None, timeout=1
         d, ic, icp, _ = request_spec(r)
         tickets[srv.submit(d, ic, r["seed"], icp, r["steps"])] = r
     if late:
-        time.sleep(0.05)
+        # join while the first batch is on the device: wait for a few ticks
+        t_end = time.time() + timeout
+        while srv.stats()["ticks"] < 4:
+            assert time.time() < t_end
+            time.sleep(0.0002)
         for r in late:
             d, ic, icp, _ = request_spec(r)
             tickets[srv.submit(d, ic, r["seed"], icp, r["steps"])] = r
@@ -122,7 +126,7 @@ def test_late_arrivals_join_running_batch():
     reqs = _mixed_requests()
     first, late = reqs[:6], reqs[6:]
     for r in first:
-        r["steps"] = 400
+        r["steps"] = 3000
     results, st = _serve(first, steps_per_tick=8, late=late)
     assert len(results) == len(reqs)
     admits_first = max(results[r["id"]][0]["t_admit"] for r in first)
