@@ -37,11 +37,13 @@ T0 = time.perf_counter()
 
 
 def source_hash():
+    """Hash of the device-code sources (kernels and the headers they include)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_10508_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        if f.endswith(".hip") or f in ("pf_device.h", "pf_internal.h", "pf_dispatch.h"):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -88,20 +90,23 @@ def run_ch(P, n, prec, steps, warmup, seed=202):
     m.step(steps)
     m.sync()
     t1 = time.perf_counter()
-    kernel_ms, launches = m.timing_read()
+    kernel_ms, launches, ksteps = m.timing_read()
     hi, lo = m.reduce_history(P.PF_RED_MASS0, steps)
     mass = hi + lo
     drift = float(abs(mass - mass[0]).max())
     chunk, family = m.tile()
+    tb = m.time_block()
     m.close()
     sites = float(n) * n
     wall = t1 - t0
     per_launch = kernel_ms / launches
-    alg_bytes = 2 * 1 * (8 if prec == P.PF_FP64 else 4) * sites
+    # algorithmic bytes of one launch: every field read and written once per
+    # time step it advances (a two-step launch counts two steps)
+    alg_bytes = 2 * 1 * (8 if prec == P.PF_FP64 else 4) * sites * (ksteps / launches)
     return dict(sites=sites, wall=wall, su_s=sites * steps / wall, ms_per_step=wall / steps * 1e3,
-                kernel_ms=per_launch, alg_bytes=alg_bytes,
+                kernel_ms=per_launch, alg_bytes=alg_bytes, steps_per_launch=ksteps / launches,
                 achieved_gbs=alg_bytes / (per_launch * 1e-3) / 1e9, mass_drift=drift,
-                chunk=chunk, family=family)
+                chunk=chunk, family=family, time_block=tb)
 
 
 def cpu_baseline(n=4096, seconds=10.0, batch=10):
@@ -137,10 +142,10 @@ def run_gs3d(P, n, prec, steps, warmup, seed=303):
     m.step(steps)
     m.sync()
     wall = time.perf_counter() - t0
-    kernel_ms, launches = m.timing_read()
+    kernel_ms, launches, ksteps = m.timing_read()
     m.close()
     sites = float(n) ** 3
-    per = kernel_ms / launches
+    per = kernel_ms / ksteps
     gbs = 2 * 2 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
     return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
             "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
@@ -182,7 +187,8 @@ def main():
             "value": fp32["su_s"], "ms_per_step": round(fp32["ms_per_step"], 4),
             "kernel_ms": round(fp32["kernel_ms"], 4), "achieved_gbs": round(fp32["achieved_gbs"], 1),
             "frac_of_peak": round(fp32["achieved_gbs"] / PEAK_GBS, 4),
-            "mass_drift": fp32["mass_drift"], "chunk": fp32["chunk"]}
+            "mass_drift": fp32["mass_drift"], "chunk": fp32["chunk"],
+            "time_block": fp32["time_block"]}
         log("CH FP32: %.3f ms/step" % fp32["ms_per_step"])
     if not args.skip_3d:
         extra["gs3d_1024_fp64"] = run_gs3d(P, 1024, P.PF_FP64, max(10, args.steps // 4), 5)
@@ -190,6 +196,8 @@ def main():
         log("GS 3D done")
     extra["fp64_mass_drift"] = fp64["mass_drift"]
     extra["fp64_chunk"] = fp64["chunk"]
+    extra["fp64_time_block"] = fp64["time_block"]
+    extra["fp64_kernel_ms_per_launch"] = round(fp64["kernel_ms"], 4)
     if args.serving:
         from paper_2511_10508_amd import serving
         extra["serving"] = serving.compare(args.serving, log=log)

@@ -225,21 +225,34 @@ pf_status pf_set_tile(pf_model *m, int32_t chunk);
 pf_status pf_get_tile(pf_model *m, int32_t *chunk, int32_t *family);
 
 /*
- * Autotuner: times each candidate tile on the model's own buffers (the
- * state is saved and restored), keeps the fastest and records it in an
- * in-process cache keyed by (kind, ndim, order, precision, size class) that
- * later models of the same class reuse.  trials = timed steps per candidate.
+ * Temporal blocking: tb = 2 fuses two time steps into one sweep over the
+ * fields (the intermediate state stays in registers), halving HBM traffic per
+ * step; available for 2D grids with order 2 or 4 on the fused kernels
+ * (otherwise PF_ERR_UNSUPPORTED).  Results are bitwise those of tb = 1.  An
+ * odd remainder of a pf_step call runs one single step.
+ */
+pf_status pf_set_time_block(pf_model *m, int32_t tb);
+int32_t pf_get_time_block(const pf_model *m);
+
+/*
+ * Autotuner: times each candidate (chunk length, time-block factor) on the
+ * model's own buffers by re-running steps from the current state (whose
+ * buffer is never written, so the state is unchanged), keeps the fastest per
+ * step and records it in an in-process cache keyed by (kind, ndim, order,
+ * precision, size class) that later models of the same class reuse.
+ * trials = timed launches per candidate.
  */
 pf_status pf_autotune(pf_model *m, int32_t trials);
 
 /*
  * Kernel timing on the model's stream: while enabled, pf_step records a HIP
- * event pair around every step-kernel launch; pf_timing_read synchronises
- * and returns the summed kernel milliseconds and the number of launches
- * since the last enable.
+ * event pair around every step-kernel launch (graph replay is off);
+ * pf_timing_read synchronises and returns the summed kernel milliseconds,
+ * the number of launches and the number of time steps they advanced since
+ * the last enable (any output pointer may be NULL).
  */
 pf_status pf_timing_enable(pf_model *m, int32_t on);
-pf_status pf_timing_read(pf_model *m, double *total_ms, int64_t *launches);
+pf_status pf_timing_read(pf_model *m, double *total_ms, int64_t *launches, int64_t *steps);
 
 /*
  * Measurement helper: stream `bytes` from src to dst (device pointers,

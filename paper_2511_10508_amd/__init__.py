@@ -85,9 +85,11 @@ SIGNATURES = {
     "pf_stream": (_i32, [_vp, _P(_vp)]),
     "pf_set_tile": (_i32, [_vp, _i32]),
     "pf_get_tile": (_i32, [_vp, _pi32, _pi32]),
+    "pf_set_time_block": (_i32, [_vp, _i32]),
+    "pf_get_time_block": (_i32, [_vp]),
     "pf_autotune": (_i32, [_vp, _i32]),
     "pf_timing_enable": (_i32, [_vp, _i32]),
-    "pf_timing_read": (_i32, [_vp, _pd, _pi64]),
+    "pf_timing_read": (_i32, [_vp, _pd, _pi64, _pi64]),
     "pf_copy_probe": (_i32, [_vp, _vp, _u64, _vp, _i32, _pd]),
     "pf_server_create": (_i32, [_i32, _u64, _i32, _i32, _P(_vp)]),
     "pf_server_submit": (_i32, [_vp, _P(pf_desc), _i32, _u64, _pd, _i32, _i64, _P(_u64)]),
@@ -248,9 +250,16 @@ class Model:
         check(lib().pf_timing_enable(self.h, 1 if on else 0))
 
     def timing_read(self):
-        ms, n = _d(), _i64()
-        check(lib().pf_timing_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
+        """(kernel ms, launches, steps) since timing(True)."""
+        ms, n, st = _d(), _i64(), _i64()
+        check(lib().pf_timing_read(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(st)))
+        return ms.value, n.value, st.value
+
+    def set_time_block(self, tb):
+        check(lib().pf_set_time_block(self.h, tb))
+
+    def time_block(self):
+        return lib().pf_get_time_block(self.h)
 
     def stream(self):
         s = _vp()

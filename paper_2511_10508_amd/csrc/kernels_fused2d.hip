@@ -5,8 +5,14 @@
 namespace pf {
 
 using Fused2DRadii = RList<1, 2, 3, 4>;
+using TimeBlockRadii = RList<1, 2>;  // radii with a two-step (TB = 2) kernel
 
-bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int32_t *strips,
+bool time_block_available(const Launch &L)
+{
+    return L.ndim == 2 && (L.r == 1 || L.r == 2);
+}
+
+bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int tb, int32_t *strips,
                   int32_t *ow, int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads)
 {
     bool ok = false;
@@ -16,9 +22,10 @@ bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int32_t
             constexpr int KIND = decltype(kc)::value;
             ok = dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
-                using S = Shape<T, KIND, R>;
-                const int64_t st = cdiv(nx, S::OWMAX);
-                int64_t w = cdiv(cdiv(nx, st), S::V) * S::V;
+                const int owmax = tb == 2 ? Shape<T, KIND, R, 2>::OWMAX : Shape<T, KIND, R, 1>::OWMAX;
+                constexpr int V = Shape<T, KIND, R>::V;
+                const int64_t st = cdiv(nx, owmax);
+                int64_t w = cdiv(cdiv(nx, st), V) * V;
                 *strips = (int32_t)st;
                 *ow = (int32_t)w;
                 *chunks = (int32_t)cdiv(ny, clen);
@@ -33,7 +40,7 @@ bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int32_t
 }
 
 hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
-                          int red, hipStream_t s)
+                          int red, int tb, hipStream_t s)
 {
     hipError_t err = hipErrorInvalidValue;
     dispatch_prec(L.fp32, [&](auto tz) {
@@ -41,12 +48,23 @@ hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
         dispatch_kind(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
+            if (tb == 2) {
+                dispatch_r(L.r, TimeBlockRadii{}, [&](auto rc) {
+                    constexpr int R = decltype(rc)::value;
+                    if (red)
+                        hipLaunchKernelGGL((k_step2d<T, KIND, R, true, 2>), dim3(blocks), dim3(threads), 0, s, a);
+                    else
+                        hipLaunchKernelGGL((k_step2d<T, KIND, R, false, 2>), dim3(blocks), dim3(threads), 0, s, a);
+                    err = hipGetLastError();
+                });
+                return;
+            }
             dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
                 if (red)
-                    hipLaunchKernelGGL((k_step2d<T, KIND, R, true>), dim3(blocks), dim3(threads), 0, s, a);
+                    hipLaunchKernelGGL((k_step2d<T, KIND, R, true, 1>), dim3(blocks), dim3(threads), 0, s, a);
                 else
-                    hipLaunchKernelGGL((k_step2d<T, KIND, R, false>), dim3(blocks), dim3(threads), 0, s, a);
+                    hipLaunchKernelGGL((k_step2d<T, KIND, R, false, 1>), dim3(blocks), dim3(threads), 0, s, a);
                 err = hipGetLastError();
             });
         });

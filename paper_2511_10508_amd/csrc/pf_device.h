@@ -179,6 +179,15 @@ __device__ __forceinline__ void gs_update(const StepArgs<T> &a, T u0, T v0, cons
     vn = av;
 }
 
+// Landau free-energy density at a site from its chemical potential
+// mu = c2 x^3 - c1 x - L x: the density -(1/2) x Lx + (c2/4) x^4 - (c1/2) x^2
+// equals (1/2) x mu - (c2/4) x^4.  Used when mu is already FP64.
+__device__ __forceinline__ double energy_from_mu(double c2, double x, double mu)
+{
+    const double x2 = x * x;
+    return fma(0.5 * x, mu, -(0.25 * c2) * (x2 * x2));
+}
+
 // Landau free-energy density in FP64 at a site: -(1/2) x Lx + (c2/4) x^4 -
 // (c1/2) x^2, with Lx from FP64 neighbour sums S64 (same pairing order).
 template <int R>
@@ -225,10 +234,10 @@ __device__ __forceinline__ void gather_x(const T (&c)[V], T (&e)[V + 2 * R])
     });
 }
 
-template <typename T, int KIND, int R>
+template <typename T, int KIND, int R, int TB = 1>
 struct Shape {
     static constexpr int V = Vec<T>::V;
-    static constexpr int H = KIND == kCH ? 2 * R : R;  // halo of one step
+    static constexpr int H = (KIND == kCH ? 2 * R : R) * TB;  // halo of TB fused steps
     static constexpr int HV = (H + V - 1) / V * V;     // halo rounded to whole lanes
     static constexpr int SW = 64 * V;                  // strip width (loaded columns)
     static constexpr int OWMAX = SW - 2 * HV;          // most outputs per strip
@@ -294,16 +303,166 @@ __device__ __forceinline__ void store_row(T *__restrict__ row, int64_t xl, const
 // ===========================================================================
 // 2D fused marching step.  One wave owns a strip of SW = 64 V columns (V
 // values per lane, x-neighbours by lane shuffles) and marches along y over
-// one chunk of output rows, keeping the last K = 2r+1 rows of every field
-// (and for CH of mu) in registers.  Loads run K rows ahead (prefetch ring).
-// CH computes mu = c2 c^3 - c1 c - L c for row t - r and the update for row
-// t - 2r in the same sweep: the biharmonic never touches memory.
-template <typename T, int KIND, int R, bool RED, bool FAST>
+// one chunk of output rows.  Each radius-r stencil evaluation is a "stage"
+// that consumes a ring of the last K = 2r+1 rows of its input stream (in
+// registers) and produces one row of its output stream r rows behind:
+//   AC, GS:  state n -> state n+1                       (1 stage per step)
+//   CH:      state n -> mu -> state n+1                  (2 stages per step)
+// With TB = 2 the stages of two time steps are chained, so one sweep over HBM
+// advances the grid two steps; the intermediate state never leaves the
+// registers.  Every stage uses the same per-site functions, so TB = 2 is
+// bitwise equal to two TB = 1 steps.  Loads run K rows ahead (prefetch ring).
+
+// Neighbour pair sums (x pair + y pair) at element v for j = 1..R around the
+// centre row CS of a ring, with the centre row's x-neighbourhood in e.
+template <typename T, int V, int R, int K, int CS>
+__device__ __forceinline__ void pairs2d(const T (&rg)[K][V], const T (&e)[V + 2 * R], int v,
+                                        T (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = (e[R + v + j] + e[R + v - j]) + (rg[sp][v] + rg[sm][v]);
+    });
+}
+
+template <typename T, int V, int R, int K, int CS>
+__device__ __forceinline__ void pairs2d64(const T (&rg)[K][V], const T (&e)[V + 2 * R], int v,
+                                          double (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = ((double)e[R + v + j] + (double)e[R + v - j]) +
+                   ((double)rg[sp][v] + (double)rg[sm][v]);
+    });
+}
+
+// AC / GS step of the centre row CS of the state rings rg (NF fields); with
+// RED the state at that row is reduced (masked by om and red_row).
+template <typename T, int KIND, int R, int K, int CS, bool RED>
+__device__ __forceinline__ void stage_acgs(const StepArgs<T> &a,
+                                           const T (&rg)[KIND == kGS ? 2 : 1][K][Vec<T>::V],
+                                           T (&res)[KIND == kGS ? 2 : 1][Vec<T>::V],
+                                           const OutMask<Vec<T>::V> &om, bool red_row,
+                                           RedState &red)
+{
+    constexpr int V = Vec<T>::V, NF = KIND == kGS ? 2 : 1;
+    T e[NF][V + 2 * R];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) gather_x<T, V, R>(rg[f][CS], e[f]);
+    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sf[NF][R];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) pairs2d<T, V, R, K, CS>(rg[f], e[f], v, Sf[f]);
+        const T u0 = rg[0][CS][v];
+        if constexpr (KIND == kAC) {
+            res[0][v] = ac_update<T, R>(a, u0, Sf[0], u0 * T(4));
+        } else {
+            const T v0 = rg[NF - 1][CS][v];
+            gs_update<T, R>(a, u0, v0, Sf[0], Sf[NF - 1], u0 * T(4), v0 * T(4), res[0][v],
+                            res[NF - 1][v]);
+        }
+        if constexpr (RED) {
+            if (red_row && om.ov[v]) {
+                const double x = (double)u0;
+                rs0 += x;
+                rbad += finite_val(x) ? 0.0 : 1.0;
+                if constexpr (KIND == kAC) {
+                    if constexpr (std::is_same<T, double>::value) {
+                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 4.0);
+                    } else {
+                        double S64[R];
+                        pairs2d64<T, V, R, K, CS>(rg[0], e[0], v, S64);
+                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                    }
+                } else {
+                    const double y = (double)rg[NF - 1][CS][v];
+                    rs1 += y;
+                    rbad += finite_val(y) ? 0.0 : 1.0;
+                }
+            }
+        }
+    }
+    if constexpr (RED) {
+        if (red_row) {
+            acc_add(red.q0, rs0);
+            acc_add(red.q1, rs1);
+            red.bad += rbad;
+        }
+    }
+}
+
+// CH chemical potential of the centre row CS of the concentration ring c.
+template <typename T, int R, int K, int CS, bool RED>
+__device__ __forceinline__ void stage_mu(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                         T (&mu)[Vec<T>::V], const OutMask<Vec<T>::V> &om,
+                                         bool red_row, RedState &red)
+{
+    constexpr int V = Vec<T>::V;
+    T e[V + 2 * R];
+    gather_x<T, V, R>(c[CS], e);
+    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sc[R];
+        pairs2d<T, V, R, K, CS>(c, e, v, Sc);
+        const T c0 = c[CS][v];
+        mu[v] = ch_mu<T, R>(a, c0, Sc, c0 * T(4));
+        if constexpr (RED) {
+            if (red_row && om.ov[v]) {
+                const double x = (double)c0;
+                rs0 += x;
+                if constexpr (std::is_same<T, double>::value) {
+                    rs1 += energy_from_mu(a.c2, x, mu[v]);
+                } else {
+                    double S64[R];
+                    pairs2d64<T, V, R, K, CS>(c, e, v, S64);
+                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                }
+                rbad += finite_val(x) ? 0.0 : 1.0;
+            }
+        }
+    }
+    if constexpr (RED) {
+        if (red_row) {
+            acc_add(red.q0, rs0);
+            acc_add(red.q1, rs1);
+            red.bad += rbad;
+        }
+    }
+}
+
+// CH update of the centre row CS: c' = c + dt L mu.
+template <typename T, int R, int K, int CS>
+__device__ __forceinline__ void stage_chupd(const StepArgs<T> &a, const T (&m)[K][Vec<T>::V],
+                                            const T (&c0)[Vec<T>::V], T (&res)[Vec<T>::V])
+{
+    constexpr int V = Vec<T>::V;
+    T em[V + 2 * R];
+    gather_x<T, V, R>(m[CS], em);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sm[R];
+        pairs2d<T, V, R, K, CS>(m, em, v, Sm);
+        res[v] = ch_update<T, R>(a, c0[v], Sm, m[CS][v] * T(4));
+    }
+}
+
+template <int K, int D>
+struct Slot {
+    template <int PH>
+    static constexpr int at = ((PH - D) % K + 2 * K) % K;
+};
+
+template <typename T, int KIND, int R, bool RED, bool FAST, int TB>
 __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t xb, int64_t y0,
                                         int64_t y1, int lane, int64_t pslot)
 {
-    using S = Shape<T, KIND, R>;
-    constexpr int V = S::V, H = S::H, HV = S::HV, NE = S::NE, K = S::K, NF = S::NF;
+    using S = Shape<T, KIND, R, TB>;
+    constexpr int V = S::V, H = S::H, HV = S::HV, K = S::K, NF = S::NF;
     const int64_t nx = a.nx, ny = a.ny, pitch = a.pitch;
     const int64_t xl = xb + lane * V;
     const int pl = lane * V;
@@ -318,10 +477,12 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
     const T *in[2] = {a.buf[0][par], a.buf[NF - 1][par]};
     T *out[2] = {a.buf[0][par ^ 1], a.buf[NF - 1][par ^ 1]};
 
-    T ring[NF][K][V];
-    T pre[NF][K][V];
-    T mring[KIND == kCH ? K : 1][V];
-    RedState red;
+    T ring[NF][K][V];                                    // state n (loaded)
+    T pre[NF][K][V];                                     // prefetched rows
+    T r1[TB == 2 ? NF : 1][K][V];                        // state n+1 (TB = 2)
+    T m0[KIND == kCH ? K : 1][V];                        // mu of state n
+    T m1[(KIND == kCH && TB == 2) ? K : 1][V];           // mu of state n+1
+    RedState red[TB];
 
     const int64_t tb0 = y0 - H, tend = y1 + H;
     static_for<0, K>([&](auto phc) {
@@ -339,6 +500,7 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
             constexpr int ph = decltype(phc)::value;
             const int64_t t = tb + ph;
             if (t < tend) {
+                const int64_t age = t - tb0;  // a stage of depth k is valid once age >= 2 k r
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -349,162 +511,103 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
                     for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
                 }
                 if constexpr (KIND != kCH) {
-                    constexpr int co = (ph - R + K) % K;
-                    const int64_t o = t - R;
-                    if (o >= y0) {
-                        T e[NF][NE];
-#pragma unroll
-                        for (int f = 0; f < NF; ++f) gather_x<T, V, R>(ring[f][co], e[f]);
+                    constexpr int s1 = Slot<K, R>::template at<ph>;
+                    if (age >= 2 * R) {
+                        const int64_t row = t - R;
                         T res[NF][V];
-                        double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+                        stage_acgs<T, KIND, R, K, s1, RED>(a, ring, res, om, row >= y0 && row < y1,
+                                                           red[0]);
+                        if constexpr (TB == 1) {
+                            const int64_t ooff = wrap_any(row, ny) * pitch;
 #pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            T Sf[NF][R];
-                            static_for<1, R + 1>([&](auto jc) {
-                                constexpr int j = decltype(jc)::value;
-                                constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
+                            for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                        } else {
 #pragma unroll
-                                for (int f = 0; f < NF; ++f)
-                                    Sf[f][j - 1] = (e[f][R + v + j] + e[f][R + v - j]) +
-                                                   (ring[f][sp][v] + ring[f][sm][v]);
-                            });
-                            const T u0 = ring[0][co][v];
-                            if constexpr (KIND == kAC) {
-                                res[0][v] = ac_update<T, R>(a, u0, Sf[0], u0 * T(4));
-                            } else {
-                                const T v0 = ring[NF - 1][co][v];
-                                gs_update<T, R>(a, u0, v0, Sf[0], Sf[NF - 1], u0 * T(4),
-                                                v0 * T(4), res[0][v], res[NF - 1][v]);
-                            }
-                            if constexpr (RED) {
-                                if (om.ov[v]) {
-                                    const double x = (double)u0;
-                                    rs0 += x;
-                                    rbad += finite_val(x) ? 0.0 : 1.0;
-                                    if constexpr (KIND == kAC) {
-                                        double S64[R];
-                                        static_for<1, R + 1>([&](auto jc) {
-                                            constexpr int j = decltype(jc)::value;
-                                            constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
-                                            S64[j - 1] = ((double)e[0][R + v + j] +
-                                                          (double)e[0][R + v - j]) +
-                                                         ((double)ring[0][sp][v] +
-                                                          (double)ring[0][sm][v]);
-                                        });
-                                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
-                                    } else {
-                                        const double y = (double)ring[NF - 1][co][v];
-                                        rs1 += y;
-                                        rbad += finite_val(y) ? 0.0 : 1.0;
-                                    }
-                                }
-                            }
+                            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                                for (int v = 0; v < V; ++v) r1[f][s1][v] = res[f][v];
                         }
-                        if constexpr (RED) {
-                            acc_add(red.q0, rs0);
-                            acc_add(red.q1, rs1);
-                            red.bad += rbad;
-                        }
-                        const int64_t ooff = wrap_any(o, ny) * pitch;
+                    }
+                    if constexpr (TB == 2) {
+                        constexpr int s2 = Slot<K, 2 * R>::template at<ph>;
+                        if (age >= 4 * R) {
+                            const int64_t row = t - 2 * R;
+                            T res[NF][V];
+                            stage_acgs<T, KIND, R, K, s2, RED>(a, r1, res, om, row >= y0 && row < y1,
+                                                               red[TB - 1]);
+                            const int64_t ooff = wrap_any(row, ny) * pitch;
 #pragma unroll
-                        for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                            for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                        }
                     }
                 } else {
-                    // chemical potential of row m = t - r
-                    constexpr int cm = (ph - R + K) % K;
-                    const int64_t m = t - R;
-                    if (m >= y0 - R) {
-                        T e[NE];
-                        gather_x<T, V, R>(ring[0][cm], e);
-                        double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
-                        const bool red_row = RED && m >= y0 && m < y1;
+                    constexpr int s1 = Slot<K, R>::template at<ph>;
+                    constexpr int s2 = Slot<K, 2 * R>::template at<ph>;
+                    if (age >= 2 * R) {
+                        const int64_t row = t - R;
+                        stage_mu<T, R, K, s1, RED>(a, ring[0], m0[s1], om, row >= y0 && row < y1,
+                                                   red[0]);
+                    }
+                    if (age >= 4 * R) {
+                        T res[V];
+                        stage_chupd<T, R, K, s2>(a, m0, ring[0][s2], res);
+                        if constexpr (TB == 1) {
+                            store_row<T, V>(out[0] + wrap_any(t - 2 * R, ny) * pitch, xl, om, res);
+                        } else {
 #pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            T Sc[R];
-                            static_for<1, R + 1>([&](auto jc) {
-                                constexpr int j = decltype(jc)::value;
-                                constexpr int sp = (cm + j) % K, sm = (cm - j + K) % K;
-                                Sc[j - 1] = (e[R + v + j] + e[R + v - j]) +
-                                            (ring[0][sp][v] + ring[0][sm][v]);
-                            });
-                            const T c0 = ring[0][cm][v];
-                            mring[cm][v] = ch_mu<T, R>(a, c0, Sc, c0 * T(4));
-                            if constexpr (RED) {
-                                if (red_row && om.ov[v]) {
-                                    const double x = (double)c0;
-                                    double S64[R];
-                                    static_for<1, R + 1>([&](auto jc) {
-                                        constexpr int j = decltype(jc)::value;
-                                        constexpr int sp = (cm + j) % K, sm = (cm - j + K) % K;
-                                        S64[j - 1] = ((double)e[R + v + j] + (double)e[R + v - j]) +
-                                                     ((double)ring[0][sp][v] +
-                                                      (double)ring[0][sm][v]);
-                                    });
-                                    rs0 += x;
-                                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
-                                    rbad += finite_val(x) ? 0.0 : 1.0;
-                                }
-                            }
-                        }
-                        if constexpr (RED) {
-                            if (red_row) {
-                                acc_add(red.q0, rs0);
-                                acc_add(red.q1, rs1);
-                                red.bad += rbad;
-                            }
+                            for (int v = 0; v < V; ++v) r1[0][s2][v] = res[v];
                         }
                     }
-                    // update of row o = t - 2r
-                    constexpr int co = (ph - 2 * R + K) % K;
-                    const int64_t o = t - 2 * R;
-                    if (o >= y0) {
-                        T em[NE];
-                        gather_x<T, V, R>(mring[co], em);
-                        T res[V];
-#pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            T Sm[R];
-                            static_for<1, R + 1>([&](auto jc) {
-                                constexpr int j = decltype(jc)::value;
-                                constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
-                                Sm[j - 1] = (em[R + v + j] + em[R + v - j]) +
-                                            (mring[sp][v] + mring[sm][v]);
-                            });
-                            res[v] = ch_update<T, R>(a, ring[0][co][v], Sm, mring[co][v] * T(4));
+                    if constexpr (TB == 2) {
+                        constexpr int s3 = Slot<K, 3 * R>::template at<ph>;
+                        constexpr int s4 = Slot<K, 4 * R>::template at<ph>;
+                        if (age >= 6 * R) {
+                            const int64_t row = t - 3 * R;
+                            stage_mu<T, R, K, s3, RED>(a, r1[0], m1[s3], om, row >= y0 && row < y1,
+                                                       red[TB - 1]);
                         }
-                        store_row<T, V>(out[0] + wrap_any(o, ny) * pitch, xl, om, res);
+                        if (age >= 8 * R) {
+                            T res[V];
+                            stage_chupd<T, R, K, s4>(a, m1, r1[0][s4], res);
+                            store_row<T, V>(out[0] + wrap_any(t - 4 * R, ny) * pitch, xl, om, res);
+                        }
                     }
                 }
             }
         });
     }
-    if constexpr (RED) red_flush(red, a.part, a.pstride, pslot, lane);
+    if constexpr (RED) {
+        red_flush(red[0], a.part, a.pstride, pslot, lane);
+        if constexpr (TB == 2) red_flush(red[TB - 1], a.part, a.pstride, pslot + a.items, lane);
+    }
 }
 
-template <typename T, int KIND, int R, bool RED>
+template <typename T, int KIND, int R, bool RED, int TB>
 __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32_t item,
                                             int lane, int64_t pslot)
 {
-    using S = Shape<T, KIND, R>;
+    using S = Shape<T, KIND, R, TB>;
     const int32_t strip = item % a.strips;
     const int32_t chunk = item / a.strips;
     const int64_t xb = (int64_t)strip * a.ow - S::HV;
     const int64_t y0 = (int64_t)chunk * a.clen;
     const int64_t y1 = min(y0 + (int64_t)a.clen, a.ny);
     if (xb >= 0 && xb + S::SW <= a.nx)
-        march2d<T, KIND, R, RED, true>(a, par, xb, y0, y1, lane, pslot);
+        march2d<T, KIND, R, RED, true, TB>(a, par, xb, y0, y1, lane, pslot);
     else
-        march2d<T, KIND, R, RED, false>(a, par, xb, y0, y1, lane, pslot);
+        march2d<T, KIND, R, RED, false, TB>(a, par, xb, y0, y1, lane, pslot);
 }
 
-template <typename T, int KIND, int R, bool RED>
+// Single-model 2D launch of TB fused steps: reads buf[parity], writes
+// buf[parity ^ 1].
+template <typename T, int KIND, int R, bool RED, int TB>
 __global__ void __launch_bounds__(64 * kWaves2D) k_step2d(StepArgs<T> a)
 {
     const int32_t nwg = gridDim.x;
     const int32_t wg = xcd_item(blockIdx.x, nwg);
     const int32_t item = wg * kWaves2D + (threadIdx.x >> 6);
     if (item >= a.items) return;
-    step2d_item<T, KIND, R, RED>(a, a.parity, item, threadIdx.x & 63, item);
+    step2d_item<T, KIND, R, RED, TB>(a, a.parity, item, threadIdx.x & 63, item);
 }
 
 // Request of global work item g in a batch table (binary search over the
@@ -533,8 +636,8 @@ __global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> 
         const int i = batch_request(tb, n, g);
         if (k >= tb.steps[i]) continue;
         const StepArgs<T> &a = tb.args[i];
-        step2d_item<T, KIND, R, false>(a, (a.parity + k) & 1, g - tb.item_start[i],
-                                       threadIdx.x & 63, 0);
+        step2d_item<T, KIND, R, false, 1>(a, (a.parity + k) & 1, g - tb.item_start[i],
+                                          threadIdx.x & 63, 0);
     }
 }
 
@@ -714,7 +817,14 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                             });
                             const T c0 = ring[0][cm][v];
                             mring[cm][v] = ch_mu<T, R>(a, c0, Sc, c0 * T(6));
-                            if constexpr (RED) {
+                            if constexpr (RED && std::is_same<T, double>::value) {
+                                if (red_row && om.ov[v]) {
+                                    const double x = (double)c0;
+                                    rs0 += x;
+                                    rs1 += energy_from_mu(a.c2, x, mring[cm][v]);
+                                    rbad += finite_val(x) ? 0.0 : 1.0;
+                                }
+                            } else if constexpr (RED) {
                                 if (red_row && om.ov[v]) {
                                     const double x = (double)c0;
                                     double S64[R];

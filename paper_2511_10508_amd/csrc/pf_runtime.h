@@ -27,6 +27,7 @@ struct Model {
 
     // decomposition of the fused family (family 0) or per-site (family 1)
     int family = 1;
+    int tb = 1;                   // time steps fused per launch (2D, r <= 2)
     int32_t clen = 0, strips = 0, ow = 0, ytiles = 1, chunks = 0, items = 0, blocks = 0,
             threads = 0;
     int64_t fused_slots = 0;
@@ -45,12 +46,12 @@ struct Model {
     struct Graph {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        int par = 0, steps = 0;
+        int par = 0, steps = 0, launches = 0;
         bool red = false;
     };
     std::vector<Graph> graphs;
     bool graphs_valid = false;
-    int64_t captures = 0, replays = 0, launches = 0;
+    int64_t captures = 0, replays = 0, launches = 0, timed_steps = 0;
 
     bool timing = false;
     std::vector<hipEvent_t> events;

@@ -184,16 +184,23 @@ static bool plan(Model *m)
     Launch L = m->L;
     const pf_desc &d = m->desc;
     m->family = 1;
-    if (d.flags & PF_FORCE_GENERIC) return true;
+    if (!time_block_available(L)) m->tb = 1;
+    if (d.flags & PF_FORCE_GENERIC) {
+        m->tb = 1;
+        return true;
+    }
     int32_t strips, ow, ytiles = 1, chunks, items, blocks, threads;
     bool ok;
     if (d.ndim == 2)
-        ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, &strips, &ow, &chunks, &items, &blocks,
-                          &threads);
+        ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, m->tb, &strips, &ow, &chunks, &items,
+                          &blocks, &threads);
     else
         ok = plan_fused3d(L, d.n[0], d.n[1], d.n[2], m->clen, &strips, &ow, &ytiles, &chunks,
                           &items, &blocks, &threads);
-    if (!ok) return true;
+    if (!ok) {
+        m->tb = 1;
+        return true;
+    }
     m->family = 0;
     m->strips = strips;
     m->ow = ow;
@@ -229,7 +236,7 @@ int32_t default_chunk(const pf_desc *d)
 }
 
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int, int, int, int, int>, int32_t> g_tune_cache;
+static std::map<std::tuple<int, int, int, int, int, int, int>, std::pair<int32_t, int>> g_tune_cache;
 
 static std::tuple<int, int, int, int, int, int, int> tune_key(const pf_desc &d)
 {
@@ -255,7 +262,7 @@ static void dev_free(Model *m, void *p)
 static pf_status ensure_partials(Model *m)
 {
     const int64_t N = m->desc.n[0] * m->desc.n[1] * m->desc.n[2];
-    int64_t need = std::max<int64_t>(reduce_partial_slots(N), m->family == 0 ? m->fused_slots : 0);
+    int64_t need = std::max<int64_t>(reduce_partial_slots(N), m->family == 0 ? m->tb * m->fused_slots : 0);
     need = std::max<int64_t>(need, 1);
     if (need <= m->pstride && m->part) return PF_OK;
     if (m->part) {
@@ -305,9 +312,10 @@ static pf_status ensure_scratch(Model *m)
     return PF_OK;
 }
 
-// Launch one step from parity `par` (writes 1 - par).  red: fuse the
-// reductions of the input state; their finalised result goes to `res`.
-static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool timed)
+// Launch `tb` fused steps from parity `par` (writes 1 - par).  red: fuse the
+// reductions of the state at the start of each of those steps; the finalised
+// results go to res[0 .. kNumQ) and, for tb = 2, res[kNumQ .. 2 kNumQ).
+static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool timed, int tb = 1)
 {
     const pf_desc &d = m->desc;
     union {
@@ -341,13 +349,16 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
     }
     if (m->family == 0) {
         if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
-        hipError_t e = d.ndim == 2 ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, m->stream)
+        hipError_t e = d.ndim == 2 ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
                                    : launch_fused3d(m->L, ap, m->blocks, m->threads, red, m->stream);
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
         if (red) {
-            hipError_t f = launch_finalize(m->part, m->pstride, m->fused_slots, m->part2, res, m->stream);
-            if (f != hipSuccess) return hip_fail(f, "finalize launch");
+            for (int s = 0; s < tb; ++s) {
+                hipError_t f = launch_finalize(m->part + (int64_t)s * m->items, m->pstride, m->fused_slots,
+                                               m->part2, res + kNumQ * s, m->stream);
+                if (f != hipSuccess) return hip_fail(f, "finalize launch");
+            }
         }
     } else {
         if (red) {
@@ -365,6 +376,7 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
         if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
     }
     m->launches++;
+    m->timed_steps += timed ? tb : 0;
     return PF_OK;
 }
 
@@ -402,9 +414,11 @@ static pf_status capture_graph(Model *m, int par, int k, bool red, Model::Graph 
     PF_HIP(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     pf_status st = PF_OK;
     int p = par;
-    for (int i = 0; i < k && st == PF_OK; ++i) {
-        st = launch_step(m, p, red, m->stage + kNumQ * i, false);
+    g.launches = 0;
+    for (int i = 0; i < k && st == PF_OK; i += m->tb) {
+        st = launch_step(m, p, red, m->stage + kNumQ * i, false, m->tb);
         p ^= 1;
+        g.launches++;
     }
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(m->stream, &graph);
@@ -455,17 +469,19 @@ pf_status do_steps(Model *m, int64_t nsteps)
                                       sizeof(double2) * kNumQ * kGraphSteps,
                                       hipMemcpyDeviceToDevice, m->stream),
                        "hipMemcpyAsync(history)");
-            m->parity ^= (kGraphSteps & 1);
+            m->parity ^= (g.launches & 1);
             done += kGraphSteps;
             m->steps_done += kGraphSteps;
         }
     }
-    for (; done < nsteps; ++done) {
+    while (done < nsteps) {
+        const int tb = (m->tb == 2 && nsteps - done >= 2) ? 2 : 1;
         pf_status st = launch_step(m, m->parity, each, each ? m->hist + kNumQ * done : nullptr,
-                                   m->timing);
+                                   m->timing, tb);
         if (st != PF_OK) return st;
         m->parity ^= 1;
-        m->steps_done++;
+        m->steps_done += tb;
+        done += tb;
     }
     return PF_OK;
 }
@@ -607,10 +623,13 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
         return hip_fail(e, "hipMalloc(result)");
     }
     int32_t chunk = 0;
-    {
+    if (!m->async_alloc) {  // served requests keep the default tile (batched kernels are TB = 1)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(*desc));
-        if (it != g_tune_cache.end()) chunk = it->second;
+        if (it != g_tune_cache.end()) {
+            chunk = it->second.first;
+            m->tb = it->second.second;
+        }
     }
     st = set_chunk(m, chunk);
     if (st != PF_OK) {
@@ -728,50 +747,66 @@ pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int3
     return PF_OK;
 }
 
+// Times every candidate (chunk length, time-block factor) on the model's own
+// buffers: each trial re-runs steps from the current parity, whose buffer is
+// never written, so the state is untouched.  Keeps the fastest per step.
 pf_status autotune(Model *m, int32_t trials)
 {
     if (m->family != 0) return PF_OK;
     const pf_desc &d = m->desc;
+    const bool red = (d.flags & PF_REDUCE_EACH_STEP) != 0;
     const int64_t march = d.ndim == 2 ? d.n[1] : d.n[2];
     std::vector<int32_t> cand;
-    const int32_t base[] = {16, 32, 64, 128, 256, 512, 1024, 2048};
+    const int32_t base[] = {16, 32, 64, 128, 256, 512, 1024};
     for (int32_t c : base)
         if (c <= march * 2 || cand.empty()) cand.push_back((int32_t)std::min<int64_t>(c, march));
     std::sort(cand.begin(), cand.end());
     cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    std::vector<int> tbs = {1};
+    if (time_block_available(m->L)) tbs.push_back(2);
     if (trials < 1) trials = 3;
-    const int32_t keep = m->clen;
+    const int32_t keep_c = m->clen;
+    const int keep_tb = m->tb;
     hipEvent_t a, b;
     PF_HIP(hipEventCreate(&a), "hipEventCreate");
     PF_HIP(hipEventCreate(&b), "hipEventCreate");
+    double2 *scratch = nullptr;
+    if (red) PF_HIP(hipMalloc((void **)&scratch, sizeof(double2) * kNumQ * 2), "hipMalloc(tune)");
     float best = 1e30f;
-    int32_t best_c = keep;
-    for (int32_t c : cand) {
-        pf_status st = set_chunk(m, c);
-        if (st != PF_OK) break;
-        // Re-run the step from the current parity: the input buffer is never
-        // written, so the state is untouched.
-        st = launch_step(m, m->parity, false, nullptr, false);
-        if (st != PF_OK) break;
-        (void)hipEventRecord(a, m->stream);
-        for (int t = 0; t < trials && st == PF_OK; ++t) st = launch_step(m, m->parity, false, nullptr, false);
-        (void)hipEventRecord(b, m->stream);
-        (void)hipEventSynchronize(b);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, a, b);
-        if (st == PF_OK && ms < best) {
-            best = ms;
-            best_c = c;
+    int32_t best_c = keep_c;
+    int best_tb = keep_tb;
+    pf_status st = PF_OK;
+    for (int tb : tbs)
+        for (int32_t c : cand) {
+            m->tb = tb;
+            st = set_chunk(m, c);
+            if (st != PF_OK || m->family != 0 || m->tb != tb) break;
+            st = launch_step(m, m->parity, red, scratch, false, tb);
+            if (st != PF_OK) break;
+            (void)hipEventRecord(a, m->stream);
+            for (int t = 0; t < trials && st == PF_OK; ++t) st = launch_step(m, m->parity, red, scratch, false, tb);
+            (void)hipEventRecord(b, m->stream);
+            (void)hipEventSynchronize(b);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, a, b);
+            ms /= tb;
+            if (st == PF_OK && ms < best) {
+                best = ms;
+                best_c = c;
+                best_tb = tb;
+            }
         }
-    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    pf_status st = set_chunk(m, best_c);
+    if (scratch) (void)hipFree(scratch);
+    if (st != PF_OK) return st;
+    m->tb = best_tb;
+    st = set_chunk(m, best_c);
     if (st != PF_OK) return st;
     m->launches = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[tune_key(d)] = best_c;
+        g_tune_cache[tune_key(d)] = {best_c, best_tb};
     }
     return PF_OK;
 }
@@ -1036,6 +1071,21 @@ PF_API pf_status pf_get_tile(pf_model *m, int32_t *chunk, int32_t *family)
     return PF_OK;
 }
 
+PF_API pf_status pf_set_time_block(pf_model *m, int32_t tb)
+{
+    if (!m || (tb != 1 && tb != 2)) return fail(PF_ERR_ARG, "time block must be 1 or 2");
+    Model *mm = M(m);
+    PF_HIP(hipStreamSynchronize(mm->stream), "hipStreamSynchronize");
+    if (tb == 2 && (!time_block_available(mm->L) || mm->desc.flags & PF_FORCE_GENERIC))
+        return fail(PF_ERR_UNSUPPORTED, "two-step kernels exist for 2D orders 2 and 4");
+    mm->tb = tb;
+    pf_status st = set_chunk(mm, mm->clen);
+    if (st == PF_OK && mm->tb != tb) return fail(PF_ERR_UNSUPPORTED, "two-step kernel not available");
+    return st;
+}
+
+PF_API int32_t pf_get_time_block(const pf_model *m) { return m ? reinterpret_cast<const Model *>(m)->tb : -1; }
+
 PF_API pf_status pf_autotune(pf_model *m, int32_t trials)
 {
     if (!m) return fail(PF_ERR_ARG, "model is NULL");
@@ -1049,10 +1099,11 @@ PF_API pf_status pf_timing_enable(pf_model *mm, int32_t on)
     PF_HIP(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
     m->timing = on != 0;
     m->ev_used = 0;
+    m->timed_steps = 0;
     return PF_OK;
 }
 
-PF_API pf_status pf_timing_read(pf_model *mm, double *total_ms, int64_t *launches)
+PF_API pf_status pf_timing_read(pf_model *mm, double *total_ms, int64_t *launches, int64_t *steps)
 {
     Model *m = M(mm);
     if (!m) return fail(PF_ERR_ARG, "model is NULL");
@@ -1065,6 +1116,7 @@ PF_API pf_status pf_timing_read(pf_model *mm, double *total_ms, int64_t *launche
     }
     if (total_ms) *total_ms = tot;
     if (launches) *launches = (int64_t)(m->ev_used / 2);
+    if (steps) *steps = m->timed_steps;
     return PF_OK;
 }
 

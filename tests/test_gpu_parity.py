@@ -290,3 +290,75 @@ def test_get_window_matches_full_field():
     zz, yy, xx = np.meshgrid((np.arange(5) + 8) % 10, (np.arange(9) + 15) % 20,
                              (np.arange(11) + 25) % 30, indexing="ij")
     assert np.array_equal(w, full[zz, yy, xx])
+
+
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("order", [2, 4])
+def test_two_step_blocking_is_bitwise_two_single_steps(kind, order, prec):
+    """Temporal blocking (two steps per sweep) against one step per sweep,
+    including an odd step count (the last step runs alone) and ragged tiles."""
+    shape, ndim = (1, 83, 301), 2
+    params = BASE[kind][0]
+    dt = dt_for(kind, ndim, order, params)
+    f0 = fields_for(kind, shape, 31)
+    n = (shape[2], shape[1])
+    outs = []
+    for tb in (1, 2):
+        d = P.make_desc(kind, n, dt=dt, order=order, precision=prec, params=params)
+        m = P.Model(d)
+        m.set_tile(24)
+        m.set_time_block(tb)
+        assert m.time_block() == tb
+        for f, a in enumerate(f0):
+            m.set_field(f, a)
+        m.step(37)
+        assert m.steps_done() == 37
+        outs.append([m.get_field(f) for f in range(len(f0))])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+    ref = oracle_run(kind, shape, ndim, order, params, dt, 37, 31)[1]
+    for g, r in zip(outs[1], ref):
+        assert float(np.max(np.abs(g - r))) <= TOL[prec]
+
+
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+def test_two_step_history_and_graphs(kind):
+    """Fused per-step reductions and graph replay with two-step sweeps."""
+    shape, ndim, order = (1, 64, 200), 2, 4
+    params = BASE[kind][0]
+    dt = dt_for(kind, ndim, order, params)
+    f0 = fields_for(kind, shape, 41)
+    n = (shape[2], shape[1])
+    hist = []
+    fields = []
+    for tb, flags in ((1, 0), (2, 0), (2, P.PF_USE_GRAPH)):
+        d = P.make_desc(kind, n, dt=dt, order=order, params=params,
+                        flags=P.PF_REDUCE_EACH_STEP | flags)
+        m = P.Model(d)
+        m.set_tile(16)
+        m.set_time_block(tb)
+        for f, a in enumerate(f0):
+            m.set_field(f, a)
+        m.step(70)
+        which = P.PF_RED_MASS1 if kind == P.PF_GS else P.PF_RED_ENERGY
+        hist.append([sum(m.reduce_history(P.PF_RED_MASS0, 70)), sum(m.reduce_history(which, 70))])
+        fields.append([m.get_field(f) for f in range(len(f0))])
+    for other in (1, 2):
+        for x, y in zip(fields[0], fields[other]):
+            assert np.array_equal(x, y)
+        for q in range(2):
+            a, b = hist[0][q], hist[other][q]
+            assert np.max(np.abs(a - b)) <= 1e-13 * max(1.0, float(np.max(np.abs(a))))
+
+
+def test_time_block_refused_where_unavailable():
+    d = P.make_desc(P.PF_GS, (40, 30, 20), dt=0.3)
+    m = P.Model(d)
+    with pytest.raises(P.PfError) as e:
+        m.set_time_block(2)
+    assert e.value.status == P.PF_ERR_UNSUPPORTED
+    d = P.make_desc(P.PF_AC, (40, 30), dt=0.01, order=8)
+    m = P.Model(d)
+    with pytest.raises(P.PfError):
+        m.set_time_block(2)
