@@ -227,8 +227,8 @@ pf_status pf_get_tile(pf_model *m, int32_t *chunk, int32_t *family);
 /*
  * Temporal blocking: tb = 2 fuses two time steps into one sweep over the
  * fields (the intermediate state stays in registers), halving HBM traffic per
- * step; available for 2D grids with order 2 or 4 on the fused kernels
- * (otherwise PF_ERR_UNSUPPORTED).  Results are bitwise those of tb = 1.  An
+ * step; available on the fused kernels for 2D grids with order 2 or 4 and
+ * 3D grids with order 2 (otherwise PF_ERR_UNSUPPORTED).  Results are bitwise those of tb = 1.  An
  * odd remainder of a pf_step call runs one single step.
  */
 pf_status pf_set_time_block(pf_model *m, int32_t tb);

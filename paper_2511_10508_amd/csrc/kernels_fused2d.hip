@@ -9,7 +9,7 @@ using TimeBlockRadii = RList<1, 2>;  // radii with a two-step (TB = 2) kernel
 
 bool time_block_available(const Launch &L)
 {
-    return L.ndim == 2 && (L.r == 1 || L.r == 2);
+    return (L.ndim == 2 && (L.r == 1 || L.r == 2)) || (L.ndim == 3 && L.r == 1);
 }
 
 bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int tb, int32_t *strips,

@@ -644,24 +644,174 @@ __global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> 
 // ===========================================================================
 // 3D fused marching step.  A workgroup of NW = 16 waves owns a tile of 16
 // rows (y) of one x-strip and marches along z.  Wave w holds tile row
-// y0 - H + w; its z-window of K planes stays in registers, x-neighbours come
-// from lane shuffles and y-neighbours from the other waves' rows through a
-// double-buffered LDS plane (one barrier per plane).  Rows within H of the
-// tile edge are halo: only rows [H, NW - H) are written.
-template <typename T, int KIND, int R>
+// y0 - H + w.  As in 2D the step is a chain of radius-r stages (two per CH
+// step, one per AC/GS step; TB steps per sweep); each stage keeps a z-window
+// of K = 2r+1 planes of its input stream in registers, takes x-neighbours by
+// lane shuffles and y-neighbours from the other waves' rows of its centre
+// plane in LDS.  Stage k's centre plane was produced r iterations earlier,
+// so every stage's LDS row is written before one barrier per plane; a stage
+// at depth k is valid for rows [k r, NW - k r) of the tile, and only rows
+// [H, NW - H) are written.
+
+template <typename T, int KIND, int R, int TB>
 struct Lds3D {
-    using S = Shape<T, KIND, R>;
-    static constexpr int NL = KIND == kCH ? 2 : S::NF;  // planes per buffer
-    using type = T[2][NL][kWaves3D][S::SW];
+    using S = Shape<T, KIND, R, TB>;
+    static constexpr int NST = (KIND == kCH ? 2 : 1) * TB;  // stages
+    static constexpr int NFS = KIND == kCH ? 1 : S::NF;      // fields per stage input
+    static constexpr int NB = NST * NFS <= 2 ? 2 : 1;        // buffers (double when it fits)
+    using type = T[NB][NST][NFS][kWaves3D][S::SW];
 };
 
-template <typename T, int KIND, int R, bool RED, bool FAST>
+// Pair sums at element v around centre plane slot CS of a ring, with the
+// centre row's x-neighbourhood e and the centre plane's rows in LDS L.
+template <typename T, int V, int R, int K, int CS, int SW>
+__device__ __forceinline__ void pairs3d(const T (&rg)[K][V], const T (&e)[V + 2 * R],
+                                        const T (&L)[kWaves3D][SW], int w, int pl, int v,
+                                        T (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = ((e[R + v + j] + e[R + v - j]) + (L[w + j][pl + v] + L[w - j][pl + v])) +
+                   (rg[sp][v] + rg[sm][v]);
+    });
+}
+
+template <typename T, int V, int R, int K, int CS, int SW>
+__device__ __forceinline__ void pairs3d64(const T (&rg)[K][V], const T (&e)[V + 2 * R],
+                                          const T (&L)[kWaves3D][SW], int w, int pl, int v,
+                                          double (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = (((double)e[R + v + j] + (double)e[R + v - j]) +
+                    ((double)L[w + j][pl + v] + (double)L[w - j][pl + v])) +
+                   ((double)rg[sp][v] + (double)rg[sm][v]);
+    });
+}
+
+template <typename T, int KIND, int R, int K, int CS, int SW, bool RED>
+__device__ __forceinline__ void stage3_acgs(const StepArgs<T> &a,
+                                            const T (&rg)[KIND == kGS ? 2 : 1][K][Vec<T>::V],
+                                            const T (&L)[KIND == kGS ? 2 : 1][kWaves3D][SW], int w,
+                                            T (&res)[KIND == kGS ? 2 : 1][Vec<T>::V],
+                                            const OutMask<Vec<T>::V> &om, bool red_row, RedState &red)
+{
+    constexpr int V = Vec<T>::V, NF = KIND == kGS ? 2 : 1;
+    const int pl = (threadIdx.x & 63) * V;
+    T e[NF][V + 2 * R];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) gather_x<T, V, R>(rg[f][CS], e[f]);
+    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sf[NF][R];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) pairs3d<T, V, R, K, CS, SW>(rg[f], e[f], L[f], w, pl, v, Sf[f]);
+        const T u0 = rg[0][CS][v];
+        if constexpr (KIND == kAC) {
+            res[0][v] = ac_update<T, R>(a, u0, Sf[0], u0 * T(6));
+        } else {
+            const T v0 = rg[NF - 1][CS][v];
+            gs_update<T, R>(a, u0, v0, Sf[0], Sf[NF - 1], u0 * T(6), v0 * T(6), res[0][v],
+                            res[NF - 1][v]);
+        }
+        if constexpr (RED) {
+            if (red_row && om.ov[v]) {
+                const double x = (double)u0;
+                rs0 += x;
+                rbad += finite_val(x) ? 0.0 : 1.0;
+                if constexpr (KIND == kAC) {
+                    if constexpr (std::is_same<T, double>::value) {
+                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 6.0);
+                    } else {
+                        double S64[R];
+                        pairs3d64<T, V, R, K, CS, SW>(rg[0], e[0], L[0], w, pl, v, S64);
+                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
+                    }
+                } else {
+                    const double y = (double)rg[NF - 1][CS][v];
+                    rs1 += y;
+                    rbad += finite_val(y) ? 0.0 : 1.0;
+                }
+            }
+        }
+    }
+    if constexpr (RED) {
+        if (red_row) {
+            acc_add(red.q0, rs0);
+            acc_add(red.q1, rs1);
+            red.bad += rbad;
+        }
+    }
+}
+
+template <typename T, int R, int K, int CS, int SW, bool RED>
+__device__ __forceinline__ void stage3_mu(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                          const T (&L)[kWaves3D][SW], int w, T (&mu)[Vec<T>::V],
+                                          const OutMask<Vec<T>::V> &om, bool red_row, RedState &red)
+{
+    constexpr int V = Vec<T>::V;
+    const int pl = (threadIdx.x & 63) * V;
+    T e[V + 2 * R];
+    gather_x<T, V, R>(c[CS], e);
+    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sc[R];
+        pairs3d<T, V, R, K, CS, SW>(c, e, L, w, pl, v, Sc);
+        const T c0 = c[CS][v];
+        mu[v] = ch_mu<T, R>(a, c0, Sc, c0 * T(6));
+        if constexpr (RED) {
+            if (red_row && om.ov[v]) {
+                const double x = (double)c0;
+                rs0 += x;
+                if constexpr (std::is_same<T, double>::value) {
+                    rs1 += energy_from_mu(a.c2, x, mu[v]);
+                } else {
+                    double S64[R];
+                    pairs3d64<T, V, R, K, CS, SW>(c, e, L, w, pl, v, S64);
+                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
+                }
+                rbad += finite_val(x) ? 0.0 : 1.0;
+            }
+        }
+    }
+    if constexpr (RED) {
+        if (red_row) {
+            acc_add(red.q0, rs0);
+            acc_add(red.q1, rs1);
+            red.bad += rbad;
+        }
+    }
+}
+
+template <typename T, int R, int K, int CS, int SW>
+__device__ __forceinline__ void stage3_chupd(const StepArgs<T> &a, const T (&m)[K][Vec<T>::V],
+                                             const T (&L)[kWaves3D][SW], int w,
+                                             const T (&c0)[Vec<T>::V], T (&res)[Vec<T>::V])
+{
+    constexpr int V = Vec<T>::V;
+    const int pl = (threadIdx.x & 63) * V;
+    T em[V + 2 * R];
+    gather_x<T, V, R>(m[CS], em);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sm[R];
+        pairs3d<T, V, R, K, CS, SW>(m, em, L, w, pl, v, Sm);
+        res[v] = ch_update<T, R>(a, c0[v], Sm, m[CS][v] * T(6));
+    }
+}
+
+template <typename T, int KIND, int R, bool RED, bool FAST, int TB>
 __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t xb, int64_t yrow,
                                         bool out_row, int64_t z0, int64_t z1, int64_t pslot,
-                                        typename Lds3D<T, KIND, R>::type &lds)
+                                        typename Lds3D<T, KIND, R, TB>::type &lds)
 {
-    using S = Shape<T, KIND, R>;
-    constexpr int V = S::V, H = S::H, HV = S::HV, NE = S::NE, K = S::K, NF = S::NF;
+    using S = Shape<T, KIND, R, TB>;
+    using LD = Lds3D<T, KIND, R, TB>;
+    constexpr int V = S::V, H = S::H, HV = S::HV, K = S::K, NF = S::NF, SW = S::SW;
     constexpr int NW = kWaves3D;
     static_assert(2 * H < NW, "halo too wide for the 3D tile");
 
@@ -684,12 +834,25 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
 
     T ring[NF][K][V];
     T pre[NF][K][V];
-    T mring[KIND == kCH ? K : 1][V];
+    T r1[TB == 2 ? NF : 1][K][V];
+    T m0[KIND == kCH ? K : 1][V];
+    T m1[(KIND == kCH && TB == 2) ? K : 1][V];
+    // rings that feed LDS rows before first being computed hold zeros
 #pragma unroll
-    for (int i = 0; i < (KIND == kCH ? K : 1); ++i)
+    for (int i = 0; i < K; ++i)
 #pragma unroll
-        for (int v = 0; v < V; ++v) mring[i][v] = T(0);
-    RedState red;
+        for (int v = 0; v < V; ++v) {
+            if constexpr (KIND == kCH) {
+                m0[i][v] = T(0);
+                if constexpr (TB == 2) m1[i][v] = T(0);
+            }
+            if constexpr (TB == 2)
+#pragma unroll
+                for (int f = 0; f < NF; ++f) r1[f][i][v] = T(0);
+        }
+    RedState red[TB];
+    // a stage at depth k computes rows [k r, NW - k r) of the tile
+    auto rows_ok = [&](int k) { return w >= k * R && w < NW - k * R; };
 
     const int64_t tb0 = z0 - H, tend = z1 + H;
     static_for<0, K>([&](auto phc) {
@@ -707,7 +870,9 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
             constexpr int ph = decltype(phc)::value;
             const int64_t t = tb + ph;
             if (t < tend) {
-                const int buf = (int)(t & 1);
+                const int64_t age = t - tb0;
+                const int buf = LD::NB == 2 ? (int)(t & 1) : 0;
+                auto &L = lds[buf];
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -717,171 +882,114 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
 #pragma unroll
                     for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
                 }
+                constexpr int s1 = Slot<K, R>::template at<ph>;
+                constexpr int s2 = Slot<K, 2 * R>::template at<ph>;
+                constexpr int s3 = Slot<K, 3 * R>::template at<ph>;
+                constexpr int s4 = Slot<K, 4 * R>::template at<ph>;
+                if constexpr (LD::NB == 1) __syncthreads();  // previous plane's readers are done
+                // centre rows of every stage's input stream
                 if constexpr (KIND != kCH) {
-                    constexpr int co = (ph - R + K) % K;
-                    const int64_t o = t - R;
 #pragma unroll
                     for (int f = 0; f < NF; ++f)
 #pragma unroll
-                        for (int v = 0; v < V; ++v) lds[buf][f][w][pl + v] = ring[f][co][v];
-                    __syncthreads();
-                    if (o >= z0 && w >= R && w < NW - R) {
-                        T e[NF][NE];
-#pragma unroll
-                        for (int f = 0; f < NF; ++f) gather_x<T, V, R>(ring[f][co], e[f]);
-                        T res[NF][V];
-                        double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
-#pragma unroll
                         for (int v = 0; v < V; ++v) {
-                            T Sf[NF][R];
-                            static_for<1, R + 1>([&](auto jc) {
-                                constexpr int j = decltype(jc)::value;
-                                constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
+                            L[0][f][w][pl + v] = ring[f][s1][v];
+                            if constexpr (TB == 2) L[TB - 1][f][w][pl + v] = r1[f][s2][v];
+                        }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        L[0][0][w][pl + v] = ring[0][s1][v];
+                        L[1][0][w][pl + v] = m0[s2][v];
+                        if constexpr (TB == 2) {
+                            L[TB][0][w][pl + v] = r1[0][s3][v];
+                            L[TB + 1][0][w][pl + v] = m1[s4][v];
+                        }
+                    }
+                }
+                __syncthreads();
+                if constexpr (KIND != kCH) {
+                    if (age >= 2 * R && rows_ok(1)) {
+                        const int64_t pz = t - R;
+                        T res[NF][V];
+                        stage3_acgs<T, KIND, R, K, s1, SW, RED>(a, ring, L[0], w, res, om,
+                                                                pz >= z0 && pz < z1, red[0]);
+                        if constexpr (TB == 1) {
+                            if (out_row) {
+                                const int64_t ooff = wrap_any(pz, nz) * plane + rowoff;
 #pragma unroll
                                 for (int f = 0; f < NF; ++f)
-                                    Sf[f][j - 1] =
-                                        ((e[f][R + v + j] + e[f][R + v - j]) +
-                                         (lds[buf][f][w + j][pl + v] + lds[buf][f][w - j][pl + v])) +
-                                        (ring[f][sp][v] + ring[f][sm][v]);
-                            });
-                            const T u0 = ring[0][co][v];
-                            if constexpr (KIND == kAC) {
-                                res[0][v] = ac_update<T, R>(a, u0, Sf[0], u0 * T(6));
-                            } else {
-                                const T v0 = ring[NF - 1][co][v];
-                                gs_update<T, R>(a, u0, v0, Sf[0], Sf[NF - 1], u0 * T(6),
-                                                v0 * T(6), res[0][v], res[NF - 1][v]);
+                                    store_row<T, V>(out[f] + ooff, xl, om, res[f]);
                             }
-                            if constexpr (RED) {
-                                if (om.ov[v]) {
-                                    const double x = (double)u0;
-                                    rs0 += x;
-                                    rbad += finite_val(x) ? 0.0 : 1.0;
-                                    if constexpr (KIND == kAC) {
-                                        double S64[R];
-                                        static_for<1, R + 1>([&](auto jc) {
-                                            constexpr int j = decltype(jc)::value;
-                                            constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
-                                            S64[j - 1] =
-                                                (((double)e[0][R + v + j] +
-                                                  (double)e[0][R + v - j]) +
-                                                 ((double)lds[buf][0][w + j][pl + v] +
-                                                  (double)lds[buf][0][w - j][pl + v])) +
-                                                ((double)ring[0][sp][v] + (double)ring[0][sm][v]);
-                                        });
-                                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
-                                    } else {
-                                        const double y = (double)ring[NF - 1][co][v];
-                                        rs1 += y;
-                                        rbad += finite_val(y) ? 0.0 : 1.0;
-                                    }
-                                }
-                            }
-                        }
-                        if constexpr (RED) {
-                            acc_add(red.q0, rs0);
-                            acc_add(red.q1, rs1);
-                            red.bad += rbad;
-                        }
-                        if (out_row) {
-                            const int64_t ooff = wrap_any(o, nz) * plane + rowoff;
+                        } else {
 #pragma unroll
-                            for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                                for (int v = 0; v < V; ++v) r1[f][s1][v] = res[f][v];
+                        }
+                    }
+                    if constexpr (TB == 2) {
+                        if (age >= 4 * R && rows_ok(2)) {
+                            const int64_t pz = t - 2 * R;
+                            T res[NF][V];
+                            stage3_acgs<T, KIND, R, K, s2, SW, RED>(a, r1, L[TB - 1], w, res, om,
+                                                                    pz >= z0 && pz < z1, red[TB - 1]);
+                            if (out_row) {
+                                const int64_t ooff = wrap_any(pz, nz) * plane + rowoff;
+#pragma unroll
+                                for (int f = 0; f < NF; ++f)
+                                    store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                            }
                         }
                     }
                 } else {
-                    constexpr int cm = (ph - R + K) % K;
-                    constexpr int co = (ph - 2 * R + K) % K;
-                    const int64_t m = t - R;
-                    const int64_t o = t - 2 * R;
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        lds[buf][0][w][pl + v] = ring[0][cm][v];
-                        lds[buf][1][w][pl + v] = mring[co][v];
+                    if (age >= 2 * R && rows_ok(1)) {
+                        const int64_t pz = t - R;
+                        stage3_mu<T, R, K, s1, SW, RED>(a, ring[0], L[0][0], w, m0[s1], om,
+                                                        pz >= z0 && pz < z1, red[0]);
                     }
-                    __syncthreads();
-                    if (m >= z0 - R && w >= R && w < NW - R) {
-                        T e[NE];
-                        gather_x<T, V, R>(ring[0][cm], e);
-                        double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
-                        const bool red_row = RED && m >= z0 && m < z1;
-#pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            T Sc[R];
-                            static_for<1, R + 1>([&](auto jc) {
-                                constexpr int j = decltype(jc)::value;
-                                constexpr int sp = (cm + j) % K, sm = (cm - j + K) % K;
-                                Sc[j - 1] = ((e[R + v + j] + e[R + v - j]) +
-                                             (lds[buf][0][w + j][pl + v] + lds[buf][0][w - j][pl + v])) +
-                                            (ring[0][sp][v] + ring[0][sm][v]);
-                            });
-                            const T c0 = ring[0][cm][v];
-                            mring[cm][v] = ch_mu<T, R>(a, c0, Sc, c0 * T(6));
-                            if constexpr (RED && std::is_same<T, double>::value) {
-                                if (red_row && om.ov[v]) {
-                                    const double x = (double)c0;
-                                    rs0 += x;
-                                    rs1 += energy_from_mu(a.c2, x, mring[cm][v]);
-                                    rbad += finite_val(x) ? 0.0 : 1.0;
-                                }
-                            } else if constexpr (RED) {
-                                if (red_row && om.ov[v]) {
-                                    const double x = (double)c0;
-                                    double S64[R];
-                                    static_for<1, R + 1>([&](auto jc) {
-                                        constexpr int j = decltype(jc)::value;
-                                        constexpr int sp = (cm + j) % K, sm = (cm - j + K) % K;
-                                        S64[j - 1] =
-                                            (((double)e[R + v + j] + (double)e[R + v - j]) +
-                                             ((double)lds[buf][0][w + j][pl + v] +
-                                              (double)lds[buf][0][w - j][pl + v])) +
-                                            ((double)ring[0][sp][v] + (double)ring[0][sm][v]);
-                                    });
-                                    rs0 += x;
-                                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
-                                    rbad += finite_val(x) ? 0.0 : 1.0;
-                                }
-                            }
-                        }
-                        if constexpr (RED) {
-                            if (red_row) {
-                                acc_add(red.q0, rs0);
-                                acc_add(red.q1, rs1);
-                                red.bad += rbad;
-                            }
-                        }
-                    }
-                    if (o >= z0 && o < z1 && w >= 2 * R && w < NW - 2 * R) {
-                        T em[NE];
-                        gather_x<T, V, R>(mring[co], em);
+                    if (age >= 4 * R && rows_ok(2)) {
                         T res[V];
+                        stage3_chupd<T, R, K, s2, SW>(a, m0, L[1][0], w, ring[0][s2], res);
+                        if constexpr (TB == 1) {
+                            if (out_row)
+                                store_row<T, V>(out[0] + wrap_any(t - 2 * R, nz) * plane + rowoff, xl,
+                                                om, res);
+                        } else {
 #pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            T Sm[R];
-                            static_for<1, R + 1>([&](auto jc) {
-                                constexpr int j = decltype(jc)::value;
-                                constexpr int sp = (co + j) % K, sm = (co - j + K) % K;
-                                Sm[j - 1] = ((em[R + v + j] + em[R + v - j]) +
-                                             (lds[buf][1][w + j][pl + v] + lds[buf][1][w - j][pl + v])) +
-                                            (mring[sp][v] + mring[sm][v]);
-                            });
-                            res[v] = ch_update<T, R>(a, ring[0][co][v], Sm, mring[co][v] * T(6));
+                            for (int v = 0; v < V; ++v) r1[0][s2][v] = res[v];
                         }
-                        if (out_row)
-                            store_row<T, V>(out[0] + wrap_any(o, nz) * plane + rowoff, xl, om, res);
+                    }
+                    if constexpr (TB == 2) {
+                        if (age >= 6 * R && rows_ok(3)) {
+                            const int64_t pz = t - 3 * R;
+                            stage3_mu<T, R, K, s3, SW, RED>(a, r1[0], L[TB][0], w, m1[s3], om,
+                                                            pz >= z0 && pz < z1, red[TB - 1]);
+                        }
+                        if (age >= 8 * R && rows_ok(4)) {
+                            T res[V];
+                            stage3_chupd<T, R, K, s4, SW>(a, m1, L[TB + 1][0], w, r1[0][s4], res);
+                            if (out_row)
+                                store_row<T, V>(out[0] + wrap_any(t - 4 * R, nz) * plane + rowoff,
+                                                xl, om, res);
+                        }
                     }
                 }
             }
         });
     }
-    if constexpr (RED) red_flush(red, a.part, a.pstride, pslot, lane);
+    if constexpr (RED) {
+        red_flush(red[0], a.part, a.pstride, pslot, lane);
+        if constexpr (TB == 2)
+            red_flush(red[TB - 1], a.part, a.pstride, pslot + (int64_t)a.items * kWaves3D, lane);
+    }
 }
 
-template <typename T, int KIND, int R, bool RED>
+template <typename T, int KIND, int R, bool RED, int TB>
 __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32_t item,
                                             int64_t pslot_base)
 {
-    using S = Shape<T, KIND, R>;
+    using S = Shape<T, KIND, R, TB>;
     constexpr int NW = kWaves3D;
     const int w = threadIdx.x >> 6;
     const int32_t strip = item % a.strips;
@@ -893,20 +1001,20 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
     const bool out_row = (w >= S::H) && (w < NW - S::H) && (yrow < a.ny);
     const int64_t z0 = (int64_t)chunk * a.clen;
     const int64_t z1 = min(z0 + (int64_t)a.clen, a.nz);
-    __shared__ typename Lds3D<T, KIND, R>::type lds;
+    __shared__ typename Lds3D<T, KIND, R, TB>::type lds;
     // the FAST choice is uniform over the workgroup (it depends on the strip only)
     if (xb >= 0 && xb + S::SW <= a.nx)
-        march3d<T, KIND, R, RED, true>(a, par, xb, yrow, out_row, z0, z1, pslot_base + w, lds);
+        march3d<T, KIND, R, RED, true, TB>(a, par, xb, yrow, out_row, z0, z1, pslot_base + w, lds);
     else
-        march3d<T, KIND, R, RED, false>(a, par, xb, yrow, out_row, z0, z1, pslot_base + w, lds);
+        march3d<T, KIND, R, RED, false, TB>(a, par, xb, yrow, out_row, z0, z1, pslot_base + w, lds);
 }
 
-template <typename T, int KIND, int R, bool RED>
+template <typename T, int KIND, int R, bool RED, int TB>
 __global__ void __launch_bounds__(64 * kWaves3D) k_step3d(StepArgs<T> a)
 {
     const int32_t item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.items) return;  // uniform over the workgroup
-    step3d_item<T, KIND, R, RED>(a, a.parity, item, (int64_t)item * kWaves3D);
+    step3d_item<T, KIND, R, RED, TB>(a, a.parity, item, (int64_t)item * kWaves3D);
 }
 
 // Persistent batched 3D step (see k_step2d_batched); the item loop is uniform
@@ -920,7 +1028,7 @@ __global__ void __launch_bounds__(64 * kWaves3D) k_step3d_batched(BatchTable<T> 
         const int i = batch_request(tb, n, g);
         if (k >= tb.steps[i]) continue;
         const StepArgs<T> &a = tb.args[i];
-        step3d_item<T, KIND, R, false>(a, (a.parity + k) & 1, g - tb.item_start[i], 0);
+        step3d_item<T, KIND, R, false, 1>(a, (a.parity + k) & 1, g - tb.item_start[i], 0);
     }
 }
 

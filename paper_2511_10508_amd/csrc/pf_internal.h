@@ -70,13 +70,13 @@ struct Launch {
 bool time_block_available(const Launch &L);
 bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int tb, int32_t *strips,
                   int32_t *ow, int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads);
-bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen,
+bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
                   int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items,
                   int32_t *blocks, int32_t *threads);
 hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
                           int red, int tb, hipStream_t s);
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
-                          int red, hipStream_t s);
+                          int red, int tb, hipStream_t s);
 hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
                                   hipStream_t s);
 hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,

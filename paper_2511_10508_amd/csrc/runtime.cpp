@@ -195,8 +195,8 @@ static bool plan(Model *m)
         ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, m->tb, &strips, &ow, &chunks, &items,
                           &blocks, &threads);
     else
-        ok = plan_fused3d(L, d.n[0], d.n[1], d.n[2], m->clen, &strips, &ow, &ytiles, &chunks,
-                          &items, &blocks, &threads);
+        ok = plan_fused3d(L, d.n[0], d.n[1], d.n[2], m->clen, m->tb, &strips, &ow, &ytiles,
+                          &chunks, &items, &blocks, &threads);
     if (!ok) {
         m->tb = 1;
         return true;
@@ -350,12 +350,12 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
     if (m->family == 0) {
         if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
         hipError_t e = d.ndim == 2 ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
-                                   : launch_fused3d(m->L, ap, m->blocks, m->threads, red, m->stream);
+                                   : launch_fused3d(m->L, ap, m->blocks, m->threads, red, tb, m->stream);
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
         if (red) {
             for (int s = 0; s < tb; ++s) {
-                hipError_t f = launch_finalize(m->part + (int64_t)s * m->items, m->pstride, m->fused_slots,
+                hipError_t f = launch_finalize(m->part + (int64_t)s * m->fused_slots, m->pstride, m->fused_slots,
                                                m->part2, res + kNumQ * s, m->stream);
                 if (f != hipSuccess) return hip_fail(f, "finalize launch");
             }
@@ -1077,7 +1077,7 @@ PF_API pf_status pf_set_time_block(pf_model *m, int32_t tb)
     Model *mm = M(m);
     PF_HIP(hipStreamSynchronize(mm->stream), "hipStreamSynchronize");
     if (tb == 2 && (!time_block_available(mm->L) || mm->desc.flags & PF_FORCE_GENERIC))
-        return fail(PF_ERR_UNSUPPORTED, "two-step kernels exist for 2D orders 2 and 4");
+        return fail(PF_ERR_UNSUPPORTED, "two-step kernels exist for 2D orders 2 and 4 and 3D order 2");
     mm->tb = tb;
     pf_status st = set_chunk(mm, mm->clen);
     if (st == PF_OK && mm->tb != tb) return fail(PF_ERR_UNSUPPORTED, "two-step kernel not available");

@@ -353,7 +353,7 @@ def test_two_step_history_and_graphs(kind):
 
 
 def test_time_block_refused_where_unavailable():
-    d = P.make_desc(P.PF_GS, (40, 30, 20), dt=0.3)
+    d = P.make_desc(P.PF_GS, (40, 30, 20), dt=0.3, order=4)
     m = P.Model(d)
     with pytest.raises(P.PfError) as e:
         m.set_time_block(2)
@@ -362,3 +362,33 @@ def test_time_block_refused_where_unavailable():
     m = P.Model(d)
     with pytest.raises(P.PfError):
         m.set_time_block(2)
+
+
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+def test_two_step_blocking_3d(kind, prec):
+    """3D two-step sweeps (order 2) against single steps, bitwise, with ragged
+    strips, y tiles and z chunks, an odd step count and fused reductions."""
+    shape, ndim, order = (29, 37, 150), 3, 2
+    params = BASE[kind][0]
+    dt = dt_for(kind, ndim, order, params)
+    f0 = fields_for(kind, shape, 51)
+    n = (shape[2], shape[1], shape[0])
+    outs, hist = [], []
+    for tb in (1, 2):
+        d = P.make_desc(kind, n, dt=dt, order=order, precision=prec, params=params,
+                        flags=P.PF_REDUCE_EACH_STEP)
+        m = P.Model(d)
+        m.set_tile(8)
+        m.set_time_block(tb)
+        for f, a in enumerate(f0):
+            m.set_field(f, a)
+        m.step(23)
+        outs.append([m.get_field(f) for f in range(len(f0))])
+        hist.append(sum(m.reduce_history(P.PF_RED_MASS0, 23)))
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+    assert np.max(np.abs(hist[0] - hist[1])) <= 1e-13 * max(1.0, float(np.max(np.abs(hist[0]))))
+    ref = oracle_run(kind, shape, ndim, order, params, dt, 23, 51)[1]
+    for g, r in zip(outs[1], ref):
+        assert float(np.max(np.abs(g - r))) <= TOL[prec]
