@@ -213,11 +213,44 @@ __device__ __forceinline__ int32_t xcd_item(int32_t b, int32_t nwg)
     return x * per + (x < rem ? x : rem) + q;
 }
 
+// Whole-wave lane moves by DPP (a VALU move, no LDS round trip):
+// wave_shl:1 gives lane i the value of lane i + 1, wave_shr:1 that of lane
+// i - 1; lanes without a source receive 0 (they are halo lanes).
+__device__ __forceinline__ int dpp_from_next(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_from_prev(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false);
+}
+
+// Value of lane (lane + D), D != 0, by |D| single-lane moves.
+template <int D>
+__device__ __forceinline__ float lane_shift(float x)
+{
+    int v = __builtin_bit_cast(int, x);
+#pragma unroll
+    for (int i = 0; i < (D > 0 ? D : -D); ++i) v = D > 0 ? dpp_from_next(v) : dpp_from_prev(v);
+    return __builtin_bit_cast(float, v);
+}
+template <int D>
+__device__ __forceinline__ double lane_shift(double x)
+{
+    const long long b = __builtin_bit_cast(long long, x);
+    int lo = (int)b, hi = (int)(b >> 32);
+#pragma unroll
+    for (int i = 0; i < (D > 0 ? D : -D); ++i) {
+        lo = D > 0 ? dpp_from_next(lo) : dpp_from_prev(lo);
+        hi = D > 0 ? dpp_from_next(hi) : dpp_from_prev(hi);
+    }
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Gather the x-neighbourhood a radius-R stencil needs around a lane's V
 // values: e[k + R] is the value at column offset k (k = -R .. V-1+R) from the
-// lane's first column, taken from lane floor(k / V) away by a lane shuffle.
-// Edge lanes receive values from the other end of the wave; their results
-// are masked as halo.
+// lane's first column, taken from lane floor(k / V) away.  Edge lanes receive
+// zeros or values from beyond the strip; their results are masked as halo.
 template <typename T, int V, int R>
 __device__ __forceinline__ void gather_x(const T (&c)[V], T (&e)[V + 2 * R])
 {
@@ -227,10 +260,8 @@ __device__ __forceinline__ void gather_x(const T (&c)[V], T (&e)[V + 2 * R])
         constexpr int el = k - d * V;
         if constexpr (d == 0)
             e[k + R] = c[el];
-        else if constexpr (d > 0)
-            e[k + R] = __shfl_down(c[el], d);
         else
-            e[k + R] = __shfl_up(c[el], -d);
+            e[k + R] = lane_shift<d>(c[el]);
     });
 }
 
