@@ -36,14 +36,15 @@ def log(msg):
 T0 = time.perf_counter()
 
 
-def source_hash():
-    """Hash of the device-code sources (kernels and the headers they include)."""
+def source_hash(family="2d"):
+    """Hash of the device-code sources of one kernel family ("2d" or "3d"):
+    its marching header and instantiation file plus the shared headers."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_10508_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith(".hip") or f in ("pf_device.h", "pf_internal.h", "pf_dispatch.h"):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in ("pf_device.h", "pf_internal.h", "pf_dispatch.h", "pf_march%s.h" % family,
+              "kernels_fused%s.hip" % family):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -143,13 +144,15 @@ def run_gs3d(P, n, prec, steps, warmup, seed=303):
     m.sync()
     wall = time.perf_counter() - t0
     kernel_ms, launches, ksteps = m.timing_read()
+    chunk, tb, rows = m.tile()[0], m.time_block(), m.tile_rows()
     m.close()
     sites = float(n) ** 3
     per = kernel_ms / ksteps
     gbs = 2 * 2 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
     return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
             "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
-            "frac_of_peak": round(gbs / PEAK_GBS, 4)}
+            "frac_of_peak": round(gbs / PEAK_GBS, 4), "chunk": chunk, "time_block": tb,
+            "tile_rows": rows}
 
 
 def main():
@@ -177,10 +180,10 @@ def main():
 
     attain = copy_probe(P, torch)
     log("copy probe %.1f GB/s" % attain)
-    src = source_hash()
+    src, src3 = source_hash("2d"), source_hash("3d")
     fp64 = run_ch(P, args.n, P.PF_FP64, args.steps, args.warmup)
     log("CH FP64: %.3f ms/step" % fp64["ms_per_step"])
-    extra = {"copy_probe_gbs": round(attain, 1), "source_hash": src}
+    extra = {"copy_probe_gbs": round(attain, 1), "source_hash": src, "source_hash_3d": src3}
     if not args.skip_fp32:
         fp32 = run_ch(P, args.n, P.PF_FP32, args.steps, args.warmup)
         extra["fp32"] = {
@@ -191,8 +194,10 @@ def main():
             "time_block": fp32["time_block"]}
         log("CH FP32: %.3f ms/step" % fp32["ms_per_step"])
     if not args.skip_3d:
-        extra["gs3d_1024_fp64"] = run_gs3d(P, 1024, P.PF_FP64, max(10, args.steps // 4), 5)
-        extra["gs3d_1024_fp32"] = run_gs3d(P, 1024, P.PF_FP32, max(10, args.steps // 4), 5)
+        for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
+            r = run_gs3d(P, 1024, prec, max(10, args.steps // 4), 5)
+            r["hbm_bytes_per_launch"] = measured_traffic("gs3d_1024_" + tag, src3)
+            extra["gs3d_1024_" + tag] = r
         log("GS 3D done")
     extra["fp64_mass_drift"] = fp64["mass_drift"]
     extra["fp64_chunk"] = fp64["chunk"]

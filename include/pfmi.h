@@ -217,8 +217,9 @@ pf_status pf_stream(pf_model *m, void **hip_stream);
 
 /*
  * Tile shape of the step kernels: chunk = sites marched per work item along
- * the slowest axis (y in 2D, z in 3D), 0 = the library's choice.  Results
- * do not depend on it (bitwise).  pf_get_tile reports the current one and
+ * the slowest axis (y in 2D, z in 3D), 0 = the library's choice.  Fields
+ * do not depend on it (bitwise); fused reductions agree to their compensated
+ * accuracy (the partition into partial sums changes).  pf_get_tile reports the current one and
  * the kernel family in use (0 fused marching, 1 per-site generic).
  */
 pf_status pf_set_tile(pf_model *m, int32_t chunk);
@@ -235,11 +236,26 @@ pf_status pf_set_time_block(pf_model *m, int32_t tb);
 int32_t pf_get_time_block(const pf_model *m);
 
 /*
- * Autotuner: times each candidate (chunk length, time-block factor) on the
- * model's own buffers by re-running steps from the current state (whose
- * buffer is never written, so the state is unchanged), keeps the fastest per
- * step and records it in an in-process cache keyed by (kind, ndim, order,
- * precision, size class) that later models of the same class reuse.
+ * 3D tile layout of the fused kernels: rows = tile rows held by each wave.
+ * 2: each wave holds two rows of 32 lanes (32-row tiles, 512-byte row
+ * segments; built for every 3D kernel).  1: one row of 64 lanes (16-row
+ * tiles, 1 KiB segments; built for FP64 Allen-Cahn with order <= 4 and
+ * FP64 Gray-Scott with order 2, where it is the default).  0 restores the default.  Fields
+ * are bitwise independent of it.  PF_ERR_UNSUPPORTED for a 2D model, the
+ * per-site family, or a layout not built for this model.  pf_get_tile_rows
+ * returns the layout in use (0 for 2D models and the per-site family, -1 for
+ * NULL).
+ */
+pf_status pf_set_tile_rows(pf_model *m, int32_t rows);
+int32_t pf_get_tile_rows(const pf_model *m);
+
+/*
+ * Autotuner: times each candidate (chunk length, time-block factor, 3D tile
+ * layout) on the model's own buffers by re-running steps from the current
+ * state (whose buffer is never written, so the state is unchanged), keeps the
+ * fastest per step and records it in an in-process cache keyed by (kind,
+ * ndim, order, precision, per-step reductions, size class) that later models
+ * of the same class reuse.
  * trials = timed launches per candidate.
  */
 pf_status pf_autotune(pf_model *m, int32_t trials);

@@ -87,6 +87,8 @@ SIGNATURES = {
     "pf_get_tile": (_i32, [_vp, _pi32, _pi32]),
     "pf_set_time_block": (_i32, [_vp, _i32]),
     "pf_get_time_block": (_i32, [_vp]),
+    "pf_set_tile_rows": (_i32, [_vp, _i32]),
+    "pf_get_tile_rows": (_i32, [_vp]),
     "pf_autotune": (_i32, [_vp, _i32]),
     "pf_timing_enable": (_i32, [_vp, _i32]),
     "pf_timing_read": (_i32, [_vp, _pd, _pi64, _pi64]),
@@ -260,6 +262,12 @@ class Model:
 
     def time_block(self):
         return lib().pf_get_time_block(self.h)
+
+    def set_tile_rows(self, rows):
+        check(lib().pf_set_tile_rows(self.h, rows))
+
+    def tile_rows(self):
+        return lib().pf_get_tile_rows(self.h)
 
     def stream(self):
         s = _vp()

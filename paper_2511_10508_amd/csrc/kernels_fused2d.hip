@@ -1,5 +1,5 @@
 // Instantiations and launchers of the 2D fused marching kernels.
-#include "pf_device.h"
+#include "pf_march2d.h"
 #include "pf_dispatch.h"
 
 namespace pf {

@@ -1,5 +1,5 @@
 // Instantiations and launchers of the 3D fused marching kernels.
-#include "pf_device.h"
+#include "pf_march3d.h"
 #include "pf_dispatch.h"
 
 namespace pf {
@@ -19,64 +19,106 @@ bool dispatch_r3d(int r, F &&f)
 
 using TimeBlockRadii3D = RList<1>;  // radii with a two-step (TB = 2) 3D kernel
 
-bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
-                  int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items,
-                  int32_t *blocks, int32_t *threads)
+// One row per wave is built besides two for FP64 Allen-Cahn with r <= 2 and
+// FP64 Gray-Scott with r = 1, where it measures faster (and is the default).
+template <typename T, int KIND, int R>
+constexpr bool has_one_row_per_wave()
+{
+    return std::is_same<T, double>::value && ((KIND == kAC && R <= 2) || (KIND == kGS && R == 1));
+}
+
+// Calls f(T, KIND, R, TB) for the instantiated 3D kernel of L and tb.
+template <typename F>
+bool dispatch3d(const Launch &L, int tb, F &&f)
 {
     bool ok = false;
     dispatch_prec(L.fp32, [&](auto tz) {
-        using T = decltype(tz);
         dispatch_kind(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
-            ok = dispatch_r3d<KIND>(L.r, [&](auto rc) {
-                constexpr int R = decltype(rc)::value;
-                constexpr int V = Shape<T, KIND, R>::V;
-                const int owmax = tb == 2 ? Shape<T, KIND, R, 2>::OWMAX : Shape<T, KIND, R, 1>::OWMAX;
-                const int h = tb == 2 ? Shape<T, KIND, R, 2>::H : Shape<T, KIND, R, 1>::H;
-                const int64_t st = cdiv(nx, owmax);
-                *strips = (int32_t)st;
-                *ow = (int32_t)(cdiv(cdiv(nx, st), V) * V);
-                *ytiles = (int32_t)cdiv(ny, kWaves3D - 2 * h);
-                *chunks = (int32_t)cdiv(nz, clen);
-                const int64_t it = st * (int64_t)*ytiles * *chunks;
-                *items = (int32_t)it;
-                *blocks = (int32_t)it;
-                *threads = 64 * kWaves3D;
-            });
+            if (tb == 2)
+                ok = dispatch_r(L.r, TimeBlockRadii3D{}, [&](auto rc) {
+                    f(tz, kc, rc, std::integral_constant<int, 2>{});
+                });
+            else if (tb == 1)
+                ok = dispatch_r3d<KIND>(L.r, [&](auto rc) {
+                    f(tz, kc, rc, std::integral_constant<int, 1>{});
+                });
         });
     });
     return ok;
 }
 
-hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
-                          int red, int tb, hipStream_t s)
+bool rows_per_wave_available(const Launch &L, int tb, int rpw)
 {
-    hipError_t err = hipErrorInvalidValue;
-    dispatch_prec(L.fp32, [&](auto tz) {
+    bool has1 = false;
+    if (!dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto) {
+            has1 = has_one_row_per_wave<decltype(tz), decltype(kc)::value, decltype(rc)::value>();
+        }))
+        return false;
+    return rpw == 2 || (rpw == 1 && has1);
+}
+
+int rows_per_wave_default(const Launch &L, int tb) { return rows_per_wave_available(L, tb, 1) ? 1 : 2; }
+
+bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
+                  int rpw, int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks,
+                  int32_t *items, int32_t *blocks, int32_t *threads)
+{
+    if (!rows_per_wave_available(L, tb, rpw)) return false;
+    return dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
         using T = decltype(tz);
-        const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
-        dispatch_kind(L.kind, [&](auto kc) {
-            constexpr int KIND = decltype(kc)::value;
-            if (tb == 2) {
-                dispatch_r(L.r, TimeBlockRadii3D{}, [&](auto rc) {
-                    constexpr int R = decltype(rc)::value;
-                    if (red)
-                        hipLaunchKernelGGL((k_step3d<T, KIND, R, true, 2>), dim3(blocks), dim3(threads), 0, s, a);
-                    else
-                        hipLaunchKernelGGL((k_step3d<T, KIND, R, false, 2>), dim3(blocks), dim3(threads), 0, s, a);
-                    err = hipGetLastError();
-                });
+        constexpr int KIND = decltype(kc)::value, R = decltype(rc)::value;
+        constexpr int TB = decltype(tbc)::value;
+        auto plan = [&](auto tl) {
+            using TL = decltype(tl);
+            const int64_t st = cdiv(nx, TL::OWMAX);
+            *strips = (int32_t)st;
+            *ow = (int32_t)(cdiv(cdiv(nx, st), TL::V) * TL::V);
+            *ytiles = (int32_t)cdiv(ny, TL::NR - 2 * TL::H);
+            *chunks = (int32_t)cdiv(nz, clen);
+            const int64_t it = st * (int64_t)*ytiles * *chunks;
+            *items = (int32_t)it;
+            *blocks = (int32_t)it;
+            *threads = 64 * kWaves3D;
+        };
+        if constexpr (has_one_row_per_wave<T, KIND, R>()) {
+            if (rpw == 1) {
+                plan(Tile3D<T, KIND, R, TB, 1>{});
                 return;
             }
-            dispatch_r3d<KIND>(L.r, [&](auto rc) {
-                constexpr int R = decltype(rc)::value;
-                if (red)
-                    hipLaunchKernelGGL((k_step3d<T, KIND, R, true, 1>), dim3(blocks), dim3(threads), 0, s, a);
-                else
-                    hipLaunchKernelGGL((k_step3d<T, KIND, R, false, 1>), dim3(blocks), dim3(threads), 0, s, a);
-                err = hipGetLastError();
-            });
-        });
+        }
+        plan(Tile3D<T, KIND, R, TB, 2>{});
+    });
+}
+
+template <typename T, int KIND, int R, int TB, int RPW>
+static hipError_t launch3d(const StepArgs<T> &a, int32_t blocks, int32_t threads, int red,
+                           hipStream_t s)
+{
+    if (red)
+        hipLaunchKernelGGL((k_step3d<T, KIND, R, true, TB, RPW>), dim3(blocks), dim3(threads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step3d<T, KIND, R, false, TB, RPW>), dim3(blocks), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
+                          int red, int tb, int rpw, hipStream_t s)
+{
+    hipError_t err = hipErrorInvalidValue;
+    if (!rows_per_wave_available(L, tb, rpw)) return err;
+    dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
+        using T = decltype(tz);
+        constexpr int KIND = decltype(kc)::value, R = decltype(rc)::value;
+        constexpr int TB = decltype(tbc)::value;
+        const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
+        if constexpr (has_one_row_per_wave<T, KIND, R>()) {
+            if (rpw == 1) {
+                err = launch3d<T, KIND, R, TB, 1>(a, blocks, threads, red, s);
+                return;
+            }
+        }
+        err = launch3d<T, KIND, R, TB, 2>(a, blocks, threads, red, s);
     });
     return err;
 }

@@ -10,7 +10,7 @@ constexpr int kAC = 1, kCH = 2, kGS = 3;
 constexpr int kMaxR = 8;            // stencil radius r = order / 2 (order <= 16)
 constexpr int kNumQ = 3;            // reduction quantities per partial slot
 constexpr int kWaves2D = 4;         // waves per workgroup, 2D kernels
-constexpr int kWaves3D = 16;        // waves (= tile rows) per workgroup, 3D kernels
+constexpr int kWaves3D = 16;        // waves per workgroup of the 3D kernels (two tile rows each)
 
 // Reduction quantities of one partial slot:
 //   q0 = sum of field 0, q1 = sum of field 1 (GS) or of the energy density
@@ -57,7 +57,7 @@ struct BatchTable {
     int32_t *steps;          // device array [n]: steps of this tick
 };
 
-// Kernel-family launchers (defined in kernels.hip).  Every launcher returns
+// Kernel-family launchers (defined in kernels_*.hip).  Every launcher returns
 // the hipError_t of the launch.
 //   family 0: fused marching kernels; family 1: per-site generic kernels.
 struct Launch {
@@ -70,13 +70,18 @@ struct Launch {
 bool time_block_available(const Launch &L);
 bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int tb, int32_t *strips,
                   int32_t *ow, int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads);
+// 3D tiles hold one or two rows per wave (rpw); every 3D kernel has rpw = 2,
+// some also rpw = 1 (rows_per_wave_available); rows_per_wave_default is the
+// layout used until one is set or tuned.
+bool rows_per_wave_available(const Launch &L, int tb, int rpw);
+int rows_per_wave_default(const Launch &L, int tb);
 bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
-                  int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items,
-                  int32_t *blocks, int32_t *threads);
+                  int rpw, int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks,
+                  int32_t *items, int32_t *blocks, int32_t *threads);
 hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
                           int red, int tb, hipStream_t s);
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
-                          int red, int tb, hipStream_t s);
+                          int red, int tb, int rpw, hipStream_t s);
 hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
                                   hipStream_t s);
 hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,

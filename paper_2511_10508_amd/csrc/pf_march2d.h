@@ -1,0 +1,338 @@
+// 2D fused marching kernels of libpfmi (gfx950, wave64): see the section
+// comment below for the work decomposition.
+#pragma once
+
+#include "pf_device.h"
+
+namespace pf {
+
+// ===========================================================================
+// 2D fused marching step.  One wave owns a strip of SW = 64 V columns (V
+// values per lane, x-neighbours by lane shuffles) and marches along y over
+// one chunk of output rows.  Each radius-r stencil evaluation is a "stage"
+// that consumes a ring of the last K = 2r+1 rows of its input stream (in
+// registers) and produces one row of its output stream r rows behind:
+//   AC, GS:  state n -> state n+1                       (1 stage per step)
+//   CH:      state n -> mu -> state n+1                  (2 stages per step)
+// With TB = 2 the stages of two time steps are chained, so one sweep over HBM
+// advances the grid two steps; the intermediate state never leaves the
+// registers.  Every stage uses the same per-site functions, so TB = 2 is
+// bitwise equal to two TB = 1 steps.  Loads run K rows ahead (prefetch ring).
+
+// Neighbour pair sums (x pair + y pair) at element v for j = 1..R around the
+// centre row CS of a ring, with the centre row's x-neighbourhood in e.
+template <typename T, int V, int R, int K, int CS>
+__device__ __forceinline__ void pairs2d(const T (&rg)[K][V], const T (&e)[V + 2 * R], int v,
+                                        T (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = (e[R + v + j] + e[R + v - j]) + (rg[sp][v] + rg[sm][v]);
+    });
+}
+
+template <typename T, int V, int R, int K, int CS>
+__device__ __forceinline__ void pairs2d64(const T (&rg)[K][V], const T (&e)[V + 2 * R], int v,
+                                          double (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = ((double)e[R + v + j] + (double)e[R + v - j]) +
+                   ((double)rg[sp][v] + (double)rg[sm][v]);
+    });
+}
+
+// AC / GS step of the centre row CS of the state rings rg (NF fields); with
+// RED the state at that row is reduced (masked by om and red_row).
+template <typename T, int KIND, int R, int K, int CS, bool RED>
+__device__ __forceinline__ void stage_acgs(const StepArgs<T> &a,
+                                           const T (&rg)[KIND == kGS ? 2 : 1][K][Vec<T>::V],
+                                           T (&res)[KIND == kGS ? 2 : 1][Vec<T>::V],
+                                           const OutMask<Vec<T>::V> &om, bool red_row,
+                                           RedState &red)
+{
+    constexpr int V = Vec<T>::V, NF = KIND == kGS ? 2 : 1;
+    T e[NF][V + 2 * R];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) gather_x<T, V, R>(rg[f][CS], e[f]);
+    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sf[NF][R];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) pairs2d<T, V, R, K, CS>(rg[f], e[f], v, Sf[f]);
+        const T u0 = rg[0][CS][v];
+        if constexpr (KIND == kAC) {
+            res[0][v] = ac_update<T, R>(a, u0, Sf[0], u0 * T(4));
+        } else {
+            const T v0 = rg[NF - 1][CS][v];
+            gs_update<T, R>(a, u0, v0, Sf[0], Sf[NF - 1], u0 * T(4), v0 * T(4), res[0][v],
+                            res[NF - 1][v]);
+        }
+        if constexpr (RED) {
+            if (red_row && om.ov[v]) {
+                const double x = (double)u0;
+                rs0 += x;
+                rbad += finite_val(x) ? 0.0 : 1.0;
+                if constexpr (KIND == kAC) {
+                    if constexpr (std::is_same<T, double>::value) {
+                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 4.0);
+                    } else {
+                        double S64[R];
+                        pairs2d64<T, V, R, K, CS>(rg[0], e[0], v, S64);
+                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                    }
+                } else {
+                    const double y = (double)rg[NF - 1][CS][v];
+                    rs1 += y;
+                    rbad += finite_val(y) ? 0.0 : 1.0;
+                }
+            }
+        }
+    }
+    if constexpr (RED) {
+        if (red_row) {
+            acc_add(red.q0, rs0);
+            acc_add(red.q1, rs1);
+            red.bad += rbad;
+        }
+    }
+}
+
+// CH chemical potential of the centre row CS of the concentration ring c.
+template <typename T, int R, int K, int CS, bool RED>
+__device__ __forceinline__ void stage_mu(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                         T (&mu)[Vec<T>::V], const OutMask<Vec<T>::V> &om,
+                                         bool red_row, RedState &red)
+{
+    constexpr int V = Vec<T>::V;
+    T e[V + 2 * R];
+    gather_x<T, V, R>(c[CS], e);
+    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sc[R];
+        pairs2d<T, V, R, K, CS>(c, e, v, Sc);
+        const T c0 = c[CS][v];
+        mu[v] = ch_mu<T, R>(a, c0, Sc, c0 * T(4));
+        if constexpr (RED) {
+            if (red_row && om.ov[v]) {
+                const double x = (double)c0;
+                rs0 += x;
+                if constexpr (std::is_same<T, double>::value) {
+                    rs1 += energy_from_mu(a.c2, x, mu[v]);
+                } else {
+                    double S64[R];
+                    pairs2d64<T, V, R, K, CS>(c, e, v, S64);
+                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                }
+                rbad += finite_val(x) ? 0.0 : 1.0;
+            }
+        }
+    }
+    if constexpr (RED) {
+        if (red_row) {
+            acc_add(red.q0, rs0);
+            acc_add(red.q1, rs1);
+            red.bad += rbad;
+        }
+    }
+}
+
+// CH update of the centre row CS: c' = c + dt L mu.
+template <typename T, int R, int K, int CS>
+__device__ __forceinline__ void stage_chupd(const StepArgs<T> &a, const T (&m)[K][Vec<T>::V],
+                                            const T (&c0)[Vec<T>::V], T (&res)[Vec<T>::V])
+{
+    constexpr int V = Vec<T>::V;
+    T em[V + 2 * R];
+    gather_x<T, V, R>(m[CS], em);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sm[R];
+        pairs2d<T, V, R, K, CS>(m, em, v, Sm);
+        res[v] = ch_update<T, R>(a, c0[v], Sm, m[CS][v] * T(4));
+    }
+}
+
+template <typename T, int KIND, int R, bool RED, bool FAST, int TB>
+__device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t xb, int64_t y0,
+                                        int64_t y1, int lane, int64_t pslot)
+{
+    using S = Shape<T, KIND, R, TB>;
+    constexpr int V = S::V, H = S::H, HV = S::HV, K = S::K, NF = S::NF;
+    const int64_t nx = a.nx, ny = a.ny, pitch = a.pitch;
+    const int64_t xl = xb + lane * V;
+    const int pl = lane * V;
+    OutMask<V> om;
+    om.all = true;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        om.ov[v] = (pl + v >= HV) && (pl + v < HV + a.ow) && (xl + v < nx);
+        om.all = om.all && om.ov[v];
+    }
+    const RowIO<T, V, FAST> io(xb, lane, nx);
+    const T *in[2] = {a.buf[0][par], a.buf[NF - 1][par]};
+    T *out[2] = {a.buf[0][par ^ 1], a.buf[NF - 1][par ^ 1]};
+
+    T ring[NF][K][V];                                    // state n (loaded)
+    T pre[NF][K][V];                                     // prefetched rows
+    T r1[TB == 2 ? NF : 1][K][V];                        // state n+1 (TB = 2)
+    T m0[KIND == kCH ? K : 1][V];                        // mu of state n
+    T m1[(KIND == kCH && TB == 2) ? K : 1][V];           // mu of state n+1
+    RedState red[TB];
+
+    const int64_t tb0 = y0 - H, tend = y1 + H;
+    // The first K rows are loaded unconditionally (a row past the march is a
+    // valid wrapped row, read and not used), so that every load of the
+    // unguarded main loop below has a fixed number of loads issued after it
+    // and the compiler can wait for it alone instead of draining all of them.
+    static_for<0, K>([&](auto phc) {
+        constexpr int ph = decltype(phc)::value;
+        const int64_t off = wrap_any(tb0 + ph, ny) * pitch;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
+    });
+
+    // One row t of the march at ring phase ph; G guards the rows and the
+    // prefetch against the end of the march (the tail only).
+    auto phase = [&](auto phc, auto gc, int64_t tb) {
+        constexpr int ph = decltype(phc)::value;
+        constexpr bool G = decltype(gc)::value;
+        const int64_t t = tb + ph;
+        if (!G || t < tend) {
+            const int64_t age = t - tb0;  // a stage of depth k is valid once age >= 2 k r
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int v = 0; v < V; ++v) ring[f][ph][v] = pre[f][ph][v];
+            if (!G || t + K < tend) {
+                const int64_t off = wrap_any(t + K, ny) * pitch;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
+            }
+            if constexpr (KIND != kCH) {
+                constexpr int s1 = Slot<K, R>::template at<ph>;
+                if (age >= 2 * R) {
+                    const int64_t row = t - R;
+                    T res[NF][V];
+                    stage_acgs<T, KIND, R, K, s1, RED>(a, ring, res, om, row >= y0 && row < y1,
+                                                       red[0]);
+                    if constexpr (TB == 1) {
+                        const int64_t ooff = wrap_any(row, ny) * pitch;
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                    } else {
+#pragma unroll
+                        for (int f = 0; f < NF; ++f)
+#pragma unroll
+                            for (int v = 0; v < V; ++v) r1[f][s1][v] = res[f][v];
+                    }
+                }
+                if constexpr (TB == 2) {
+                    constexpr int s2 = Slot<K, 2 * R>::template at<ph>;
+                    if (age >= 4 * R) {
+                        const int64_t row = t - 2 * R;
+                        T res[NF][V];
+                        stage_acgs<T, KIND, R, K, s2, RED>(a, r1, res, om, row >= y0 && row < y1,
+                                                           red[TB - 1]);
+                        const int64_t ooff = wrap_any(row, ny) * pitch;
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                    }
+                }
+            } else {
+                constexpr int s1 = Slot<K, R>::template at<ph>;
+                constexpr int s2 = Slot<K, 2 * R>::template at<ph>;
+                if (age >= 2 * R) {
+                    const int64_t row = t - R;
+                    stage_mu<T, R, K, s1, RED>(a, ring[0], m0[s1], om, row >= y0 && row < y1,
+                                               red[0]);
+                }
+                if (age >= 4 * R) {
+                    T res[V];
+                    stage_chupd<T, R, K, s2>(a, m0, ring[0][s2], res);
+                    if constexpr (TB == 1) {
+                        store_row<T, V>(out[0] + wrap_any(t - 2 * R, ny) * pitch, xl, om, res);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) r1[0][s2][v] = res[v];
+                    }
+                }
+                if constexpr (TB == 2) {
+                    constexpr int s3 = Slot<K, 3 * R>::template at<ph>;
+                    constexpr int s4 = Slot<K, 4 * R>::template at<ph>;
+                    if (age >= 6 * R) {
+                        const int64_t row = t - 3 * R;
+                        stage_mu<T, R, K, s3, RED>(a, r1[0], m1[s3], om, row >= y0 && row < y1,
+                                                   red[TB - 1]);
+                    }
+                    if (age >= 8 * R) {
+                        T res[V];
+                        stage_chupd<T, R, K, s4>(a, m1, r1[0][s4], res);
+                        store_row<T, V>(out[0] + wrap_any(t - 4 * R, ny) * pitch, xl, om, res);
+                    }
+                }
+            }
+        }
+    };
+    int64_t tb = tb0;
+    for (; tb + 2 * K <= tend; tb += K)
+        static_for<0, K>([&](auto phc) { phase(phc, std::false_type{}, tb); });
+    for (; tb < tend; tb += K)
+        static_for<0, K>([&](auto phc) { phase(phc, std::true_type{}, tb); });
+    if constexpr (RED) {
+        red_flush(red[0], a.part, a.pstride, pslot, lane);
+        if constexpr (TB == 2) red_flush(red[TB - 1], a.part, a.pstride, pslot + a.items, lane);
+    }
+}
+
+template <typename T, int KIND, int R, bool RED, int TB>
+__device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32_t item,
+                                            int lane, int64_t pslot)
+{
+    using S = Shape<T, KIND, R, TB>;
+    const int32_t strip = item % a.strips;
+    const int32_t chunk = item / a.strips;
+    const int64_t xb = (int64_t)strip * a.ow - S::HV;
+    const int64_t y0 = (int64_t)chunk * a.clen;
+    const int64_t y1 = min(y0 + (int64_t)a.clen, a.ny);
+    if (xb >= 0 && xb + S::SW <= a.nx)
+        march2d<T, KIND, R, RED, true, TB>(a, par, xb, y0, y1, lane, pslot);
+    else
+        march2d<T, KIND, R, RED, false, TB>(a, par, xb, y0, y1, lane, pslot);
+}
+
+// Single-model 2D launch of TB fused steps: reads buf[parity], writes
+// buf[parity ^ 1].
+template <typename T, int KIND, int R, bool RED, int TB>
+__global__ void __launch_bounds__(64 * kWaves2D) k_step2d(StepArgs<T> a)
+{
+    const int32_t nwg = gridDim.x;
+    const int32_t wg = xcd_item(blockIdx.x, nwg);
+    const int32_t item = wg * kWaves2D + (threadIdx.x >> 6);
+    if (item >= a.items) return;
+    step2d_item<T, KIND, R, RED, TB>(a, a.parity, item, threadIdx.x & 63, item);
+}
+
+// Persistent batched 2D step: a fixed grid strides over the work items of
+// every request in the table (step k of the tick; requests with fewer steps
+// this tick skip).  Each request is stepped exactly as by k_step2d.
+template <typename T, int KIND, int R>
+__global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> tb, int32_t k)
+{
+    const int32_t n = *tb.count;
+    const int32_t total = tb.item_start[n];
+    const int32_t stride = gridDim.x * kWaves2D;
+    for (int32_t g = blockIdx.x * kWaves2D + (threadIdx.x >> 6); g < total; g += stride) {
+        const int i = batch_request(tb, n, g);
+        if (k >= tb.steps[i]) continue;
+        const StepArgs<T> &a = tb.args[i];
+        step2d_item<T, KIND, R, false, 1>(a, (a.parity + k) & 1, g - tb.item_start[i],
+                                          threadIdx.x & 63, 0);
+    }
+}
+
+}  // namespace pf

@@ -1,0 +1,435 @@
+// 3D fused marching kernels of libpfmi (gfx950, wave64): see the section
+// comment below for the work decomposition.
+#pragma once
+
+#include "pf_device.h"
+
+namespace pf {
+
+// ===========================================================================
+// 3D fused marching step.  A workgroup of 16 waves owns a tile of NR rows
+// (y) of one x-strip and marches along z.  Each wave holds RPW tile rows:
+// with RPW = 1 the wave's 64 lanes hold row w (RW = 64 V columns); with
+// RPW = 2 lanes 0-31 hold row 2w and lanes 32-63 row 2w+1 (RW = 32 V
+// columns, 512 contiguous bytes each).  Two rows per wave double the tile
+// height for the same registers per lane, which halves the share of the tile
+// lost to the y-halo (2H of NR rows) at the price of a wider share lost to
+// the x-halo (2HV of RW columns); the layout is chosen per kernel.
+// As in 2D the step is a chain of radius-r stages (two per CH step, one per
+// AC/GS step; TB steps per sweep); each stage keeps a z-window of K = 2r+1
+// planes of its input stream in registers, takes x-neighbours by lane
+// shifts and y-neighbours from the other rows of its centre plane in LDS.
+// With two rows per wave a shift across the middle of the wave brings the
+// other row's edge value into a halo column, on which no valid output
+// depends.  Stage k's centre plane was produced r iterations earlier, so
+// every stage's LDS row is written before one barrier per plane; a stage at
+// depth k is valid for rows [k r, NR - k r) of the tile, and only rows
+// [H, NR - H) are written.
+
+template <typename T, int KIND, int R, int TB, int RPW_ = 2>
+struct Tile3D {
+    using S = Shape<T, KIND, R, TB>;
+    static constexpr int V = S::V, H = S::H, HV = S::HV;
+    static constexpr int RPW = RPW_;                         // rows per wave (1 or 2)
+    static constexpr int LPR = 64 / RPW;                     // lanes per row
+    static constexpr int NR = RPW * kWaves3D;                // tile rows
+    static constexpr int RW = LPR * V;                       // loaded columns per row
+    static constexpr int OWMAX = RW - 2 * HV;                // most outputs per row
+    static constexpr int NST = (KIND == kCH ? 2 : 1) * TB;  // stages
+    static constexpr int NFS = KIND == kCH ? 1 : S::NF;      // fields per stage input
+    static constexpr int NB = NST * NFS <= 2 ? 2 : 1;        // LDS buffers (double when it fits)
+    using lds_type = T[NB][NST][NFS][NR][RW];
+    static_assert(RPW == 1 || RPW == 2, "one or two rows per wave");
+    static_assert(2 * H < NR && OWMAX > 0, "halo too wide for the 3D tile");
+};
+
+// Pair sums at element v around centre plane slot CS of a ring, with the
+// centre row's x-neighbourhood e and the centre plane's rows in LDS L (this
+// lane's row rw, first column pl).
+template <typename T, int V, int R, int K, int CS, int NR, int RW>
+__device__ __forceinline__ void pairs3d(const T (&rg)[K][V], const T (&e)[V + 2 * R],
+                                        const T (&L)[NR][RW], int rw, int pl, int v, T (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = ((e[R + v + j] + e[R + v - j]) + (L[rw + j][pl + v] + L[rw - j][pl + v])) +
+                   (rg[sp][v] + rg[sm][v]);
+    });
+}
+
+template <typename T, int V, int R, int K, int CS, int NR, int RW>
+__device__ __forceinline__ void pairs3d64(const T (&rg)[K][V], const T (&e)[V + 2 * R],
+                                          const T (&L)[NR][RW], int rw, int pl, int v,
+                                          double (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = (((double)e[R + v + j] + (double)e[R + v - j]) +
+                    ((double)L[rw + j][pl + v] + (double)L[rw - j][pl + v])) +
+                   ((double)rg[sp][v] + (double)rg[sm][v]);
+    });
+}
+
+template <typename T, int KIND, int R, int K, int CS, int NR, int RW, bool RED>
+__device__ __forceinline__ void stage3_acgs(const StepArgs<T> &a,
+                                            const T (&rg)[KIND == kGS ? 2 : 1][K][Vec<T>::V],
+                                            const T (&L)[KIND == kGS ? 2 : 1][NR][RW], int rw,
+                                            int pl, T (&res)[KIND == kGS ? 2 : 1][Vec<T>::V],
+                                            const OutMask<Vec<T>::V> &om, bool red_row, RedState &red)
+{
+    constexpr int V = Vec<T>::V, NF = KIND == kGS ? 2 : 1;
+    T e[NF][V + 2 * R];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) gather_x<T, V, R>(rg[f][CS], e[f]);
+    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sf[NF][R];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            pairs3d<T, V, R, K, CS, NR, RW>(rg[f], e[f], L[f], rw, pl, v, Sf[f]);
+        const T u0 = rg[0][CS][v];
+        if constexpr (KIND == kAC) {
+            res[0][v] = ac_update<T, R>(a, u0, Sf[0], u0 * T(6));
+        } else {
+            const T v0 = rg[NF - 1][CS][v];
+            gs_update<T, R>(a, u0, v0, Sf[0], Sf[NF - 1], u0 * T(6), v0 * T(6), res[0][v],
+                            res[NF - 1][v]);
+        }
+        if constexpr (RED) {
+            if (red_row && om.ov[v]) {
+                const double x = (double)u0;
+                rs0 += x;
+                rbad += finite_val(x) ? 0.0 : 1.0;
+                if constexpr (KIND == kAC) {
+                    if constexpr (std::is_same<T, double>::value) {
+                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 6.0);
+                    } else {
+                        double S64[R];
+                        pairs3d64<T, V, R, K, CS, NR, RW>(rg[0], e[0], L[0], rw, pl, v, S64);
+                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
+                    }
+                } else {
+                    const double y = (double)rg[NF - 1][CS][v];
+                    rs1 += y;
+                    rbad += finite_val(y) ? 0.0 : 1.0;
+                }
+            }
+        }
+    }
+    if constexpr (RED) {
+        if (red_row) {
+            acc_add(red.q0, rs0);
+            acc_add(red.q1, rs1);
+            red.bad += rbad;
+        }
+    }
+}
+
+template <typename T, int R, int K, int CS, int NR, int RW, bool RED>
+__device__ __forceinline__ void stage3_mu(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                          const T (&L)[NR][RW], int rw, int pl, T (&mu)[Vec<T>::V],
+                                          const OutMask<Vec<T>::V> &om, bool red_row, RedState &red)
+{
+    constexpr int V = Vec<T>::V;
+    T e[V + 2 * R];
+    gather_x<T, V, R>(c[CS], e);
+    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sc[R];
+        pairs3d<T, V, R, K, CS, NR, RW>(c, e, L, rw, pl, v, Sc);
+        const T c0 = c[CS][v];
+        mu[v] = ch_mu<T, R>(a, c0, Sc, c0 * T(6));
+        if constexpr (RED) {
+            if (red_row && om.ov[v]) {
+                const double x = (double)c0;
+                rs0 += x;
+                if constexpr (std::is_same<T, double>::value) {
+                    rs1 += energy_from_mu(a.c2, x, mu[v]);
+                } else {
+                    double S64[R];
+                    pairs3d64<T, V, R, K, CS, NR, RW>(c, e, L, rw, pl, v, S64);
+                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
+                }
+                rbad += finite_val(x) ? 0.0 : 1.0;
+            }
+        }
+    }
+    if constexpr (RED) {
+        if (red_row) {
+            acc_add(red.q0, rs0);
+            acc_add(red.q1, rs1);
+            red.bad += rbad;
+        }
+    }
+}
+
+template <typename T, int R, int K, int CS, int NR, int RW>
+__device__ __forceinline__ void stage3_chupd(const StepArgs<T> &a, const T (&m)[K][Vec<T>::V],
+                                             const T (&L)[NR][RW], int rw, int pl,
+                                             const T (&c0)[Vec<T>::V], T (&res)[Vec<T>::V])
+{
+    constexpr int V = Vec<T>::V;
+    T em[V + 2 * R];
+    gather_x<T, V, R>(m[CS], em);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sm[R];
+        pairs3d<T, V, R, K, CS, NR, RW>(m, em, L, rw, pl, v, Sm);
+        res[v] = ch_update<T, R>(a, c0[v], Sm, m[CS][v] * T(6));
+    }
+}
+
+// Prefetch depth PD of the input planes: K planes ahead, or one plane where
+// the K-deep prefetch ring would not fit the 128 registers a lane of a
+// 16-wave workgroup can hold (wider stencils, where a plane's work is also
+// long enough to hide one plane's load latency).
+template <typename T, int KIND, int R, int TB, bool RED>
+constexpr int prefetch_depth()
+{
+    return R >= 2 ? 1 : 2 * R + 1;
+}
+
+template <typename T, int KIND, int R, bool RED, bool FAST, int TB, int RPW>
+__device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t xb, int64_t yrow,
+                                        bool out_row, int64_t z0, int64_t z1, int64_t pslot,
+                                        typename Tile3D<T, KIND, R, TB, RPW>::lds_type &lds)
+{
+    using S = Shape<T, KIND, R, TB>;
+    using TL = Tile3D<T, KIND, R, TB, RPW>;
+    constexpr int V = S::V, H = S::H, HV = S::HV, K = S::K, NF = S::NF;
+    constexpr int NR = TL::NR, RW = TL::RW;
+
+    const int lane = threadIdx.x & 63;
+    const int lx = lane % TL::LPR;                           // lane within the row segment
+    const int rw = TL::RPW * (threadIdx.x >> 6) + lane / TL::LPR;  // tile row
+    const int64_t nx = a.nx, ny = a.ny, nz = a.nz, pitch = a.pitch, plane = a.plane;
+    const int64_t xl = xb + lx * V;
+    const int64_t rowoff = wrap_any(yrow, ny) * pitch;
+    const int pl = lx * V;
+    OutMask<V> om;
+    om.all = true;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        om.ov[v] = out_row && (pl + v >= HV) && (pl + v < HV + a.ow) && (xl + v < nx);
+        om.all = om.all && om.ov[v];
+    }
+    const RowIO<T, V, FAST> io(xb, lx, nx);
+    const T *in[2] = {a.buf[0][par], a.buf[NF - 1][par]};
+    T *out[2] = {a.buf[0][par ^ 1], a.buf[NF - 1][par ^ 1]};
+
+    T ring[NF][K][V];
+    constexpr int PD = prefetch_depth<T, KIND, R, TB, RED>();
+    T pre[NF][PD][V];                                // planes t+1 .. t+PD
+    T r1[TB == 2 ? NF : 1][K][V];
+    T m0[KIND == kCH ? K : 1][V];
+    T m1[(KIND == kCH && TB == 2) ? K : 1][V];
+    // rings that feed LDS rows before first being computed hold zeros
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if constexpr (KIND == kCH) {
+                m0[i][v] = T(0);
+                if constexpr (TB == 2) m1[i][v] = T(0);
+            }
+            if constexpr (TB == 2)
+#pragma unroll
+                for (int f = 0; f < NF; ++f) r1[f][i][v] = T(0);
+        }
+    RedState red[TB];
+    // a stage at depth k computes rows [k r, NR - k r) of the tile
+    auto rows_ok = [&](int k) { return rw >= k * R && rw < NR - k * R; };
+
+    const int64_t tb0 = z0 - H, tend = z1 + H;
+    // The first PD planes are loaded unconditionally (a plane past the march
+    // is a valid wrapped plane, read and not used), so that every load of the
+    // unguarded main loop below has a fixed number of loads issued after it
+    // and the compiler can wait for it alone instead of draining all of them.
+    static_for<0, PD>([&](auto phc) {
+        constexpr int ph = decltype(phc)::value;
+        const int64_t off = wrap_any(tb0 + ph, nz) * plane + rowoff;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
+    });
+
+    // One plane t of the march at ring phase ph; G guards the planes and the
+    // prefetch against the end of the march (the tail only).  The guards are
+    // uniform over the workgroup, so every wave reaches the same barriers.
+    auto phase = [&](auto phc, auto gc, int64_t tb) {
+        constexpr int ph = decltype(phc)::value;
+        constexpr bool G = decltype(gc)::value;
+        const int64_t t = tb + ph;
+        if (!G || t < tend) {
+            const int64_t age = t - tb0;
+            const int buf = TL::NB == 2 ? (int)(t & 1) : 0;
+            auto &L = lds[buf];
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int v = 0; v < V; ++v) ring[f][ph][v] = pre[f][ph % PD][v];
+            if (!G || t + PD < tend) {
+                const int64_t off = wrap_any(t + PD, nz) * plane + rowoff;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph % PD]);
+            }
+            constexpr int s1 = Slot<K, R>::template at<ph>;
+            constexpr int s2 = Slot<K, 2 * R>::template at<ph>;
+            constexpr int s3 = Slot<K, 3 * R>::template at<ph>;
+            constexpr int s4 = Slot<K, 4 * R>::template at<ph>;
+            if constexpr (TL::NB == 1) __syncthreads();  // previous plane's readers are done
+            // centre rows of every stage's input stream
+            if constexpr (KIND != kCH) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        L[0][f][rw][pl + v] = ring[f][s1][v];
+                        if constexpr (TB == 2) L[TB - 1][f][rw][pl + v] = r1[f][s2][v];
+                    }
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    L[0][0][rw][pl + v] = ring[0][s1][v];
+                    L[1][0][rw][pl + v] = m0[s2][v];
+                    if constexpr (TB == 2) {
+                        L[TB][0][rw][pl + v] = r1[0][s3][v];
+                        L[TB + 1][0][rw][pl + v] = m1[s4][v];
+                    }
+                }
+            }
+            __syncthreads();
+            if constexpr (KIND != kCH) {
+                if (age >= 2 * R && rows_ok(1)) {
+                    const int64_t pz = t - R;
+                    T res[NF][V];
+                    stage3_acgs<T, KIND, R, K, s1, NR, RW, RED>(a, ring, L[0], rw, pl, res, om,
+                                                                pz >= z0 && pz < z1, red[0]);
+                    if constexpr (TB == 1) {
+                        if (out_row) {
+                            const int64_t ooff = wrap_any(pz, nz) * plane + rowoff;
+#pragma unroll
+                            for (int f = 0; f < NF; ++f)
+                                store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int f = 0; f < NF; ++f)
+#pragma unroll
+                            for (int v = 0; v < V; ++v) r1[f][s1][v] = res[f][v];
+                    }
+                }
+                if constexpr (TB == 2) {
+                    if (age >= 4 * R && rows_ok(2)) {
+                        const int64_t pz = t - 2 * R;
+                        T res[NF][V];
+                        stage3_acgs<T, KIND, R, K, s2, NR, RW, RED>(
+                            a, r1, L[TB - 1], rw, pl, res, om, pz >= z0 && pz < z1, red[TB - 1]);
+                        if (out_row) {
+                            const int64_t ooff = wrap_any(pz, nz) * plane + rowoff;
+#pragma unroll
+                            for (int f = 0; f < NF; ++f)
+                                store_row<T, V>(out[f] + ooff, xl, om, res[f]);
+                        }
+                    }
+                }
+            } else {
+                if (age >= 2 * R && rows_ok(1)) {
+                    const int64_t pz = t - R;
+                    stage3_mu<T, R, K, s1, NR, RW, RED>(a, ring[0], L[0][0], rw, pl, m0[s1], om,
+                                                        pz >= z0 && pz < z1, red[0]);
+                }
+                if (age >= 4 * R && rows_ok(2)) {
+                    T res[V];
+                    stage3_chupd<T, R, K, s2, NR, RW>(a, m0, L[1][0], rw, pl, ring[0][s2], res);
+                    if constexpr (TB == 1) {
+                        if (out_row)
+                            store_row<T, V>(out[0] + wrap_any(t - 2 * R, nz) * plane + rowoff, xl,
+                                            om, res);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) r1[0][s2][v] = res[v];
+                    }
+                }
+                if constexpr (TB == 2) {
+                    if (age >= 6 * R && rows_ok(3)) {
+                        const int64_t pz = t - 3 * R;
+                        stage3_mu<T, R, K, s3, NR, RW, RED>(a, r1[0], L[TB][0], rw, pl, m1[s3],
+                                                            om, pz >= z0 && pz < z1, red[TB - 1]);
+                    }
+                    if (age >= 8 * R && rows_ok(4)) {
+                        T res[V];
+                        stage3_chupd<T, R, K, s4, NR, RW>(a, m1, L[TB + 1][0], rw, pl, r1[0][s4],
+                                                          res);
+                        if (out_row)
+                            store_row<T, V>(out[0] + wrap_any(t - 4 * R, nz) * plane + rowoff,
+                                            xl, om, res);
+                    }
+                }
+            }
+        }
+    };
+    int64_t tb = tb0;
+    for (; tb + K + PD <= tend; tb += K)
+        static_for<0, K>([&](auto phc) { phase(phc, std::false_type{}, tb); });
+    for (; tb < tend; tb += K)
+        static_for<0, K>([&](auto phc) { phase(phc, std::true_type{}, tb); });
+    if constexpr (RED) {
+        red_flush(red[0], a.part, a.pstride, pslot, lane);
+        if constexpr (TB == 2)
+            red_flush(red[TB - 1], a.part, a.pstride, pslot + (int64_t)a.items * kWaves3D, lane);
+    }
+}
+
+template <typename T, int KIND, int R, bool RED, int TB, int RPW>
+__device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32_t item,
+                                            int64_t pslot_base)
+{
+    using TL = Tile3D<T, KIND, R, TB, RPW>;
+    const int w = threadIdx.x >> 6;
+    const int rw = TL::RPW * w + (int)(threadIdx.x & 63) / TL::LPR;
+    const int32_t strip = item % a.strips;
+    const int32_t rest = item / a.strips;
+    const int32_t ytile = rest % a.ytiles;
+    const int32_t chunk = rest / a.ytiles;
+    const int64_t xb = (int64_t)strip * a.ow - TL::HV;
+    const int64_t yrow = (int64_t)ytile * (TL::NR - 2 * TL::H) - TL::H + rw;
+    const bool out_row = (rw >= TL::H) && (rw < TL::NR - TL::H) && (yrow < a.ny);
+    const int64_t z0 = (int64_t)chunk * a.clen;
+    const int64_t z1 = min(z0 + (int64_t)a.clen, a.nz);
+    __shared__ typename TL::lds_type lds;
+    // the FAST choice is uniform over the workgroup (it depends on the strip only)
+    if (xb >= 0 && xb + TL::RW <= a.nx)
+        march3d<T, KIND, R, RED, true, TB, RPW>(a, par, xb, yrow, out_row, z0, z1, pslot_base + w, lds);
+    else
+        march3d<T, KIND, R, RED, false, TB, RPW>(a, par, xb, yrow, out_row, z0, z1, pslot_base + w, lds);
+}
+
+template <typename T, int KIND, int R, bool RED, int TB, int RPW>
+__global__ void __launch_bounds__(64 * kWaves3D) k_step3d(StepArgs<T> a)
+{
+    const int32_t item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= a.items) return;  // uniform over the workgroup
+    step3d_item<T, KIND, R, RED, TB, RPW>(a, a.parity, item, (int64_t)item * kWaves3D);
+}
+
+// Persistent batched 3D step (see k_step2d_batched), two rows per wave; the
+// item loop is uniform over the workgroup, so every wave reaches the same
+// barriers.
+template <typename T, int KIND, int R>
+__global__ void __launch_bounds__(64 * kWaves3D) k_step3d_batched(BatchTable<T> tb, int32_t k)
+{
+    const int32_t n = *tb.count;
+    const int32_t total = tb.item_start[n];
+    for (int32_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const int i = batch_request(tb, n, g);
+        if (k >= tb.steps[i]) continue;
+        const StepArgs<T> &a = tb.args[i];
+        step3d_item<T, KIND, R, false, 1, 2>(a, (a.parity + k) & 1, g - tb.item_start[i], 0);
+    }
+}
+
+}  // namespace pf

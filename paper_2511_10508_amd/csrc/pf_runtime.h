@@ -28,6 +28,7 @@ struct Model {
     // decomposition of the fused family (family 0) or per-site (family 1)
     int family = 1;
     int tb = 1;                   // time steps fused per launch (2D, r <= 2)
+    int rpw_req = 0, rpw = 2;     // 3D tile rows per wave: requested (0: default), in use
     int32_t clen = 0, strips = 0, ow = 0, ytiles = 1, chunks = 0, items = 0, blocks = 0,
             threads = 0;
     int64_t fused_slots = 0;

@@ -194,9 +194,13 @@ static bool plan(Model *m)
     if (d.ndim == 2)
         ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, m->tb, &strips, &ow, &chunks, &items,
                           &blocks, &threads);
-    else
-        ok = plan_fused3d(L, d.n[0], d.n[1], d.n[2], m->clen, m->tb, &strips, &ow, &ytiles,
-                          &chunks, &items, &blocks, &threads);
+    else {
+        m->rpw = m->rpw_req && rows_per_wave_available(L, m->tb, m->rpw_req)
+                     ? m->rpw_req
+                     : rows_per_wave_default(L, m->tb);
+        ok = plan_fused3d(L, d.n[0], d.n[1], d.n[2], m->clen, m->tb, m->rpw, &strips, &ow,
+                          &ytiles, &chunks, &items, &blocks, &threads);
+    }
     if (!ok) {
         m->tb = 1;
         return true;
@@ -215,12 +219,13 @@ static bool plan(Model *m)
 
 // Default chunk length along the marching axis: long enough to amortise the
 // 2H warm-up rows, short enough that small grids still expose thousands of
-// work items (about 4096 waves in 2D, 1024 workgroups of 16 waves in 3D).
+// work items (about 4096 waves in 2D, 1024 workgroups in 3D, whose tiles
+// are half as wide as a 2D strip and 32 rows high).
 int32_t default_chunk(const pf_desc *d)
 {
     const int64_t march = d->ndim == 2 ? d->n[1] : d->n[2];
-    const int64_t lanes = d->precision == PF_FP32 ? 256 : 128;
-    const int64_t strips = std::max<int64_t>(1, (d->n[0] + lanes - 1) / lanes);
+    const int64_t cols = (d->precision == PF_FP32 ? 256 : 128) / (d->ndim == 2 ? 1 : 2);
+    const int64_t strips = std::max<int64_t>(1, (d->n[0] + cols - 1) / cols);
     const int64_t cmin = 8;
     int64_t cmax, c;
     if (d->ndim == 2) {
@@ -228,20 +233,28 @@ int32_t default_chunk(const pf_desc *d)
         c = march * strips / 4096;
     } else {
         cmax = 64;
-        const int64_t ytiles = std::max<int64_t>(1, (d->n[1] + 7) / 8);
+        const int64_t ytiles = std::max<int64_t>(1, (d->n[1] + 23) / 24);
         c = march * strips * ytiles / 1024;
     }
     c = std::max(cmin, std::min(cmax, c));
     return (int32_t)std::max<int64_t>(1, std::min<int64_t>(c, march));
 }
 
+// Tuned decompositions, keyed by model, order, precision, whether reductions
+// ride on every step, and the log2 of each extent.
+struct TuneChoice {
+    int32_t chunk;
+    int tb, rpw;
+};
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int>;
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int, int, int, int, int>, std::pair<int32_t, int>> g_tune_cache;
+static std::map<TuneKey, TuneChoice> g_tune_cache;
 
-static std::tuple<int, int, int, int, int, int, int> tune_key(const pf_desc &d)
+static TuneKey tune_key(const pf_desc &d)
 {
     auto lg = [](int64_t v) { int b = 0; while ((1ll << (b + 1)) <= v) ++b; return b; };
-    return std::make_tuple(d.kind, d.ndim, d.order, d.precision, lg(d.n[0]), lg(d.n[1]),
+    return std::make_tuple(d.kind, d.ndim, d.order, d.precision,
+                           (d.flags & PF_REDUCE_EACH_STEP) ? 1 : 0, lg(d.n[0]), lg(d.n[1]),
                            lg(d.n[2]));
 }
 
@@ -349,8 +362,9 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
     }
     if (m->family == 0) {
         if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
-        hipError_t e = d.ndim == 2 ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
-                                   : launch_fused3d(m->L, ap, m->blocks, m->threads, red, tb, m->stream);
+        hipError_t e = d.ndim == 2
+                           ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
+                           : launch_fused3d(m->L, ap, m->blocks, m->threads, red, tb, m->rpw, m->stream);
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
         if (red) {
@@ -627,8 +641,9 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(*desc));
         if (it != g_tune_cache.end()) {
-            chunk = it->second.first;
-            m->tb = it->second.second;
+            chunk = it->second.chunk;
+            m->tb = it->second.tb;
+            m->rpw_req = it->second.rpw;
         }
     }
     st = set_chunk(m, chunk);
@@ -766,47 +781,54 @@ pf_status autotune(Model *m, int32_t trials)
     if (time_block_available(m->L)) tbs.push_back(2);
     if (trials < 1) trials = 3;
     const int32_t keep_c = m->clen;
-    const int keep_tb = m->tb;
+    const int keep_tb = m->tb, keep_rpw = m->rpw_req;
     hipEvent_t a, b;
     PF_HIP(hipEventCreate(&a), "hipEventCreate");
     PF_HIP(hipEventCreate(&b), "hipEventCreate");
     double2 *scratch = nullptr;
     if (red) PF_HIP(hipMalloc((void **)&scratch, sizeof(double2) * kNumQ * 2), "hipMalloc(tune)");
     float best = 1e30f;
-    int32_t best_c = keep_c;
-    int best_tb = keep_tb;
+    TuneChoice bestc{keep_c, keep_tb, keep_rpw};
     pf_status st = PF_OK;
-    for (int tb : tbs)
-        for (int32_t c : cand) {
-            m->tb = tb;
-            st = set_chunk(m, c);
-            if (st != PF_OK || m->family != 0 || m->tb != tb) break;
-            st = launch_step(m, m->parity, red, scratch, false, tb);
-            if (st != PF_OK) break;
-            (void)hipEventRecord(a, m->stream);
-            for (int t = 0; t < trials && st == PF_OK; ++t) st = launch_step(m, m->parity, red, scratch, false, tb);
-            (void)hipEventRecord(b, m->stream);
-            (void)hipEventSynchronize(b);
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, a, b);
-            ms /= tb;
-            if (st == PF_OK && ms < best) {
-                best = ms;
-                best_c = c;
-                best_tb = tb;
+    for (int tb : tbs) {
+        for (int rpw : {2, 1}) {
+            if (d.ndim == 2 ? rpw != 2 : !rows_per_wave_available(m->L, tb, rpw)) continue;
+            for (int32_t c : cand) {
+                m->tb = tb;
+                m->rpw_req = d.ndim == 3 ? rpw : 0;
+                st = set_chunk(m, c);
+                if (st != PF_OK || m->family != 0 || m->tb != tb) break;
+                st = launch_step(m, m->parity, red, scratch, false, tb);
+                if (st != PF_OK) break;
+                (void)hipEventRecord(a, m->stream);
+                for (int t = 0; t < trials && st == PF_OK; ++t)
+                    st = launch_step(m, m->parity, red, scratch, false, tb);
+                (void)hipEventRecord(b, m->stream);
+                (void)hipEventSynchronize(b);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, a, b);
+                ms /= tb;
+                if (st == PF_OK && ms < best) {
+                    best = ms;
+                    bestc = {c, tb, m->rpw_req};
+                }
             }
+            if (st != PF_OK) break;
         }
+        if (st != PF_OK) break;
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (scratch) (void)hipFree(scratch);
     if (st != PF_OK) return st;
-    m->tb = best_tb;
-    st = set_chunk(m, best_c);
+    m->tb = bestc.tb;
+    m->rpw_req = bestc.rpw;
+    st = set_chunk(m, bestc.chunk);
     if (st != PF_OK) return st;
     m->launches = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[tune_key(d)] = {best_c, best_tb};
+        g_tune_cache[tune_key(d)] = bestc;
     }
     return PF_OK;
 }
@@ -1085,6 +1107,26 @@ PF_API pf_status pf_set_time_block(pf_model *m, int32_t tb)
 }
 
 PF_API int32_t pf_get_time_block(const pf_model *m) { return m ? reinterpret_cast<const Model *>(m)->tb : -1; }
+
+PF_API pf_status pf_set_tile_rows(pf_model *m, int32_t rows)
+{
+    if (!m || rows < 0 || rows > 2) return fail(PF_ERR_ARG, "tile rows must be 0, 1 or 2");
+    Model *mm = M(m);
+    PF_HIP(hipStreamSynchronize(mm->stream), "hipStreamSynchronize");
+    if (mm->desc.ndim != 3 || mm->family != 0)
+        return fail(PF_ERR_UNSUPPORTED, "tile rows apply to the fused 3D kernels");
+    if (rows && !rows_per_wave_available(mm->L, mm->tb, rows))
+        return fail(PF_ERR_UNSUPPORTED, "one row per wave is built for FP64 AC (order <= 4) and GS (order 2)");
+    mm->rpw_req = rows;
+    return set_chunk(mm, mm->clen);
+}
+
+PF_API int32_t pf_get_tile_rows(const pf_model *m)
+{
+    if (!m) return -1;
+    const Model *mm = reinterpret_cast<const Model *>(m);
+    return (mm->desc.ndim == 3 && mm->family == 0) ? mm->rpw : 0;
+}
 
 PF_API pf_status pf_autotune(pf_model *m, int32_t trials)
 {

@@ -392,3 +392,63 @@ def test_two_step_blocking_3d(kind, prec):
     ref = oracle_run(kind, shape, ndim, order, params, dt, 23, 51)[1]
     for g, r in zip(outs[1], ref):
         assert float(np.max(np.abs(g - r))) <= TOL[prec]
+
+
+@pytest.mark.parametrize("tb", [1, 2])
+@pytest.mark.parametrize("kind,order", [(P.PF_AC, 2), (P.PF_AC, 4), (P.PF_GS, 2)])
+def test_3d_tile_rows_bitwise(kind, order, tb):
+    """FP64 3D Allen-Cahn / Gray-Scott: one and two tile rows per wave give
+    bitwise equal fields (ragged strips, y tiles and z chunks, an odd step
+    count, fused reductions) that match the oracle."""
+    if tb == 2 and order != 2:
+        pytest.skip("two-step 3D kernels are built for order 2")
+    shape, ndim, steps = (23, 45, 150), 3, 17
+    params = BASE[kind][0]
+    dt = dt_for(kind, ndim, order, params)
+    f0 = fields_for(kind, shape, 61)
+    n = (shape[2], shape[1], shape[0])
+    outs, hist = [], []
+    for rows in (1, 2):
+        d = P.make_desc(kind, n, dt=dt, order=order, params=params, flags=P.PF_REDUCE_EACH_STEP)
+        m = P.Model(d)
+        m.set_tile(8)
+        m.set_time_block(tb)
+        m.set_tile_rows(rows)
+        assert m.tile_rows() == rows
+        for f, a in enumerate(f0):
+            m.set_field(f, a)
+        m.step(steps)
+        outs.append([m.get_field(f) for f in range(len(f0))])
+        hist.append(sum(m.reduce_history(P.PF_RED_MASS0, steps)))
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+    assert np.max(np.abs(hist[0] - hist[1])) <= 1e-13 * max(1.0, float(np.max(np.abs(hist[0]))))
+    ref = oracle_run(kind, shape, ndim, order, params, dt, steps, 61)[1]
+    for g, r in zip(outs[0], ref):
+        assert float(np.max(np.abs(g - r))) <= TOL[P.PF_FP64]
+
+
+def test_tile_rows_defaults_and_refusals():
+    gs = P.Model(P.make_desc(P.PF_GS, (40, 30, 20), dt=0.3, order=2))
+    assert gs.tile_rows() == 1            # FP64 Gray-Scott default
+    gs.set_tile_rows(2)
+    assert gs.tile_rows() == 2
+    gs.set_tile_rows(0)
+    assert gs.tile_rows() == 1
+    with pytest.raises(P.PfError) as e:
+        gs.set_tile_rows(3)
+    assert e.value.status == P.PF_ERR_ARG
+    ch = P.Model(P.make_desc(P.PF_CH, (40, 30, 20), dt=0.001, order=2))
+    assert ch.tile_rows() == 2
+    with pytest.raises(P.PfError) as e:
+        ch.set_tile_rows(1)
+    assert e.value.status == P.PF_ERR_UNSUPPORTED
+    ac32 = P.Model(P.make_desc(P.PF_AC, (40, 30, 20), dt=0.01, order=2, precision=P.PF_FP32))
+    assert ac32.tile_rows() == 2
+    with pytest.raises(P.PfError):
+        ac32.set_tile_rows(1)
+    flat = P.Model(P.make_desc(P.PF_AC, (40, 30), dt=0.01, order=2))
+    assert flat.tile_rows() == 0
+    with pytest.raises(P.PfError) as e:
+        flat.set_tile_rows(2)
+    assert e.value.status == P.PF_ERR_UNSUPPORTED
