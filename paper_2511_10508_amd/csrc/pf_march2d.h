@@ -157,6 +157,16 @@ __device__ __forceinline__ void stage_chupd(const StepArgs<T> &a, const T (&m)[K
     }
 }
 
+// Prefetch depth PD of the input rows: the loads for row t + PD are issued
+// while row t is processed.  K rows ahead, except for the FP64 two-step
+// Cahn-Hilliard kernel with fused reductions, where one row ahead frees the
+// registers for a third wave per SIMD and measures faster.
+template <typename T, int KIND, int R, int TB, bool RED>
+constexpr int prefetch_depth2d()
+{
+    return (std::is_same<T, double>::value && KIND == kCH && TB == 2 && RED) ? 1 : 2 * R + 1;
+}
+
 template <typename T, int KIND, int R, bool RED, bool FAST, int TB>
 __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t xb, int64_t y0,
                                         int64_t y1, int lane, int64_t pslot)
@@ -178,18 +188,19 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
     T *out[2] = {a.buf[0][par ^ 1], a.buf[NF - 1][par ^ 1]};
 
     T ring[NF][K][V];                                    // state n (loaded)
-    T pre[NF][K][V];                                     // prefetched rows
+    constexpr int PD = prefetch_depth2d<T, KIND, R, TB, RED>();
+    T pre[NF][PD][V];                                    // rows t+1 .. t+PD
     T r1[TB == 2 ? NF : 1][K][V];                        // state n+1 (TB = 2)
     T m0[KIND == kCH ? K : 1][V];                        // mu of state n
     T m1[(KIND == kCH && TB == 2) ? K : 1][V];           // mu of state n+1
     RedState red[TB];
 
     const int64_t tb0 = y0 - H, tend = y1 + H;
-    // The first K rows are loaded unconditionally (a row past the march is a
+    // The first PD rows are loaded unconditionally (a row past the march is a
     // valid wrapped row, read and not used), so that every load of the
     // unguarded main loop below has a fixed number of loads issued after it
     // and the compiler can wait for it alone instead of draining all of them.
-    static_for<0, K>([&](auto phc) {
+    static_for<0, PD>([&](auto phc) {
         constexpr int ph = decltype(phc)::value;
         const int64_t off = wrap_any(tb0 + ph, ny) * pitch;
 #pragma unroll
@@ -207,11 +218,11 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int v = 0; v < V; ++v) ring[f][ph][v] = pre[f][ph][v];
-            if (!G || t + K < tend) {
-                const int64_t off = wrap_any(t + K, ny) * pitch;
+                for (int v = 0; v < V; ++v) ring[f][ph][v] = pre[f][ph % PD][v];
+            if (!G || t + PD < tend) {
+                const int64_t off = wrap_any(t + PD, ny) * pitch;
 #pragma unroll
-                for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
+                for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph % PD]);
             }
             if constexpr (KIND != kCH) {
                 constexpr int s1 = Slot<K, R>::template at<ph>;
@@ -279,7 +290,7 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
         }
     };
     int64_t tb = tb0;
-    for (; tb + 2 * K <= tend; tb += K)
+    for (; tb + K + PD <= tend; tb += K)
         static_for<0, K>([&](auto phc) { phase(phc, std::false_type{}, tb); });
     for (; tb < tend; tb += K)
         static_for<0, K>([&](auto phc) { phase(phc, std::true_type{}, tb); });

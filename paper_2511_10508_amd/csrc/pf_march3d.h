@@ -185,12 +185,13 @@ __device__ __forceinline__ void stage3_chupd(const StepArgs<T> &a, const T (&m)[
 
 // Prefetch depth PD of the input planes: K planes ahead, or one plane where
 // the K-deep prefetch ring would not fit the 128 registers a lane of a
-// 16-wave workgroup can hold (wider stencils, where a plane's work is also
-// long enough to hide one plane's load latency).
+// 16-wave workgroup can hold (wider stencils, and two-step sweeps with fused
+// reductions), where a plane's work is also long enough to hide one plane's
+// load latency.
 template <typename T, int KIND, int R, int TB, bool RED>
 constexpr int prefetch_depth()
 {
-    return R >= 2 ? 1 : 2 * R + 1;
+    return (R >= 2 || (TB == 2 && RED)) ? 1 : 2 * R + 1;
 }
 
 template <typename T, int KIND, int R, bool RED, bool FAST, int TB, int RPW>

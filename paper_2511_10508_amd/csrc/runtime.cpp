@@ -637,7 +637,10 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
         return hip_fail(e, "hipMalloc(result)");
     }
     int32_t chunk = 0;
-    if (!m->async_alloc) {  // served requests keep the default tile (batched kernels are TB = 1)
+    // served requests keep the default chunk and the batched kernels' layout
+    // (one step per launch, two tile rows per wave in 3D)
+    if (m->async_alloc) m->rpw_req = 2;
+    if (!m->async_alloc) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(*desc));
         if (it != g_tune_cache.end()) {

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -33,9 +34,9 @@ namespace {
 
 constexpr int kPersist2D = 2048;  // workgroups of a persistent 2D batched launch
 constexpr int kPersist3D = 512;   // workgroups of a persistent 3D batched launch
-constexpr int kMaxGraphs = 64;
+constexpr int kMaxGraphs = 256;  // cached executable graphs (cleared when full; PFMI_SERVER_MAX_GRAPHS)
 
-enum ReqState { QUEUED = 0, RUNNING = 1, FINISHED = 2 };
+enum ReqState { QUEUED = 0, ADMITTING = 1, RUNNING = 2, FINISHED = 3 };
 
 struct Req {
     uint64_t ticket = 0;
@@ -85,6 +86,7 @@ struct Server {
     uint64_t budget = 0, used = 0;
     int max_slots = 0;
     int spt = 64;
+    int max_graphs = kMaxGraphs;
     hipStream_t stream = nullptr, copy_stream = nullptr;
     std::chrono::steady_clock::time_point t0;
 
@@ -215,7 +217,10 @@ static hipError_t run_graph(Server *s, const std::vector<int> &cls, int set, int
     }
     auto it = s->graphs.find(key);
     if (it == s->graphs.end()) {
-        if ((int)s->graphs.size() >= kMaxGraphs) {
+        if ((int)s->graphs.size() >= s->max_graphs) {
+            // the previous tick's graph may still run: wait before destroying
+            hipError_t se = hipStreamSynchronize(s->stream);
+            if (se != hipSuccess) return se;
             for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
             s->graphs.clear();
         }
@@ -393,7 +398,10 @@ static void worker_main(Server *s)
         std::vector<Req *> admitted;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            for (Req *r : s->to_free) free_req(s, r);
+            for (Req *r : s->to_free) {
+                free_req(s, r);
+                delete r;
+            }
             s->to_free.clear();
             if (s->stop) break;
             // FIFO admission by footprint and slots
@@ -402,6 +410,7 @@ static void worker_main(Server *s)
                 if (s->used + r->footprint > s->budget) break;
                 s->queue.pop_front();
                 s->used += r->footprint;
+                r->state = ADMITTING;  // no longer cancellable as queued
                 admitted.push_back(r);
             }
             if (admitted.empty() && s->active.empty() && !pending[0] && !pending[1]) {
@@ -431,7 +440,7 @@ static void worker_main(Server *s)
             }
             r->cls = class_of(s, m);
             r->state = RUNNING;
-            s->active.push_back(r);
+            s->active.push_back(r);  // a cancel during admission takes effect at the next tick
         }
         std::vector<Req *> run;
         {
@@ -489,6 +498,7 @@ PF_API pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t m
     s->device = device;
     s->max_slots = max_slots;
     s->spt = steps_per_tick ? steps_per_tick : 64;
+    if (const char *g = std::getenv("PFMI_SERVER_MAX_GRAPHS")) s->max_graphs = std::max(1, std::atoi(g));
     s->t0 = std::chrono::steady_clock::now();
     if (hbm_budget == 0) {
         size_t fr = 0, tot = 0;
@@ -631,7 +641,7 @@ PF_API pf_status pf_server_cancel(pf_server *ss, uint64_t ticket)
         fill_result(r);
         s->unfinished--;
         s->done_cv.notify_all();
-    } else if (r->state == RUNNING) {
+    } else if (r->state == RUNNING || r->state == ADMITTING) {
         r->cancel = true;
     }
     return PF_OK;

@@ -29,6 +29,8 @@ def _mixed_requests():
         (2, 2, (1, 40, 40), 8, True, [1.0, 1.0], 0.005),   # r = 4
         (2, 3, (12, 12, 12), 8, False, [1.0, 1.0], 0.001),  # 3D CH r = 4: stepped on its own
         (3, 2, (1, 128, 128), 4, True, [0.2, 0.1, 0.04, 0.06], 0.4),
+        (1, 3, (20, 26, 70), 2, False, [1.0, 1.0], 0.05),   # FP64 3D AC / GS order 2: the
+        (3, 3, (14, 40, 66), 2, False, [0.2, 0.1, 0.04, 0.06], 0.5),  # batched tile layout
     ]
     for i, (kind, ndim, shape, order, fp32, params, dt) in enumerate(specs):
         reqs.append(dict(id=i, kind=kind, ndim=ndim, shape=shape, steps=37 + 11 * i, order=order,
@@ -186,3 +188,19 @@ def test_unstable_request_is_refused():
         srv.submit(d, P.PF_IC_GS_CUBES, 1, (4, 4, 0.01), 10)
     assert e.value.status == P.PF_ERR_UNSTABLE
     srv.close()
+
+
+def test_graph_cache_turnover_keeps_results(monkeypatch):
+    """With a one-entry graph cache every new class set destroys the cached
+    executable graphs; the server waits for the graph in flight first, and
+    the results stay bitwise those of each request stepped alone."""
+    monkeypatch.setenv("PFMI_SERVER_MAX_GRAPHS", "1")
+    reqs = _mixed_requests()
+    results, st = _serve(reqs, steps_per_tick=4)
+    assert st["captures"] > 2, st
+    for r in reqs:
+        res, fields = results[r["id"]]
+        assert res["status"] == 0 and res["steps_done"] == r["steps"]
+        alone, _ = _alone(r)
+        for a, b in zip(alone, fields):
+            assert np.array_equal(a, b), r
