@@ -309,7 +309,10 @@ typedef struct pf_result {
 /*
  * hbm_budget: bytes of device memory the server may hold for requests
  * (0 = 90 % of free memory at creation); max_slots: most requests resident
- * at once; steps_per_tick: steps per request per tick (0 = 64).
+ * at once, running or finished and not yet released (a finished request keeps
+ * its memory and slot until pf_server_release); steps_per_tick: steps per
+ * request per tick (0 = 64).  The environment variable PFMI_SERVER_MAX_GRAPHS
+ * bounds the cache of captured tick graphs (default 256).
  */
 pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t max_slots,
                            int32_t steps_per_tick, pf_server **out);
@@ -327,7 +330,7 @@ pf_status pf_server_poll(pf_server *s, pf_result *out, int32_t max, int32_t *n);
 pf_status pf_server_fetch(pf_server *s, uint64_t ticket, int32_t field, double *host,
                           int64_t count);
 
-/* Free a finished request's device memory. */
+/* Free a finished request's device memory and slot. */
 pf_status pf_server_release(pf_server *s, uint64_t ticket);
 
 /* Cancel a queued or running request (it finishes with PF_ERR_STATE). */

@@ -332,6 +332,31 @@ __device__ __forceinline__ void store_row(T *__restrict__ row, int64_t xl, const
 }
 
 // ---------------------------------------------------------------------------
+// Row end of a lane's reductions: s0, s1 are the row's masked sums (mass and
+// energy density, or the two fields' sums when TWO); value(f, v) returns the
+// reduced value of field f at element v.  Non-finite values are counted only
+// when a row sum is not finite, which is exact: a NaN or infinity among the
+// addends always makes the sum non-finite, and a sum of finite values that
+// overflows is recounted to zero.
+template <int V, bool TWO, typename F>
+__device__ __forceinline__ void red_row_end(RedState &red, const OutMask<V> &om, double s0,
+                                            double s1, F &&value)
+{
+    if (!(finite_val(s0) && finite_val(s1))) {
+        double bad = 0.0;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (om.ov[v]) {
+                bad += finite_val(value(0, v)) ? 0.0 : 1.0;
+                if constexpr (TWO) bad += finite_val(value(1, v)) ? 0.0 : 1.0;
+            }
+        red.bad += bad;
+    }
+    acc_add(red.q0, s0);
+    acc_add(red.q1, s1);
+}
+
+// ---------------------------------------------------------------------------
 // Ring slot holding the row (plane) D iterations behind phase PH of a K-long
 // ring that is written at slot PH on phase PH.
 template <int K, int D>

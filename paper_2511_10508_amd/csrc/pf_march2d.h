@@ -57,7 +57,7 @@ __device__ __forceinline__ void stage_acgs(const StepArgs<T> &a,
     T e[NF][V + 2 * R];
 #pragma unroll
     for (int f = 0; f < NF; ++f) gather_x<T, V, R>(rg[f][CS], e[f]);
-    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+    double s0 = 0.0, s1 = 0.0;  // the row's masked reduction sums
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         T Sf[NF][R];
@@ -72,33 +72,28 @@ __device__ __forceinline__ void stage_acgs(const StepArgs<T> &a,
                             res[NF - 1][v]);
         }
         if constexpr (RED) {
-            if (red_row && om.ov[v]) {
+            if (om.ov[v]) {
                 const double x = (double)u0;
-                rs0 += x;
-                rbad += finite_val(x) ? 0.0 : 1.0;
+                s0 += x;
                 if constexpr (KIND == kAC) {
                     if constexpr (std::is_same<T, double>::value) {
-                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 4.0);
+                        s1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 4.0);
                     } else {
                         double S64[R];
                         pairs2d64<T, V, R, K, CS>(rg[0], e[0], v, S64);
-                        rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                        s1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
                     }
                 } else {
-                    const double y = (double)rg[NF - 1][CS][v];
-                    rs1 += y;
-                    rbad += finite_val(y) ? 0.0 : 1.0;
+                    s1 += (double)rg[NF - 1][CS][v];
                 }
             }
         }
     }
-    if constexpr (RED) {
-        if (red_row) {
-            acc_add(red.q0, rs0);
-            acc_add(red.q1, rs1);
-            red.bad += rbad;
-        }
-    }
+    if constexpr (RED)
+        if (red_row)
+            red_row_end<V, KIND == kGS>(red, om, s0, s1, [&](int f, int v) {
+                return (double)rg[f == 0 ? 0 : NF - 1][CS][v];
+            });
 }
 
 // CH chemical potential of the centre row CS of the concentration ring c.
@@ -110,7 +105,7 @@ __device__ __forceinline__ void stage_mu(const StepArgs<T> &a, const T (&c)[K][V
     constexpr int V = Vec<T>::V;
     T e[V + 2 * R];
     gather_x<T, V, R>(c[CS], e);
-    double rs0 = 0.0, rs1 = 0.0, rbad = 0.0;
+    double s0 = 0.0, s1 = 0.0;  // the row's masked reduction sums
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         T Sc[R];
@@ -118,27 +113,22 @@ __device__ __forceinline__ void stage_mu(const StepArgs<T> &a, const T (&c)[K][V
         const T c0 = c[CS][v];
         mu[v] = ch_mu<T, R>(a, c0, Sc, c0 * T(4));
         if constexpr (RED) {
-            if (red_row && om.ov[v]) {
+            if (om.ov[v]) {
                 const double x = (double)c0;
-                rs0 += x;
+                s0 += x;
                 if constexpr (std::is_same<T, double>::value) {
-                    rs1 += energy_from_mu(a.c2, x, mu[v]);
+                    s1 += energy_from_mu(a.c2, x, mu[v]);
                 } else {
                     double S64[R];
                     pairs2d64<T, V, R, K, CS>(c, e, v, S64);
-                    rs1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                    s1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
                 }
-                rbad += finite_val(x) ? 0.0 : 1.0;
             }
         }
     }
-    if constexpr (RED) {
-        if (red_row) {
-            acc_add(red.q0, rs0);
-            acc_add(red.q1, rs1);
-            red.bad += rbad;
-        }
-    }
+    if constexpr (RED)
+        if (red_row)
+            red_row_end<V, false>(red, om, s0, s1, [&](int, int v) { return (double)c[CS][v]; });
 }
 
 // CH update of the centre row CS: c' = c + dt L mu.

@@ -6,8 +6,11 @@
 //      conditions are enqueued in stream order, no host synchronisation);
 //   2. groups the running requests by kernel class (model, dimension,
 //      stencil radius, precision) and uploads one work-item table per class;
-//   3. replays a captured HIP graph of `steps_per_tick` persistent batched
-//      launches per class (captured once per class set and table buffer);
+//   3. launches, per class and on the class's own stream, a captured HIP
+//      graph of `steps_per_tick` chained persistent batched launches
+//      (captured once per class, table buffer and grid bucket); the class
+//      streams fork from and join back into the scheduler stream, so the
+//      classes run concurrently;
 //   4. enqueues the final reductions of requests that finish in this tick.
 // Ticks are pipelined two deep: tick i+1 is enqueued before the host waits
 // for tick i, and requests that finished in tick i are retired (results
@@ -53,7 +56,8 @@ struct Req {
     uint64_t footprint = 0;
     int64_t finish_tick = -1;
     int cls = -1;            // batched class, -1 = stepped on its own
-    double2 *pinned = nullptr;  // final reductions (host-pinned, kNumQ pairs)
+    double2 *pinned = nullptr;  // final reductions (slot of the server's pinned pool)
+    int slot = -1;
     pf_result res{};
 };
 
@@ -101,9 +105,12 @@ struct Server {
     bool stop = false;
     std::thread worker;
 
+    double2 *pinned_pool = nullptr;  // max_slots x kNumQ result pairs (host-pinned)
+    std::vector<int> free_slots;
+
     std::map<ClassKey, int> class_index;
     std::vector<ClassTables> classes;
-    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;  // (class, set, steps, grid) -> graph
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr;
     int64_t tick = 0, launches = 0, captures = 0, replays = 0;
@@ -145,8 +152,9 @@ static void free_req(Server *s, Req *r)
         model_release_async(r->m);
         r->m = nullptr;
     }
-    if (r->pinned) {
-        (void)hipHostFree(r->pinned);
+    if (r->slot >= 0) {
+        s->free_slots.push_back(r->slot);
+        r->slot = -1;
         r->pinned = nullptr;
     }
     s->used -= std::min(s->used, r->footprint);
@@ -203,54 +211,72 @@ static hipError_t launch_class(Server *s, int c, int set, int S, hipStream_t st)
     return hipSuccess;
 }
 
-// One graph per (buffer set, steps, class set with grid buckets).  Each class
-// is a branch of S chained launches on its own stream, forked from and joined
-// back into the server stream, so different classes run concurrently.
-static hipError_t run_graph(Server *s, const std::vector<int> &cls, int set, int S)
+// The graph of S chained batched launches of class c for table buffer `set`
+// at this tick's grid bucket, captured on the class stream the first time.
+static std::vector<int64_t> graph_key(Server *s, int c, int set, int S)
 {
-    std::vector<int64_t> key;
-    key.push_back(set);
-    key.push_back(S);
-    for (int c : cls) {
-        key.push_back(c);
-        key.push_back(s->classes[c].blocks[set]);
-    }
+    return {c, set, S, s->classes[c].blocks[set]};
+}
+
+static hipError_t class_graph(Server *s, int c, int set, int S, hipGraphExec_t *out)
+{
+    ClassTables &t = s->classes[c];
+    const std::vector<int64_t> key = graph_key(s, c, set, S);
     auto it = s->graphs.find(key);
-    if (it == s->graphs.end()) {
-        if ((int)s->graphs.size() >= s->max_graphs) {
-            // the previous tick's graph may still run: wait before destroying
-            hipError_t se = hipStreamSynchronize(s->stream);
-            if (se != hipSuccess) return se;
-            for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
-            s->graphs.clear();
-        }
-        hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return e;
-        hipError_t le = hipEventRecord(s->fork, s->stream);
-        for (int c : cls) {
-            ClassTables &t = s->classes[c];
-            if (le == hipSuccess) le = hipStreamWaitEvent(t.stream, s->fork, 0);
-            if (le == hipSuccess) le = launch_class(s, c, set, S, t.stream);
-            if (le == hipSuccess) le = hipEventRecord(t.join, t.stream);
-            if (le == hipSuccess) le = hipStreamWaitEvent(s->stream, t.join, 0);
-        }
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(s->stream, &g);
-        if (le != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return le;
-        }
-        if (e != hipSuccess) return e;
-        hipGraphExec_t ex = nullptr;
-        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return e;
-        it = s->graphs.emplace(key, ex).first;
-        s->captures++;
-    } else {
+    if (it != s->graphs.end()) {
         s->replays++;
+        *out = it->second;
+        return hipSuccess;
     }
-    return hipGraphLaunch(it->second, s->stream);
+    hipError_t e = hipStreamBeginCapture(t.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t le = launch_class(s, c, set, S, t.stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(t.stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    s->graphs.emplace(key, ex);
+    s->captures++;
+    *out = ex;
+    return hipSuccess;
+}
+
+// Runs the classes' graphs concurrently: each class stream waits for the
+// scheduler stream (tables uploaded), launches its graph and is joined back.
+static hipError_t run_classes(Server *s, const std::vector<int> &cls, int set, int S)
+{
+    int missing = 0;
+    for (int c : cls) missing += s->graphs.count(graph_key(s, c, set, S)) ? 0 : 1;
+    if (missing && (int)s->graphs.size() + missing > s->max_graphs) {
+        // the cache is full: clear it before this tick takes any graph from it.
+        // Graphs of the previous tick may still run (they are joined into the
+        // scheduler stream): wait for them before destroying any.
+        hipError_t se = hipStreamSynchronize(s->stream);
+        if (se != hipSuccess) return se;
+        for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
+        s->graphs.clear();
+    }
+    std::vector<hipGraphExec_t> ex(cls.size());
+    for (size_t i = 0; i < cls.size(); ++i) {
+        hipError_t e = class_graph(s, cls[i], set, S, &ex[i]);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(s->fork, s->stream);
+    for (size_t i = 0; i < cls.size() && e == hipSuccess; ++i) {
+        ClassTables &t = s->classes[cls[i]];
+        e = hipStreamWaitEvent(t.stream, s->fork, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(ex[i], t.stream);
+        if (e == hipSuccess) e = hipEventRecord(t.join, t.stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, t.join, 0);
+    }
+    return e;
 }
 
 template <typename T>
@@ -319,7 +345,7 @@ static bool enqueue_tick(Server *s, std::vector<Req *> &run, int set)
         }
     }
     if (!cls.empty()) {
-        hipError_t e = run_graph(s, cls, set, S);
+        hipError_t e = run_classes(s, cls, set, S);
         if (e != hipSuccess) {
             s->fatal = std::string("batched launch: ") + hipGetErrorString(e);
             return false;
@@ -405,11 +431,16 @@ static void worker_main(Server *s)
             s->to_free.clear();
             if (s->stop) break;
             // FIFO admission by footprint and slots
-            while (!s->queue.empty() && (int)s->active.size() + (int)admitted.size() < s->max_slots) {
+            // (finished requests hold their result slot until released)
+            while (!s->queue.empty() && (int)s->active.size() + (int)admitted.size() < s->max_slots &&
+                   !s->free_slots.empty()) {
                 Req *r = s->queue.front();
                 if (s->used + r->footprint > s->budget) break;
                 s->queue.pop_front();
                 s->used += r->footprint;
+                r->slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                r->pinned = s->pinned_pool + (size_t)r->slot * kNumQ;
                 r->state = ADMITTING;  // no longer cancellable as queued
                 admitted.push_back(r);
             }
@@ -423,9 +454,6 @@ static void worker_main(Server *s)
             pf_status st = model_create(&r->desc, s->stream, nullptr, 0, &m, true);
             if (st == PF_OK)
                 st = init_fields(m, r->ic, r->seed, r->icp.data(), (int32_t)r->icp.size());
-            if (st == PF_OK && hipHostMalloc((void **)&r->pinned, sizeof(double2) * kNumQ,
-                                             hipHostMallocDefault) != hipSuccess)
-                st = PF_ERR_NOMEM;
             std::lock_guard<std::mutex> lk(s->mu);
             r->m = m;
             r->t_admit = s->now();
@@ -515,10 +543,14 @@ PF_API pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t m
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&s->pinned_pool, sizeof(double2) * kNumQ * (size_t)max_slots,
+                          hipHostMallocDefault);
     if (e != hipSuccess) {
         delete s;
-        return hip_fail(e, "server stream/event");
+        return hip_fail(e, "server stream/event/pinned pool");
     }
+    for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->worker = std::thread(worker_main, s);
     *out = reinterpret_cast<pf_server *>(s);
     return PF_OK;
@@ -700,6 +732,7 @@ PF_API void pf_server_destroy(pf_server *ss)
         (void)hipStreamDestroy(t.stream);
         (void)hipEventDestroy(t.join);
     }
+    (void)hipHostFree(s->pinned_pool);
     (void)hipEventDestroy(s->fork);
     (void)hipEventDestroy(s->ev[0]);
     (void)hipEventDestroy(s->ev[1]);

@@ -106,8 +106,21 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else float("nan")
 
 
-def run_batched(trace, max_slots=256, steps_per_tick=64, budget=0):
+def _progress(log, every=30.0):
+    """Calls log(msg) at most every `every` seconds."""
+    last = [time.perf_counter()]
+
+    def tick(msg):
+        now = time.perf_counter()
+        if log and now - last[0] >= every:
+            last[0] = now
+            log(msg)
+    return tick
+
+
+def run_batched(trace, max_slots=256, steps_per_tick=64, budget=0, log=None):
     srv = Server(hbm_budget=budget, max_slots=max_slots, steps_per_tick=steps_per_tick)
+    progress = _progress(log)
     specs = [request_spec(r) for r in trace]
     work = sum(s[3] * r["steps"] for s, r in zip(specs, trace))
     t_arr = {}
@@ -133,6 +146,7 @@ def run_batched(trace, max_slots=256, steps_per_tick=64, budget=0):
             while res["ticket"] not in t_arr:
                 time.sleep(0.0005)
             lat.append(now - t_arr[res["ticket"]])
+        progress("  batched: %d of %d requests done" % (len(done), len(trace)))
         time.sleep(0.0005)
     th.join()
     makespan = time.perf_counter() - start
@@ -143,12 +157,14 @@ def run_batched(trace, max_slots=256, steps_per_tick=64, budget=0):
                 su_per_s=work / makespan, failed=bad, **st)
 
 
-def run_serial(trace):
+def run_serial(trace, log=None):
     specs = [request_spec(r) for r in trace]
     work = sum(s[3] * r["steps"] for s, r in zip(specs, trace))
     lat = []
+    progress = _progress(log)
     start = time.perf_counter()
     for r, (d, ic, icp, _) in zip(trace, specs):
+        progress("  serial: %d of %d requests done" % (len(lat), len(trace)))
         wait = r["arrival"] - (time.perf_counter() - start)
         if wait > 0:
             time.sleep(wait)
@@ -169,15 +185,15 @@ def compare(nreq, seed=505, load=0.8, steps_per_tick=64, log=None):
     p99 of completion minus arrival."""
     log = log or (lambda m: None)
     burst = synth.serving_trace(nreq, seed=seed, rate=None)
-    cap_b = run_batched(burst, steps_per_tick=steps_per_tick)
+    cap_b = run_batched(burst, steps_per_tick=steps_per_tick, log=log)
     log("serving batched capacity: %.2f s" % cap_b["makespan_s"])
-    cap_s = run_serial(burst)
+    cap_s = run_serial(burst, log=log)
     log("serving serial capacity: %.2f s" % cap_s["makespan_s"])
     rate = load * nreq / cap_b["makespan_s"]
     trace = synth.serving_trace(nreq, seed=seed, rate=rate)
-    lat_b = run_batched(trace, steps_per_tick=steps_per_tick)
+    lat_b = run_batched(trace, steps_per_tick=steps_per_tick, log=log)
     log("serving batched at %.1f req/s: %.2f s" % (rate, lat_b["makespan_s"]))
-    lat_s = run_serial(trace)
+    lat_s = run_serial(trace, log=log)
     log("serving serial at %.1f req/s: %.2f s" % (rate, lat_s["makespan_s"]))
     return dict(requests=nreq, site_updates=sum(request_spec(r)[3] * r["steps"] for r in burst),
                 batched_su_per_s=cap_b["su_per_s"], serial_su_per_s=cap_s["su_per_s"],

@@ -452,3 +452,34 @@ def test_tile_rows_defaults_and_refusals():
     with pytest.raises(P.PfError) as e:
         flat.set_tile_rows(2)
     assert e.value.status == P.PF_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("ndim,shape", [(2, (1, 70, 300)), (3, (20, 37, 150))])
+def test_fused_reductions_count_nonfinite_values(kind, ndim, shape, prec):
+    """The fused per-step reductions count NaN and infinities exactly (in both
+    fields of Gray-Scott), including at strip edges and periodic seams, and do
+    not count a finite value whose energy density overflows."""
+    f0 = fields_for(kind, shape, 71)
+    rng = np.random.default_rng(5)
+    sites = [(0, 0, 0), (shape[0] - 1, shape[1] - 1, shape[2] - 1), (0, 5, 63), (0, 6, 64)]
+    sites += [tuple(int(rng.integers(0, s)) for s in shape) for _ in range(8)]
+    bad = 0
+    for i, (z, y, x) in enumerate(sites):
+        f = f0[i % len(f0)]
+        if np.isfinite(f[z, y, x]):
+            f[z, y, x] = (np.nan, np.inf, -np.inf)[i % 3]
+            bad += 1
+    if kind != P.PF_GS and prec == P.PF_FP64 and np.isfinite(f0[0][0, 1, 1]):
+        f0[0][0, 1, 1] = 1e100          # x^4 overflows: energy is infinite, x is not
+    n = (shape[2], shape[1]) if ndim == 2 else (shape[2], shape[1], shape[0])
+    params = BASE[kind][0]
+    d = P.make_desc(kind, n, dt=dt_for(kind, ndim, 2, params), order=2, precision=prec,
+                    params=params, flags=P.PF_REDUCE_EACH_STEP)
+    m = P.Model(d)
+    for i, a in enumerate(f0):
+        m.set_field(i, a)
+    m.step(1)
+    hi, _ = m.reduce_history(P.PF_RED_NONFINITE, 1)
+    assert hi[0] == bad

@@ -75,3 +75,46 @@ def test_precision_study_512_mass_and_fp32_gap(order):
           "FP32 %.3e" % (order, gap, np.abs(np.diff(ma)).max(), np.abs(np.diff(mb)).max()))
     assert gap <= 1e-4
     assert np.abs(np.diff(ma)).max() <= 512 ** 3 * 2.3e-16
+
+
+def _golden(order):
+    """Oracle state of the 512^3 precision-study workload after 100 steps at
+    sampled sites (tests/golden/make_ch512_golden.py)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ch3d_512_p%d_100.txt" % order)
+    vals, sites = {}, []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        if ":" in line:
+            k, v = line.split(":")
+            vals[k.strip()] = float(v)
+        else:
+            z, y, x, val = line.split()
+            sites.append((int(z), int(y), int(x), float(val)))
+    return vals, sites
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_precision_study_512_against_the_oracle(order):
+    """512^3, the study's own grid: FP64 and FP32 storage after 100 steps
+    against the FP64 oracle at 2056 sampled sites (corners included), and the
+    fused mass reductions against the oracle's exact sums."""
+    g, sites = _golden(order)
+    z, y, x, ref = (np.array(c) for c in zip(*sites))
+    n = (512, 512, 512)
+    for prec, name in ((P.PF_FP64, "FP64"), (P.PF_FP32, "FP32")):
+        out, mass = _gpu(n, order, prec, [100])
+        err = float(np.max(np.abs(out[100][z, y, x] - ref)))
+        dm0 = abs(mass[0] - g["mass0"])
+        dm = abs(mass[-1] - g["mass"])
+        print("\n3D CH 512^3 order %d %s: max|err| @100 = %.3e at sampled sites; "
+              "|M_0 - exact| = %.2e, |M_100 - oracle exact| = %.2e" % (order, name, err, dm0, dm))
+        if prec == P.PF_FP64:
+            assert err <= 1e-12
+            assert dm0 <= 1e-15 * 512 ** 3 * 0.05
+            assert dm <= 1e-8
+        else:
+            assert err <= 1e-4
+            assert dm0 <= 512 ** 3 * 0.05 * 6e-8   # FP32 rounding of the initial state
+            assert dm <= 1e-2
