@@ -32,6 +32,12 @@ __device__ __forceinline__ int64_t wrap_any(int64_t i, int64_t n)
     int64_t m = i % n;
     return m < 0 ? m + n : m;
 }
+__device__ __forceinline__ int32_t wrap32(int32_t i, int32_t n)
+{
+    if (i >= 0 && i < n) return i;
+    int32_t m = i % n;
+    return m < 0 ? m + n : m;
+}
 
 // 16-byte vector access of V consecutive values.
 __device__ __forceinline__ void vload(const double *p, double (&o)[2])
@@ -215,14 +221,15 @@ __device__ __forceinline__ int32_t xcd_item(int32_t b, int32_t nwg)
 
 // Whole-wave lane moves by DPP (a VALU move, no LDS round trip):
 // wave_shl:1 gives lane i the value of lane i + 1, wave_shr:1 that of lane
-// i - 1; lanes without a source receive 0 (they are halo lanes).
+// i - 1; lanes without a source receive 0 (bound control: they are halo
+// lanes), so the move needs no initialised destination.
 __device__ __forceinline__ int dpp_from_next(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int dpp_from_prev(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
 }
 
 // Value of lane (lane + D), D != 0, by |D| single-lane moves.

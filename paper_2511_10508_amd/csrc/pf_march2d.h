@@ -158,12 +158,13 @@ constexpr int prefetch_depth2d()
 }
 
 template <typename T, int KIND, int R, bool RED, bool FAST, int TB>
-__device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t xb, int64_t y0,
-                                        int64_t y1, int lane, int64_t pslot)
+__device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t xb, int32_t y0,
+                                        int32_t y1, int lane, int64_t pslot)
 {
     using S = Shape<T, KIND, R, TB>;
     constexpr int V = S::V, H = S::H, HV = S::HV, K = S::K, NF = S::NF;
-    const int64_t nx = a.nx, ny = a.ny, pitch = a.pitch;
+    const int64_t nx = a.nx, pitch = a.pitch;
+    const int32_t ny = (int32_t)a.ny;  // rows are 32-bit: scalar compares and modulo
     const int64_t xl = xb + lane * V;
     const int pl = lane * V;
     OutMask<V> om;
@@ -185,44 +186,44 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
     T m1[(KIND == kCH && TB == 2) ? K : 1][V];           // mu of state n+1
     RedState red[TB];
 
-    const int64_t tb0 = y0 - H, tend = y1 + H;
+    const int32_t tb0 = y0 - H, tend = y1 + H;
     // The first PD rows are loaded unconditionally (a row past the march is a
     // valid wrapped row, read and not used), so that every load of the
     // unguarded main loop below has a fixed number of loads issued after it
     // and the compiler can wait for it alone instead of draining all of them.
     static_for<0, PD>([&](auto phc) {
         constexpr int ph = decltype(phc)::value;
-        const int64_t off = wrap_any(tb0 + ph, ny) * pitch;
+        const int64_t off = (int64_t)wrap32(tb0 + ph, ny) * pitch;
 #pragma unroll
         for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
     });
 
     // One row t of the march at ring phase ph; G guards the rows and the
     // prefetch against the end of the march (the tail only).
-    auto phase = [&](auto phc, auto gc, int64_t tb) {
+    auto phase = [&](auto phc, auto gc, int32_t tb) {
         constexpr int ph = decltype(phc)::value;
         constexpr bool G = decltype(gc)::value;
-        const int64_t t = tb + ph;
+        const int32_t t = tb + ph;
         if (!G || t < tend) {
-            const int64_t age = t - tb0;  // a stage of depth k is valid once age >= 2 k r
+            const int32_t age = t - tb0;  // a stage of depth k is valid once age >= 2 k r
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
                 for (int v = 0; v < V; ++v) ring[f][ph][v] = pre[f][ph % PD][v];
             if (!G || t + PD < tend) {
-                const int64_t off = wrap_any(t + PD, ny) * pitch;
+                const int64_t off = (int64_t)wrap32(t + PD, ny) * pitch;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph % PD]);
             }
             if constexpr (KIND != kCH) {
                 constexpr int s1 = Slot<K, R>::template at<ph>;
                 if (age >= 2 * R) {
-                    const int64_t row = t - R;
+                    const int32_t row = t - R;
                     T res[NF][V];
                     stage_acgs<T, KIND, R, K, s1, RED>(a, ring, res, om, row >= y0 && row < y1,
                                                        red[0]);
                     if constexpr (TB == 1) {
-                        const int64_t ooff = wrap_any(row, ny) * pitch;
+                        const int64_t ooff = (int64_t)wrap32(row, ny) * pitch;
 #pragma unroll
                         for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
                     } else {
@@ -235,11 +236,11 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
                 if constexpr (TB == 2) {
                     constexpr int s2 = Slot<K, 2 * R>::template at<ph>;
                     if (age >= 4 * R) {
-                        const int64_t row = t - 2 * R;
+                        const int32_t row = t - 2 * R;
                         T res[NF][V];
                         stage_acgs<T, KIND, R, K, s2, RED>(a, r1, res, om, row >= y0 && row < y1,
                                                            red[TB - 1]);
-                        const int64_t ooff = wrap_any(row, ny) * pitch;
+                        const int64_t ooff = (int64_t)wrap32(row, ny) * pitch;
 #pragma unroll
                         for (int f = 0; f < NF; ++f) store_row<T, V>(out[f] + ooff, xl, om, res[f]);
                     }
@@ -248,7 +249,7 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
                 constexpr int s1 = Slot<K, R>::template at<ph>;
                 constexpr int s2 = Slot<K, 2 * R>::template at<ph>;
                 if (age >= 2 * R) {
-                    const int64_t row = t - R;
+                    const int32_t row = t - R;
                     stage_mu<T, R, K, s1, RED>(a, ring[0], m0[s1], om, row >= y0 && row < y1,
                                                red[0]);
                 }
@@ -256,7 +257,7 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
                     T res[V];
                     stage_chupd<T, R, K, s2>(a, m0, ring[0][s2], res);
                     if constexpr (TB == 1) {
-                        store_row<T, V>(out[0] + wrap_any(t - 2 * R, ny) * pitch, xl, om, res);
+                        store_row<T, V>(out[0] + (int64_t)wrap32(t - 2 * R, ny) * pitch, xl, om, res);
                     } else {
 #pragma unroll
                         for (int v = 0; v < V; ++v) r1[0][s2][v] = res[v];
@@ -266,20 +267,20 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
                     constexpr int s3 = Slot<K, 3 * R>::template at<ph>;
                     constexpr int s4 = Slot<K, 4 * R>::template at<ph>;
                     if (age >= 6 * R) {
-                        const int64_t row = t - 3 * R;
+                        const int32_t row = t - 3 * R;
                         stage_mu<T, R, K, s3, RED>(a, r1[0], m1[s3], om, row >= y0 && row < y1,
                                                    red[TB - 1]);
                     }
                     if (age >= 8 * R) {
                         T res[V];
                         stage_chupd<T, R, K, s4>(a, m1, r1[0][s4], res);
-                        store_row<T, V>(out[0] + wrap_any(t - 4 * R, ny) * pitch, xl, om, res);
+                        store_row<T, V>(out[0] + (int64_t)wrap32(t - 4 * R, ny) * pitch, xl, om, res);
                     }
                 }
             }
         }
     };
-    int64_t tb = tb0;
+    int32_t tb = tb0;
     for (; tb + K + PD <= tend; tb += K)
         static_for<0, K>([&](auto phc) { phase(phc, std::false_type{}, tb); });
     for (; tb < tend; tb += K)
@@ -298,8 +299,8 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
     const int32_t strip = item % a.strips;
     const int32_t chunk = item / a.strips;
     const int64_t xb = (int64_t)strip * a.ow - S::HV;
-    const int64_t y0 = (int64_t)chunk * a.clen;
-    const int64_t y1 = min(y0 + (int64_t)a.clen, a.ny);
+    const int32_t y0 = chunk * a.clen;
+    const int32_t y1 = min(y0 + a.clen, (int32_t)a.ny);
     if (xb >= 0 && xb + S::SW <= a.nx)
         march2d<T, KIND, R, RED, true, TB>(a, par, xb, y0, y1, lane, pslot);
     else
@@ -308,12 +309,27 @@ __device__ __forceinline__ void step2d_item(const StepArgs<T> &a, int par, int32
 
 // Single-model 2D launch of TB fused steps: reads buf[parity], writes
 // buf[parity ^ 1].
+// Waves per SIMD the register allocation must allow (1: no constraint).  The
+// FP64 two-step Cahn-Hilliard kernel with reductions lands a few registers
+// above 128; held to 128 (four waves per SIMD instead of three) it spills one
+// register pair and runs 6 % faster.  The same hint measured slower on the
+// two-step Gray-Scott kernels, so it is not applied generally.
 template <typename T, int KIND, int R, bool RED, int TB>
-__global__ void __launch_bounds__(64 * kWaves2D) k_step2d(StepArgs<T> a)
+constexpr int min_waves2d()
+{
+    return (std::is_same<T, double>::value && KIND == kCH && R == 2 && RED && TB == 2) ? 4 : 1;
+}
+
+template <typename T, int KIND, int R, bool RED, int TB>
+__global__ void __launch_bounds__(64 * kWaves2D)
+    __attribute__((amdgpu_waves_per_eu(min_waves2d<T, KIND, R, RED, TB>())))
+    k_step2d(StepArgs<T> a)
 {
     const int32_t nwg = gridDim.x;
     const int32_t wg = xcd_item(blockIdx.x, nwg);
-    const int32_t item = wg * kWaves2D + (threadIdx.x >> 6);
+    // a wave's item is uniform over its lanes: say so, so that the strip and
+    // row arithmetic of the march runs on the scalar unit
+    const int32_t item = __builtin_amdgcn_readfirstlane(wg * kWaves2D + (int)(threadIdx.x >> 6));
     if (item >= a.items) return;
     step2d_item<T, KIND, R, RED, TB>(a, a.parity, item, threadIdx.x & 63, item);
 }
@@ -327,7 +343,8 @@ __global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> 
     const int32_t n = *tb.count;
     const int32_t total = tb.item_start[n];
     const int32_t stride = gridDim.x * kWaves2D;
-    for (int32_t g = blockIdx.x * kWaves2D + (threadIdx.x >> 6); g < total; g += stride) {
+    for (int32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves2D + (int)(threadIdx.x >> 6));
+         g < total; g += stride) {
         const int i = batch_request(tb, n, g);
         if (k >= tb.steps[i]) continue;
         const StepArgs<T> &a = tb.args[i];

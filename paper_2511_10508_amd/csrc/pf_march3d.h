@@ -43,6 +43,19 @@ struct Tile3D {
     static_assert(2 * H < NR && OWMAX > 0, "halo too wide for the 3D tile");
 };
 
+// Tile row of this lane: the wave index with one row per wave (uniform over
+// the wave, which lets its row arithmetic run on the scalar unit), else
+// RPW rows per wave of LPR lanes each.
+template <int RPW, int LPR>
+__device__ __forceinline__ int tile_row()
+{
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if constexpr (RPW == 1)
+        return w;
+    else
+        return RPW * w + (int)(threadIdx.x & 63) / LPR;
+}
+
 // Pair sums at element v around centre plane slot CS of a ring, with the
 // centre row's x-neighbourhood e and the centre plane's rows in LDS L (this
 // lane's row rw, first column pl).
@@ -186,7 +199,7 @@ constexpr int prefetch_depth()
 
 template <typename T, int KIND, int R, bool RED, bool FAST, int TB, int RPW>
 __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t xb, int64_t yrow,
-                                        bool out_row, int64_t z0, int64_t z1, int64_t pslot,
+                                        bool out_row, int32_t z0, int32_t z1, int64_t pslot,
                                         typename Tile3D<T, KIND, R, TB, RPW>::lds_type &lds)
 {
     using S = Shape<T, KIND, R, TB>;
@@ -196,8 +209,9 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
 
     const int lane = threadIdx.x & 63;
     const int lx = lane % TL::LPR;                           // lane within the row segment
-    const int rw = TL::RPW * (threadIdx.x >> 6) + lane / TL::LPR;  // tile row
-    const int64_t nx = a.nx, ny = a.ny, nz = a.nz, pitch = a.pitch, plane = a.plane;
+    const int rw = tile_row<TL::RPW, TL::LPR>();             // tile row
+    const int64_t nx = a.nx, ny = a.ny, pitch = a.pitch, plane = a.plane;
+    const int32_t nz = (int32_t)a.nz;  // planes are 32-bit: scalar compares and modulo
     const int64_t xl = xb + lx * V;
     const int64_t rowoff = wrap_any(yrow, ny) * pitch;
     const int pl = lx * V;
@@ -235,14 +249,14 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
     // a stage at depth k computes rows [k r, NR - k r) of the tile
     auto rows_ok = [&](int k) { return rw >= k * R && rw < NR - k * R; };
 
-    const int64_t tb0 = z0 - H, tend = z1 + H;
+    const int32_t tb0 = z0 - H, tend = z1 + H;
     // The first PD planes are loaded unconditionally (a plane past the march
     // is a valid wrapped plane, read and not used), so that every load of the
     // unguarded main loop below has a fixed number of loads issued after it
     // and the compiler can wait for it alone instead of draining all of them.
     static_for<0, PD>([&](auto phc) {
         constexpr int ph = decltype(phc)::value;
-        const int64_t off = wrap_any(tb0 + ph, nz) * plane + rowoff;
+        const int64_t off = (int64_t)wrap32(tb0 + ph, nz) * plane + rowoff;
 #pragma unroll
         for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph]);
     });
@@ -250,12 +264,12 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
     // One plane t of the march at ring phase ph; G guards the planes and the
     // prefetch against the end of the march (the tail only).  The guards are
     // uniform over the workgroup, so every wave reaches the same barriers.
-    auto phase = [&](auto phc, auto gc, int64_t tb) {
+    auto phase = [&](auto phc, auto gc, int32_t tb) {
         constexpr int ph = decltype(phc)::value;
         constexpr bool G = decltype(gc)::value;
-        const int64_t t = tb + ph;
+        const int32_t t = tb + ph;
         if (!G || t < tend) {
-            const int64_t age = t - tb0;
+            const int32_t age = t - tb0;
             const int buf = TL::NB == 2 ? (int)(t & 1) : 0;
             auto &L = lds[buf];
 #pragma unroll
@@ -263,7 +277,7 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
 #pragma unroll
                 for (int v = 0; v < V; ++v) ring[f][ph][v] = pre[f][ph % PD][v];
             if (!G || t + PD < tend) {
-                const int64_t off = wrap_any(t + PD, nz) * plane + rowoff;
+                const int64_t off = (int64_t)wrap32(t + PD, nz) * plane + rowoff;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph % PD]);
             }
@@ -295,13 +309,13 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
             __syncthreads();
             if constexpr (KIND != kCH) {
                 if (age >= 2 * R && rows_ok(1)) {
-                    const int64_t pz = t - R;
+                    const int32_t pz = t - R;
                     T res[NF][V];
                     stage3_acgs<T, KIND, R, K, s1, NR, RW, RED>(a, ring, L[0], rw, pl, res, om,
                                                                 pz >= z0 && pz < z1, red[0]);
                     if constexpr (TB == 1) {
                         if (out_row) {
-                            const int64_t ooff = wrap_any(pz, nz) * plane + rowoff;
+                            const int64_t ooff = (int64_t)wrap32(pz, nz) * plane + rowoff;
 #pragma unroll
                             for (int f = 0; f < NF; ++f)
                                 store_row<T, V>(out[f] + ooff, xl, om, res[f]);
@@ -315,12 +329,12 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                 }
                 if constexpr (TB == 2) {
                     if (age >= 4 * R && rows_ok(2)) {
-                        const int64_t pz = t - 2 * R;
+                        const int32_t pz = t - 2 * R;
                         T res[NF][V];
                         stage3_acgs<T, KIND, R, K, s2, NR, RW, RED>(
                             a, r1, L[TB - 1], rw, pl, res, om, pz >= z0 && pz < z1, red[TB - 1]);
                         if (out_row) {
-                            const int64_t ooff = wrap_any(pz, nz) * plane + rowoff;
+                            const int64_t ooff = (int64_t)wrap32(pz, nz) * plane + rowoff;
 #pragma unroll
                             for (int f = 0; f < NF; ++f)
                                 store_row<T, V>(out[f] + ooff, xl, om, res[f]);
@@ -329,7 +343,7 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                 }
             } else {
                 if (age >= 2 * R && rows_ok(1)) {
-                    const int64_t pz = t - R;
+                    const int32_t pz = t - R;
                     stage3_mu<T, R, K, s1, NR, RW, RED>(a, ring[0], L[0][0], rw, pl, m0[s1], om,
                                                         pz >= z0 && pz < z1, red[0]);
                 }
@@ -338,7 +352,7 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                     stage3_chupd<T, R, K, s2, NR, RW>(a, m0, L[1][0], rw, pl, ring[0][s2], res);
                     if constexpr (TB == 1) {
                         if (out_row)
-                            store_row<T, V>(out[0] + wrap_any(t - 2 * R, nz) * plane + rowoff, xl,
+                            store_row<T, V>(out[0] + (int64_t)wrap32(t - 2 * R, nz) * plane + rowoff, xl,
                                             om, res);
                     } else {
 #pragma unroll
@@ -347,7 +361,7 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                 }
                 if constexpr (TB == 2) {
                     if (age >= 6 * R && rows_ok(3)) {
-                        const int64_t pz = t - 3 * R;
+                        const int32_t pz = t - 3 * R;
                         stage3_mu<T, R, K, s3, NR, RW, RED>(a, r1[0], L[TB][0], rw, pl, m1[s3],
                                                             om, pz >= z0 && pz < z1, red[TB - 1]);
                     }
@@ -356,14 +370,14 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                         stage3_chupd<T, R, K, s4, NR, RW>(a, m1, L[TB + 1][0], rw, pl, r1[0][s4],
                                                           res);
                         if (out_row)
-                            store_row<T, V>(out[0] + wrap_any(t - 4 * R, nz) * plane + rowoff,
+                            store_row<T, V>(out[0] + (int64_t)wrap32(t - 4 * R, nz) * plane + rowoff,
                                             xl, om, res);
                     }
                 }
             }
         }
     };
-    int64_t tb = tb0;
+    int32_t tb = tb0;
     for (; tb + K + PD <= tend; tb += K)
         static_for<0, K>([&](auto phc) { phase(phc, std::false_type{}, tb); });
     for (; tb < tend; tb += K)
@@ -380,8 +394,8 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
                                             int64_t pslot_base)
 {
     using TL = Tile3D<T, KIND, R, TB, RPW>;
-    const int w = threadIdx.x >> 6;
-    const int rw = TL::RPW * w + (int)(threadIdx.x & 63) / TL::LPR;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rw = tile_row<TL::RPW, TL::LPR>();
     const int32_t strip = item % a.strips;
     const int32_t rest = item / a.strips;
     const int32_t ytile = rest % a.ytiles;
@@ -389,8 +403,8 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
     const int64_t xb = (int64_t)strip * a.ow - TL::HV;
     const int64_t yrow = (int64_t)ytile * (TL::NR - 2 * TL::H) - TL::H + rw;
     const bool out_row = (rw >= TL::H) && (rw < TL::NR - TL::H) && (yrow < a.ny);
-    const int64_t z0 = (int64_t)chunk * a.clen;
-    const int64_t z1 = min(z0 + (int64_t)a.clen, a.nz);
+    const int32_t z0 = chunk * a.clen;
+    const int32_t z1 = min(z0 + a.clen, (int32_t)a.nz);
     __shared__ typename TL::lds_type lds;
     // the FAST choice is uniform over the workgroup (it depends on the strip only)
     if (xb >= 0 && xb + TL::RW <= a.nx)
