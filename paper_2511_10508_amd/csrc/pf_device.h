@@ -208,6 +208,23 @@ __device__ __forceinline__ double energy_density(double c1, double c2, const dou
     return fma(-0.5 * x, lx, x2 * fma(0.25 * c2, x2, -0.5 * c1));
 }
 
+// The same energy summed by parts, for FP32 storage (the state widened to
+// FP64): over the periodic grid, -(1/2) sum_i x_i (L x)_i equals
+// sum_i x_i sum_j w_j sum_axes (x_i - x_{i + j e_axis}), so each site takes
+// only its forward neighbours.  D[j-1] holds sum_axes (x - x_forward) at
+// distance j.  The per-site values differ from energy_density, the sum over
+// the grid (every reduction reports only sums) is the same up to rounding.
+template <int R>
+__device__ __forceinline__ double energy_by_parts(double c1, double c2, const double *w64, double x,
+                                                  const double (&D)[R])
+{
+    double g = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) g = fma(w64[j], D[j], g);
+    const double x2 = x * x;
+    return fma(x, g, x2 * fma(0.25 * c2, x2, -0.5 * c1));
+}
+
 // ---------------------------------------------------------------------------
 // Work-item order: workgroups are dealt to the 8 XCDs round-robin
 // (blockIdx % 8); remap so that each XCD runs one contiguous range of items,

@@ -32,15 +32,16 @@ __device__ __forceinline__ void pairs2d(const T (&rg)[K][V], const T (&e)[V + 2 
     });
 }
 
+// Forward differences sum_axes (x - x_forward) at distances 1..R of element
+// v, in FP64 from the widened values (x forward along +x, y along the ring).
 template <typename T, int V, int R, int K, int CS>
-__device__ __forceinline__ void pairs2d64(const T (&rg)[K][V], const T (&e)[V + 2 * R], int v,
-                                          double (&S)[R])
+__device__ __forceinline__ void fwd2d64(const T (&rg)[K][V], const T (&e)[V + 2 * R], int v,
+                                        double x, double (&D)[R])
 {
     static_for<1, R + 1>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
-        S[j - 1] = ((double)e[R + v + j] + (double)e[R + v - j]) +
-                   ((double)rg[sp][v] + (double)rg[sm][v]);
+        constexpr int sp = (CS + j) % K;
+        D[j - 1] = (x - (double)e[R + v + j]) + (x - (double)rg[sp][v]);
     });
 }
 
@@ -79,9 +80,9 @@ __device__ __forceinline__ void stage_acgs(const StepArgs<T> &a,
                     if constexpr (std::is_same<T, double>::value) {
                         s1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 4.0);
                     } else {
-                        double S64[R];
-                        pairs2d64<T, V, R, K, CS>(rg[0], e[0], v, S64);
-                        s1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                        double D[R];
+                        fwd2d64<T, V, R, K, CS>(rg[0], e[0], v, x, D);
+                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
                     }
                 } else {
                     s1 += (double)rg[NF - 1][CS][v];
@@ -119,9 +120,9 @@ __device__ __forceinline__ void stage_mu(const StepArgs<T> &a, const T (&c)[K][V
                 if constexpr (std::is_same<T, double>::value) {
                     s1 += energy_from_mu(a.c2, x, mu[v]);
                 } else {
-                    double S64[R];
-                    pairs2d64<T, V, R, K, CS>(c, e, v, S64);
-                    s1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 4.0);
+                    double D[R];
+                    fwd2d64<T, V, R, K, CS>(c, e, v, x, D);
+                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
                 }
             }
         }

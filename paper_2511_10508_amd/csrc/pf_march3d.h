@@ -71,17 +71,19 @@ __device__ __forceinline__ void pairs3d(const T (&rg)[K][V], const T (&e)[V + 2 
     });
 }
 
+// Forward differences sum_axes (x - x_forward) at distances 1..R of element
+// v, in FP64 from the widened values (+x from e, +y from the LDS rows, +z
+// along the ring).
 template <typename T, int V, int R, int K, int CS, int NR, int RW>
-__device__ __forceinline__ void pairs3d64(const T (&rg)[K][V], const T (&e)[V + 2 * R],
-                                          const T (&L)[NR][RW], int rw, int pl, int v,
-                                          double (&S)[R])
+__device__ __forceinline__ void fwd3d64(const T (&rg)[K][V], const T (&e)[V + 2 * R],
+                                        const T (&L)[NR][RW], int rw, int pl, int v, double x,
+                                        double (&D)[R])
 {
     static_for<1, R + 1>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
-        S[j - 1] = (((double)e[R + v + j] + (double)e[R + v - j]) +
-                    ((double)L[rw + j][pl + v] + (double)L[rw - j][pl + v])) +
-                   ((double)rg[sp][v] + (double)rg[sm][v]);
+        constexpr int sp = (CS + j) % K;
+        D[j - 1] = ((x - (double)e[R + v + j]) + (x - (double)L[rw + j][pl + v])) +
+                   (x - (double)rg[sp][v]);
     });
 }
 
@@ -119,9 +121,9 @@ __device__ __forceinline__ void stage3_acgs(const StepArgs<T> &a,
                     if constexpr (std::is_same<T, double>::value) {
                         s1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 6.0);
                     } else {
-                        double S64[R];
-                        pairs3d64<T, V, R, K, CS, NR, RW>(rg[0], e[0], L[0], rw, pl, v, S64);
-                        s1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
+                        double D[R];
+                        fwd3d64<T, V, R, K, CS, NR, RW>(rg[0], e[0], L[0], rw, pl, v, x, D);
+                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
                     }
                 } else {
                     s1 += (double)rg[NF - 1][CS][v];
@@ -158,9 +160,9 @@ __device__ __forceinline__ void stage3_mu(const StepArgs<T> &a, const T (&c)[K][
                 if constexpr (std::is_same<T, double>::value) {
                     s1 += energy_from_mu(a.c2, x, mu[v]);
                 } else {
-                    double S64[R];
-                    pairs3d64<T, V, R, K, CS, NR, RW>(c, e, L, rw, pl, v, S64);
-                    s1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, x * 6.0);
+                    double D[R];
+                    fwd3d64<T, V, R, K, CS, NR, RW>(c, e, L, rw, pl, v, x, D);
+                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
                 }
             }
         }
