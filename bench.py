@@ -168,9 +168,9 @@ def main():
     ap.add_argument("--skip-3d", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(requests shard per GPU, the solver by slabs; see the design notes). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(requests would shard per GPU, a single model by slabs along its slowest "
+              "axis). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

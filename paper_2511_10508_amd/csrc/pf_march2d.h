@@ -8,7 +8,7 @@ namespace pf {
 
 // ===========================================================================
 // 2D fused marching step.  One wave owns a strip of SW = 64 V columns (V
-// values per lane, x-neighbours by lane shuffles) and marches along y over
+// values per lane, x-neighbours by DPP lane shifts) and marches along y over
 // one chunk of output rows.  Each radius-r stencil evaluation is a "stage"
 // that consumes a ring of the last K = 2r+1 rows of its input stream (in
 // registers) and produces one row of its output stream r rows behind:
@@ -17,7 +17,8 @@ namespace pf {
 // With TB = 2 the stages of two time steps are chained, so one sweep over HBM
 // advances the grid two steps; the intermediate state never leaves the
 // registers.  Every stage uses the same per-site functions, so TB = 2 is
-// bitwise equal to two TB = 1 steps.  Loads run K rows ahead (prefetch ring).
+// bitwise equal to two TB = 1 steps.  Loads run PD rows ahead (a prefetch
+// ring; PD = K except where the registers are short).
 
 // Neighbour pair sums (x pair + y pair) at element v for j = 1..R around the
 // centre row CS of a ring, with the centre row's x-neighbourhood in e.
