@@ -18,6 +18,7 @@ timed with HIP events on the model's stream.
 import argparse
 import ctypes
 import hashlib
+import re
 import json
 import os
 import sys
@@ -37,14 +38,17 @@ T0 = time.perf_counter()
 
 
 def source_hash(family="2d"):
-    """Hash of the device-code sources of one kernel family ("2d" or "3d"):
-    its marching header and instantiation file plus the shared headers."""
+    """Hash of the device code of one kernel family ("2d" or "3d"): its
+    marching header and instantiation file plus the shared headers, with
+    comments and whitespace removed (they do not change the kernels)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_10508_amd", "csrc")
     for f in ("pf_device.h", "pf_internal.h", "pf_dispatch.h", "pf_march%s.h" % family,
               "kernels_fused%s.hip" % family):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(f.encode() + " ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
