@@ -1,8 +1,9 @@
 """CPU FP64 oracle for the explicit finite-difference phase-field step.
 
 TEST INFRASTRUCTURE ONLY.  A plain, slow, obviously correct implementation of
-what the GPU library computes (SymPhas 2.0, arXiv 2511.10508: Models A and B,
-Eqs. model-a and model-b; Gray-Scott as named in the Introduction), used by
+what the GPU library computes (SymPhas 2.0, arXiv 2511.10508: Models A, B and
+C, Eqs. model-a, model-b and model-c; Gray-Scott as named in the
+Introduction), used by
 the tests, by the smoke check and by the CPU-baseline leg of the benchmark.
 The product library never imports or links it, and it imports nothing from
 the product.
@@ -25,8 +26,8 @@ import numpy as np
 
 from .weights import second_derivative_weights, second_derivative_weights_exact
 
-AC, CH, GS = 1, 2, 3
-NFIELDS = {AC: 1, CH: 1, GS: 2}
+AC, CH, GS, MC = 1, 2, 3, 4
+NFIELDS = {AC: 1, CH: 1, GS: 2, MC: 2}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -121,7 +122,8 @@ def _stack(fields):
 
 
 def rhs(kind, fields, ndim, dx, order, params):
-    """Right-hand sides of Eq. model-a (AC), Eq. model-b (CH) or Gray-Scott."""
+    """Right-hand sides of Eq. model-a (AC), Eq. model-b (CH), Gray-Scott or
+    Eq. model-c (MC: phi then rho)."""
     lib = _load()
     st, shape = _stack(fields)
     if st.shape[0] != NFIELDS[kind]:
@@ -179,7 +181,7 @@ def reduce(kind, fields, ndim, dx, order, params):
     if bad:
         return None, None, int(bad)
     m = [float(mass[f]) for f in range(NFIELDS[kind])]
-    return m, (float(energy[0]) if kind != GS else None), 0
+    return m, (float(energy[0]) if kind in (AC, CH) else None), 0
 
 
 def dt_max(kind, ndim, dx, order, params):
@@ -191,11 +193,13 @@ def dt_max(kind, ndim, dx, order, params):
       AC: |lam*| + 2 c1        (linearisation about phi^2 <= c1/c2)
       CH: lam*^2 + 2 c1 |lam*|
       GS: max(Du, Dv) |lam*| + F + k + 1     (u, v in [0, 1])
+      MC: |lam*| + 2 c1        (as AC: linearisation about small phi, rho;
+                                rho alone diffuses with |lam*|)
     """
     w = second_derivative_weights_exact(order)
     sigma = w[0] + 2 * sum(wj * (-1) ** j for j, wj in enumerate(w) if j > 0)
     lam = abs(float(sigma)) * ndim / (dx * dx)
-    if kind == AC:
+    if kind in (AC, MC):
         rho = lam + 2 * abs(params[0])
     elif kind == CH:
         rho = lam * lam + 2 * abs(params[0]) * lam

@@ -50,6 +50,14 @@ def run_exact(kind, fields, ndim, dx, dt, order, params, nsteps):
             mu = {k: c2 * F[0][k] ** 3 - c1 * F[0][k] - L[k] for k in keys}
             Lm = _lap(mu, shape, ndim, dx, w)
             F = [{k: F[0][k] + dt * Lm[k] for k in keys}]
+        elif kind == 4:
+            c1, c2, c3 = P[0], P[1], P[2]
+            phi, rho = F
+            Lp = _lap(phi, shape, ndim, dx, w)
+            Lg = _lap({k: rho[k] + c3 * phi[k] ** 2 for k in keys}, shape, ndim, dx, w)
+            F = [{k: phi[k] + dt * (Lp[k] + c1 * phi[k] - c2 * phi[k] ** 3 - 2 * phi[k] * rho[k])
+                  for k in keys},
+                 {k: rho[k] + dt * Lg[k] for k in keys}]
         else:
             Du, Dv, Fr, kr = P[0], P[1], P[2], P[3]
             u, v = F

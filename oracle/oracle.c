@@ -38,6 +38,7 @@
 #define ORC_AC 1
 #define ORC_CH 2
 #define ORC_GS 3
+#define ORC_MC 4
 
 static int64_t wrap(int64_t i, int64_t n)
 {
@@ -90,13 +91,16 @@ void orc_laplacian(int ndim, const int64_t n[3], double dx, int r,
 static int64_t nsites(const int64_t n[3]) { return n[0] * n[1] * n[2]; }
 
 /*
- * Right-hand sides of the three models at the current state.
+ * Right-hand sides of the four models at the current state.
  *   AC: rhs = L phi + c1 phi - c2 phi^3                    (Eq. model-a)
  *   CH: mu  = c2 rho^3 - c1 rho - L rho;  rhs = L mu       (Eq. model-b)
  *   GS: ru  = Du L u - u v^2 + F (1 - u)
  *       rv  = Dv L v + u v^2 - (F + k) v
- * params: AC, CH: {c1, c2};  GS: {Du, Dv, F, k}.
- * in/rhs hold nfields arrays of nsites each (AC, CH: 1 field; GS: u then v).
+ *   MC: rphi = L phi + c1 phi - c2 phi^3 - 2 phi rho        (Eq. model-c)
+ *       rrho = L (rho + c3 phi^2)
+ * params: AC, CH: {c1, c2};  GS: {Du, Dv, F, k};  MC: {c1, c2, c3}.
+ * in/rhs hold nfields arrays of nsites each (AC, CH: 1 field; GS: u then v;
+ * MC: phi then rho).
  */
 void orc_rhs(int kind, int ndim, const int64_t n[3], double dx, int r,
              const double *w, const double *params,
@@ -136,11 +140,25 @@ void orc_rhs(int kind, int ndim, const int64_t n[3], double dx, int r,
             rhs[N + i] = (Dv * lapv[i] + uvv) - (F + k) * v[i];
         }
         free(lapv);
+    } else if (kind == ORC_MC) {
+        const double c1 = params[0], c2 = params[1], c3 = params[2];
+        const double *phi = in, *rho = in + N;
+        double *g = (double *)malloc(sizeof(double) * (size_t)N);
+        orc_laplacian(ndim, n, dx, r, w, phi, lap);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) g[i] = rho[i] + c3 * (phi[i] * phi[i]);
+        orc_laplacian(ndim, n, dx, r, w, g, rhs + N);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            const double p = phi[i];
+            rhs[i] = ((lap[i] + c1 * p) - c2 * (p * p * p)) - 2.0 * p * rho[i];
+        }
+        free(g);
     }
     free(lap);
 }
 
-static int nfields_of(int kind) { return kind == ORC_GS ? 2 : 1; }
+static int nfields_of(int kind) { return (kind == ORC_GS || kind == ORC_MC) ? 2 : 1; }
 
 /*
  * nsteps forward-Euler steps x <- x + dt * rhs(x), in place on `fields`
@@ -150,7 +168,7 @@ int orc_run(int kind, int ndim, const int64_t n[3], double dx, double dt,
             int r, const double *w, const double *params,
             double *fields, int64_t nsteps)
 {
-    if (kind != ORC_AC && kind != ORC_CH && kind != ORC_GS) return -1;
+    if (kind != ORC_AC && kind != ORC_CH && kind != ORC_GS && kind != ORC_MC) return -1;
     const int64_t M = nsites(n) * nfields_of(kind);
     double *rhs = (double *)malloc(sizeof(double) * (size_t)M);
     for (int64_t s = 0; s < nsteps; ++s) {
@@ -253,7 +271,7 @@ int64_t orc_reduce(int kind, int ndim, const int64_t n[3], double dx, int r,
         if (!isfinite(fields[i])) ++bad;
     if (bad) return bad;
     for (int f = 0; f < nf; ++f) mass[f] = vol * orc_exact_sum(fields + f * N, N, 1);
-    if (kind != ORC_GS && energy) {
+    if ((kind == ORC_AC || kind == ORC_CH) && energy) {
         double *e = (double *)malloc(sizeof(double) * (size_t)N);
         orc_energy_density(ndim, n, dx, r, w, params, fields, e);
         *energy = vol * orc_exact_sum(e, N, 1);

@@ -33,6 +33,12 @@ MUTANTS = {
     "energy_quartic_coeff": ("(0.25 * c2)", "(0.5 * c2)"),
     "energy_drop_gradient": ("((-0.5 * v) * lap[i] + (0.25 * c2)", "((-0.0 * v) * lap[i] + (0.25 * c2)"),
     "exact_sum_drop_error": ("if (lo != 0.0) part[k++] = lo;", "(void)lo;"),
+    "mc_coupling_sign": ("- 2.0 * p * rho[i];", "+ 2.0 * p * rho[i];"),
+    "mc_coupling_factor": ("- 2.0 * p * rho[i];", "- p * rho[i];"),
+    "mc_drop_c3": ("g[i] = rho[i] + c3 * (phi[i] * phi[i]);", "g[i] = rho[i];"),
+    "mc_phi_not_squared": ("g[i] = rho[i] + c3 * (phi[i] * phi[i]);", "g[i] = rho[i] + c3 * phi[i];"),
+    "mc_rho_laplacian_of_rho_only": ("orc_laplacian(ndim, n, dx, r, w, g, rhs + N);",
+                                     "orc_laplacian(ndim, n, dx, r, w, rho, rhs + N);"),
 }
 
 

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import AC, CH, GS
+from oracle import AC, CH, GS, MC
 from oracle.exact import run_exact
 from oracle.weights import second_derivative_weights_exact
 
@@ -416,3 +416,98 @@ def test_gray_scott_3d_dt1_is_unstable():
     u, v = oracle.run(GS, [u0, v0], 3, 1.0, 1.0, 2, [0.2, 0.1, 0.04, 0.06], 10)
     amp = np.max(np.abs(u - 1.0)) / 1e-6
     assert math.isclose(amp, 1.44 ** 10, rel_tol=1e-6)
+
+
+# ------------------------------------------------------- Model C pins --
+# Eq. model-c: phi_t = L phi + c1 phi - c2 phi^3 - 2 phi rho,
+#              rho_t = L (rho + c3 phi^2).
+
+@pytest.mark.parametrize("shape,ndim,order", [((1, 4, 4), 2, 2), ((1, 4, 4), 2, 4), ((3, 3, 3), 3, 2)])
+def test_model_c_exact_rational_brute_force(shape, ndim, order):
+    rng = np.random.default_rng(13)
+    fields = [rng.uniform(-0.5, 0.5, size=shape) for _ in range(2)]
+    params, dt, nsteps = [1.1, 0.9, 0.5], 0.01, 4
+    got = oracle.run(MC, fields, ndim, 1.0, dt, order, params, nsteps)
+    ex = run_exact(MC, fields, ndim, 1.0, dt, order, params, nsteps)
+    for g, e in zip(got, ex):
+        e = np.array([[[float(v) for v in row] for row in pl] for pl in e])
+        assert np.max(np.abs(g - e)) < 5e-15
+    # rho is conserved exactly by the scheme (a sum of Laplacians vanishes)
+    r0 = sum(Fraction(float(v)) for v in fields[1].ravel())
+    r4 = sum(v for pl in ex[1] for row in pl for v in row)
+    assert r4 == r0
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("shape,ndim", [((1, 24, 30), 2), ((8, 9, 10), 3)])
+def test_model_c_rho_mass_conservation(order, shape, ndim):
+    rng = np.random.default_rng(17)
+    phi, rho = rng.uniform(-0.1, 0.1, shape), rng.uniform(-0.1, 0.1, shape)
+    n = 20
+    out = oracle.run(MC, [phi, rho], ndim, 1.0, 0.01, order, [1.0, 1.0, 0.5], n)
+    drift = abs(oracle.exact_sum(out[1]) - oracle.exact_sum(rho))
+    assert drift <= n * rho.size * 2.3e-16 * 0.2
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8])
+def test_model_c_fixed_point_bitwise(order):
+    """phi = 0 with any constant rho is a fixed point, exactly."""
+    shape = (4, 5, 6)
+    phi, rho = np.zeros(shape), np.full(shape, 0.37)
+    out = oracle.run(MC, [phi, rho], 3, 1.0, 0.01, order, [1.0, 1.0, 0.5], 10)
+    assert np.array_equal(out[0], phi) and np.array_equal(out[1], rho)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("shape,ndim,modes", [((1, 16, 20), 2, (0, 3, 2)), ((6, 8, 10), 3, (1, 2, 3))])
+def test_model_c_linear_modes(order, shape, ndim, modes):
+    """c2 = c3 = 0 and rho = rho0: phi = A mode grows by 1 + dt (lam + c1 - 2 rho0),
+    rho stays rho0 (the coupling sign and factor 2 are pinned).  c3 = 0 and
+    rho = rho0 + B mode: rho diffuses by 1 + dt lam whatever phi is."""
+    dx, n, dt = 1.0, 25, 0.01
+    m, th = _mode(shape, ndim, modes)
+    lam = _eig(order, th, dx)
+    A0, c1, rho0 = 0.01, 0.7, 0.3
+    phi, rho = oracle.run(MC, [A0 * m, np.full(shape, rho0)], ndim, dx, dt, order, [c1, 0.0, 0.0], n)
+    g = 1 + dt * (lam + c1 - 2 * rho0)
+    assert np.max(np.abs(phi - A0 * g ** n * m)) <= 1e-15 * n * 4
+    assert np.all(rho == rho0)
+    rng = np.random.default_rng(19)
+    phi0 = rng.uniform(-0.2, 0.2, shape)
+    _, rho = oracle.run(MC, [phi0, rho0 + A0 * m], ndim, dx, dt, order, [1.0, 1.0, 0.0], n)
+    assert np.max(np.abs(rho - (rho0 + A0 * (1 + dt * lam) ** n * m))) <= 1e-15 * n * 4
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_model_c_coupling_one_step(order):
+    """phi = A cos(theta.x), rho = 0, c1 = c2 = 0: after one step
+    rho = dt c3 L(phi^2) = dt c3 (A^2 / 2) lam(2 theta) cos(2 theta.x) and
+    phi = (1 + dt lam(theta)) phi (pins c3, the square and the outer L)."""
+    shape, ndim, dx, dt, c3, A = (1, 16, 24), 2, 1.0, 0.01, 0.5, 0.2
+    m, th = _mode(shape, ndim, (0, 3, 2))
+    m2, th2 = _mode(shape, ndim, (0, 6, 4))
+    phi, rho = oracle.run(MC, [A * m, np.zeros(shape)], ndim, dx, dt, order, [0.0, 0.0, c3], 1)
+    assert np.max(np.abs(phi - (1 + dt * _eig(order, th, dx)) * A * m)) <= 1e-16
+    assert np.max(np.abs(rho - dt * c3 * A * A / 2 * _eig(order, th2, dx) * m2)) <= 1e-17
+
+
+def test_model_c_reduces_to_model_a():
+    """c3 = 0 and rho = 0: rho stays 0 and phi follows Eq. model-a bitwise."""
+    rng = np.random.default_rng(23)
+    shape = (1, 20, 22)
+    phi0 = rng.uniform(-0.1, 0.1, shape)
+    phi, rho = oracle.run(MC, [phi0, np.zeros(shape)], 2, 1.0, 0.05, 4, [1.0, 1.0, 0.0], 30)
+    ref = oracle.run(AC, [phi0], 2, 1.0, 0.05, 4, [1.0, 1.0], 30)[0]
+    assert np.array_equal(phi, ref) and np.all(rho == 0.0)
+
+
+def test_model_c_dt_max_separates_growth_from_decay():
+    shape = (1, 8, 8)
+    z, y, x = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    cb = ((-1.0) ** (x + y)) * 1e-3
+    lim = oracle.dt_max(MC, 2, 1.0, 4, [0.0, 0.0, 0.5])
+    for f in range(2):
+        init = [cb if g == f else np.zeros(shape) for g in range(2)]
+        up = oracle.run(MC, init, 2, 1.0, lim * 1.02, 4, [0.0, 0.0, 0.5], 200)[f]
+        dn = oracle.run(MC, init, 2, 1.0, lim * 0.98, 4, [0.0, 0.0, 0.5], 200)[f]
+        assert np.max(np.abs(up)) > 1e-3 and np.max(np.abs(dn)) < 1e-3
