@@ -49,8 +49,9 @@ typedef enum {
     PF_ERR_NOTFOUND = 8      /* unknown ticket */
 } pf_status;
 
-/* Model kinds. */
-enum { PF_AC = 1, PF_CH = 2, PF_GS = 3 };
+/* Model kinds: Allen-Cahn (Eq. model-a), Cahn-Hilliard (Eq. model-b),
+ * Gray-Scott, Model C (Eq. model-c). */
+enum { PF_AC = 1, PF_CH = 2, PF_GS = 3, PF_MC = 4 };
 /* Storage / arithmetic precision of the bulk step. */
 enum { PF_FP64 = 0, PF_FP32 = 1 };
 /* Descriptor flags. */
@@ -67,8 +68,9 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
 
 /*
  * Model descriptor.  struct_size must be sizeof(pf_desc) (ABI check).
- *   kind      PF_AC, PF_CH or PF_GS
- *   nfields   1 for AC and CH, 2 for GS (u, v); anything else -> PF_ERR_ARG
+ *   kind      PF_AC, PF_CH, PF_GS or PF_MC
+ *   nfields   1 for AC and CH, 2 for GS (u, v) and MC (phi, rho); anything
+ *             else -> PF_ERR_ARG
  *   ndim      2 or 3; n[ndim..2] must be 1.  A 1D problem is a 2D grid with
  *             n[1] = 1 (the y stencil of a length-1 periodic axis is exactly 0)
  *   n         grid extents (x, y, z), each >= 1, N = n0 n1 n2 < 2^40
@@ -77,7 +79,9 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
  *   precision PF_FP64 or PF_FP32 (FP32: storage, weights, parameters, the
  *             stencil, the nonlinear terms and the update in FP32; the
  *             reductions stay FP64 with compensation)
- *   params    AC, CH: {c1, c2};  GS: {Du, Dv, F, k};  nparams must match
+ *   params    AC, CH: {c1, c2};  GS: {Du, Dv, F, k};  MC: {c1, c2, c3} with
+ *             phi_t = L phi + c1 phi - c2 phi^3 - 2 phi rho and
+ *             rho_t = L(rho + c3 phi^2);  nparams must match
  *   flags     PF_* flags above
  */
 typedef struct pf_desc {
@@ -193,7 +197,7 @@ pf_status pf_step(pf_model *m, int64_t nsteps);
  * combined in a fixed order: value = hi + lo (double-double).
  *   PF_RED_MASS0 / PF_RED_MASS1: dx^d sum of field 0 / 1
  *   PF_RED_ENERGY: dx^d sum of -(1/2) x L x + (c2/4) x^4 - (c1/2) x^2 (AC, CH
- *                  only; GS -> PF_ERR_UNSUPPORTED)
+ *                  only; GS, MC -> PF_ERR_UNSUPPORTED)
  *   PF_RED_NONFINITE: number of NaN / Inf values (hi = count, lo = 0)
  * Synchronises the stream.
  */

@@ -24,7 +24,7 @@ LIBPATH = os.path.join(_HERE, "libpfmi.so")
 
 PF_OK, PF_ERR_ARG, PF_ERR_UNSTABLE, PF_ERR_NOMEM, PF_ERR_DEVICE = 0, 1, 2, 3, 4
 PF_ERR_STATE, PF_ERR_UNSUPPORTED, PF_ERR_BUSY, PF_ERR_NOTFOUND = 5, 6, 7, 8
-PF_AC, PF_CH, PF_GS = 1, 2, 3
+PF_AC, PF_CH, PF_GS, PF_MC = 1, 2, 3, 4
 PF_FP64, PF_FP32 = 0, 1
 PF_ALLOW_UNSTABLE, PF_USE_GRAPH, PF_REDUCE_EACH_STEP, PF_FORCE_GENERIC = 1, 2, 4, 8
 PF_IC_UNIFORM, PF_IC_GS_CUBES, PF_IC_CONST = 1, 2, 3
@@ -150,11 +150,11 @@ def make_desc(kind, n, dx=1.0, dt=0.01, order=2, precision=PF_FP64, params=None,
     while len(n) < 3:
         n.append(1)
     if params is None:
-        params = [0.2, 0.1, 0.04, 0.06] if kind == PF_GS else [1.0, 1.0]
+        params = {PF_GS: [0.2, 0.1, 0.04, 0.06], PF_MC: [1.0, 1.0, 0.5]}.get(kind, [1.0, 1.0])
     d = pf_desc()
     d.struct_size = ctypes.sizeof(pf_desc)
     d.kind = kind
-    d.nfields = 2 if kind == PF_GS else 1
+    d.nfields = 2 if kind in (PF_GS, PF_MC) else 1
     d.ndim = ndim
     for a in range(3):
         d.n[a] = int(n[a])

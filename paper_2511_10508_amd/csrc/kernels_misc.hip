@@ -46,7 +46,7 @@ struct Field {
     }
 };
 
-// PASS 0: AC / GS full step; PASS 1: CH chemical potential into scratch;
+// PASS 0: AC / GS / MC full step; PASS 1: CH chemical potential into scratch;
 // PASS 2: CH update from scratch.
 template <typename T, int KIND, int R, int PASS>
 __global__ void __launch_bounds__(256) k_generic(StepArgs<T> a, T *scratch, int ndim)
@@ -74,6 +74,17 @@ __global__ void __launch_bounds__(256) k_generic(StepArgs<T> a, T *scratch, int 
         gs_update<T, R>(a, u0, v0, Su, Sv, u0 * ctrk, v0 * ctrk, un, vn);
         a.buf[0][par ^ 1][off] = un;
         a.buf[1][par ^ 1][off] = vn;
+    } else if constexpr (KIND == kMC) {
+        Field<T> f1{a.buf[1][par], a.nx, a.ny, a.nz, a.pitch, a.plane};
+        auto g = [&](int64_t x, int64_t y, int64_t z) { return mc_g(a, f0(x, y, z), f1(x, y, z)); };
+        T Sp[R], Sg[R];
+        pair_sums<T, R>(f0, s, ndim, Sp);
+        pair_sums<T, R>(g, s, ndim, Sg);
+        const T p0 = f0.p[off], r0 = f1.p[off];
+        T pn, rn;
+        mc_update<T, R>(a, p0, r0, Sp, Sg, p0 * ctrk, mc_g(a, p0, r0) * ctrk, pn, rn);
+        a.buf[0][par ^ 1][off] = pn;
+        a.buf[1][par ^ 1][off] = rn;
     } else if constexpr (PASS == 1) {
         T S[R];
         pair_sums<T, R>(f0, s, ndim, S);
@@ -97,7 +108,7 @@ __global__ void __launch_bounds__(256) k_reduce_state(StepArgs<T> a, int ndim)
     const int64_t N = a.nx * a.ny * a.nz;
     const int par = a.parity;
     Field<T> f0{a.buf[0][par], a.nx, a.ny, a.nz, a.pitch, a.plane};
-    Field<T> f1{a.buf[KIND == kGS ? 1 : 0][par], a.nx, a.ny, a.nz, a.pitch, a.plane};
+    Field<T> f1{a.buf[nfields_kind(KIND) == 2 ? 1 : 0][par], a.nx, a.ny, a.nz, a.pitch, a.plane};
     RedState red;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -106,7 +117,7 @@ __global__ void __launch_bounds__(256) k_reduce_state(StepArgs<T> a, int ndim)
         const double x = (double)f0.p[off];
         acc_add(red.q0, x);
         red.bad += finite_val(x) ? 0.0 : 1.0;
-        if constexpr (KIND == kGS) {
+        if constexpr (nfields_kind(KIND) == 2) {
             const double y = (double)f1.p[off];
             acc_add(red.q1, y);
             red.bad += finite_val(y) ? 0.0 : 1.0;

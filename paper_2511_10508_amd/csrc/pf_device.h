@@ -185,6 +185,30 @@ __device__ __forceinline__ void gs_update(const StepArgs<T> &a, T u0, T v0, cons
     vn = av;
 }
 
+// Model C (Eq. model-c): k0 = dt c1, k1 = dt c2, k2 = 2 dt, k3 = c3, wu = wv =
+// dt w_j/dx^2.  The rho equation diffuses g = rho + c3 phi^2 (mc_g); Sp are
+// the neighbour sums of phi, Sg those of g, ctrp / ctrg the centre terms.
+template <typename T>
+__device__ __forceinline__ T mc_g(const StepArgs<T> &a, T p, T r)
+{
+    return fma(a.k3, p * p, r);
+}
+template <typename T, int R>
+__device__ __forceinline__ void mc_update(const StepArgs<T> &a, T p0, T r0, const T (&Sp)[R],
+                                          const T (&Sg)[R], T ctrp, T ctrg, T &pn, T &rn)
+{
+    const T g = fma(-(a.k1 * p0), p0, a.k0) - a.k2 * r0;  // dt (c1 - c2 phi^2 - 2 rho)
+    T acc = fma(g, p0, p0);
+    T accr = r0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        acc = fma(a.wu[j], Sp[j] - ctrp, acc);
+        accr = fma(a.wv[j], Sg[j] - ctrg, accr);
+    }
+    pn = acc;
+    rn = accr;
+}
+
 // Landau free-energy density at a site from its chemical potential
 // mu = c2 x^3 - c1 x - L x: the density -(1/2) x Lx + (c2/4) x^4 - (c1/2) x^2
 // equals (1/2) x mu - (c2/4) x^4.  Used when mu is already FP64.
@@ -298,7 +322,7 @@ struct Shape {
     static constexpr int OWMAX = SW - 2 * HV;          // most outputs per strip
     static constexpr int NE = V + 2 * R;               // gathered x-neighbourhood
     static constexpr int K = 2 * R + 1;                // ring length (rows or planes)
-    static constexpr int NF = KIND == kGS ? 2 : 1;
+    static constexpr int NF = nfields_kind(KIND);
 };
 
 // Row access of one lane.  FAST strips lie inside the row: the row pointer

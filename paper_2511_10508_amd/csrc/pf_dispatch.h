@@ -30,6 +30,7 @@ bool dispatch_kind(int kind, F &&f)
     case kAC: f(std::integral_constant<int, kAC>{}); return true;
     case kCH: f(std::integral_constant<int, kCH>{}); return true;
     case kGS: f(std::integral_constant<int, kGS>{}); return true;
+    case kMC: f(std::integral_constant<int, kMC>{}); return true;
     default: return false;
     }
 }

@@ -6,7 +6,10 @@
 
 namespace pf {
 
-constexpr int kAC = 1, kCH = 2, kGS = 3;
+constexpr int kAC = 1, kCH = 2, kGS = 3, kMC = 4;
+
+// Fields of a model: Gray-Scott (u, v) and Model C (phi, rho) have two.
+constexpr int nfields_kind(int kind) { return (kind == kGS || kind == kMC) ? 2 : 1; }
 constexpr int kMaxR = 8;            // stencil radius r = order / 2 (order <= 16)
 constexpr int kNumQ = 3;            // reduction quantities per partial slot
 constexpr int kWaves2D = 4;         // waves per workgroup, 2D kernels
@@ -36,7 +39,7 @@ struct StepArgs {
     int32_t red;             // fuse reductions into this launch
     T wi[kMaxR];             // w_j / dx^2 (inner Laplacian: CH chemical potential)
     T wu[kMaxR];             // update weights of field 0 (dt-scaled)
-    T wv[kMaxR];             // update weights of field 1 (GS)
+    T wv[kMaxR];             // update weights of field 1 (GS, MC)
     T k0, k1, k2, k3;        // model constants (see kernels)
     double w64[kMaxR];       // w_j / dx^2 in FP64 (energy)
     double c1, c2;           // FP64 Landau constants (energy)

@@ -46,28 +46,57 @@ __device__ __forceinline__ void fwd2d64(const T (&rg)[K][V], const T (&e)[V + 2 
     });
 }
 
-// AC / GS step of the centre row CS of the state rings rg (NF fields); with
-// RED the state at that row is reduced (masked by om and red_row).
+// Neighbour pair sums of g = rho + c3 phi^2 (Model C) at element v: the
+// x-neighbours come gathered in eg, the y-neighbours' g from the rings.
+template <typename T, int V, int R, int K, int CS>
+__device__ __forceinline__ void pairs2d_g(const StepArgs<T> &a, const T (&rp)[K][V],
+                                          const T (&rr)[K][V], const T (&eg)[V + 2 * R], int v,
+                                          T (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = (eg[R + v + j] + eg[R + v - j]) +
+                   (mc_g(a, rp[sp][v], rr[sp][v]) + mc_g(a, rp[sm][v], rr[sm][v]));
+    });
+}
+
+// AC / GS / Model C step of the centre row CS of the state rings rg (NF
+// fields); with RED the state at that row is reduced (masked by om and
+// red_row).
 template <typename T, int KIND, int R, int K, int CS, bool RED>
 __device__ __forceinline__ void stage_acgs(const StepArgs<T> &a,
-                                           const T (&rg)[KIND == kGS ? 2 : 1][K][Vec<T>::V],
-                                           T (&res)[KIND == kGS ? 2 : 1][Vec<T>::V],
+                                           const T (&rg)[nfields_kind(KIND)][K][Vec<T>::V],
+                                           T (&res)[nfields_kind(KIND)][Vec<T>::V],
                                            const OutMask<Vec<T>::V> &om, bool red_row,
                                            RedState &red)
 {
-    constexpr int V = Vec<T>::V, NF = KIND == kGS ? 2 : 1;
+    constexpr int V = Vec<T>::V, NF = nfields_kind(KIND);
     T e[NF][V + 2 * R];
+    T gc[V];  // Model C: g of the centre row
+    gather_x<T, V, R>(rg[0][CS], e[0]);
+    if constexpr (KIND == kMC) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) gather_x<T, V, R>(rg[f][CS], e[f]);
+        for (int v = 0; v < V; ++v) gc[v] = mc_g(a, rg[0][CS][v], rg[1][CS][v]);
+        gather_x<T, V, R>(gc, e[1]);
+    } else if constexpr (NF == 2) {
+        gather_x<T, V, R>(rg[1][CS], e[1]);
+    }
     double s0 = 0.0, s1 = 0.0;  // the row's masked reduction sums
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         T Sf[NF][R];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) pairs2d<T, V, R, K, CS>(rg[f], e[f], v, Sf[f]);
+        pairs2d<T, V, R, K, CS>(rg[0], e[0], v, Sf[0]);
+        if constexpr (KIND == kMC)
+            pairs2d_g<T, V, R, K, CS>(a, rg[0], rg[1], e[1], v, Sf[1]);
+        else if constexpr (NF == 2)
+            pairs2d<T, V, R, K, CS>(rg[1], e[1], v, Sf[1]);
         const T u0 = rg[0][CS][v];
         if constexpr (KIND == kAC) {
             res[0][v] = ac_update<T, R>(a, u0, Sf[0], u0 * T(4));
+        } else if constexpr (KIND == kMC) {
+            mc_update<T, R>(a, u0, rg[1][CS][v], Sf[0], Sf[1], u0 * T(4), gc[v] * T(4), res[0][v],
+                            res[1][v]);
         } else {
             const T v0 = rg[NF - 1][CS][v];
             gs_update<T, R>(a, u0, v0, Sf[0], Sf[NF - 1], u0 * T(4), v0 * T(4), res[0][v],
@@ -93,7 +122,7 @@ __device__ __forceinline__ void stage_acgs(const StepArgs<T> &a,
     }
     if constexpr (RED)
         if (red_row)
-            red_row_end<V, KIND == kGS>(red, om, s0, s1, [&](int f, int v) {
+            red_row_end<V, NF == 2>(red, om, s0, s1, [&](int f, int v) {
                 return (double)rg[f == 0 ? 0 : NF - 1][CS][v];
             });
 }

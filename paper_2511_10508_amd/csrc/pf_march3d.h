@@ -87,27 +87,56 @@ __device__ __forceinline__ void fwd3d64(const T (&rg)[K][V], const T (&e)[V + 2 
     });
 }
 
+// Neighbour pair sums of g = rho + c3 phi^2 (Model C) at element v: x from
+// the gathered eg, y from the centre plane's g rows in LDS, z from the rings.
+template <typename T, int V, int R, int K, int CS, int NR, int RW>
+__device__ __forceinline__ void pairs3d_g(const StepArgs<T> &a, const T (&rp)[K][V],
+                                          const T (&rr)[K][V], const T (&eg)[V + 2 * R],
+                                          const T (&Lg)[NR][RW], int rw, int pl, int v, T (&S)[R])
+{
+    static_for<1, R + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int sp = (CS + j) % K, sm = (CS - j + K) % K;
+        S[j - 1] = ((eg[R + v + j] + eg[R + v - j]) + (Lg[rw + j][pl + v] + Lg[rw - j][pl + v])) +
+                   (mc_g(a, rp[sp][v], rr[sp][v]) + mc_g(a, rp[sm][v], rr[sm][v]));
+    });
+}
+
+// AC / GS / Model C step of the centre plane CS of the rings rg; the centre
+// plane's rows of every field (Model C: phi and g) are in L.
 template <typename T, int KIND, int R, int K, int CS, int NR, int RW, bool RED>
 __device__ __forceinline__ void stage3_acgs(const StepArgs<T> &a,
-                                            const T (&rg)[KIND == kGS ? 2 : 1][K][Vec<T>::V],
-                                            const T (&L)[KIND == kGS ? 2 : 1][NR][RW], int rw,
-                                            int pl, T (&res)[KIND == kGS ? 2 : 1][Vec<T>::V],
+                                            const T (&rg)[nfields_kind(KIND)][K][Vec<T>::V],
+                                            const T (&L)[nfields_kind(KIND)][NR][RW], int rw,
+                                            int pl, T (&res)[nfields_kind(KIND)][Vec<T>::V],
                                             const OutMask<Vec<T>::V> &om, bool red_row, RedState &red)
 {
-    constexpr int V = Vec<T>::V, NF = KIND == kGS ? 2 : 1;
+    constexpr int V = Vec<T>::V, NF = nfields_kind(KIND);
     T e[NF][V + 2 * R];
+    T gc[V];  // Model C: g of the centre row
+    gather_x<T, V, R>(rg[0][CS], e[0]);
+    if constexpr (KIND == kMC) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) gather_x<T, V, R>(rg[f][CS], e[f]);
+        for (int v = 0; v < V; ++v) gc[v] = mc_g(a, rg[0][CS][v], rg[1][CS][v]);
+        gather_x<T, V, R>(gc, e[1]);
+    } else if constexpr (NF == 2) {
+        gather_x<T, V, R>(rg[1][CS], e[1]);
+    }
     double s0 = 0.0, s1 = 0.0;  // the row's masked reduction sums
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         T Sf[NF][R];
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-            pairs3d<T, V, R, K, CS, NR, RW>(rg[f], e[f], L[f], rw, pl, v, Sf[f]);
+        pairs3d<T, V, R, K, CS, NR, RW>(rg[0], e[0], L[0], rw, pl, v, Sf[0]);
+        if constexpr (KIND == kMC)
+            pairs3d_g<T, V, R, K, CS, NR, RW>(a, rg[0], rg[1], e[1], L[1], rw, pl, v, Sf[1]);
+        else if constexpr (NF == 2)
+            pairs3d<T, V, R, K, CS, NR, RW>(rg[1], e[1], L[1], rw, pl, v, Sf[1]);
         const T u0 = rg[0][CS][v];
         if constexpr (KIND == kAC) {
             res[0][v] = ac_update<T, R>(a, u0, Sf[0], u0 * T(6));
+        } else if constexpr (KIND == kMC) {
+            mc_update<T, R>(a, u0, rg[1][CS][v], Sf[0], Sf[1], u0 * T(6), gc[v] * T(6), res[0][v],
+                            res[1][v]);
         } else {
             const T v0 = rg[NF - 1][CS][v];
             gs_update<T, R>(a, u0, v0, Sf[0], Sf[NF - 1], u0 * T(6), v0 * T(6), res[0][v],
@@ -133,7 +162,7 @@ __device__ __forceinline__ void stage3_acgs(const StepArgs<T> &a,
     }
     if constexpr (RED)
         if (red_row)
-            red_row_end<V, KIND == kGS>(red, om, s0, s1, [&](int f, int v) {
+            red_row_end<V, NF == 2>(red, om, s0, s1, [&](int f, int v) {
                 return (double)rg[f == 0 ? 0 : NF - 1][CS][v];
             });
 }
@@ -294,8 +323,14 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                 for (int f = 0; f < NF; ++f)
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
-                        L[0][f][rw][pl + v] = ring[f][s1][v];
-                        if constexpr (TB == 2) L[TB - 1][f][rw][pl + v] = r1[f][s2][v];
+                        // Model C keeps phi and g = rho + c3 phi^2 (the diffused field) in LDS
+                        L[0][f][rw][pl + v] = (KIND == kMC && f == 1)
+                                                  ? mc_g(a, ring[0][s1][v], ring[1][s1][v])
+                                                  : ring[f][s1][v];
+                        if constexpr (TB == 2)
+                            L[TB - 1][f][rw][pl + v] = (KIND == kMC && f == 1)
+                                                           ? mc_g(a, r1[0][s2][v], r1[1][s2][v])
+                                                           : r1[f][s2][v];
                     }
             } else {
 #pragma unroll

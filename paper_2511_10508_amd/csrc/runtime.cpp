@@ -42,17 +42,17 @@ pf_status hip_fail(hipError_t e, const char *what)
     } while (0)
 
 // ------------------------------------------------------------------ desc --
-int nfields_of(int kind) { return kind == kGS ? 2 : 1; }
+int nfields_of(int kind) { return nfields_kind(kind); }
 
 pf_status check_desc(const pf_desc *d)
 {
     if (!d) return fail(PF_ERR_ARG, "descriptor is NULL");
     if (d->struct_size != sizeof(pf_desc))
         return fail(PF_ERR_ARG, "pf_desc.struct_size does not match this library");
-    if (d->kind != kAC && d->kind != kCH && d->kind != kGS)
+    if (d->kind != kAC && d->kind != kCH && d->kind != kGS && d->kind != kMC)
         return fail(PF_ERR_ARG, "unknown model kind");
     if (d->nfields != nfields_of(d->kind))
-        return fail(PF_ERR_ARG, "nfields does not match the model (AC, CH: 1; GS: 2)");
+        return fail(PF_ERR_ARG, "nfields does not match the model (AC, CH: 1; GS, MC: 2)");
     if (d->ndim != 2 && d->ndim != 3) return fail(PF_ERR_ARG, "ndim must be 2 or 3");
     for (int a = 0; a < 3; ++a)
         if (d->n[a] < 1) return fail(PF_ERR_ARG, "grid extents must be >= 1");
@@ -67,8 +67,8 @@ pf_status check_desc(const pf_desc *d)
         return fail(PF_ERR_ARG, "order must be even, 2..16");
     if (d->precision != PF_FP64 && d->precision != PF_FP32)
         return fail(PF_ERR_ARG, "precision must be PF_FP64 or PF_FP32");
-    const int np = d->kind == kGS ? 4 : 2;
-    if (d->nparams != np) return fail(PF_ERR_ARG, "nparams must be 2 (AC, CH) or 4 (GS)");
+    const int np = d->kind == kGS ? 4 : d->kind == kMC ? 3 : 2;
+    if (d->nparams != np) return fail(PF_ERR_ARG, "nparams must be 2 (AC, CH), 4 (GS) or 3 (MC)");
     for (int i = 0; i < np; ++i)
         if (!std::isfinite(d->params[i])) return fail(PF_ERR_ARG, "parameters must be finite");
     if (d->kind == kGS)
@@ -85,7 +85,7 @@ double stability_limit(const pf_desc *d)
     for (int j = 1; j <= d->order / 2; ++j) sigma += 2.0 * w[j] * ((j & 1) ? -1.0 : 1.0);
     const double lam = std::fabs(sigma) * d->ndim / (d->dx * d->dx);
     double rho;
-    if (d->kind == kAC)
+    if (d->kind == kAC || d->kind == kMC)  // MC: phi as AC about small fields, rho diffuses
         rho = lam + 2.0 * std::fabs(d->params[0]);
     else if (d->kind == kCH)
         rho = lam * lam + 2.0 * std::fabs(d->params[0]) * lam;
@@ -157,6 +157,9 @@ static void fill_args(Model *m, StepArgs<T> &a)
         if (d.kind == kGS) {
             a.wu[j - 1] = (T)(d.dt * d.params[0] * wl);
             a.wv[j - 1] = (T)(d.dt * d.params[1] * wl);
+        } else if (d.kind == kMC) {
+            a.wu[j - 1] = (T)(d.dt * wl);
+            a.wv[j - 1] = (T)(d.dt * wl);
         } else {
             a.wu[j - 1] = (T)(d.dt * wl);
         }
@@ -167,13 +170,18 @@ static void fill_args(Model *m, StepArgs<T> &a)
     } else if (d.kind == kCH) {
         a.k0 = (T)d.params[0];
         a.k1 = (T)d.params[1];
+    } else if (d.kind == kMC) {
+        a.k0 = (T)(d.dt * d.params[0]);
+        a.k1 = (T)(d.dt * d.params[1]);
+        a.k2 = (T)(2.0 * d.dt);
+        a.k3 = (T)d.params[2];
     } else {
         a.k0 = (T)(d.dt * d.params[2]);
         a.k1 = (T)(d.dt * (d.params[2] + d.params[3]));
         a.k2 = (T)d.dt;
     }
-    a.c1 = d.kind == kGS ? 0.0 : d.params[0];
-    a.c2 = d.kind == kGS ? 0.0 : d.params[1];
+    a.c1 = (d.kind == kAC || d.kind == kCH) ? d.params[0] : 0.0;
+    a.c2 = (d.kind == kAC || d.kind == kCH) ? d.params[1] : 0.0;
     a.part = m->part;
     a.pstride = m->pstride;
 }
@@ -544,12 +552,13 @@ pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double 
         *lo = q[0].y * vol;
         return PF_OK;
     case PF_RED_MASS1:
-        if (d.kind != kGS) return fail(PF_ERR_UNSUPPORTED, "mass of field 1 needs Gray-Scott");
+        if (nfields_of(d.kind) != 2) return fail(PF_ERR_UNSUPPORTED, "mass of field 1 needs Gray-Scott or Model C");
         *hi = q[1].x * vol;
         *lo = q[1].y * vol;
         return PF_OK;
     case PF_RED_ENERGY:
-        if (d.kind == kGS) return fail(PF_ERR_UNSUPPORTED, "no free energy for Gray-Scott");
+        if (d.kind == kGS || d.kind == kMC)
+            return fail(PF_ERR_UNSUPPORTED, "free energy is reduced for Allen-Cahn and Cahn-Hilliard only");
         *hi = q[1].x * vol;
         *lo = q[1].y * vol;
         return PF_OK;

@@ -175,7 +175,7 @@ static void fill_result(Req *r)
         const double vol = volume(r->desc);
         const double2 *q = r->pinned;
         o.mass[0] = (q[0].x + q[0].y) * vol;
-        if (r->desc.kind == kGS) {
+        if (nfields_kind(r->desc.kind) == 2) {
             o.mass[1] = (q[1].x + q[1].y) * vol;
             o.energy = 0.0;
         } else {

@@ -143,7 +143,7 @@ def gray_scott_fields(seed, shape, ncubes=20, side=16, noise=0.01,
 
 
 def initial_fields(kind, shape, seed, ic=None, ic_params=None, origin=(0, 0, 0), wshape=None):
-    """Initial state for a model kind (1 AC, 2 CH, 3 GS) as FP64 arrays.
+    """Initial state for a model kind (1 AC, 2 CH, 3 GS, 4 MC) as FP64 arrays.
 
     ic / ic_params follow the library's pf_init convention:
       IC_UNIFORM  params (lo, hi): field f from stream f
@@ -152,7 +152,7 @@ def initial_fields(kind, shape, seed, ic=None, ic_params=None, origin=(0, 0, 0),
     """
     if ic is None:
         ic = IC_GS_CUBES if kind == 3 else IC_UNIFORM
-    nf = 2 if kind == 3 else 1
+    nf = 2 if kind in (3, 4) else 1
     if ic == IC_UNIFORM:
         lo, hi = (ic_params or (-0.05, 0.05))[:2]
         return [uniform_field(seed, f, shape, lo, hi, origin, wshape) for f in range(nf)]

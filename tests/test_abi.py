@@ -55,6 +55,7 @@ def test_weights_reject_bad_order():
 @pytest.mark.parametrize("kind,ndim,order,params", [
     (P.PF_AC, 2, 2, [1.0, 1.0]), (P.PF_CH, 2, 4, [1.0, 1.0]), (P.PF_CH, 3, 6, [1.0, 1.0]),
     (P.PF_GS, 3, 2, [0.2, 0.1, 0.04, 0.06]), (P.PF_AC, 3, 8, [0.7, 1.3]),
+    (P.PF_MC, 2, 4, [1.0, 1.0, 0.5]), (P.PF_MC, 3, 2, [0.8, 1.2, 0.5]),
 ])
 def test_stability_matches_oracle(kind, ndim, order, params):
     n = (16,) * ndim
@@ -79,6 +80,20 @@ def test_footprint_against_paper_table():
         assert 2 * f <= per_site < 2 * f + 0.2
     d = P.make_desc(P.PF_GS, (256, 256, 256))
     assert 4 <= P.footprint_bytes(d) / (256 ** 3 * 8) < 4.2
+    # Model C: the paper's two-pass design holds 5 arrays, the fused kernels 2f = 4
+    assert rows["C"] == (2, 1, 5)
+    d = P.make_desc(P.PF_MC, (1024, 1024))
+    assert 4 <= P.footprint_bytes(d) / (1024 * 1024 * 8) < 4.2
+
+
+def test_model_c_descriptor_checks():
+    d = P.make_desc(P.PF_MC, (64, 64), dt=0.01, order=4)
+    assert d.nfields == 2 and d.nparams == 3
+    for field, value in (("nfields", 1), ("nparams", 2)):
+        bad = P.make_desc(P.PF_MC, (64, 64), dt=0.01, order=4)
+        setattr(bad, field, value)
+        h = ctypes.c_void_p()
+        assert P.lib().pf_create(ctypes.byref(bad), None, ctypes.byref(h)) == P.PF_ERR_ARG
 
 
 def test_padded_pitch_and_buffer_elems():

@@ -21,7 +21,7 @@ TOL = {P.PF_FP64: 1e-12, P.PF_FP32: 1e-4}
 
 
 def _check_windows(m, kind, ndim, n, order, params, dt, steps, seed, ic, icp, halo, windows, W, prec):
-    nf = 2 if kind == P.PF_GS else 1
+    nf = 2 if kind in (P.PF_GS, P.PF_MC) else 1
     shape = (n[2] if ndim == 3 else 1, n[1], n[0])
     margin = steps * halo
     for origin in windows:

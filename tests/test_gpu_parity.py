@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {P.PF_FP64: 1e-12, P.PF_FP32: 1e-4}
 BASE = {P.PF_AC: ([1.0, 1.0], 0.05), P.PF_CH: ([1.0, 1.0], 0.01),
-        P.PF_GS: ([0.2, 0.1, 0.04, 0.06], 0.5)}
+        P.PF_GS: ([0.2, 0.1, 0.04, 0.06], 0.5), P.PF_MC: ([1.0, 1.0, 0.5], 0.01)}
 
 
 def dt_for(kind, ndim, order, params, dx=1.0):
@@ -32,6 +32,8 @@ def fields_for(kind, shape, seed):
         return synth.initial_fields(1, shape, seed, synth.IC_UNIFORM, (-0.1, 0.1))
     if kind == P.PF_CH:
         return synth.initial_fields(2, shape, seed, synth.IC_UNIFORM, (-0.05, 0.05))
+    if kind == P.PF_MC:
+        return synth.initial_fields(4, shape, seed, synth.IC_UNIFORM, (-0.1, 0.1))
     return synth.initial_fields(3, shape, seed, synth.IC_GS_CUBES, (6, 4, 0.01))
 
 
@@ -61,7 +63,7 @@ def oracle_run(kind, shape, ndim, order, params, dt, nsteps, seed):
 
 
 CASES = []
-for kind in (P.PF_AC, P.PF_CH, P.PF_GS):
+for kind in (P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC):
     for ndim, shape, chunk in ((2, (1, 75, 301), 32), (3, (21, 37, 150), 8)):
         for order in (2, 4, 6):
             CASES.append((kind, ndim, shape, chunk, order))
@@ -89,7 +91,7 @@ def test_parity_100_steps(case, prec):
 
 
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 @pytest.mark.parametrize("ndim,shape", [(2, (1, 67, 277)), (3, (19, 35, 140))])
 def test_fused_equals_generic_bitwise(kind, ndim, shape, prec):
     order = 4
@@ -116,7 +118,7 @@ def test_tile_shape_invariance_bitwise(kind, ndim, shape, chunks):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 def test_graph_replay_equals_eager_bitwise(kind):
     shape, ndim, order = (1, 64, 96), 2, 4
     params = BASE[kind][0]
@@ -144,13 +146,14 @@ def test_config_allen_cahn_128_1000_steps():
     (P.PF_CH, 3, (9, 10, 11), P.PF_IC_UNIFORM, (-0.05, 0.05)),
     (P.PF_GS, 3, (20, 18, 17), P.PF_IC_GS_CUBES, (5, 4, 0.01)),
     (P.PF_GS, 2, (1, 40, 50), P.PF_IC_CONST, (1.0, 0.0)),
+    (P.PF_MC, 2, (1, 40, 50), P.PF_IC_UNIFORM, (-0.1, 0.1)),
 ])
 def test_device_init_matches_generator(kind, ndim, shape, ic, icp, prec):
     n = (shape[2], shape[1]) if ndim == 2 else (shape[2], shape[1], shape[0])
     d = P.make_desc(kind, n, dt=0.001, precision=prec)
     m = P.Model(d)
     m.init(ic, 4242, icp)
-    ref = synth.initial_fields({1: 1, 2: 2, 3: 3}[kind], shape, 4242, ic, icp)
+    ref = synth.initial_fields(kind, shape, 4242, ic, icp)
     for f, r in enumerate(ref):
         g = m.get_field(f)
         if prec == P.PF_FP32:
@@ -178,7 +181,8 @@ def _oracle_reductions(kind, fields, ndim, order, params):
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("kind,ndim,shape", [
     (P.PF_AC, 2, (1, 70, 200)), (P.PF_CH, 2, (1, 64, 250)), (P.PF_CH, 3, (16, 20, 70)),
-    (P.PF_GS, 3, (16, 20, 70)), (P.PF_AC, 3, (12, 30, 40)),
+    (P.PF_GS, 3, (16, 20, 70)), (P.PF_AC, 3, (12, 30, 40)), (P.PF_MC, 2, (1, 66, 210)),
+    (P.PF_MC, 3, (14, 22, 70)),
 ])
 def test_reductions_match_exact_sums_of_the_state(kind, ndim, shape, prec):
     """pf_reduce of the GPU state vs the oracle's exact sums of the same downloaded state."""
@@ -192,7 +196,7 @@ def test_reductions_match_exact_sums_of_the_state(kind, ndim, shape, prec):
     hi, lo = m.reduce(P.PF_RED_MASS0)
     scale = float(np.sum(np.abs(got[0])))
     assert abs((hi + lo) - mass[0]) <= 1e-15 * scale + 1e-300
-    if kind == P.PF_GS:
+    if kind in (P.PF_GS, P.PF_MC):
         hi, lo = m.reduce(P.PF_RED_MASS1)
         assert abs((hi + lo) - mass[1]) <= 1e-15 * float(np.sum(np.abs(got[1])))
         with pytest.raises(P.PfError):
@@ -209,7 +213,8 @@ def test_reductions_match_exact_sums_of_the_state(kind, ndim, shape, prec):
 @pytest.mark.parametrize("kind,ndim,shape,generic", [
     (P.PF_CH, 2, (1, 64, 250), False), (P.PF_AC, 3, (12, 30, 40), False),
     (P.PF_GS, 3, (12, 30, 40), False), (P.PF_CH, 3, (12, 30, 40), False),
-    (P.PF_CH, 2, (1, 30, 40), True),
+    (P.PF_CH, 2, (1, 30, 40), True), (P.PF_MC, 2, (1, 64, 250), False),
+    (P.PF_MC, 3, (12, 30, 40), False), (P.PF_MC, 2, (1, 30, 40), True),
 ])
 def test_fused_history_matches_oracle(kind, ndim, shape, generic, prec):
     """PF_REDUCE_EACH_STEP: entry k reduces the state at the start of step k."""
@@ -221,7 +226,7 @@ def test_fused_history_matches_oracle(kind, ndim, shape, generic, prec):
     nsteps = 6
     got, m = gpu_run(kind, f0, ndim, order, prec, params, dt, nsteps, flags=flags, chunk=16)
     h0, l0 = m.reduce_history(P.PF_RED_MASS0, nsteps)
-    which1 = P.PF_RED_MASS1 if kind == P.PF_GS else P.PF_RED_ENERGY
+    which1 = P.PF_RED_MASS1 if kind in (P.PF_GS, P.PF_MC) else P.PF_RED_ENERGY
     h1, l1 = m.reduce_history(which1, nsteps)
     state = [a.copy() for a in f0]
     if prec == P.PF_FP32:
@@ -231,7 +236,7 @@ def test_fused_history_matches_oracle(kind, ndim, shape, generic, prec):
         mass, energy = _oracle_reductions(kind, state, ndim, order, params)
         N = state[0].size
         assert abs(h0[k] + l0[k] - mass[0]) <= tol * N * 1e-2 + 1e-13
-        ref1 = mass[1] if kind == P.PF_GS else energy
+        ref1 = mass[1] if kind in (P.PF_GS, P.PF_MC) else energy
         assert abs(h1[k] + l1[k] - ref1) <= tol * N * 1e-1 + 1e-12
         state = oracle.run(kind, state, ndim, 1.0, dt, order, params, 1)
 
@@ -246,7 +251,7 @@ def test_cahn_hilliard_mass_drift_on_gpu():
     assert np.max(np.abs((h + l) - m0)) <= 200 * shape[1] * shape[2] * 2.2e-16 * 0.1
 
 
-@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 @pytest.mark.parametrize("n", [(5, 3), (2, 1), (64, 1), (3, 4, 2)])
 def test_tiny_and_degenerate_grids(kind, n):
     """Extents smaller than the stencil (true periodic wrap), 1D as ny = 1, 1-site axes."""
@@ -293,7 +298,7 @@ def test_get_window_matches_full_field():
 
 
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 @pytest.mark.parametrize("order", [2, 4])
 def test_two_step_blocking_is_bitwise_two_single_steps(kind, order, prec):
     """Temporal blocking (two steps per sweep) against one step per sweep,
@@ -322,7 +327,7 @@ def test_two_step_blocking_is_bitwise_two_single_steps(kind, order, prec):
         assert float(np.max(np.abs(g - r))) <= TOL[prec]
 
 
-@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 def test_two_step_history_and_graphs(kind):
     """Fused per-step reductions and graph replay with two-step sweeps."""
     shape, ndim, order = (1, 64, 200), 2, 4
@@ -341,7 +346,7 @@ def test_two_step_history_and_graphs(kind):
         for f, a in enumerate(f0):
             m.set_field(f, a)
         m.step(70)
-        which = P.PF_RED_MASS1 if kind == P.PF_GS else P.PF_RED_ENERGY
+        which = P.PF_RED_MASS1 if kind in (P.PF_GS, P.PF_MC) else P.PF_RED_ENERGY
         hist.append([sum(m.reduce_history(P.PF_RED_MASS0, 70)), sum(m.reduce_history(which, 70))])
         fields.append([m.get_field(f) for f in range(len(f0))])
     for other in (1, 2):
@@ -365,7 +370,7 @@ def test_time_block_refused_where_unavailable():
 
 
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 def test_two_step_blocking_3d(kind, prec):
     """3D two-step sweeps (order 2) against single steps, bitwise, with ragged
     strips, y tiles and z chunks, an odd step count and fused reductions."""
@@ -455,7 +460,7 @@ def test_tile_rows_defaults_and_refusals():
 
 
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS])
+@pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 @pytest.mark.parametrize("ndim,shape", [(2, (1, 70, 300)), (3, (20, 37, 150))])
 def test_fused_reductions_count_nonfinite_values(kind, ndim, shape, prec):
     """The fused per-step reductions count NaN and infinities exactly (in both
@@ -483,3 +488,15 @@ def test_fused_reductions_count_nonfinite_values(kind, ndim, shape, prec):
     m.step(1)
     hi, _ = m.reduce_history(P.PF_RED_NONFINITE, 1)
     assert hi[0] == bad
+
+
+@pytest.mark.parametrize("ndim,shape", [(2, (1, 128, 192)), (3, (40, 44, 70))])
+def test_model_c_rho_mass_conserved_on_gpu(ndim, shape):
+    """Eq. model-c conserves rho: the fused per-step mass of rho stays at its
+    initial exact sum to FP64 rounding (the phi mass is not conserved)."""
+    f0 = fields_for(P.PF_MC, shape, 25)
+    r0 = oracle.exact_sum(f0[1])
+    got, m = gpu_run(P.PF_MC, f0, ndim, 4, P.PF_FP64, [1.0, 1.0, 0.5], 0.01, 200,
+                     flags=P.PF_REDUCE_EACH_STEP)
+    h, l = m.reduce_history(P.PF_RED_MASS1, 200)
+    assert np.max(np.abs((h + l) - r0)) <= 200 * got[1].size * 2.2e-16 * 0.1

@@ -31,6 +31,8 @@ def _mixed_requests():
         (3, 2, (1, 128, 128), 4, True, [0.2, 0.1, 0.04, 0.06], 0.4),
         (1, 3, (20, 26, 70), 2, False, [1.0, 1.0], 0.05),   # FP64 3D AC / GS order 2: the
         (3, 3, (14, 40, 66), 2, False, [0.2, 0.1, 0.04, 0.06], 0.5),  # batched tile layout
+        (4, 2, (1, 90, 110), 4, True, [1.0, 1.0, 0.5], 0.01),   # Model C
+        (4, 3, (16, 20, 70), 2, False, [0.9, 1.1, 0.5], 0.01),
     ]
     for i, (kind, ndim, shape, order, fp32, params, dt) in enumerate(specs):
         reqs.append(dict(id=i, kind=kind, ndim=ndim, shape=shape, steps=37 + 11 * i, order=order,
@@ -44,7 +46,7 @@ def _alone(req):
     m = P.Model(d)
     m.init(ic, req["seed"], icp)
     m.step(req["steps"])
-    out = [m.get_field(f) for f in range(2 if req["kind"] == 3 else 1)]
+    out = [m.get_field(f) for f in range(2 if req["kind"] in (3, 4) else 1)]
     mass = m.reduce(P.PF_RED_MASS0)
     return out, mass
 
@@ -74,7 +76,7 @@ def _serve(reqs, steps_per_tick=16, budget=0, max_slots=64, late=None, timeout=1
         for res in srv.poll(1024):
             r = tickets[res["ticket"]]
             shape = r["shape"]
-            fields = [srv.fetch(res["ticket"], f, shape) for f in range(2 if r["kind"] == 3 else 1)]
+            fields = [srv.fetch(res["ticket"], f, shape) for f in range(2 if r["kind"] in (3, 4) else 1)]
             results[r["id"]] = (res, fields)
             srv.release(res["ticket"])
         time.sleep(0.001)
