@@ -24,7 +24,8 @@ import subprocess
 
 import numpy as np
 
-from .weights import second_derivative_weights, second_derivative_weights_exact
+from .weights import (fourth_derivative_weights, fourth_derivative_weights_exact,
+                      second_derivative_weights, second_derivative_weights_exact)
 
 AC, CH, GS, MC = 1, 2, 3, 4
 NFIELDS = {AC: 1, CH: 1, GS: 2, MC: 2}
@@ -68,6 +69,12 @@ def _load():
     lib.orc_rhs.restype = None
     lib.orc_run.argtypes = [i32, i32, pi64, d, d, i32, pd, pd, pd, i64]
     lib.orc_run.restype = i32
+    lib.orc_biharmonic_direct.argtypes = [i32, pi64, d, i32, pd, i32, pd, pd, pd]
+    lib.orc_biharmonic_direct.restype = None
+    lib.orc_rhs_chd.argtypes = [i32, pi64, d, i32, pd, i32, pd, pd, pd, pd]
+    lib.orc_rhs_chd.restype = None
+    lib.orc_run_chd.argtypes = [i32, pi64, d, d, i32, pd, i32, pd, pd, pd, i64]
+    lib.orc_run_chd.restype = None
     lib.orc_exact_sum.argtypes = [pd, i64, i64]
     lib.orc_exact_sum.restype = d
     lib.orc_energy_density.argtypes = [i32, pi64, d, i32, pd, pd, pd, pd]
@@ -94,6 +101,10 @@ def _w(order):
     return w
 
 
+def _w4(order):
+    return np.asarray(fourth_derivative_weights(order), dtype=np.float64)
+
+
 def _grid(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     if a.ndim == 2:
@@ -113,6 +124,18 @@ def laplacian(u, ndim, dx, order):
     return out
 
 
+def biharmonic_direct(u, ndim, dx, order):
+    """Direct discrete biharmonic of u: fourth-derivative stencils along each
+    axis plus twice the mixed second-derivative products, periodic."""
+    lib = _load()
+    u = _grid(u)
+    out = np.empty_like(u)
+    w, w4 = _w(order), _w4(order)
+    lib.orc_biharmonic_direct(ndim, _dims(u.shape), dx, order // 2, _dptr(w), order // 2 + 1,
+                              _dptr(w4), _dptr(u), _dptr(out))
+    return out
+
+
 def _stack(fields):
     fs = [_grid(f) for f in fields]
     shape = fs[0].shape
@@ -121,28 +144,50 @@ def _stack(fields):
     return np.ascontiguousarray(np.stack(fs)), shape
 
 
-def rhs(kind, fields, ndim, dx, order, params):
+def _check_biharmonic(kind, biharmonic):
+    if biharmonic not in ("composed", "direct"):
+        raise ValueError("biharmonic is 'composed' or 'direct'")
+    if biharmonic == "direct" and kind != CH:
+        raise ValueError("the direct biharmonic applies to Cahn-Hilliard only")
+    return biharmonic == "direct"
+
+
+def rhs(kind, fields, ndim, dx, order, params, biharmonic="composed"):
     """Right-hand sides of Eq. model-a (AC), Eq. model-b (CH), Gray-Scott or
-    Eq. model-c (MC: phi then rho)."""
+    Eq. model-c (MC: phi then rho).  biharmonic="direct": Cahn-Hilliard with
+    the direct biharmonic stencil in place of the Laplacian applied twice."""
     lib = _load()
+    direct = _check_biharmonic(kind, biharmonic)
     st, shape = _stack(fields)
     if st.shape[0] != NFIELDS[kind]:
         raise ValueError("wrong number of fields")
     out = np.empty_like(st)
     w = _w(order)
     p = np.asarray(list(params) + [0.0] * (4 - len(params)), dtype=np.float64)
+    if direct:
+        w4 = _w4(order)
+        lib.orc_rhs_chd(ndim, _dims(shape), dx, order // 2, _dptr(w), order // 2 + 1, _dptr(w4),
+                        _dptr(p), _dptr(st), _dptr(out))
+        return [out[0]]
     lib.orc_rhs(kind, ndim, _dims(shape), dx, order // 2, _dptr(w), _dptr(p), _dptr(st), _dptr(out))
     return [out[f] for f in range(st.shape[0])]
 
 
-def run(kind, fields, ndim, dx, dt, order, params, nsteps):
-    """nsteps forward-Euler steps from `fields` (list of arrays); returns new list."""
+def run(kind, fields, ndim, dx, dt, order, params, nsteps, biharmonic="composed"):
+    """nsteps forward-Euler steps from `fields` (list of arrays); returns new list.
+    biharmonic as in rhs()."""
     lib = _load()
+    direct = _check_biharmonic(kind, biharmonic)
     st, shape = _stack(fields)
     if st.shape[0] != NFIELDS[kind]:
         raise ValueError("wrong number of fields")
     w = _w(order)
     p = np.asarray(list(params) + [0.0] * (4 - len(params)), dtype=np.float64)
+    if direct:
+        w4 = _w4(order)
+        lib.orc_run_chd(ndim, _dims(shape), dx, dt, order // 2, _dptr(w), order // 2 + 1,
+                        _dptr(w4), _dptr(p), _dptr(st), int(nsteps))
+        return [st[0].copy()]
     rc = lib.orc_run(kind, ndim, _dims(shape), dx, dt, order // 2, _dptr(w), _dptr(p),
                      _dptr(st), int(nsteps))
     if rc != 0:
@@ -184,7 +229,7 @@ def reduce(kind, fields, ndim, dx, order, params):
     return m, (float(energy[0]) if kind in (AC, CH) else None), 0
 
 
-def dt_max(kind, ndim, dx, order, params):
+def dt_max(kind, ndim, dx, order, params, biharmonic="composed"):
     """Forward-Euler stability limit from the Nyquist-mode symbol.
 
     The most negative eigenvalue of the discrete Laplacian is lam* =
@@ -192,6 +237,9 @@ def dt_max(kind, ndim, dx, order, params):
     linearised step is stable while dt * rho <= 2 where rho is
       AC: |lam*| + 2 c1        (linearisation about phi^2 <= c1/c2)
       CH: lam*^2 + 2 c1 |lam*|
+          direct biharmonic: beta* + 2 c1 |lam*| with beta* = ndim tau / dx^4
+          + ndim (ndim - 1) (sigma / dx^2)^2, tau = w4_0 + 2 sum_j w4_j (-1)^j
+          (the direct operator's symbol at the Nyquist mode)
       GS: max(Du, Dv) |lam*| + F + k + 1     (u, v in [0, 1])
       MC: |lam*| + 2 c1        (as AC: linearisation about small phi, rho;
                                 rho alone diffuses with |lam*|)
@@ -199,8 +247,15 @@ def dt_max(kind, ndim, dx, order, params):
     w = second_derivative_weights_exact(order)
     sigma = w[0] + 2 * sum(wj * (-1) ** j for j, wj in enumerate(w) if j > 0)
     lam = abs(float(sigma)) * ndim / (dx * dx)
+    direct = _check_biharmonic(kind, biharmonic)
     if kind in (AC, MC):
         rho = lam + 2 * abs(params[0])
+    elif kind == CH and direct:
+        w4 = fourth_derivative_weights_exact(order)
+        tau = w4[0] + 2 * sum(wj * (-1) ** j for j, wj in enumerate(w4) if j > 0)
+        s1 = abs(float(sigma)) / (dx * dx)
+        beta = ndim * abs(float(tau)) / dx ** 4 + ndim * (ndim - 1) * s1 * s1
+        rho = beta + 2 * abs(params[0]) * lam
     elif kind == CH:
         rho = lam * lam + 2 * abs(params[0]) * lam
     else:

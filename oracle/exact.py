@@ -8,7 +8,7 @@ Python loops: use grids of a few dozen sites and a handful of steps.
 """
 from fractions import Fraction
 
-from .weights import second_derivative_weights_exact
+from .weights import fourth_derivative_weights_exact, second_derivative_weights_exact
 
 
 def _lap(u, shape, ndim, dx, w):
@@ -30,9 +30,42 @@ def _lap(u, shape, ndim, dx, w):
     return out
 
 
-def run_exact(kind, fields, ndim, dx, dt, order, params, nsteps):
-    """Exact forward-Euler run.  fields: list of nested lists/arrays (nz, ny, nx)."""
+def _axis(u, shape, a, scale, w):
+    """One axis of a centred even-derivative stencil, times `scale`."""
+    nz, ny, nx = shape
+    out = {}
+    for (z, y, x), u0 in u.items():
+        acc = Fraction(0)
+        for j in range(1, len(w)):
+            d = [0, 0, 0]
+            d[a] = j
+            up = u[((z + d[2]) % nz, (y + d[1]) % ny, (x + d[0]) % nx)]
+            um = u[((z - d[2]) % nz, (y - d[1]) % ny, (x - d[0]) % nx)]
+            acc += w[j] * scale * (up + um - 2 * u0)
+        out[(z, y, x)] = acc
+    return out
+
+
+def biharmonic_direct_exact(u, shape, ndim, dx, w, w4):
+    """sum_a D4_a u + 2 sum_{a<b} D2_a D2_b u in Fractions (u: dict site -> value)."""
+    out = {k: Fraction(0) for k in u}
+    for a in range(ndim):
+        t = _axis(u, shape, a, 1 / dx ** 4, w4)
+        for k in out:
+            out[k] += t[k]
+    for a in range(ndim):
+        for b in range(a + 1, ndim):
+            t = _axis(_axis(u, shape, b, 1 / (dx * dx), w), shape, a, 1 / (dx * dx), w)
+            for k in out:
+                out[k] += 2 * t[k]
+    return out
+
+
+def run_exact(kind, fields, ndim, dx, dt, order, params, nsteps, biharmonic="composed"):
+    """Exact forward-Euler run.  fields: list of nested lists/arrays (nz, ny, nx).
+    biharmonic="direct": Cahn-Hilliard as L g - B c with the direct stencil."""
     w = second_derivative_weights_exact(order)
+    w4 = fourth_derivative_weights_exact(order)
     shape = (len(fields[0]), len(fields[0][0]), len(fields[0][0][0]))
     nz, ny, nx = shape
     keys = [(z, y, x) for z in range(nz) for y in range(ny) for x in range(nx)]
@@ -44,6 +77,11 @@ def run_exact(kind, fields, ndim, dx, dt, order, params, nsteps):
             c1, c2 = P[0], P[1]
             L = _lap(F[0], shape, ndim, dx, w)
             F = [{k: F[0][k] + dt * (L[k] + c1 * F[0][k] - c2 * F[0][k] ** 3) for k in keys}]
+        elif kind == 2 and biharmonic == "direct":
+            c1, c2 = P[0], P[1]
+            Lg = _lap({k: c2 * F[0][k] ** 3 - c1 * F[0][k] for k in keys}, shape, ndim, dx, w)
+            B = biharmonic_direct_exact(F[0], shape, ndim, dx, w, w4)
+            F = [{k: F[0][k] + dt * (Lg[k] - B[k]) for k in keys}]
         elif kind == 2:
             c1, c2 = P[0], P[1]
             L = _lap(F[0], shape, ndim, dx, w)

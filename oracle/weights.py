@@ -53,6 +53,50 @@ def second_derivative_weights_exact(order):
     return [rows[i][nvar] for i in range(nvar)]
 
 
+def fourth_derivative_weights_exact(order):
+    """Exact centred fourth-derivative weights [w_0, w_1, .., w_r4], r4 = order/2 + 1.
+
+    The same construction for the derivative of order 4 (Sec. "Compile-Time
+    Stencil Generation"): accuracy `order` (even, >= 2) needs a polynomial of
+    degree 4 + order - 1, so the centred stencil has 2 r4 + 1 = order + 3
+    points, and symmetry leaves the unknowns w_0..w_r4 with the even-moment
+    equations
+
+        sum_{j=-r4..r4} w_j j^k = 24 if k == 4 else 0,      k = 0, 2, .., 2 r4.
+    """
+    if order < 2 or order % 2:
+        raise ValueError("accuracy order must be an even integer >= 2")
+    r4 = order // 2 + 1
+    rows = []
+    for m in range(r4 + 1):
+        k = 2 * m
+        row = [Fraction(1 if k == 0 else 0)]
+        row += [Fraction(2 * j ** k) for j in range(1, r4 + 1)]
+        rows.append(row + [Fraction(24 if k == 4 else 0)])
+    return _solve(rows)
+
+
+def _solve(rows):
+    """Gauss-Jordan elimination over Fractions of an augmented square system."""
+    nvar = len(rows)
+    rows = [list(r) for r in rows]
+    for col in range(nvar):
+        piv = next(i for i in range(col, nvar) if rows[i][col] != 0)
+        rows[col], rows[piv] = rows[piv], rows[col]
+        p = rows[col][col]
+        rows[col] = [v / p for v in rows[col]]
+        for i in range(nvar):
+            if i != col and rows[i][col] != 0:
+                f = rows[i][col]
+                rows[i] = [a - f * b for a, b in zip(rows[i], rows[col])]
+    return [rows[i][nvar] for i in range(nvar)]
+
+
+def fourth_derivative_weights(order):
+    """FP64 fourth-derivative weights [w_0..w_r4], each rounded to nearest once."""
+    return [float(w) for w in fourth_derivative_weights_exact(order)]
+
+
 def second_derivative_weights(order):
     """FP64 weights [w_0..w_r]: each exact rational rounded to nearest once."""
     return [float(w) for w in second_derivative_weights_exact(order)]

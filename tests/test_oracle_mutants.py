@@ -39,6 +39,14 @@ MUTANTS = {
     "mc_phi_not_squared": ("g[i] = rho[i] + c3 * (phi[i] * phi[i]);", "g[i] = rho[i] + c3 * phi[i];"),
     "mc_rho_laplacian_of_rho_only": ("orc_laplacian(ndim, n, dx, r, w, g, rhs + N);",
                                      "orc_laplacian(ndim, n, dx, r, w, rho, rhs + N);"),
+    "chd_mixed_factor": ("out[i] = out[i] + 2.0 * tt[i];", "out[i] = out[i] + tt[i];"),
+    "chd_mixed_same_axis": ("orc_axis(a, n, inv_dx2, r, w, t, tt);", "orc_axis(b, n, inv_dx2, r, w, t, tt);"),
+    "chd_dx_cubed": ("1.0 / (dx * dx * dx * dx)", "1.0 / (dx * dx * dx)"),
+    "chd_biharmonic_sign": ("rhs[i] = rhs[i] - b[i];", "rhs[i] = rhs[i] + b[i];"),
+    "chd_d4_skip_last_j": ("for (int j = 1; j <= r; ++j) {\n                    int64_t dp",
+                           "for (int j = 1; j < r; ++j) {\n                    int64_t dp"),
+    "chd_drop_c1": ("g[i] = c2 * (c * c * c) - c1 * c;", "g[i] = c2 * (c * c * c);"),
+    "chd_mixed_includes_diagonal": ("for (int b = a + 1; b < ndim; ++b) {", "for (int b = a; b < ndim; ++b) {"),
 }
 
 

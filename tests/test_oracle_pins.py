@@ -14,7 +14,7 @@ import pytest
 import oracle
 from oracle import AC, CH, GS, MC
 from oracle.exact import run_exact
-from oracle.weights import second_derivative_weights_exact
+from oracle.weights import fourth_derivative_weights_exact, second_derivative_weights_exact
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -140,7 +140,8 @@ def _mode(shape, ndim, modes):
 
 
 @pytest.mark.parametrize("order", [2, 4, 6])
-@pytest.mark.parametrize("shape,ndim,modes", [((1, 16, 20), 2, (0, 3, 2)), ((6, 8, 10), 3, (1, 2, 3))])
+@pytest.mark.parametrize("shape,ndim,modes", [((1, 1, 22), 1, (0, 0, 3)), ((1, 16, 20), 2, (0, 3, 2)),
+                                               ((6, 8, 10), 3, (1, 2, 3))])
 def test_single_mode_decay_all_models(order, shape, ndim, modes):
     dx, n = 1.0, 25
     m, th = _mode(shape, ndim, modes)
@@ -278,6 +279,9 @@ def test_tanh_profile_sign_pins():
     (CH, (3, 3, 3), 3, 2, [1.1, 0.8], 0.01),
     (GS, (3, 3, 3), 3, 2, [0.2, 0.1, 0.04, 0.06], 0.5),
     (GS, (1, 4, 4), 2, 6, [0.2, 0.1, 0.04, 0.06], 0.3),
+    (AC, (1, 1, 9), 1, 4, [1.0, 1.0], 0.05),
+    (CH, (1, 1, 11), 1, 6, [1.0, 1.0], 0.01),
+    (GS, (1, 1, 7), 1, 2, [0.2, 0.1, 0.04, 0.06], 0.5),
 ])
 def test_exact_rational_brute_force(kind, shape, ndim, order, params, dt):
     rng = np.random.default_rng(11)
@@ -422,7 +426,8 @@ def test_gray_scott_3d_dt1_is_unstable():
 # Eq. model-c: phi_t = L phi + c1 phi - c2 phi^3 - 2 phi rho,
 #              rho_t = L (rho + c3 phi^2).
 
-@pytest.mark.parametrize("shape,ndim,order", [((1, 4, 4), 2, 2), ((1, 4, 4), 2, 4), ((3, 3, 3), 3, 2)])
+@pytest.mark.parametrize("shape,ndim,order", [((1, 4, 4), 2, 2), ((1, 4, 4), 2, 4), ((3, 3, 3), 3, 2),
+                                              ((1, 1, 10), 1, 6)])
 def test_model_c_exact_rational_brute_force(shape, ndim, order):
     rng = np.random.default_rng(13)
     fields = [rng.uniform(-0.5, 0.5, size=shape) for _ in range(2)]
@@ -511,3 +516,129 @@ def test_model_c_dt_max_separates_growth_from_decay():
         up = oracle.run(MC, init, 2, 1.0, lim * 1.02, 4, [0.0, 0.0, 0.5], 200)[f]
         dn = oracle.run(MC, init, 2, 1.0, lim * 0.98, 4, [0.0, 0.0, 0.5], 200)[f]
         assert np.max(np.abs(up)) > 1e-3 and np.max(np.abs(dn)) < 1e-3
+
+
+# ------------------------------------------------- direct biharmonic pins --
+# Cahn-Hilliard with the biharmonic's own stencil: fourth-derivative weights
+# along each axis plus twice the mixed products of second-derivative stencils
+# (Secs. "Advanced Derivative Support", "Compile-Time Stencil Generation").
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_d4_weights_polynomial_exactness_off_grid(order):
+    """Applied around an off-grid point x0, the stencil returns the exact
+    fourth derivative of every polynomial of degree <= order + 3, and not of
+    degree order + 4."""
+    w4 = fourth_derivative_weights_exact(order)
+    r4 = order // 2 + 1
+    x0 = Fraction(3, 7)
+    for deg in range(0, order + 5):
+        f = lambda x: (x - x0 + Fraction(1, 3)) ** deg
+        d4 = (Fraction(math.factorial(deg), math.factorial(deg - 4)) * Fraction(1, 3) ** (deg - 4)
+              if deg >= 4 else Fraction(0))
+        val = sum(w4[abs(j)] * f(x0 + j) for j in range(-r4, r4 + 1))
+        if deg <= order + 3:
+            assert val == d4, (order, deg)
+        else:
+            assert val != d4, (order, deg)
+
+
+def test_d4_weights_golden_table():
+    with open(os.path.join(GOLDEN, "centered_d4_weights.txt")) as f:
+        rows = [l for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for line in rows:
+        p, vals = line.split(":")
+        assert fourth_derivative_weights_exact(int(p)) == [Fraction(v) for v in vals.split()]
+
+
+def _d2_sym(order, th):
+    """Symbol of the second-derivative stencil, closed form in s = sin^2(th/2)."""
+    s = math.sin(th / 2) ** 2
+    return {2: -4 * s, 4: -4 * s * (1 + s / 3)}[order]
+
+
+def _d4_sym(order, th):
+    """Symbol of the fourth-derivative stencil, closed form in s = sin^2(th/2)."""
+    s = math.sin(th / 2) ** 2
+    return {2: 16 * s * s, 4: 16 * s * s * (1 + 2 * s / 3)}[order]
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("shape,ndim,modes", [
+    ((1, 1, 24), 1, (0, 0, 5)),
+    ((1, 18, 24), 2, (0, 2, 5)),
+    ((1, 18, 24), 2, (0, 7, 3)),
+    ((8, 10, 12), 3, (3, 1, 4)),
+    ((8, 10, 12), 3, (1, 4, 2)),
+])
+def test_biharmonic_direct_fourier_symbol(order, shape, ndim, modes):
+    """B of a separable Fourier mode is its symbol: sum_a D4(th_a)/dx^4 +
+    2 sum_{a<b} D2(th_a) D2(th_b)/dx^4 (closed forms derived by hand)."""
+    nz, ny, nx = shape
+    dx = 0.7
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ths = [2 * math.pi * modes[2] / nx, 2 * math.pi * modes[1] / ny, 2 * math.pi * modes[0] / nz][:ndim]
+    u = np.cos(ths[0] * x + 0.3)
+    if ndim >= 2:
+        u = u * np.sin(ths[1] * y + 0.1)
+    if ndim == 3:
+        u = u * np.cos(ths[2] * z)
+    sym = sum(_d4_sym(order, t) for t in ths)
+    sym += 2 * sum(_d2_sym(order, ths[a]) * _d2_sym(order, ths[b])
+                   for a in range(ndim) for b in range(a + 1, ndim))
+    sym /= dx ** 4
+    bu = oracle.biharmonic_direct(u, ndim, dx, order)
+    assert np.max(np.abs(bu - sym * u)) <= 1e-12 * (1 + abs(sym)) * 64 / dx ** 4
+    # the same mode through the Cahn-Hilliard right-hand side (linear: c1 = c2 = 0)
+    r = oracle.rhs(CH, [u], ndim, dx, order, [0.0, 0.0], biharmonic="direct")[0]
+    assert np.max(np.abs(r + sym * u)) <= 1e-12 * (1 + abs(sym)) * 64 / dx ** 4
+
+
+@pytest.mark.parametrize("shape,ndim", [((1, 1, 9), 1), ((1, 5, 6), 2), ((3, 4, 5), 3)])
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_biharmonic_direct_exact_rational_brute_force(shape, ndim, order):
+    """The FP64 oracle agrees with the exact-rational run to rounding error,
+    and mass is conserved exactly by the exact run."""
+    f = [np.random.default_rng(7).uniform(-0.3, 0.3, size=shape)]
+    dx, dt, params = 0.9, 0.004, [0.8, 1.3]
+    ex = run_exact(CH, f, ndim, dx, dt, order, params, 2, biharmonic="direct")
+    got = oracle.run(CH, f, ndim, dx, dt, order, params, 2, biharmonic="direct")[0]
+    exf = np.array([[[float(v) for v in row] for row in pl] for pl in ex[0]])
+    assert np.max(np.abs(got - exf)) <= 1e-14
+    m0 = sum(Fraction(float(v)) for v in f[0].ravel())
+    assert sum(v for pl in ex[0] for row in pl for v in row) == m0
+
+
+@pytest.mark.parametrize("shape,ndim", [((1, 4, 5), 2), ((3, 3, 4), 3)])
+def test_biharmonic_direct_order2_is_composed(shape, ndim):
+    """At accuracy 2 the fourth-derivative stencil is the square of the
+    second-derivative one, so the direct and composed schemes are the same
+    scheme: exactly equal in rational arithmetic."""
+    f = [np.random.default_rng(8).uniform(-0.3, 0.3, size=shape)]
+    a = run_exact(CH, f, ndim, 1.1, 0.003, 2, [1.0, 1.0], 2, biharmonic="direct")
+    b = run_exact(CH, f, ndim, 1.1, 0.003, 2, [1.0, 1.0], 2)
+    assert a == b
+    c = run_exact(CH, f, ndim, 1.1, 0.003, 4, [1.0, 1.0], 1, biharmonic="direct")
+    d = run_exact(CH, f, ndim, 1.1, 0.003, 4, [1.0, 1.0], 1)
+    assert c != d
+
+
+@pytest.mark.parametrize("order,ndim", [(2, 1), (4, 2), (6, 3), (4, 3)])
+def test_biharmonic_direct_dt_max_is_nyquist_flip(order, ndim):
+    """At dt_max the linear (c1 = c2 = 0) direct scheme maps the checkerboard
+    to minus itself: 1 - dt_max * beta* = -1."""
+    shape = {1: (1, 1, 8), 2: (1, 8, 8), 3: (4, 4, 4)}[ndim]
+    z, y, x = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    cb = (-1.0) ** (x + (y if ndim >= 2 else 0) + (z if ndim == 3 else 0))
+    lim = oracle.dt_max(CH, ndim, 1.3, order, [0.0, 0.0], biharmonic="direct")
+    out = oracle.run(CH, [cb], ndim, 1.3, lim, order, [0.0, 0.0], 1, biharmonic="direct")[0]
+    assert np.max(np.abs(out + cb)) <= 1e-12
+
+
+def test_biharmonic_direct_dimension_reduction():
+    """A 2D grid with ny = 1 gives the 1D result: the mixed term vanishes."""
+    u = np.random.default_rng(9).uniform(-1, 1, size=(1, 1, 29))
+    for order in (2, 4, 6):
+        a = oracle.biharmonic_direct(u, 1, 0.8, order)
+        b = oracle.biharmonic_direct(u, 2, 0.8, order)
+        assert np.array_equal(a, b)
