@@ -143,6 +143,39 @@ def run_mc(P, n, prec, steps, warmup, seed=606):
             "chunk": chunk, "time_block": tb}
 
 
+def run_ch_variant(P, n, prec, steps, warmup, direct, ndim, seed=202):
+    """Cahn-Hilliard (Eq. model-b) p = 4, dt = 0.01, c1 = c2 = 1, c0 =
+    U[-0.05, 0.05], fused mass / energy reductions every step: either the 2D
+    n^2 grid with the direct biharmonic stencil (direct=True), or a 1D row of
+    n sites with the composed operator."""
+    flags = P.PF_REDUCE_EACH_STEP | (P.PF_BIHARMONIC_DIRECT if direct else 0)
+    shape = (n, n) if ndim == 2 else (n,)
+    d = P.make_desc(P.PF_CH, shape, dx=1.0, dt=0.01, order=4, precision=prec,
+                    params=[1.0, 1.0], flags=flags)
+    m = P.Model(d)
+    m.init(P.PF_IC_UNIFORM, seed, (-0.05, 0.05))
+    m.autotune(2)
+    m.step(warmup)
+    m.sync()
+    m.timing(True)
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.sync()
+    wall = time.perf_counter() - t0
+    kernel_ms, launches, ksteps = m.timing_read()
+    hi, lo = m.reduce_history(P.PF_RED_MASS0, steps)
+    drift = float(abs((hi + lo) - (hi[0] + lo[0])).max())
+    chunk, tb = m.tile()[0], m.time_block()
+    m.close()
+    sites = float(n) ** ndim
+    per = kernel_ms / ksteps
+    gbs = 2 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
+    return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
+            "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
+            "frac_of_peak": round(gbs / PEAK_GBS, 4), "mass_drift": drift,
+            "chunk": chunk, "time_block": tb}
+
+
 def cpu_baseline(n=4096, seconds=10.0, batch=10):
     """The oracle as it stands on the host cores: CH 2D p4 FP64 on an n^2
     sample of the workload, stepped in batches until `seconds` have passed."""
@@ -200,6 +233,8 @@ def main():
                     help="requests in the serving comparison (0 skips it)")
     ap.add_argument("--skip-3d", action="store_true")
     ap.add_argument("--skip-mc", action="store_true", help="skip the Model C lines")
+    ap.add_argument("--skip-next", action="store_true",
+                    help="skip the direct-biharmonic and 1D lines")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -237,6 +272,13 @@ def main():
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             extra["mc2d_%d_%s" % (args.n, tag)] = run_mc(P, args.n, prec, max(10, args.steps // 4), 4)
         log("Model C done")
+    if not args.skip_next:
+        for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
+            extra["chd2d_%d_%s" % (args.n, tag)] = run_ch_variant(
+                P, args.n, prec, max(10, args.steps // 4), 4, direct=True, ndim=2)
+            extra["ch1d_%d_%s" % (args.n * args.n // 4, tag)] = run_ch_variant(
+                P, args.n * args.n // 4, prec, max(10, args.steps // 4), 4, direct=False, ndim=1)
+        log("direct biharmonic and 1D done")
     extra["fp64_mass_drift"] = fp64["mass_drift"]
     extra["fp64_chunk"] = fp64["chunk"]
     extra["fp64_time_block"] = fp64["time_block"]

@@ -59,7 +59,8 @@ enum {
     PF_ALLOW_UNSTABLE = 1u,    /* accept dt above the stability limit */
     PF_USE_GRAPH = 2u,         /* pf_step replays captured HIP graphs of steps */
     PF_REDUCE_EACH_STEP = 4u,  /* fuse the reductions into every step (history) */
-    PF_FORCE_GENERIC = 8u      /* use the simple per-site kernels (testing) */
+    PF_FORCE_GENERIC = 8u,     /* use the simple per-site kernels (testing) */
+    PF_BIHARMONIC_DIRECT = 16u /* Cahn-Hilliard only: direct biharmonic stencil */
 };
 /* Initial conditions for pf_init (counter-based SplitMix64 generator). */
 enum { PF_IC_UNIFORM = 1, PF_IC_GS_CUBES = 2, PF_IC_CONST = 3 };
@@ -71,8 +72,8 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
  *   kind      PF_AC, PF_CH, PF_GS or PF_MC
  *   nfields   1 for AC and CH, 2 for GS (u, v) and MC (phi, rho); anything
  *             else -> PF_ERR_ARG
- *   ndim      2 or 3; n[ndim..2] must be 1.  A 1D problem is a 2D grid with
- *             n[1] = 1 (the y stencil of a length-1 periodic axis is exactly 0)
+ *   ndim      1, 2 or 3; n[ndim..2] must be 1 (1D grids run their own
+ *             kernels, marching along x)
  *   n         grid extents (x, y, z), each >= 1, N = n0 n1 n2 < 2^40
  *   dx        uniform spacing (> 0); dt time step (> 0)
  *   order     accuracy order p of the Laplacian stencil, even, 2..16
@@ -82,7 +83,15 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
  *   params    AC, CH: {c1, c2};  GS: {Du, Dv, F, k};  MC: {c1, c2, c3} with
  *             phi_t = L phi + c1 phi - c2 phi^3 - 2 phi rho and
  *             rho_t = L(rho + c3 phi^2);  nparams must match
- *   flags     PF_* flags above
+ *   flags     PF_* flags above.  PF_BIHARMONIC_DIRECT (PF_CH only, else
+ *             PF_ERR_ARG) replaces the Laplacian applied twice by the
+ *             biharmonic's own stencil (Secs. "Advanced Derivative Support",
+ *             "Compile-Time Stencil Generation": stencils of any derivative
+ *             order): rho_t = L g - B rho, g = c2 rho^3 - c1 rho, B = sum over
+ *             axes of the centred fourth derivative of accuracy `order`
+ *             (radius order/2 + 1, pf_weights4) plus twice the products of
+ *             the second-derivative stencils of each axis pair.  At order 2
+ *             the two forms are the same stencil.  Not accepted by the server.
  */
 typedef struct pf_desc {
     uint32_t struct_size;
@@ -113,6 +122,14 @@ const char *pf_status_str(pf_status s);
  * spacing.  `w` must hold order/2 + 1 doubles (caller-owned).
  */
 pf_status pf_weights(int32_t order, double *w);
+
+/*
+ * Host FP64 centred fourth-derivative weights w4[0..order/2 + 1] (w4_{-j} =
+ * w4_j) of accuracy `order` (the direct biharmonic's axis stencil), by the
+ * same recursion on the nodes 0, +-1, .., +-(order/2 + 1).  `w4` must hold
+ * order/2 + 2 doubles (caller-owned).  PF_ERR_ARG for a bad order or NULL.
+ */
+pf_status pf_weights4(int32_t order, double *w4);
 
 /*
  * Explicit-stability limit of the descriptor's model: the largest dt for
@@ -322,7 +339,9 @@ pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t max_slot
                            int32_t steps_per_tick, pf_server **out);
 
 /* Thread-safe, non-blocking.  Footprint above the budget -> PF_ERR_NOMEM;
- * an invalid or unstable descriptor -> PF_ERR_ARG / PF_ERR_UNSTABLE. */
+ * an invalid or unstable descriptor -> PF_ERR_ARG / PF_ERR_UNSTABLE; a 1D
+ * grid or PF_BIHARMONIC_DIRECT -> PF_ERR_UNSUPPORTED (served requests run the
+ * batched 2D and 3D kernels). */
 pf_status pf_server_submit(pf_server *s, const pf_desc *desc, int32_t ic, uint64_t seed,
                            const double *ic_params, int32_t n_ic_params, int64_t nsteps,
                            uint64_t *ticket);

@@ -27,6 +27,7 @@ PF_ERR_STATE, PF_ERR_UNSUPPORTED, PF_ERR_BUSY, PF_ERR_NOTFOUND = 5, 6, 7, 8
 PF_AC, PF_CH, PF_GS, PF_MC = 1, 2, 3, 4
 PF_FP64, PF_FP32 = 0, 1
 PF_ALLOW_UNSTABLE, PF_USE_GRAPH, PF_REDUCE_EACH_STEP, PF_FORCE_GENERIC = 1, 2, 4, 8
+PF_BIHARMONIC_DIRECT = 16
 PF_IC_UNIFORM, PF_IC_GS_CUBES, PF_IC_CONST = 1, 2, 3
 PF_RED_MASS0, PF_RED_MASS1, PF_RED_ENERGY, PF_RED_NONFINITE = 0, 1, 2, 3
 
@@ -65,6 +66,7 @@ SIGNATURES = {
     "pf_last_error": (ctypes.c_char_p, []),
     "pf_status_str": (ctypes.c_char_p, [_i32]),
     "pf_weights": (_i32, [_i32, _pd]),
+    "pf_weights4": (_i32, [_i32, _pd]),
     "pf_stability": (_i32, [_P(pf_desc), _pd]),
     "pf_footprint_bytes": (_u64, [_P(pf_desc)]),
     "pf_buffer_elems": (_i64, [_P(pf_desc)]),
@@ -144,7 +146,7 @@ def check(status):
 
 
 def make_desc(kind, n, dx=1.0, dt=0.01, order=2, precision=PF_FP64, params=None, flags=0):
-    """Fill a pf_desc.  n = (nx, ny) or (nx, ny, nz); params default to the paper's unit constants."""
+    """Fill a pf_desc.  n = (nx,), (nx, ny) or (nx, ny, nz); params default to the paper's unit constants."""
     n = list(n)
     ndim = len(n)
     while len(n) < 3:
@@ -278,6 +280,12 @@ class Model:
 def weights(order):
     w = np.empty(order // 2 + 1)
     check(lib().pf_weights(order, _dp(w)))
+    return w
+
+
+def weights4(order):
+    w = np.empty(order // 2 + 2)
+    check(lib().pf_weights4(order, _dp(w)))
     return w
 
 

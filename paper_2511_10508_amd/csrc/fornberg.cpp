@@ -61,4 +61,23 @@ bool centered_d2_weights(int order, double *w)
     return true;
 }
 
+// Centred fourth-derivative weights w4[0..r+1] for accuracy order p = 2r at
+// unit spacing (the stencil of the direct biharmonic): 2(r+1)+1 = p+3 nodes,
+// the same node order and averaging.
+bool centered_d4_weights(int order, double *w4)
+{
+    if (order < 2 || order % 2 != 0 || order > 16) return false;
+    const int r4 = order / 2 + 1;
+    std::vector<double> alpha;
+    alpha.push_back(0.0);
+    for (int j = 1; j <= r4; ++j) {
+        alpha.push_back((double)j);
+        alpha.push_back((double)-j);
+    }
+    const auto d = fornberg(0.0, alpha, 4);
+    w4[0] = d[4][0];
+    for (int j = 1; j <= r4; ++j) w4[j] = 0.5 * (d[4][2 * j - 1] + d[4][2 * j]);
+    return true;
+}
+
 }  // namespace pf

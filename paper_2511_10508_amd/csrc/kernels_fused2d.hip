@@ -9,6 +9,8 @@ using TimeBlockRadii = RList<1, 2>;  // radii with a two-step (TB = 2) kernel
 
 bool time_block_available(const Launch &L)
 {
+    if (L.ndim == 1) return L.r >= 1 && L.r <= 4;  // every fused 1D kernel has a two-step form
+    if (L.kind == kCHD) return false;
     return (L.ndim == 2 && (L.r == 1 || L.r == 2)) || (L.ndim == 3 && L.r == 1);
 }
 
@@ -18,7 +20,7 @@ bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int tb,
     bool ok = false;
     dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
-        dispatch_kind(L.kind, [&](auto kc) {
+        dispatch_kind_all(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             ok = dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
@@ -46,17 +48,19 @@ hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int
     dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
-        dispatch_kind(L.kind, [&](auto kc) {
+        dispatch_kind_all(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             if (tb == 2) {
-                dispatch_r(L.r, TimeBlockRadii{}, [&](auto rc) {
-                    constexpr int R = decltype(rc)::value;
-                    if (red)
-                        hipLaunchKernelGGL((k_step2d<T, KIND, R, true, 2>), dim3(blocks), dim3(threads), 0, s, a);
-                    else
-                        hipLaunchKernelGGL((k_step2d<T, KIND, R, false, 2>), dim3(blocks), dim3(threads), 0, s, a);
-                    err = hipGetLastError();
-                });
+                if constexpr (KIND != kCHD) {  // the direct biharmonic has no two-step kernel
+                    dispatch_r(L.r, TimeBlockRadii{}, [&](auto rc) {
+                        constexpr int R = decltype(rc)::value;
+                        if (red)
+                            hipLaunchKernelGGL((k_step2d<T, KIND, R, true, 2>), dim3(blocks), dim3(threads), 0, s, a);
+                        else
+                            hipLaunchKernelGGL((k_step2d<T, KIND, R, false, 2>), dim3(blocks), dim3(threads), 0, s, a);
+                        err = hipGetLastError();
+                    });
+                }
                 return;
             }
             dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {

@@ -30,7 +30,7 @@ __device__ __forceinline__ void pair_sums(const Src &at, const Site &s, int ndim
 #pragma unroll
     for (int j = 1; j <= R; ++j) {
         T acc = at(s.x + j, s.y, s.z) + at(s.x - j, s.y, s.z);
-        acc = acc + (at(s.x, s.y + j, s.z) + at(s.x, s.y - j, s.z));
+        if (ndim >= 2) acc = acc + (at(s.x, s.y + j, s.z) + at(s.x, s.y - j, s.z));
         if (ndim == 3) acc = acc + (at(s.x, s.y, s.z + j) + at(s.x, s.y, s.z - j));
         S[j - 1] = acc;
     }
@@ -46,8 +46,36 @@ struct Field {
     }
 };
 
-// PASS 0: AC / GS / MC full step; PASS 1: CH chemical potential into scratch;
-// PASS 2: CH update from scratch.
+// Site s shifted by d along axis a.
+__device__ __forceinline__ Site shifted(Site s, int a, int64_t d)
+{
+    if (a == 0) s.x += d; else if (a == 1) s.y += d; else s.z += d;
+    return s;
+}
+
+// Direct-biharmonic chemical potential mu_a (g minus the second derivatives
+// of c along the axes other than a) at site s.
+template <typename T, int R, typename Src>
+__device__ __forceinline__ T mu_axis(const StepArgs<T> &a, const Src &c, const Site &s, int ax,
+                                     int ndim)
+{
+    T S[R];
+#pragma unroll
+    for (int j = 1; j <= R; ++j) {
+        T acc = T(0);
+        for (int b = 0; b < ndim; ++b) {
+            if (b == ax) continue;
+            const Site p = shifted(s, b, j), m = shifted(s, b, -j);
+            acc = acc + (c(p.x, p.y, p.z) + c(m.x, m.y, m.z));
+        }
+        S[j - 1] = acc;
+    }
+    const T c0 = c(s.x, s.y, s.z);
+    return ch_mu<T, R>(a, c0, S, c0 * T(2 * (ndim - 1)));
+}
+
+// PASS 0: AC / GS / MC / direct-biharmonic CH full step; PASS 1: CH chemical
+// potential into scratch; PASS 2: CH update from scratch.
 template <typename T, int KIND, int R, int PASS>
 __global__ void __launch_bounds__(256) k_generic(StepArgs<T> a, T *scratch, int ndim)
 {
@@ -85,6 +113,28 @@ __global__ void __launch_bounds__(256) k_generic(StepArgs<T> a, T *scratch, int 
         mc_update<T, R>(a, p0, r0, Sp, Sg, p0 * ctrk, mc_g(a, p0, r0) * ctrk, pn, rn);
         a.buf[0][par ^ 1][off] = pn;
         a.buf[1][par ^ 1][off] = rn;
+    } else if constexpr (KIND == kCHD) {
+        T Sm[R], S4[R + 1];
+        T ctrm = T(0);
+        for (int j = 0; j < R; ++j) Sm[j] = T(0);
+        for (int ax = 0; ax < ndim; ++ax) {
+            ctrm = ctrm + T(2) * mu_axis<T, R>(a, f0, s, ax, ndim);
+#pragma unroll
+            for (int j = 1; j <= R; ++j)
+                Sm[j - 1] = Sm[j - 1] + (mu_axis<T, R>(a, f0, shifted(s, ax, j), ax, ndim) +
+                                         mu_axis<T, R>(a, f0, shifted(s, ax, -j), ax, ndim));
+        }
+#pragma unroll
+        for (int j = 1; j <= R + 1; ++j) {
+            T acc = T(0);
+            for (int ax = 0; ax < ndim; ++ax) {
+                const Site p = shifted(s, ax, j), m = shifted(s, ax, -j);
+                acc = acc + (f0(p.x, p.y, p.z) + f0(m.x, m.y, m.z));
+            }
+            S4[j - 1] = acc;
+        }
+        const T c0 = f0.p[off];
+        a.buf[0][par ^ 1][off] = chd_update<T, R>(a, c0, Sm, ctrm, S4, c0 * ctrk);
     } else if constexpr (PASS == 1) {
         T S[R];
         pair_sums<T, R>(f0, s, ndim, S);
@@ -271,7 +321,7 @@ hipError_t launch_generic(const Launch &L, const void *args, void *scratch, hipS
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
         const int64_t N = a.nx * a.ny * a.nz;
         const dim3 grid((unsigned)cdiv(N, 256)), block(256);
-        dispatch_kind(L.kind, [&](auto kc) {
+        dispatch_kind_all(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             dispatch_r(L.r, GenericRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
@@ -304,7 +354,7 @@ hipError_t launch_reduce_state(const Launch &L, const void *args, hipStream_t s)
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
         const int64_t N = a.nx * a.ny * a.nz;
         const dim3 grid((unsigned)(reduce_partial_slots(N) / 4)), block(256);
-        dispatch_kind(L.kind, [&](auto kc) {
+        dispatch_kind_all(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             dispatch_r(L.r, GenericRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;

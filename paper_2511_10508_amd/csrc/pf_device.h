@@ -166,6 +166,31 @@ __device__ __forceinline__ T ch_update(const StepArgs<T> &a, T c0, const T (&Sm)
     return acc;
 }
 
+// Cahn-Hilliard with the direct biharmonic stencil: c' = c + dt (L g - B c),
+// g = c2 c^3 - c1 c, B = sum_a D4_a + 2 sum_{a<b} D2_a D2_b.  Split by axis,
+// L g - B c = sum_a D2_a mu_a - sum_a D4_a c with mu_a = g - sum_{b != a} D2_b c,
+// the chemical potential without the a-axis term; mu_a is ch_mu over the
+// pairs of the other axes.  chd_g: g alone (k0 = c1, k1 = c2).
+template <typename T>
+__device__ __forceinline__ T chd_g(const StepArgs<T> &a, T c0)
+{
+    return fma(a.k1 * c0, c0 * c0, -(a.k0 * c0));
+}
+// Update from Sm (pairs of mu_a along axis a, summed over axes; ctrm = the
+// matching centre terms 2 sum_a mu_a) and S4 (fourth-derivative pairs of c,
+// ctr4 = 2 ndim c): wu = dt w_j/dx^2, w4 = -dt w4_j/dx^4, j = 1..R+1.
+template <typename T, int R>
+__device__ __forceinline__ T chd_update(const StepArgs<T> &a, T c0, const T (&Sm)[R], T ctrm,
+                                        const T (&S4)[R + 1], T ctr4)
+{
+    T acc = c0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc = fma(a.wu[j], Sm[j] - ctrm, acc);
+#pragma unroll
+    for (int j = 0; j <= R; ++j) acc = fma(a.w4[j], S4[j] - ctr4, acc);
+    return acc;
+}
+
 // Gray-Scott: k0 = dt F, k1 = dt (F + k), k2 = dt, wu = dt Du w_j/dx^2,
 // wv = dt Dv w_j/dx^2.
 template <typename T, int R>
@@ -316,12 +341,14 @@ __device__ __forceinline__ void gather_x(const T (&c)[V], T (&e)[V + 2 * R])
 template <typename T, int KIND, int R, int TB = 1>
 struct Shape {
     static constexpr int V = Vec<T>::V;
-    static constexpr int H = (KIND == kCH ? 2 * R : R) * TB;  // halo of TB fused steps
+    // halo of TB fused steps: CH composes two radius-r stages, the direct
+    // biharmonic reaches r + 1
+    static constexpr int H = (KIND == kCH ? 2 * R : KIND == kCHD ? R + 1 : R) * TB;
     static constexpr int HV = (H + V - 1) / V * V;     // halo rounded to whole lanes
     static constexpr int SW = 64 * V;                  // strip width (loaded columns)
     static constexpr int OWMAX = SW - 2 * HV;          // most outputs per strip
     static constexpr int NE = V + 2 * R;               // gathered x-neighbourhood
-    static constexpr int K = 2 * R + 1;                // ring length (rows or planes)
+    static constexpr int K = KIND == kCHD ? 2 * R + 3 : 2 * R + 1;  // ring length (rows or planes)
     static constexpr int NF = nfields_kind(KIND);
 };
 

@@ -35,6 +35,18 @@ bool dispatch_kind(int kind, F &&f)
     }
 }
 
+// dispatch_kind plus the direct-biharmonic Cahn-Hilliard kernels (the
+// families that have them: 1D, 2D fused, generic, reductions).
+template <typename F>
+bool dispatch_kind_all(int kind, F &&f)
+{
+    if (kind == kCHD) {
+        f(std::integral_constant<int, kCHD>{});
+        return true;
+    }
+    return dispatch_kind(kind, f);
+}
+
 template <typename F>
 void dispatch_prec(int fp32, F &&f)
 {

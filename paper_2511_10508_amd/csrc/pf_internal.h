@@ -7,6 +7,9 @@
 namespace pf {
 
 constexpr int kAC = 1, kCH = 2, kGS = 3, kMC = 4;
+// Kernel kind of Cahn-Hilliard with the direct biharmonic stencil (a
+// descriptor flag on PF_CH; internal to the kernels and launchers).
+constexpr int kCHD = 5;
 
 // Fields of a model: Gray-Scott (u, v) and Model C (phi, rho) have two.
 constexpr int nfields_kind(int kind) { return (kind == kGS || kind == kMC) ? 2 : 1; }
@@ -40,6 +43,7 @@ struct StepArgs {
     T wi[kMaxR];             // w_j / dx^2 (inner Laplacian: CH chemical potential)
     T wu[kMaxR];             // update weights of field 0 (dt-scaled)
     T wv[kMaxR];             // update weights of field 1 (GS, MC)
+    T w4[kMaxR + 1];         // -dt w4_j/dx^4 (direct biharmonic, j = 1..r+1)
     T k0, k1, k2, k3;        // model constants (see kernels)
     double w64[kMaxR];       // w_j / dx^2 in FP64 (energy)
     double c1, c2;           // FP64 Landau constants (energy)
@@ -81,6 +85,11 @@ int rows_per_wave_default(const Launch &L, int tb);
 bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
                   int rpw, int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks,
                   int32_t *items, int32_t *blocks, int32_t *threads);
+// 1D: strips of one row, `clen` strips per wave (chunks = items = waves).
+bool plan_fused1d(const Launch &L, int64_t nx, int32_t clen, int tb, int32_t *strips, int32_t *ow,
+                  int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads);
+hipError_t launch_fused1d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
+                          int red, int tb, hipStream_t s);
 hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
                           int red, int tb, hipStream_t s);
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,

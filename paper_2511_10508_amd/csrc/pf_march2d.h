@@ -178,14 +178,97 @@ __device__ __forceinline__ void stage_chupd(const StepArgs<T> &a, const T (&m)[K
     }
 }
 
+// Direct-biharmonic Cahn-Hilliard, first half: on its arrival, row PH of the
+// concentration ring c gets mu_y = g - D2_x c (the chemical potential without
+// the y term) into the ring my.
+template <typename T, int R, int K, int PH>
+__device__ __forceinline__ void chd_row_mu_y(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                             T (&my)[K][Vec<T>::V])
+{
+    constexpr int V = Vec<T>::V;
+    T e[V + 2 * R];
+    gather_x<T, V, R>(c[PH], e);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T S[R];
+#pragma unroll
+        for (int j = 1; j <= R; ++j) S[j - 1] = e[R + v + j] + e[R + v - j];
+        const T c0 = c[PH][v];
+        my[PH][v] = ch_mu<T, R>(a, c0, S, c0 * T(2));
+    }
+}
+
+// Direct-biharmonic Cahn-Hilliard, second half: the update of the centre row
+// CS of the K = 2R+3 ring (R+1 rows behind the newest) from mu_x = g - D2_y c
+// of that row (x-pairs), the mu_y ring (y-pairs) and the fourth-derivative
+// pairs of c along x and y.  With RED the state at that row is reduced.
+template <typename T, int R, int K, int CS, bool RED>
+__device__ __forceinline__ void stage_chd(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                          const T (&my)[K][Vec<T>::V], T (&res)[Vec<T>::V],
+                                          const OutMask<Vec<T>::V> &om, bool red_row,
+                                          RedState &red)
+{
+    constexpr int V = Vec<T>::V, R4 = R + 1;
+    T mx[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T S[R];
+        static_for<1, R + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            S[j - 1] = c[(CS + j) % K][v] + c[(CS - j + K) % K][v];
+        });
+        mx[v] = ch_mu<T, R>(a, c[CS][v], S, c[CS][v] * T(2));
+    }
+    T em[V + 2 * R], ec[V + 2 * R4];
+    gather_x<T, V, R>(mx, em);
+    gather_x<T, V, R4>(c[CS], ec);
+    double s0 = 0.0, s1 = 0.0;  // the row's masked reduction sums
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sm[R], S4[R4];
+        static_for<1, R + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            Sm[j - 1] = (em[R + v + j] + em[R + v - j]) + (my[(CS + j) % K][v] + my[(CS - j + K) % K][v]);
+        });
+        static_for<1, R4 + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            S4[j - 1] = (ec[R4 + v + j] + ec[R4 + v - j]) + (c[(CS + j) % K][v] + c[(CS - j + K) % K][v]);
+        });
+        const T c0 = c[CS][v];
+        res[v] = chd_update<T, R>(a, c0, Sm, (mx[v] + my[CS][v]) * T(2), S4, c0 * T(4));
+        if constexpr (RED) {
+            if (om.ov[v]) {
+                const double x = (double)c0;
+                s0 += x;
+                if constexpr (std::is_same<T, double>::value) {
+                    // the full chemical potential: mu_x + mu_y - g
+                    s1 += energy_from_mu(a.c2, x, (mx[v] + my[CS][v]) - chd_g(a, c0));
+                } else {
+                    double D[R];
+                    static_for<1, R + 1>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        D[j - 1] = (x - (double)ec[R4 + v + j]) + (x - (double)c[(CS + j) % K][v]);
+                    });
+                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                }
+            }
+        }
+    }
+    if constexpr (RED)
+        if (red_row)
+            red_row_end<V, false>(red, om, s0, s1, [&](int, int v) { return (double)c[CS][v]; });
+}
+
 // Prefetch depth PD of the input rows: the loads for row t + PD are issued
-// while row t is processed.  K rows ahead, except for the FP64 two-step
-// Cahn-Hilliard kernel with fused reductions, where one row ahead frees the
-// registers for a third wave per SIMD and measures faster.
+// while row t is processed (PD divides the ring length K).  K rows ahead,
+// except for the FP64 two-step Cahn-Hilliard kernel with fused reductions,
+// where one row ahead frees the registers for a third wave per SIMD and
+// measures faster.
 template <typename T, int KIND, int R, int TB, bool RED>
 constexpr int prefetch_depth2d()
 {
-    return (std::is_same<T, double>::value && KIND == kCH && TB == 2 && RED) ? 1 : 2 * R + 1;
+    return (std::is_same<T, double>::value && KIND == kCH && TB == 2 && RED) ? 1
+                                                                            : Shape<T, KIND, R, TB>::K;
 }
 
 template <typename T, int KIND, int R, bool RED, bool FAST, int TB>
@@ -211,10 +294,12 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
 
     T ring[NF][K][V];                                    // state n (loaded)
     constexpr int PD = prefetch_depth2d<T, KIND, R, TB, RED>();
+    static_assert(K % PD == 0, "row t is prefetched into slot t mod PD of a K-phase loop");
     T pre[NF][PD][V];                                    // rows t+1 .. t+PD
     T r1[TB == 2 ? NF : 1][K][V];                        // state n+1 (TB = 2)
     T m0[KIND == kCH ? K : 1][V];                        // mu of state n
     T m1[(KIND == kCH && TB == 2) ? K : 1][V];           // mu of state n+1
+    T my[KIND == kCHD ? K : 1][V];                       // direct biharmonic: mu_y rows
     RedState red[TB];
 
     const int32_t tb0 = y0 - H, tend = y1 + H;
@@ -246,7 +331,17 @@ __device__ __forceinline__ void march2d(const StepArgs<T> &a, int par, int64_t x
 #pragma unroll
                 for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph % PD]);
             }
-            if constexpr (KIND != kCH) {
+            if constexpr (KIND == kCHD) {
+                chd_row_mu_y<T, R, K, ph>(a, ring[0], my);
+                constexpr int s1 = Slot<K, R + 1>::template at<ph>;
+                if (age >= 2 * (R + 1)) {
+                    const int32_t row = t - (R + 1);
+                    T res[V];
+                    stage_chd<T, R, K, s1, RED>(a, ring[0], my, res, om, row >= y0 && row < y1,
+                                                red[0]);
+                    store_row<T, V>(out[0] + (int64_t)wrap32(row, ny) * pitch, xl, om, res);
+                }
+            } else if constexpr (KIND != kCH) {
                 constexpr int s1 = Slot<K, R>::template at<ph>;
                 if (age >= 2 * R) {
                     const int32_t row = t - R;

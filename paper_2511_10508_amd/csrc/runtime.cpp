@@ -20,6 +20,7 @@
 namespace pf {
 
 bool centered_d2_weights(int order, double *w);
+bool centered_d4_weights(int order, double *w4);
 
 static thread_local std::string g_err;
 
@@ -53,10 +54,11 @@ pf_status check_desc(const pf_desc *d)
         return fail(PF_ERR_ARG, "unknown model kind");
     if (d->nfields != nfields_of(d->kind))
         return fail(PF_ERR_ARG, "nfields does not match the model (AC, CH: 1; GS, MC: 2)");
-    if (d->ndim != 2 && d->ndim != 3) return fail(PF_ERR_ARG, "ndim must be 2 or 3");
+    if (d->ndim < 1 || d->ndim > 3) return fail(PF_ERR_ARG, "ndim must be 1, 2 or 3");
     for (int a = 0; a < 3; ++a)
         if (d->n[a] < 1) return fail(PF_ERR_ARG, "grid extents must be >= 1");
-    if (d->ndim == 2 && d->n[2] != 1) return fail(PF_ERR_ARG, "2D grids need n[2] == 1");
+    if (d->ndim <= 2 && d->n[2] != 1) return fail(PF_ERR_ARG, "1D and 2D grids need n[2] == 1");
+    if (d->ndim == 1 && d->n[1] != 1) return fail(PF_ERR_ARG, "1D grids need n[1] == 1");
     const double N = (double)d->n[0] * (double)d->n[1] * (double)d->n[2];
     if (N > (double)(1ll << 40)) return fail(PF_ERR_ARG, "grid too large");
     if (d->n[0] > (1ll << 30) || d->n[1] > (1ll << 30) || d->n[2] > (1ll << 30))
@@ -71,6 +73,8 @@ pf_status check_desc(const pf_desc *d)
     if (d->nparams != np) return fail(PF_ERR_ARG, "nparams must be 2 (AC, CH), 4 (GS) or 3 (MC)");
     for (int i = 0; i < np; ++i)
         if (!std::isfinite(d->params[i])) return fail(PF_ERR_ARG, "parameters must be finite");
+    if ((d->flags & PF_BIHARMONIC_DIRECT) && d->kind != kCH)
+        return fail(PF_ERR_ARG, "PF_BIHARMONIC_DIRECT applies to Cahn-Hilliard only");
     if (d->kind == kGS)
         for (int i = 0; i < np; ++i)
             if (d->params[i] < 0.0) return fail(PF_ERR_ARG, "Gray-Scott parameters must be >= 0");
@@ -87,7 +91,19 @@ double stability_limit(const pf_desc *d)
     double rho;
     if (d->kind == kAC || d->kind == kMC)  // MC: phi as AC about small fields, rho diffuses
         rho = lam + 2.0 * std::fabs(d->params[0]);
-    else if (d->kind == kCH)
+    else if (d->kind == kCH && (d->flags & PF_BIHARMONIC_DIRECT)) {
+        // Nyquist symbol of the direct operator: ndim tau / dx^4 for the
+        // fourth derivatives, ndim (ndim - 1) (sigma / dx^2)^2 for the mixed
+        // products (tau: the fourth-derivative stencil at the Nyquist mode)
+        double w4[kMaxR + 2];
+        centered_d4_weights(d->order, w4);
+        double tau = w4[0];
+        for (int j = 1; j <= d->order / 2 + 1; ++j) tau += 2.0 * w4[j] * ((j & 1) ? -1.0 : 1.0);
+        const double s1 = std::fabs(sigma) / (d->dx * d->dx);
+        const double beta = d->ndim * std::fabs(tau) / (d->dx * d->dx * d->dx * d->dx) +
+                            d->ndim * (d->ndim - 1) * s1 * s1;
+        rho = beta + 2.0 * std::fabs(d->params[0]) * lam;
+    } else if (d->kind == kCH)
         rho = lam * lam + 2.0 * std::fabs(d->params[0]) * lam;
     else
         rho = std::max(d->params[0], d->params[1]) * lam + d->params[2] + d->params[3] + 1.0;
@@ -164,6 +180,12 @@ static void fill_args(Model *m, StepArgs<T> &a)
             a.wu[j - 1] = (T)(d.dt * wl);
         }
     }
+    if (m->L.kind == kCHD) {
+        double w4[kMaxR + 2];
+        centered_d4_weights(d.order, w4);
+        const double idx4 = idx2 * idx2;
+        for (int j = 1; j <= r + 1; ++j) a.w4[j - 1] = (T)(-d.dt * w4[j] * idx4);
+    }
     if (d.kind == kAC) {
         a.k0 = (T)(d.dt * d.params[0]);
         a.k1 = (T)(d.dt * d.params[1]);
@@ -199,7 +221,10 @@ static bool plan(Model *m)
     }
     int32_t strips, ow, ytiles = 1, chunks, items, blocks, threads;
     bool ok;
-    if (d.ndim == 2)
+    if (d.ndim == 1)
+        ok = plan_fused1d(L, d.n[0], m->clen, m->tb, &strips, &ow, &chunks, &items, &blocks,
+                          &threads);
+    else if (d.ndim == 2)
         ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, m->tb, &strips, &ow, &chunks, &items,
                           &blocks, &threads);
     else {
@@ -221,7 +246,7 @@ static bool plan(Model *m)
     m->items = items;
     m->blocks = blocks;
     m->threads = threads;
-    m->fused_slots = d.ndim == 2 ? (int64_t)items : (int64_t)items * kWaves3D;
+    m->fused_slots = d.ndim == 3 ? (int64_t)items * kWaves3D : (int64_t)items;
     return true;
 }
 
@@ -231,6 +256,11 @@ static bool plan(Model *m)
 // are half as wide as a 2D strip and 32 rows high).
 int32_t default_chunk(const pf_desc *d)
 {
+    if (d->ndim == 1) {
+        // strips per wave: about 8192 waves (8 per SIMD)
+        const int64_t strips = std::max<int64_t>(1, d->n[0] / (d->precision == PF_FP32 ? 224 : 112));
+        return (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, strips / 8192));
+    }
     const int64_t march = d->ndim == 2 ? d->n[1] : d->n[2];
     const int64_t cols = (d->precision == PF_FP32 ? 256 : 128) / (d->ndim == 2 ? 1 : 2);
     const int64_t strips = std::max<int64_t>(1, (d->n[0] + cols - 1) / cols);
@@ -262,7 +292,8 @@ static TuneKey tune_key(const pf_desc &d)
 {
     auto lg = [](int64_t v) { int b = 0; while ((1ll << (b + 1)) <= v) ++b; return b; };
     return std::make_tuple(d.kind, d.ndim, d.order, d.precision,
-                           (d.flags & PF_REDUCE_EACH_STEP) ? 1 : 0, lg(d.n[0]), lg(d.n[1]),
+                           (int)(d.flags & (PF_REDUCE_EACH_STEP | PF_BIHARMONIC_DIRECT)),
+                           lg(d.n[0]), lg(d.n[1]),
                            lg(d.n[2]));
 }
 
@@ -328,7 +359,7 @@ pf_status set_chunk(Model *m, int32_t chunk)
 
 static pf_status ensure_scratch(Model *m)
 {
-    if (m->family == 0 || m->desc.kind != kCH || m->scratch) return PF_OK;
+    if (m->family == 0 || m->L.kind != kCH || m->scratch) return PF_OK;
     PF_HIP(dev_alloc(m, &m->scratch, tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
     return PF_OK;
 }
@@ -370,9 +401,9 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
     }
     if (m->family == 0) {
         if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
-        hipError_t e = d.ndim == 2
-                           ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
-                           : launch_fused3d(m->L, ap, m->blocks, m->threads, red, tb, m->rpw, m->stream);
+        hipError_t e = d.ndim == 1   ? launch_fused1d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
+                       : d.ndim == 2 ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
+                                     : launch_fused3d(m->L, ap, m->blocks, m->threads, red, tb, m->rpw, m->stream);
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
         if (red) {
@@ -591,7 +622,8 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
     m->desc = *desc;
     m->nf = desc->nfields;
     m->fp32 = desc->precision == PF_FP32;
-    m->L = Launch{desc->kind, desc->ndim, desc->order / 2, m->fp32 ? 1 : 0};
+    m->L = Launch{(desc->kind == kCH && (desc->flags & PF_BIHARMONIC_DIRECT)) ? kCHD : desc->kind,
+                  desc->ndim, desc->order / 2, m->fp32 ? 1 : 0};
     m->pitch = pitch_of(desc);
     m->elems = buffer_elems(desc);
     hipError_t e;
@@ -782,7 +814,9 @@ pf_status autotune(Model *m, int32_t trials)
     if (m->family != 0) return PF_OK;
     const pf_desc &d = m->desc;
     const bool red = (d.flags & PF_REDUCE_EACH_STEP) != 0;
-    const int64_t march = d.ndim == 2 ? d.n[1] : d.n[2];
+    // chunk candidates up to the marching extent (1D: strips per wave)
+    const int64_t march = d.ndim == 1 ? std::max<int64_t>(1, d.n[0] / (m->fp32 ? 224 : 112))
+                          : d.ndim == 2 ? d.n[1] : d.n[2];
     std::vector<int32_t> cand;
     const int32_t base[] = {16, 32, 64, 128, 256, 512, 1024};
     for (int32_t c : base)
@@ -804,7 +838,7 @@ pf_status autotune(Model *m, int32_t trials)
     pf_status st = PF_OK;
     for (int tb : tbs) {
         for (int rpw : {2, 1}) {
-            if (d.ndim == 2 ? rpw != 2 : !rows_per_wave_available(m->L, tb, rpw)) continue;
+            if (d.ndim != 3 ? rpw != 2 : !rows_per_wave_available(m->L, tb, rpw)) continue;
             for (int32_t c : cand) {
                 m->tb = tb;
                 m->rpw_req = d.ndim == 3 ? rpw : 0;
@@ -876,6 +910,13 @@ PF_API pf_status pf_weights(int32_t order, double *w)
 {
     if (!w) return fail(PF_ERR_ARG, "w is NULL");
     if (!centered_d2_weights(order, w)) return fail(PF_ERR_ARG, "order must be even, 2..16");
+    return PF_OK;
+}
+
+PF_API pf_status pf_weights4(int32_t order, double *w4)
+{
+    if (!w4) return fail(PF_ERR_ARG, "w4 is NULL");
+    if (!centered_d4_weights(order, w4)) return fail(PF_ERR_ARG, "order must be even, 2..16");
     return PF_OK;
 }
 

@@ -45,6 +45,15 @@ def test_fornberg_matches_exact_weights(order):
         assert abs(Fraction(float(a)) - e) <= 8 * Fraction(math.ulp(float(e)) or 2.0 ** -1074) + Fraction(1, 10 ** 14) * abs(e)
 
 
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_fornberg_fourth_derivative_matches_exact_weights(order):
+    w = P.weights4(order)
+    exact = oracle.fourth_derivative_weights_exact(order)
+    assert len(w) == len(exact) == order // 2 + 2
+    for a, e in zip(w, exact):
+        assert abs(Fraction(float(a)) - e) <= 8 * Fraction(math.ulp(float(e)) or 2.0 ** -1074) + Fraction(1, 10 ** 13) * abs(e)
+
+
 def test_weights_reject_bad_order():
     with pytest.raises(P.PfError):
         P.weights(3)
@@ -61,6 +70,44 @@ def test_stability_matches_oracle(kind, ndim, order, params):
     n = (16,) * ndim
     d = P.make_desc(kind, n, dx=0.9, order=order, params=params)
     assert math.isclose(P.stability(d), oracle.dt_max(kind, ndim, 0.9, order, params), rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("ndim,order", [(1, 2), (1, 4), (2, 4), (2, 6), (3, 2), (3, 8)])
+def test_stability_direct_biharmonic_matches_oracle(ndim, order):
+    d = P.make_desc(P.PF_CH, (16,) * ndim, dx=1.1, order=order, params=[0.9, 1.0],
+                    flags=P.PF_BIHARMONIC_DIRECT)
+    ref = oracle.dt_max(oracle.CH, ndim, 1.1, order, [0.9, 1.0], biharmonic="direct")
+    assert math.isclose(P.stability(d), ref, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("kind,params", [(P.PF_AC, [1.0, 1.0]), (P.PF_CH, [1.0, 1.0]),
+                                         (P.PF_GS, [0.2, 0.1, 0.04, 0.06]), (P.PF_MC, [1.0, 1.0, 0.5])])
+def test_stability_1d_matches_oracle(kind, params):
+    d = P.make_desc(kind, (100,), dx=0.8, order=4, params=params)
+    assert d.ndim == 1 and list(d.n) == [100, 1, 1]
+    assert math.isclose(P.stability(d), oracle.dt_max(kind, 1, 0.8, 4, params), rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("kind,n,flags", [
+    (P.PF_AC, (64, 64), 16),        # the direct biharmonic is Cahn-Hilliard only
+    (P.PF_GS, (64,), 16),
+    (P.PF_MC, (64, 64, 8), 16),
+])
+def test_direct_biharmonic_flag_needs_cahn_hilliard(kind, n, flags):
+    d = P.make_desc(kind, n, dt=1e-3, order=4, flags=flags)
+    h = ctypes.c_void_p()
+    assert P.lib().pf_create(ctypes.byref(d), None, ctypes.byref(h)) == P.PF_ERR_ARG
+    assert b"Cahn-Hilliard" in P.lib().pf_last_error()
+
+
+def test_1d_descriptor_checks():
+    for ndim, n in ((1, (64, 2, 1)), (1, (64, 1, 2)), (2, (64, 8, 2)), (0, (64, 1, 1))):
+        d = P.make_desc(P.PF_AC, (64,), dt=0.01)
+        d.ndim = ndim
+        for a in range(3):
+            d.n[a] = n[a]
+        h = ctypes.c_void_p()
+        assert P.lib().pf_create(ctypes.byref(d), None, ctypes.byref(h)) == P.PF_ERR_ARG
 
 
 def test_footprint_against_paper_table():
