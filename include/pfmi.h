@@ -140,7 +140,9 @@ pf_status pf_weights4(int32_t order, double *w4);
 pf_status pf_stability(const pf_desc *desc, double *dt_max);
 
 /* Device bytes a model of this descriptor holds (2 buffers per field, padded
- * pitch, plus reduction scratch).  0 for an invalid descriptor. */
+ * pitch, plus reduction scratch, plus the field-sized temporaries of the
+ * per-site kernels where the fused ones do not apply: one for Cahn-Hilliard,
+ * ndim for the direct biharmonic).  0 for an invalid descriptor. */
 uint64_t pf_footprint_bytes(const pf_desc *desc);
 
 /* Elements of one device field buffer (pitch * n1 * n2).  -1 if invalid. */

@@ -74,8 +74,9 @@ __device__ __forceinline__ T mu_axis(const StepArgs<T> &a, const Src &c, const S
     return ch_mu<T, R>(a, c0, S, c0 * T(2 * (ndim - 1)));
 }
 
-// PASS 0: AC / GS / MC / direct-biharmonic CH full step; PASS 1: CH chemical
-// potential into scratch; PASS 2: CH update from scratch.
+// PASS 0: AC / GS / MC full step; PASS 1: CH chemical potential into
+// scratch (direct biharmonic: mu_a of every axis a into scratch + a * fsize,
+// fsize = the elements of one field buffer); PASS 2: CH update from scratch.
 template <typename T, int KIND, int R, int PASS>
 __global__ void __launch_bounds__(256) k_generic(StepArgs<T> a, T *scratch, int ndim)
 {
@@ -113,16 +114,22 @@ __global__ void __launch_bounds__(256) k_generic(StepArgs<T> a, T *scratch, int 
         mc_update<T, R>(a, p0, r0, Sp, Sg, p0 * ctrk, mc_g(a, p0, r0) * ctrk, pn, rn);
         a.buf[0][par ^ 1][off] = pn;
         a.buf[1][par ^ 1][off] = rn;
+    } else if constexpr (KIND == kCHD && PASS == 1) {
+        const int64_t fsize = a.plane * a.nz;
+        for (int ax = 0; ax < ndim; ++ax) scratch[ax * fsize + off] = mu_axis<T, R>(a, f0, s, ax, ndim);
     } else if constexpr (KIND == kCHD) {
+        const int64_t fsize = a.plane * a.nz;
         T Sm[R], S4[R + 1];
         T ctrm = T(0);
         for (int j = 0; j < R; ++j) Sm[j] = T(0);
         for (int ax = 0; ax < ndim; ++ax) {
-            ctrm = ctrm + T(2) * mu_axis<T, R>(a, f0, s, ax, ndim);
+            Field<T> fm{scratch + ax * fsize, a.nx, a.ny, a.nz, a.pitch, a.plane};
+            ctrm = ctrm + T(2) * fm.p[off];
 #pragma unroll
-            for (int j = 1; j <= R; ++j)
-                Sm[j - 1] = Sm[j - 1] + (mu_axis<T, R>(a, f0, shifted(s, ax, j), ax, ndim) +
-                                         mu_axis<T, R>(a, f0, shifted(s, ax, -j), ax, ndim));
+            for (int j = 1; j <= R; ++j) {
+                const Site p = shifted(s, ax, j), m = shifted(s, ax, -j);
+                Sm[j - 1] = Sm[j - 1] + (fm(p.x, p.y, p.z) + fm(m.x, m.y, m.z));
+            }
         }
 #pragma unroll
         for (int j = 1; j <= R + 1; ++j) {
@@ -326,7 +333,7 @@ hipError_t launch_generic(const Launch &L, const void *args, void *scratch, hipS
             dispatch_r(L.r, GenericRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
                 T *sc = static_cast<T *>(scratch);
-                if constexpr (KIND == kCH) {
+                if constexpr (KIND == kCH || KIND == kCHD) {
                     hipLaunchKernelGGL((k_generic<T, KIND, R, 1>), grid, block, 0, s, a, sc, L.ndim);
                     err = hipGetLastError();
                     if (err != hipSuccess) return;

@@ -99,8 +99,9 @@ hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k,
 hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
                                   hipStream_t s);
 
-// Generic per-site family (any r <= kMaxR, 2D and 3D).  CH runs two passes
-// through `scratch` (one field-sized buffer of T, same pitch as the fields).
+// Generic per-site family (any r <= kMaxR, 1D, 2D and 3D).  CH runs two
+// passes through `scratch`: one field-sized buffer of T (same pitch as the
+// fields), ndim of them for the direct biharmonic.
 hipError_t launch_generic(const Launch &L, const void *args, void *scratch, hipStream_t s);
 
 // Standalone reductions of the state buf[.][parity] (no step).

@@ -359,8 +359,9 @@ pf_status set_chunk(Model *m, int32_t chunk)
 
 static pf_status ensure_scratch(Model *m)
 {
-    if (m->family == 0 || m->L.kind != kCH || m->scratch) return PF_OK;
-    PF_HIP(dev_alloc(m, &m->scratch, tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
+    if (m->family == 0 || (m->L.kind != kCH && m->L.kind != kCHD) || m->scratch) return PF_OK;
+    const size_t nbuf = m->L.kind == kCHD ? (size_t)m->desc.ndim : 1;
+    PF_HIP(dev_alloc(m, &m->scratch, nbuf * tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
     return PF_OK;
 }
 
@@ -935,12 +936,27 @@ PF_API int64_t pf_buffer_elems(const pf_desc *desc)
     return buffer_elems(desc);
 }
 
+// Field-sized scratch arrays of the per-site generic kernels (CH: mu; the
+// direct biharmonic: mu_a of every axis), held where the fused kernels do not
+// cover the descriptor (1D and 2D: r <= 4; 3D: CH r <= 3, no direct form).
+static int generic_scratch_arrays(const pf_desc *d)
+{
+    if (d->kind != kCH) return 0;
+    const bool direct = (d->flags & PF_BIHARMONIC_DIRECT) != 0;
+    const int r = d->order / 2;
+    bool fused = !(d->flags & PF_FORCE_GENERIC) && r <= 4;
+    if (d->ndim == 3) fused = fused && !direct && r <= 3;
+    if (fused) return 0;
+    return direct ? d->ndim : 1;
+}
+
 PF_API uint64_t pf_footprint_bytes(const pf_desc *desc)
 {
     if (check_desc(desc) != PF_OK) return 0;
     const uint64_t P = (uint64_t)elem_bytes(desc);
     const uint64_t N = (uint64_t)(desc->n[0] * desc->n[1] * desc->n[2]);
-    uint64_t bytes = 2ull * desc->nfields * (uint64_t)buffer_elems(desc) * P;
+    uint64_t bytes = (2ull * desc->nfields + (uint64_t)generic_scratch_arrays(desc)) *
+                     (uint64_t)buffer_elems(desc) * P;
     // reduction partials (per-wave pairs) and the result block
     bytes += sizeof(double2) * kNumQ * (uint64_t)std::max<int64_t>(reduce_partial_slots((int64_t)N), N / 64 + 1);
     bytes += sizeof(double2) * kNumQ;

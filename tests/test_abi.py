@@ -177,3 +177,18 @@ def test_gray_scott_dt1_in_3d_is_refused():
     h = ctypes.c_void_p()
     assert P.lib().pf_create(ctypes.byref(d), None, ctypes.byref(h)) == P.PF_ERR_UNSTABLE
     assert P.stability(d) > 0.5  # the proposed dt = 0.5 is accepted
+
+
+def test_footprint_counts_generic_temporaries():
+    """The per-site kernels hold field-sized temporaries where the fused ones
+    do not apply: one for Cahn-Hilliard, ndim for the direct biharmonic."""
+    n3, n2 = (64, 64, 64), (256, 256)
+    base3 = P.footprint_bytes(P.make_desc(P.PF_CH, n3, dt=1e-3, order=4))
+    per3 = P.buffer_elems(P.make_desc(P.PF_CH, n3)) * 8
+    d = P.make_desc(P.PF_CH, n3, dt=1e-3, order=4, flags=P.PF_BIHARMONIC_DIRECT)
+    assert P.footprint_bytes(d) == base3 + 3 * per3
+    d = P.make_desc(P.PF_CH, n3, dt=1e-3, order=8)  # radius 4: no fused 3D CH kernel
+    assert P.footprint_bytes(d) == base3 + per3
+    base2 = P.footprint_bytes(P.make_desc(P.PF_CH, n2, dt=1e-3, order=4))
+    d = P.make_desc(P.PF_CH, n2, dt=1e-3, order=4, flags=P.PF_BIHARMONIC_DIRECT)
+    assert P.footprint_bytes(d) == base2  # fused 2D direct kernel: no temporaries

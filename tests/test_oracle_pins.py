@@ -642,3 +642,27 @@ def test_biharmonic_direct_dimension_reduction():
         a = oracle.biharmonic_direct(u, 1, 0.8, order)
         b = oracle.biharmonic_direct(u, 2, 0.8, order)
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("order,composed,direct", [
+    (2, Fraction(-1, 6), Fraction(-1, 6)),
+    (4, Fraction(-1, 45), Fraction(-7, 240)),
+])
+def test_biharmonic_forms_leading_truncation_error(order, composed, direct):
+    """Accuracy of the two forms along one axis: applied to exp(i theta j),
+    each stencil gives theta^4 + C theta^(4 + order) + ...; C follows from
+    the even moments of the weights (Taylor series of cos).  The composed form
+    D2 D2 has C = 2 C2 with C2 the second-derivative constant; the direct
+    fourth-derivative stencil has its own C (Fornberg's table: -1/6 at
+    accuracy 2, -7/240 at accuracy 4), so at accuracy 4 the composed form is
+    the more accurate one, with a wider stencil (radius 4 against 3)."""
+    def coeff(w, k):  # theta^k coefficient of w_0 + 2 sum_j w_j cos(j theta), k even
+        return sum(2 * wj * Fraction((-1) ** (k // 2) * j ** k, math.factorial(k))
+                   for j, wj in enumerate(w) if j > 0)
+    w2 = second_derivative_weights_exact(order)
+    w4 = fourth_derivative_weights_exact(order)
+    k = 4 + order
+    c2 = coeff(w2, 2 + order)           # D2 = -theta^2 + c2 theta^(2+order) + ...
+    assert coeff(w2, 2) == -1 and coeff(w4, 4) == 1
+    assert 2 * (-1) * c2 == composed    # (D2)^2 = theta^4 - 2 c2 theta^(4+order) + ...
+    assert coeff(w4, k) == direct
