@@ -17,6 +17,7 @@ Pieces
                     -ffp-contract=off into oracle/liboracle.so
   oracle/weights.py exact-rational stencil weights (polynomial interpolation)
   oracle/exact.py   Fraction-arithmetic brute force for tiny grids
+  oracle/spectral.py the semi-implicit Fourier spectral step (numpy FFT)
 """
 import ctypes
 import os
@@ -37,6 +38,19 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # loaded in place of the real one through this variable.
 _MUTANT = os.environ.get("PF_ORACLE_MUTANT_LIB")
 _lib = None
+
+# The spectral scheme (numpy); a planted-mistake copy replaces it through
+# PF_ORACLE_SPECTRAL_MUTANT in the same way.
+if os.environ.get("PF_ORACLE_SPECTRAL_MUTANT"):
+    import importlib.util
+    import sys
+    _spec = importlib.util.spec_from_file_location("oracle.spectral",
+                                                   os.environ["PF_ORACLE_SPECTRAL_MUTANT"])
+    spectral = importlib.util.module_from_spec(_spec)
+    _spec.loader.exec_module(spectral)
+    sys.modules["oracle.spectral"] = spectral
+else:
+    from . import spectral  # noqa: E402
 
 
 def build(force=False):

@@ -65,3 +65,29 @@ def test_pins_catch_planted_mistake(name, tmp_path):
                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert res.returncode != 0, "pin suite passed with planted mistake " + name
+
+
+SPECTRAL = os.path.join(ROOT, "oracle", "spectral.py")
+SPECTRAL_MUTANTS = {
+    "sp_ac_sign": ("uh = (uh + dt * nh) / (1.0 + dt * K2)", "uh = (uh - dt * nh) / (1.0 + dt * K2)"),
+    "sp_ch_k2_not_k4": ("(1.0 + dt * K2 * K2)", "(1.0 + dt * K2)"),
+    "sp_ch_drop_k2": ("uh = (uh - dt * K2 * nh)", "uh = (uh - dt * nh)"),
+    "sp_k_without_2pi": ("kx = 2 * np.pi * np.fft.rfftfreq(nx, d=dx)", "kx = np.fft.rfftfreq(nx, d=dx)"),
+    "sp_drop_ky": ("K2 += ky[None, :, None] ** 2", "K2 += 0.0 * ky[None, :, None] ** 2"),
+    "sp_ch_c1_sign": ("return c2 * (u * u * u) - c1 * u", "return c2 * (u * u * u) + c1 * u"),
+    "sp_dx_ignored_in_y": ("np.fft.fftfreq(ny, d=dx)", "np.fft.fftfreq(ny, d=1.0)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SPECTRAL_MUTANTS))
+def test_spectral_pins_catch_planted_mistake(name, tmp_path):
+    old, new = SPECTRAL_MUTANTS[name]
+    src = open(SPECTRAL).read()
+    assert src.count(old) >= 1, "mutation anchor not found: " + name
+    mut = tmp_path / "spectral_mutant.py"
+    mut.write_text(src.replace(old, new))
+    env = dict(os.environ, PF_ORACLE_SPECTRAL_MUTANT=str(mut), OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          os.path.join(ROOT, "tests", "test_oracle_spectral.py")],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, "spectral pins passed with planted mistake " + name
