@@ -68,6 +68,21 @@ def step(kind, u, ndim, dx, dt, params, K2=None):
     return np.fft.irfftn(uh, s=[u.shape[a] for a in ax], axes=ax)
 
 
+def dt_max(kind, params):
+    """Stability limit of the scheme: only the local term is explicit.
+    Linearised about the separated states u^2 = c1/c2, the explicit term has
+    slope a = -2 c1 (Model A: N' = c1 - 3 c2 u^2) or a = 2 c1 (Model B:
+    g' = 3 c2 u^2 - c1), so a mode is multiplied by
+      Model A: (1 + dt a) / (1 + dt K2),      bounded by 1 for all K2 iff dt <= 1 / c1
+      Model B: (1 - dt a K2) / (1 + dt K2^2), bounded by 1 for all K2 iff
+               dt (a K2 - K2^2) <= 2 at K2 = a / 2, i.e. dt <= 8 / a^2 = 2 / c1^2.
+    c1 = 0 leaves no limit (inf)."""
+    c1 = abs(params[0])
+    if c1 == 0.0:
+        return float("inf")
+    return 1.0 / c1 if kind == AC else 2.0 / (c1 * c1)
+
+
 def run(kind, field, ndim, dx, dt, params, nsteps):
     """nsteps semi-implicit steps from `field` ((nz, ny, nx) or (ny, nx))."""
     u = np.asarray(field, dtype=np.float64)

@@ -76,6 +76,8 @@ SPECTRAL_MUTANTS = {
     "sp_drop_ky": ("K2 += ky[None, :, None] ** 2", "K2 += 0.0 * ky[None, :, None] ** 2"),
     "sp_ch_c1_sign": ("return c2 * (u * u * u) - c1 * u", "return c2 * (u * u * u) + c1 * u"),
     "sp_dx_ignored_in_y": ("np.fft.fftfreq(ny, d=dx)", "np.fft.fftfreq(ny, d=1.0)"),
+    "sp_dt_max_ch": ("else 2.0 / (c1 * c1)", "else 4.0 / (c1 * c1)"),
+    "sp_dt_max_ac": ("return 1.0 / c1 if kind == AC", "return 2.0 / c1 if kind == AC"),
 }
 
 

@@ -110,6 +110,27 @@ def test_allen_cahn_uniform_fixed_points():
         assert np.array_equal(out, u)
 
 
+@pytest.mark.parametrize("kind,params", [(AC, [1.0, 1.0]), (AC, [0.6, 1.5]), (CH, [1.0, 1.0]),
+                                         (CH, [0.7, 1.2])])
+def test_dt_max_separates_growth_from_decay(kind, params):
+    """About a separated uniform state u = sqrt(c1/c2), a small perturbation
+    (the uniform shift for Model A, the mode with K2 = c1 for Model B, the
+    most amplified one) decays just below dt_max and grows just above it."""
+    c1, c2 = params
+    u_star = math.sqrt(c1 / c2)
+    n = 16
+    if kind == AC:
+        dx, pert = 1.0, np.full((1, 1, n), 1e-6)
+    else:
+        dx = 2 * math.pi * 2 / (n * math.sqrt(c1))  # mode m = 2 has K2 = c1
+        pert = 1e-6 * _mode((1, 1, n), 1, (0, 0, 2), phase=0.0)
+    lim = spectral.dt_max(kind, params)
+    grow = spectral.run(kind, u_star + pert, 1, dx, 1.03 * lim, params, 300)
+    decay = spectral.run(kind, u_star + pert, 1, dx, 0.97 * lim, params, 300)
+    assert np.max(np.abs(grow - u_star)) > 1e-5
+    assert np.max(np.abs(decay - u_star)) < 1e-6
+
+
 def test_linear_part_is_unconditionally_stable():
     """dt far beyond any explicit limit: with c1 = c2 = 0 every non-constant
     mode of either model decays, and nothing grows."""
