@@ -176,6 +176,41 @@ def run_ch_variant(P, n, prec, steps, warmup, direct, ndim, seed=202):
             "chunk": chunk, "time_block": tb}
 
 
+def run_spectral(P, n, prec, steps, warmup, seed=202):
+    """Semi-implicit Fourier spectral Cahn-Hilliard (Eq. model-b) on a 2D n^2
+    grid, dx = 1, dt = 0.5 (far above the explicit limit), c1 = c2 = 1, c0 =
+    U[-0.05, 0.05]: three hipFFT transforms and two element-wise kernels per
+    step.  `per_site_bytes` is the scheme's minimum HBM traffic per site and
+    step with these transforms (each transform reads and writes its data
+    once, the element-wise kernels likewise)."""
+    d = P.make_desc(P.PF_CH, (n, n), dx=1.0, dt=0.5, order=2, precision=prec,
+                    params=[1.0, 1.0], flags=P.PF_SPECTRAL)
+    m = P.Model(d)
+    m.init(P.PF_IC_UNIFORM, seed, (-0.05, 0.05))
+    m.step(warmup)
+    m.sync()
+    m.timing(True)
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.sync()
+    wall = time.perf_counter() - t0
+    kernel_ms, launches, ksteps = m.timing_read()
+    hi, lo = m.reduce(P.PF_RED_MASS0)
+    m.close()
+    Pb = 8 if prec == P.PF_FP64 else 4
+    # nonlinear: read u, write g (2P); two forward transforms: read P, write ~P
+    # each (half spectrum of 2P-byte complex values); update: read 2 spectra,
+    # write one (3P); inverse: read P, write P
+    per_site = 2 * Pb + 2 * (2 * Pb) + 3 * Pb + 2 * Pb
+    sites = float(n) * n
+    per = kernel_ms / ksteps
+    gbs = per_site * sites / (per * 1e-3) / 1e9
+    return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
+            "kernel_ms": round(per, 4), "per_site_bytes": per_site,
+            "achieved_gbs_of_min_traffic": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4),
+            "mass": hi + lo}
+
+
 def cpu_baseline(n=4096, seconds=10.0, batch=10):
     """The oracle as it stands on the host cores: CH 2D p4 FP64 on an n^2
     sample of the workload, stepped in batches until `seconds` have passed."""
@@ -234,7 +269,7 @@ def main():
     ap.add_argument("--skip-3d", action="store_true")
     ap.add_argument("--skip-mc", action="store_true", help="skip the Model C lines")
     ap.add_argument("--skip-next", action="store_true",
-                    help="skip the direct-biharmonic and 1D lines")
+                    help="skip the direct-biharmonic, 1D and spectral lines")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -279,6 +314,10 @@ def main():
             extra["ch1d_%d_%s" % (args.n * args.n // 4, tag)] = run_ch_variant(
                 P, args.n * args.n // 4, prec, max(10, args.steps // 4), 4, direct=False, ndim=1)
         log("direct biharmonic and 1D done")
+        for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
+            extra["spectral_ch2d_%d_%s" % (args.n // 2, tag)] = run_spectral(
+                P, args.n // 2, prec, max(10, args.steps // 10), 3)
+        log("spectral done")
     extra["fp64_mass_drift"] = fp64["mass_drift"]
     extra["fp64_chunk"] = fp64["chunk"]
     extra["fp64_time_block"] = fp64["time_block"]

@@ -60,7 +60,8 @@ enum {
     PF_USE_GRAPH = 2u,         /* pf_step replays captured HIP graphs of steps */
     PF_REDUCE_EACH_STEP = 4u,  /* fuse the reductions into every step (history) */
     PF_FORCE_GENERIC = 8u,     /* use the simple per-site kernels (testing) */
-    PF_BIHARMONIC_DIRECT = 16u /* Cahn-Hilliard only: direct biharmonic stencil */
+    PF_BIHARMONIC_DIRECT = 16u, /* Cahn-Hilliard only: direct biharmonic stencil */
+    PF_SPECTRAL = 32u           /* Allen-Cahn / Cahn-Hilliard: semi-implicit Fourier step */
 };
 /* Initial conditions for pf_init (counter-based SplitMix64 generator). */
 enum { PF_IC_UNIFORM = 1, PF_IC_GS_CUBES = 2, PF_IC_CONST = 3 };
@@ -92,6 +93,20 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
  *             (radius order/2 + 1, pf_weights4) plus twice the products of
  *             the second-derivative stencils of each axis pair.  At order 2
  *             the two forms are the same stencil.  Not accepted by the server.
+ *             PF_SPECTRAL (PF_AC or PF_CH; not with PF_BIHARMONIC_DIRECT,
+ *             PF_USE_GRAPH or PF_FORCE_GENERIC, else PF_ERR_ARG; N < 2^30)
+ *             replaces the finite-difference step by the semi-implicit
+ *             Fourier spectral step (Sec. "Construction of Semi-Implicit
+ *             Fourier Spectral Scheme"): with k the continuous wavenumbers
+ *             2 pi m / (n dx) and K2 = |k|^2, AC: phi^ <- (phi^ + dt N^) /
+ *             (1 + dt K2), N = c1 phi - c2 phi^3; CH: c^ <- (c^ - dt K2 g^) /
+ *             (1 + dt K2^2), g = c2 c^3 - c1 c.  `order` is checked but
+ *             unused.  Only the local term is explicit: pf_stability gives
+ *             1/c1 (AC) or 2/c1^2 (CH), the limit of the step linearised
+ *             about the separated states c^2 = c1/c2 (+inf for c1 = 0).  The
+ *             mass reductions apply, the free energy is PF_ERR_UNSUPPORTED.
+ *             The model holds two half spectra besides its fields (hipFFT
+ *             plans allocate their own work space).  Not accepted by the server.
  */
 typedef struct pf_desc {
     uint32_t struct_size;

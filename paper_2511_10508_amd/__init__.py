@@ -28,6 +28,7 @@ PF_AC, PF_CH, PF_GS, PF_MC = 1, 2, 3, 4
 PF_FP64, PF_FP32 = 0, 1
 PF_ALLOW_UNSTABLE, PF_USE_GRAPH, PF_REDUCE_EACH_STEP, PF_FORCE_GENERIC = 1, 2, 4, 8
 PF_BIHARMONIC_DIRECT = 16
+PF_SPECTRAL = 32
 PF_IC_UNIFORM, PF_IC_GS_CUBES, PF_IC_CONST = 1, 2, 3
 PF_RED_MASS0, PF_RED_MASS1, PF_RED_ENERGY, PF_RED_NONFINITE = 0, 1, 2, 3
 

@@ -64,7 +64,8 @@ def build(jobs=None, verbose=False, force=True):
                 print(msgs)
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + \
-          [o for o, _ in results] + ["-Wl,-rpath," + os.path.join(ROCM, "lib")]
+          [o for o, _ in results] + ["-L" + os.path.join(ROCM, "lib"), "-lhipfft",
+                                     "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stdout + res.stderr)

@@ -104,6 +104,19 @@ hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k,
 // fields), ndim of them for the direct biharmonic.
 hipError_t launch_generic(const Launch &L, const void *args, void *scratch, hipStream_t s);
 
+// Semi-implicit Fourier spectral step (Models A and B): the explicit term of
+// buf[0][parity] into g (pitched like the fields), and the implicit update of
+// the half spectrum uh from the explicit term's spectrum nh.
+struct SpecArgs {
+    void *uh;              // half spectrum of the state, updated in place
+    const void *nh;        // half spectrum of the explicit term
+    int64_t nxh, ny, nz;   // nx/2 + 1, ny, nz
+    double sx, sy, sz;     // 2 pi / (n_a dx)
+    double dt, inv_n;      // time step, 1 / (nx ny nz)
+};
+hipError_t launch_spectral_nonlinear(const Launch &L, const void *args, void *g, hipStream_t s);
+hipError_t launch_spectral_update(const Launch &L, const SpecArgs &a, hipStream_t s);
+
 // Standalone reductions of the state buf[.][parity] (no step).
 hipError_t launch_reduce_state(const Launch &L, const void *args, hipStream_t s);
 int64_t reduce_partial_slots(int64_t nsites);

@@ -25,7 +25,8 @@ struct Model {
     int parity = 0;
     int64_t steps_done = 0;
 
-    // decomposition of the fused family (family 0) or per-site (family 1)
+    // decomposition of the fused family (family 0), per-site (family 1) or
+    // spectral (family 2)
     int family = 1;
     int tb = 1;                   // time steps fused per launch (2D, r <= 2)
     int rpw_req = 0, rpw = 2;     // 3D tile rows per wave: requested (0: default), in use
@@ -42,7 +43,8 @@ struct Model {
     double2 *hist = nullptr;     // per-step reductions [hist_cap][kNumQ]
     int64_t hist_cap = 0, hist_len = 0;
     double2 *stage = nullptr;    // graph staging rows [kGraphSteps][kNumQ]
-    void *scratch = nullptr;     // CH mu buffer of the per-site family
+    void *scratch = nullptr;     // CH mu buffer(s) of the per-site family
+    void *spec = nullptr;        // spectral scheme state (family 2): plans and half spectra
 
     struct Graph {
         hipGraph_t graph = nullptr;
@@ -81,5 +83,11 @@ pf_status do_steps(Model *m, int64_t nsteps);
 pf_status reduce_now(Model *m, double2 *host_out);
 pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double *hi, double *lo);
 int32_t default_chunk(const pf_desc *d);
+
+// Semi-implicit Fourier spectral scheme (spectral.cpp).
+pf_status spectral_setup(Model *m);
+pf_status spectral_step(Model *m, int par, const void *step_args);
+void spectral_release(Model *m);
+uint64_t spectral_bytes(const pf_desc *d);
 
 }  // namespace pf

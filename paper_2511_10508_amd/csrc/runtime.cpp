@@ -75,6 +75,15 @@ pf_status check_desc(const pf_desc *d)
         if (!std::isfinite(d->params[i])) return fail(PF_ERR_ARG, "parameters must be finite");
     if ((d->flags & PF_BIHARMONIC_DIRECT) && d->kind != kCH)
         return fail(PF_ERR_ARG, "PF_BIHARMONIC_DIRECT applies to Cahn-Hilliard only");
+    if (d->flags & PF_SPECTRAL) {
+        if (d->kind != kAC && d->kind != kCH)
+            return fail(PF_ERR_ARG, "PF_SPECTRAL applies to Allen-Cahn and Cahn-Hilliard only");
+        if (d->flags & (PF_BIHARMONIC_DIRECT | PF_USE_GRAPH | PF_FORCE_GENERIC))
+            return fail(PF_ERR_ARG, "PF_SPECTRAL takes no PF_BIHARMONIC_DIRECT, PF_USE_GRAPH "
+                                    "or PF_FORCE_GENERIC");
+        if (d->n[0] > (1 << 30) / std::max<int64_t>(1, d->n[1] * d->n[2]))
+            return fail(PF_ERR_ARG, "PF_SPECTRAL grids must hold fewer than 2^30 sites");
+    }
     if (d->kind == kGS)
         for (int i = 0; i < np; ++i)
             if (d->params[i] < 0.0) return fail(PF_ERR_ARG, "Gray-Scott parameters must be >= 0");
@@ -83,6 +92,15 @@ pf_status check_desc(const pf_desc *d)
 
 double stability_limit(const pf_desc *d)
 {
+    // spectral scheme: the Laplacian terms are implicit and only the local
+    // term is explicit; linearised about the separated states (u^2 = c1/c2,
+    // explicit slope -2 c1 for AC, +2 c1 for CH) every mode stays bounded for
+    // dt <= 1/c1 (AC) and dt <= 2/c1^2 (CH); c1 = 0 leaves no limit
+    if (d->flags & PF_SPECTRAL) {
+        const double c1 = std::fabs(d->params[0]);
+        if (c1 == 0.0) return HUGE_VAL;
+        return d->kind == kAC ? 1.0 / c1 : 2.0 / (c1 * c1);
+    }
     double w[kMaxR + 1];
     centered_d2_weights(d->order, w);
     double sigma = w[0];
@@ -214,6 +232,11 @@ static bool plan(Model *m)
     Launch L = m->L;
     const pf_desc &d = m->desc;
     m->family = 1;
+    if (d.flags & PF_SPECTRAL) {
+        m->family = 2;
+        m->tb = 1;
+        return true;
+    }
     if (!time_block_available(L)) m->tb = 1;
     if (d.flags & PF_FORCE_GENERIC) {
         m->tb = 1;
@@ -422,12 +445,19 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
             e = launch_finalize(m->part, m->pstride, reduce_partial_slots(N), m->part2, res, m->stream);
             if (e != hipSuccess) return hip_fail(e, "finalize launch");
         }
-        pf_status st = ensure_scratch(m);
-        if (st != PF_OK) return st;
-        if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
-        hipError_t e = launch_generic(m->L, ap, m->scratch, m->stream);
-        if (e != hipSuccess) return hip_fail(e, "generic step launch");
-        if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
+        if (m->family == 2) {
+            if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
+            pf_status st = spectral_step(m, par, ap);
+            if (st != PF_OK) return st;
+            if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
+        } else {
+            pf_status st = ensure_scratch(m);
+            if (st != PF_OK) return st;
+            if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
+            hipError_t e = launch_generic(m->L, ap, m->scratch, m->stream);
+            if (e != hipSuccess) return hip_fail(e, "generic step launch");
+            if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
+        }
     }
     m->launches++;
     m->timed_steps += timed ? tb : 0;
@@ -591,6 +621,8 @@ pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double 
     case PF_RED_ENERGY:
         if (d.kind == kGS || d.kind == kMC)
             return fail(PF_ERR_UNSUPPORTED, "free energy is reduced for Allen-Cahn and Cahn-Hilliard only");
+        if (d.flags & PF_SPECTRAL)
+            return fail(PF_ERR_UNSUPPORTED, "no free energy for the spectral scheme");
         *hi = q[1].x * vol;
         *lo = q[1].y * vol;
         return PF_OK;
@@ -692,6 +724,7 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
         }
     }
     st = set_chunk(m, chunk);
+    if (st == PF_OK && (desc->flags & PF_SPECTRAL)) st = spectral_setup(m);
     if (st != PF_OK) {
         pf_destroy_model(m);
         return st;
@@ -719,6 +752,7 @@ void model_release_async(Model *m)
     dev_free(m, m->hist);
     dev_free(m, m->stage);
     dev_free(m, m->scratch);
+    spectral_release(m);
     destroy_graphs(m);
     for (auto ev : m->events) (void)hipEventDestroy(ev);
     delete m;
@@ -746,6 +780,7 @@ void pf_destroy_model(Model *m)
     if (m->hist) hipFree(m->hist);
     if (m->stage) hipFree(m->stage);
     if (m->scratch) hipFree(m->scratch);
+    spectral_release(m);
     for (auto ev : m->events) hipEventDestroy(ev);
     if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
     delete m;
@@ -957,6 +992,7 @@ PF_API uint64_t pf_footprint_bytes(const pf_desc *desc)
     const uint64_t N = (uint64_t)(desc->n[0] * desc->n[1] * desc->n[2]);
     uint64_t bytes = (2ull * desc->nfields + (uint64_t)generic_scratch_arrays(desc)) *
                      (uint64_t)buffer_elems(desc) * P;
+    if (desc->flags & PF_SPECTRAL) bytes += spectral_bytes(desc);
     // reduction partials (per-wave pairs) and the result block
     bytes += sizeof(double2) * kNumQ * (uint64_t)std::max<int64_t>(reduce_partial_slots((int64_t)N), N / 64 + 1);
     bytes += sizeof(double2) * kNumQ;

@@ -192,3 +192,30 @@ def test_footprint_counts_generic_temporaries():
     base2 = P.footprint_bytes(P.make_desc(P.PF_CH, n2, dt=1e-3, order=4))
     d = P.make_desc(P.PF_CH, n2, dt=1e-3, order=4, flags=P.PF_BIHARMONIC_DIRECT)
     assert P.footprint_bytes(d) == base2  # fused 2D direct kernel: no temporaries
+
+
+def test_spectral_host_logic():
+    """PF_SPECTRAL: Models A and B only, no explicit limit, two half spectra
+    in the footprint; refused combinations fail before touching the device."""
+    d = P.make_desc(P.PF_CH, (100, 64), dt=1.0, params=[0.8, 1.0], flags=P.PF_SPECTRAL)
+    assert math.isclose(P.stability(d), oracle.spectral.dt_max(2, [0.8, 1.0]), rel_tol=1e-15)
+    d = P.make_desc(P.PF_AC, (100, 64), dt=1.0, params=[0.8, 1.0], flags=P.PF_SPECTRAL)
+    assert math.isclose(P.stability(d), oracle.spectral.dt_max(1, [0.8, 1.0]), rel_tol=1e-15)
+    d = P.make_desc(P.PF_CH, (100, 64), dt=1.0, params=[0.0, 1.0], flags=P.PF_SPECTRAL)
+    assert math.isinf(P.stability(d))
+    d = P.make_desc(P.PF_CH, (100, 64), dt=1.0, flags=P.PF_SPECTRAL)
+    h = ctypes.c_void_p()
+    d.dt = 2.5  # above 2 / c1^2
+    assert P.lib().pf_create(ctypes.byref(d), None, ctypes.byref(h)) == P.PF_ERR_UNSTABLE
+    d.dt = 1.0
+    plain = P.footprint_bytes(P.make_desc(P.PF_CH, (100, 64), dt=1e-3))
+    assert P.footprint_bytes(d) == plain + 2 * 51 * 64 * 16
+    d32 = P.make_desc(P.PF_AC, (100, 64), dt=0.5, precision=P.PF_FP32, flags=P.PF_SPECTRAL)
+    plain32 = P.footprint_bytes(P.make_desc(P.PF_AC, (100, 64), dt=1e-3, precision=P.PF_FP32))
+    assert P.footprint_bytes(d32) == plain32 + 2 * 51 * 64 * 8
+    for kind, flags in ((P.PF_GS, 0), (P.PF_MC, 0), (P.PF_CH, P.PF_BIHARMONIC_DIRECT),
+                        (P.PF_CH, P.PF_USE_GRAPH), (P.PF_AC, P.PF_FORCE_GENERIC)):
+        bad = P.make_desc(kind, (32, 32), dt=1e-3, flags=P.PF_SPECTRAL | flags)
+        h = ctypes.c_void_p()
+        assert P.lib().pf_create(ctypes.byref(bad), None, ctypes.byref(h)) == P.PF_ERR_ARG
+        assert b"PF_SPECTRAL" in P.lib().pf_last_error()
