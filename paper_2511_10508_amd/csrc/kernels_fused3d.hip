@@ -4,15 +4,19 @@
 
 namespace pf {
 
-// Gray-Scott and Allen-Cahn: r <= 4; Cahn-Hilliard (halo 2r): r <= 3.
+// Gray-Scott and Allen-Cahn: r <= 4; Cahn-Hilliard (halo 2r): r <= 3; the
+// direct biharmonic (two rings of 2r+3 planes in 128 registers): r <= 2.
 using Fused3DRadii = RList<1, 2, 3, 4>;
 using Fused3DRadiiCH = RList<1, 2, 3>;
+using Fused3DRadiiCHD = RList<1, 2>;
 
 template <int KIND, typename F>
 bool dispatch_r3d(int r, F &&f)
 {
     if constexpr (KIND == kCH)
         return dispatch_r(r, Fused3DRadiiCH{}, f);
+    else if constexpr (KIND == kCHD)
+        return dispatch_r(r, Fused3DRadiiCHD{}, f);
     else
         return dispatch_r(r, Fused3DRadii{}, f);
 }
@@ -33,12 +37,14 @@ bool dispatch3d(const Launch &L, int tb, F &&f)
 {
     bool ok = false;
     dispatch_prec(L.fp32, [&](auto tz) {
-        dispatch_kind(L.kind, [&](auto kc) {
+        dispatch_kind_all(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
-            if (tb == 2)
-                ok = dispatch_r(L.r, TimeBlockRadii3D{}, [&](auto rc) {
-                    f(tz, kc, rc, std::integral_constant<int, 2>{});
-                });
+            if (tb == 2) {
+                if constexpr (KIND != kCHD)  // no two-step direct-biharmonic kernel
+                    ok = dispatch_r(L.r, TimeBlockRadii3D{}, [&](auto rc) {
+                        f(tz, kc, rc, std::integral_constant<int, 2>{});
+                    });
+            }
             else if (tb == 1)
                 ok = dispatch_r3d<KIND>(L.r, [&](auto rc) {
                     f(tz, kc, rc, std::integral_constant<int, 1>{});

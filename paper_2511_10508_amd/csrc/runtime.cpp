@@ -973,14 +973,14 @@ PF_API int64_t pf_buffer_elems(const pf_desc *desc)
 
 // Field-sized scratch arrays of the per-site generic kernels (CH: mu; the
 // direct biharmonic: mu_a of every axis), held where the fused kernels do not
-// cover the descriptor (1D and 2D: r <= 4; 3D: CH r <= 3, no direct form).
+// cover the descriptor (1D and 2D: r <= 4; 3D: CH r <= 3, direct form r <= 2).
 static int generic_scratch_arrays(const pf_desc *d)
 {
     if (d->kind != kCH) return 0;
     const bool direct = (d->flags & PF_BIHARMONIC_DIRECT) != 0;
     const int r = d->order / 2;
     bool fused = !(d->flags & PF_FORCE_GENERIC) && r <= 4;
-    if (d->ndim == 3) fused = fused && !direct && r <= 3;
+    if (d->ndim == 3) fused = fused && r <= (direct ? 2 : 3);
     if (fused) return 0;
     return direct ? d->ndim : 1;
 }

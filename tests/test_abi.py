@@ -185,8 +185,10 @@ def test_footprint_counts_generic_temporaries():
     n3, n2 = (64, 64, 64), (256, 256)
     base3 = P.footprint_bytes(P.make_desc(P.PF_CH, n3, dt=1e-3, order=4))
     per3 = P.buffer_elems(P.make_desc(P.PF_CH, n3)) * 8
+    d = P.make_desc(P.PF_CH, n3, dt=1e-4, order=6, flags=P.PF_BIHARMONIC_DIRECT)
+    assert P.footprint_bytes(d) == base3 + 3 * per3  # radius 3: no fused 3D direct kernel
     d = P.make_desc(P.PF_CH, n3, dt=1e-3, order=4, flags=P.PF_BIHARMONIC_DIRECT)
-    assert P.footprint_bytes(d) == base3 + 3 * per3
+    assert P.footprint_bytes(d) == base3
     d = P.make_desc(P.PF_CH, n3, dt=1e-3, order=8)  # radius 4: no fused 3D CH kernel
     assert P.footprint_bytes(d) == base3 + per3
     base2 = P.footprint_bytes(P.make_desc(P.PF_CH, n2, dt=1e-3, order=4))

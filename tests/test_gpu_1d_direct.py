@@ -2,8 +2,8 @@
 biharmonic stencil, against the CPU FP64 oracle.
 
 1D grids (ndim = 1) run their own strip-marching kernels; the direct
-biharmonic (PF_BIHARMONIC_DIRECT) has fused 1D and 2D kernels and runs the
-per-site generic kernel in 3D.  Tolerances as in the other parity tests:
+biharmonic (PF_BIHARMONIC_DIRECT) has fused 1D, 2D and 3D (r <= 2) kernels
+and runs the per-site generic kernel beyond them.  Tolerances as in the other parity tests:
 max |GPU - oracle| <= 1e-12 (FP64 storage) and <= 1e-4 (FP32 storage) after
 100 steps; kernel family, strip layout, two-step blocking and graph replay
 are checked bitwise.
@@ -192,7 +192,8 @@ def test_1d_graph_replay_equals_eager_bitwise():
 # --------------------------------------------------- direct biharmonic --
 
 CASES_D = [(2, (1, 75, 301), 32, o) for o in (2, 4, 6, 8)]
-CASES_D += [(2, (1, 40, 90), 16, 10), (3, (13, 17, 40), 8, 2), (3, (11, 14, 33), 8, 4)]
+CASES_D += [(2, (1, 40, 90), 16, 10), (3, (13, 17, 40), 8, 2), (3, (11, 14, 33), 8, 4),
+            (3, (21, 37, 150), 8, 2), (3, (19, 35, 140), 6, 4), (3, (9, 12, 30), 4, 6)]
 
 
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
@@ -205,19 +206,22 @@ def test_direct_biharmonic_parity_100_steps(case, prec):
     f0 = fields_for(CHD, shape, 17)
     ref = oracle_run(CHD, f0, ndim, order, params, dt, 100)
     got, m = gpu_run(CHD, f0, ndim, order, prec, params, dt, 100, chunk=chunk)
-    assert m.tile()[1] == (0 if ndim == 2 and order <= 8 else 1)
+    fused = (ndim == 2 and order <= 8) or (ndim == 3 and order <= 4)
+    assert m.tile()[1] == (0 if fused else 1)
     err = float(np.max(np.abs(got[0] - ref[0])))
     assert err <= TOL[prec], err
 
 
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("order", [2, 4, 6])
-def test_direct_biharmonic_fused_equals_generic_bitwise(order, prec):
+@pytest.mark.parametrize("ndim,shape,order", [(2, (1, 67, 277), 2), (2, (1, 67, 277), 4),
+                                              (2, (1, 67, 277), 6), (3, (19, 35, 140), 2),
+                                              (3, (19, 35, 140), 4)])
+def test_direct_biharmonic_fused_equals_generic_bitwise(ndim, shape, order, prec):
     params = BASE[CHD][0]
-    dt = dt_for(CHD, 2, order, params)
-    f0 = fields_for(CHD, (1, 67, 277), 5)
-    a, ma = gpu_run(CHD, f0, 2, order, prec, params, dt, 30, chunk=16)
-    b, mb = gpu_run(CHD, f0, 2, order, prec, params, dt, 30, flags=P.PF_FORCE_GENERIC)
+    dt = dt_for(CHD, ndim, order, params)
+    f0 = fields_for(CHD, shape, 5)
+    a, ma = gpu_run(CHD, f0, ndim, order, prec, params, dt, 30, chunk=16 if ndim == 2 else 7)
+    b, mb = gpu_run(CHD, f0, ndim, order, prec, params, dt, 30, flags=P.PF_FORCE_GENERIC)
     assert ma.tile()[1] == 0 and mb.tile()[1] == 1
     assert np.array_equal(a[0], b[0])
 
@@ -246,7 +250,7 @@ def test_direct_biharmonic_order2_is_the_composed_scheme():
 
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("ndim,shape,generic", [(2, (1, 64, 250), False), (2, (1, 30, 40), True),
-                                                (3, (12, 20, 30), True)])
+                                                (3, (12, 20, 30), True), (3, (14, 40, 70), False)])
 def test_direct_biharmonic_history_and_mass(ndim, shape, generic, prec):
     """Fused reductions of the direct scheme: mass and energy of the state at
     the start of every step, and mass conservation over the run."""
