@@ -1,8 +1,8 @@
 """CPU FP64 oracle for the explicit finite-difference phase-field step.
 
 TEST INFRASTRUCTURE ONLY.  A plain, slow, obviously correct implementation of
-what the GPU library computes (SymPhas 2.0, arXiv 2511.10508: Models A, B and
-C, Eqs. model-a, model-b and model-c; Gray-Scott as named in the
+what the GPU library computes (SymPhas 2.0, arXiv 2511.10508: Models A, B, C
+and H, Eqs. model-a, model-b, model-c and model-h; Gray-Scott as named in the
 Introduction), used by
 the tests, by the smoke check and by the CPU-baseline leg of the benchmark.
 The product library never imports or links it, and it imports nothing from
@@ -25,11 +25,16 @@ import subprocess
 
 import numpy as np
 
-from .weights import (fourth_derivative_weights, fourth_derivative_weights_exact,
+from .weights import (first_derivative_weights, first_derivative_weights_exact,
+                      fourth_derivative_weights, fourth_derivative_weights_exact,
                       second_derivative_weights, second_derivative_weights_exact)
 
-AC, CH, GS, MC = 1, 2, 3, 4
-NFIELDS = {AC: 1, CH: 1, GS: 2, MC: 2}
+AC, CH, GS, MC, MH = 1, 2, 3, 4, 5
+NFIELDS = {AC: 1, CH: 1, GS: 2, MC: 2}  # Model H: 1 + ndim (nfields())
+
+
+def nfields(kind, ndim):
+    return 1 + ndim if kind == MH else NFIELDS[kind]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -89,6 +94,10 @@ def _load():
     lib.orc_rhs_chd.restype = None
     lib.orc_run_chd.argtypes = [i32, pi64, d, d, i32, pd, i32, pd, pd, pd, i64]
     lib.orc_run_chd.restype = None
+    lib.orc_rhs_mh.argtypes = [i32, pi64, d, i32, pd, pd, pd, pd, pd]
+    lib.orc_rhs_mh.restype = None
+    lib.orc_run_mh.argtypes = [i32, pi64, d, d, i32, pd, pd, pd, pd, i64]
+    lib.orc_run_mh.restype = None
     lib.orc_exact_sum.argtypes = [pd, i64, i64]
     lib.orc_exact_sum.restype = d
     lib.orc_energy_density.argtypes = [i32, pi64, d, i32, pd, pd, pd, pd]
@@ -173,11 +182,16 @@ def rhs(kind, fields, ndim, dx, order, params, biharmonic="composed"):
     lib = _load()
     direct = _check_biharmonic(kind, biharmonic)
     st, shape = _stack(fields)
-    if st.shape[0] != NFIELDS[kind]:
+    if st.shape[0] != nfields(kind, ndim):
         raise ValueError("wrong number of fields")
     out = np.empty_like(st)
     w = _w(order)
     p = np.asarray(list(params) + [0.0] * (4 - len(params)), dtype=np.float64)
+    if kind == MH:
+        w1 = np.asarray(first_derivative_weights(order), dtype=np.float64)
+        lib.orc_rhs_mh(ndim, _dims(shape), dx, order // 2, _dptr(w), _dptr(w1), _dptr(p),
+                       _dptr(st), _dptr(out))
+        return [out[f] for f in range(st.shape[0])]
     if direct:
         w4 = _w4(order)
         lib.orc_rhs_chd(ndim, _dims(shape), dx, order // 2, _dptr(w), order // 2 + 1, _dptr(w4),
@@ -193,10 +207,15 @@ def run(kind, fields, ndim, dx, dt, order, params, nsteps, biharmonic="composed"
     lib = _load()
     direct = _check_biharmonic(kind, biharmonic)
     st, shape = _stack(fields)
-    if st.shape[0] != NFIELDS[kind]:
+    if st.shape[0] != nfields(kind, ndim):
         raise ValueError("wrong number of fields")
     w = _w(order)
     p = np.asarray(list(params) + [0.0] * (4 - len(params)), dtype=np.float64)
+    if kind == MH:
+        w1 = np.asarray(first_derivative_weights(order), dtype=np.float64)
+        lib.orc_run_mh(ndim, _dims(shape), dx, dt, order // 2, _dptr(w), _dptr(w1), _dptr(p),
+                       _dptr(st), int(nsteps))
+        return [st[f].copy() for f in range(st.shape[0])]
     if direct:
         w4 = _w4(order)
         lib.orc_run_chd(ndim, _dims(shape), dx, dt, order // 2, _dptr(w), order // 2 + 1,
@@ -228,7 +247,8 @@ def energy_density(x, ndim, dx, order, params):
 
 
 def reduce(kind, fields, ndim, dx, order, params):
-    """(mass list, energy or None, nonfinite count) of a state, summed exactly."""
+    """(mass list, energy or None, nonfinite count) of a state, summed exactly
+    (Model H: the mass and non-finite count of m only)."""
     lib = _load()
     st, shape = _stack(fields)
     w = _w(order)
@@ -239,7 +259,7 @@ def reduce(kind, fields, ndim, dx, order, params):
                          _dptr(st), _dptr(mass), _dptr(energy))
     if bad:
         return None, None, int(bad)
-    m = [float(mass[f]) for f in range(NFIELDS[kind])]
+    m = [float(mass[f]) for f in range(1 if kind == MH else NFIELDS[kind])]
     return m, (float(energy[0]) if kind in (AC, CH) else None), 0
 
 
@@ -257,12 +277,18 @@ def dt_max(kind, ndim, dx, order, params, biharmonic="composed"):
       GS: max(Du, Dv) |lam*| + F + k + 1     (u, v in [0, 1])
       MC: |lam*| + 2 c1        (as AC: linearisation about small phi, rho;
                                 rho alone diffuses with |lam*|)
+      MH: max(lam*^2 + 2 c1 |lam*|, |lam*|)  (m as CH, each j_a diffuses;
+                                the couplings are products of small terms)
     """
     w = second_derivative_weights_exact(order)
     sigma = w[0] + 2 * sum(wj * (-1) ** j for j, wj in enumerate(w) if j > 0)
     lam = abs(float(sigma)) * ndim / (dx * dx)
     direct = _check_biharmonic(kind, biharmonic)
-    if kind in (AC, MC):
+    if kind == MH:
+        # linearised about small m and j the couplings (products of small
+        # quantities) drop out: m as Cahn-Hilliard, each j_a diffuses
+        rho = max(lam * lam + 2 * abs(params[0]) * lam, lam)
+    elif kind in (AC, MC):
         rho = lam + 2 * abs(params[0])
     elif kind == CH and direct:
         w4 = fourth_derivative_weights_exact(order)

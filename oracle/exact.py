@@ -8,7 +8,8 @@ Python loops: use grids of a few dozen sites and a handful of steps.
 """
 from fractions import Fraction
 
-from .weights import fourth_derivative_weights_exact, second_derivative_weights_exact
+from .weights import (first_derivative_weights_exact, fourth_derivative_weights_exact,
+                      second_derivative_weights_exact)
 
 
 def _lap(u, shape, ndim, dx, w):
@@ -46,6 +47,22 @@ def _axis(u, shape, a, scale, w):
     return out
 
 
+def _d1(u, shape, a, dx, w1):
+    """Centred first derivative along axis a (antisymmetric weights w1)."""
+    nz, ny, nx = shape
+    out = {}
+    for (z, y, x) in u:
+        acc = Fraction(0)
+        for k in range(1, len(w1)):
+            d = [0, 0, 0]
+            d[a] = k
+            up = u[((z + d[2]) % nz, (y + d[1]) % ny, (x + d[0]) % nx)]
+            um = u[((z - d[2]) % nz, (y - d[1]) % ny, (x - d[0]) % nx)]
+            acc += w1[k] / dx * (up - um)
+        out[(z, y, x)] = acc
+    return out
+
+
 def biharmonic_direct_exact(u, shape, ndim, dx, w, w4):
     """sum_a D4_a u + 2 sum_{a<b} D2_a D2_b u in Fractions (u: dict site -> value)."""
     out = {k: Fraction(0) for k in u}
@@ -66,6 +83,7 @@ def run_exact(kind, fields, ndim, dx, dt, order, params, nsteps, biharmonic="com
     biharmonic="direct": Cahn-Hilliard as L g - B c with the direct stencil."""
     w = second_derivative_weights_exact(order)
     w4 = fourth_derivative_weights_exact(order)
+    w1 = first_derivative_weights_exact(order)
     shape = (len(fields[0]), len(fields[0][0]), len(fields[0][0][0]))
     nz, ny, nx = shape
     keys = [(z, y, x) for z in range(nz) for y in range(ny) for x in range(nx)]
@@ -77,6 +95,24 @@ def run_exact(kind, fields, ndim, dx, dt, order, params, nsteps, biharmonic="com
             c1, c2 = P[0], P[1]
             L = _lap(F[0], shape, ndim, dx, w)
             F = [{k: F[0][k] + dt * (L[k] + c1 * F[0][k] - c2 * F[0][k] ** 3) for k in keys}]
+        elif kind == 5:
+            c1, c2, c3 = P[0], P[1], P[2]
+            m = F[0]
+            Lm = _lap(m, shape, ndim, dx, w)
+            mu = {k: c2 * m[k] ** 3 - c1 * m[k] - Lm[k] for k in keys}
+            dm = _lap(mu, shape, ndim, dx, w)
+            newF = []
+            for a in range(ndim):
+                ja = F[1 + a]
+                div = _d1({k: m[k] * ja[k] for k in keys}, shape, a, dx, w1)
+                dm = {k: dm[k] - c3 * div[k] for k in keys}
+            newF.append({k: m[k] + dt * dm[k] for k in keys})
+            for a in range(ndim):
+                ja = F[1 + a]
+                Lj = _lap(ja, shape, ndim, dx, w)
+                gmu = _d1(mu, shape, a, dx, w1)
+                newF.append({k: ja[k] + dt * (Lj[k] + c3 * m[k] * gmu[k]) for k in keys})
+            F = newF
         elif kind == 2 and biharmonic == "direct":
             c1, c2 = P[0], P[1]
             Lg = _lap({k: c2 * F[0][k] ** 3 - c1 * F[0][k] for k in keys}, shape, ndim, dx, w)

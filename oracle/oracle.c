@@ -29,6 +29,7 @@
  *       dv/dt = Dv lap(v) + u v^2 - (F + k) v
  *   Model C, Eq. (model-c):  dphi/dt = lap(phi) + c1 phi - c2 phi^3 - 2 phi rho
  *                            drho/dt = lap(rho + c3 phi^2)
+ *   Model H, Eq. (model-h), transverse projector one: orc_rhs_mh below.
  * Cahn-Hilliard also comes with a direct biharmonic stencil in place of the
  * Laplacian applied twice (orc_rhs_chd below).
  * The time integrator is forward Euler, Jacobi style: every right-hand side
@@ -253,6 +254,83 @@ void orc_rhs_chd(int ndim, const int64_t n[3], double dx, int r, const double *w
     for (int64_t i = 0; i < N; ++i) rhs[i] = rhs[i] - b[i];
     free(g);
     free(b);
+}
+
+/*
+ * Model H (Eq. model-h) with the transverse projector set to one, as the
+ * paper does: a conserved scalar m and a vector field j of ndim components,
+ *   dm/dt = L mu - c3 div(m j),         mu = c2 m^3 - c1 m - L m
+ *   dj/dt = L j - c3 m grad(L m + c1 m - c2 m^3) = L j + c3 m grad(mu)
+ * (Sec. "Model H": the equation as printed).  grad and div use the centred
+ * first-derivative stencil of accuracy p (radius r, antisymmetric weights
+ * w1[1..r]):  (D1_a u)_i = sum_k (w1_k / dx) (u_{i + k e_a} - u_{i - k e_a}).
+ * params {c1, c2, c3}; in/rhs hold 1 + ndim arrays (m, then j_x, j_y, j_z).
+ */
+static void orc_d1(int a, const int64_t n[3], double dx, int r, const double *w1,
+                   const double *u, double *out)
+{
+    const double inv_dx = 1.0 / dx;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < n[2]; ++z)
+        for (int64_t y = 0; y < n[1]; ++y)
+            for (int64_t x = 0; x < n[0]; ++x) {
+                double acc = 0.0;
+                for (int k = 1; k <= r; ++k) {
+                    int64_t dp[3] = {0, 0, 0};
+                    dp[a] = k;
+                    const double up = u[site(n, x + dp[0], y + dp[1], z + dp[2])];
+                    const double um = u[site(n, x - dp[0], y - dp[1], z - dp[2])];
+                    acc = acc + (w1[k] * inv_dx) * (up - um);
+                }
+                out[site(n, x, y, z)] = acc;
+            }
+}
+
+void orc_rhs_mh(int ndim, const int64_t n[3], double dx, int r, const double *w,
+                const double *w1, const double *params, const double *in, double *rhs)
+{
+    const int64_t N = nsites(n);
+    const double c1 = params[0], c2 = params[1], c3 = params[2];
+    const double *m = in;
+    double *lap = (double *)malloc(sizeof(double) * (size_t)N);
+    double *mu = (double *)malloc(sizeof(double) * (size_t)N);
+    double *t = (double *)malloc(sizeof(double) * (size_t)N);
+    double *d = (double *)malloc(sizeof(double) * (size_t)N);
+    orc_laplacian(ndim, n, dx, r, w, m, lap);
+    for (int64_t i = 0; i < N; ++i) mu[i] = (c2 * (m[i] * m[i] * m[i]) - c1 * m[i]) - lap[i];
+    /* dm/dt = L mu - c3 sum_a D1_a (m j_a) */
+    orc_laplacian(ndim, n, dx, r, w, mu, rhs);
+    for (int a = 0; a < ndim; ++a) {
+        const double *ja = in + (int64_t)(1 + a) * N;
+        for (int64_t i = 0; i < N; ++i) t[i] = m[i] * ja[i];
+        orc_d1(a, n, dx, r, w1, t, d);
+        for (int64_t i = 0; i < N; ++i) rhs[i] = rhs[i] - c3 * d[i];
+    }
+    /* dj_a/dt = L j_a + c3 m D1_a mu */
+    for (int a = 0; a < ndim; ++a) {
+        const double *ja = in + (int64_t)(1 + a) * N;
+        double *ra = rhs + (int64_t)(1 + a) * N;
+        orc_laplacian(ndim, n, dx, r, w, ja, ra);
+        orc_d1(a, n, dx, r, w1, mu, d);
+        for (int64_t i = 0; i < N; ++i) ra[i] = ra[i] + c3 * (m[i] * d[i]);
+    }
+    free(lap);
+    free(mu);
+    free(t);
+    free(d);
+}
+
+/* nsteps forward-Euler steps of orc_rhs_mh, in place on 1 + ndim fields. */
+void orc_run_mh(int ndim, const int64_t n[3], double dx, double dt, int r, const double *w,
+                const double *w1, const double *params, double *fields, int64_t nsteps)
+{
+    const int64_t M = nsites(n) * (1 + ndim);
+    double *rhs = (double *)malloc(sizeof(double) * (size_t)M);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        orc_rhs_mh(ndim, n, dx, r, w, w1, params, fields, rhs);
+        for (int64_t i = 0; i < M; ++i) fields[i] = fields[i] + dt * rhs[i];
+    }
+    free(rhs);
 }
 
 /* nsteps forward-Euler steps of orc_rhs_chd, in place. */

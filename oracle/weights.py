@@ -92,6 +92,29 @@ def _solve(rows):
     return [rows[i][nvar] for i in range(nvar)]
 
 
+def first_derivative_weights_exact(order):
+    """Exact centred first-derivative weights [0, w_1, .., w_r], r = order/2
+    (antisymmetric: w_{-j} = -w_j, w_0 = 0).
+
+    The same construction for the derivative of order 1: exact on the odd
+    monomials up to degree 2r - 1, i.e. 2 sum_{j=1..r} w_j j^k = 1 if k == 1
+    else 0 for k = 1, 3, .., 2r - 1 (even k hold by antisymmetry).
+    """
+    if order < 2 or order % 2:
+        raise ValueError("accuracy order must be an even integer >= 2")
+    r = order // 2
+    rows = []
+    for m in range(r):
+        k = 2 * m + 1
+        rows.append([Fraction(2 * j ** k) for j in range(1, r + 1)] + [Fraction(1 if k == 1 else 0)])
+    return [Fraction(0)] + _solve(rows)
+
+
+def first_derivative_weights(order):
+    """FP64 first-derivative weights [0, w_1..w_r], each rounded once."""
+    return [float(w) for w in first_derivative_weights_exact(order)]
+
+
 def fourth_derivative_weights(order):
     """FP64 fourth-derivative weights [w_0..w_r4], each rounded to nearest once."""
     return [float(w) for w in fourth_derivative_weights_exact(order)]

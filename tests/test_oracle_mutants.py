@@ -46,6 +46,12 @@ MUTANTS = {
     "chd_d4_skip_last_j": ("for (int j = 1; j <= r; ++j) {\n                    int64_t dp",
                            "for (int j = 1; j < r; ++j) {\n                    int64_t dp"),
     "chd_drop_c1": ("g[i] = c2 * (c * c * c) - c1 * c;", "g[i] = c2 * (c * c * c);"),
+    "mh_div_sign": ("rhs[i] = rhs[i] - c3 * d[i];", "rhs[i] = rhs[i] + c3 * d[i];"),
+    "mh_grad_sign": ("ra[i] = ra[i] + c3 * (m[i] * d[i]);", "ra[i] = ra[i] - c3 * (m[i] * d[i]);"),
+    "mh_d1_direction": ("acc = acc + (w1[k] * inv_dx) * (up - um);", "acc = acc + (w1[k] * inv_dx) * (um - up);"),
+    "mh_div_of_j_only": ("t[i] = m[i] * ja[i];", "t[i] = ja[i];"),
+    "mh_grad_of_m_not_mu": ("orc_d1(a, n, dx, r, w1, mu, d);", "orc_d1(a, n, dx, r, w1, m, d);"),
+    "mh_j_laplacian_of_m": ("orc_laplacian(ndim, n, dx, r, w, ja, ra);", "orc_laplacian(ndim, n, dx, r, w, m, ra);"),
     "chd_mixed_includes_diagonal": ("for (int b = a + 1; b < ndim; ++b) {", "for (int b = a; b < ndim; ++b) {"),
 }
 

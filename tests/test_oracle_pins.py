@@ -14,7 +14,8 @@ import pytest
 import oracle
 from oracle import AC, CH, GS, MC
 from oracle.exact import run_exact
-from oracle.weights import fourth_derivative_weights_exact, second_derivative_weights_exact
+from oracle.weights import (first_derivative_weights_exact, fourth_derivative_weights_exact,
+                            second_derivative_weights_exact)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -666,3 +667,104 @@ def test_biharmonic_forms_leading_truncation_error(order, composed, direct):
     assert coeff(w2, 2) == -1 and coeff(w4, 4) == 1
     assert 2 * (-1) * c2 == composed    # (D2)^2 = theta^4 - 2 c2 theta^(4+order) + ...
     assert coeff(w4, k) == direct
+
+
+# ------------------------------------------------------------ Model H pins --
+# Eq. model-h with the transverse projector one:
+#   m_t = L mu - c3 div(m j),  mu = c2 m^3 - c1 m - L m;   j_t = L j + c3 m grad(mu).
+
+MH = oracle.MH
+
+
+def test_d1_weights_golden_table():
+    with open(os.path.join(GOLDEN, "centered_d1_weights.txt")) as f:
+        rows = [l for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 4
+    for line in rows:
+        p, vals = line.split(":")
+        w = first_derivative_weights_exact(int(p))
+        assert w[0] == 0 and w[1:] == [Fraction(v) for v in vals.split()]
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_d1_weights_polynomial_exactness_off_grid(order):
+    w1 = first_derivative_weights_exact(order)
+    r = order // 2
+    x0, s = Fraction(2, 9), Fraction(1, 4)
+    for deg in range(0, order + 2):
+        f = lambda x: (x - x0 + s) ** deg
+        d1 = deg * s ** (deg - 1) if deg >= 1 else Fraction(0)
+        val = sum(w1[j] * (f(x0 + j) - f(x0 - j)) for j in range(1, r + 1))
+        if deg <= order:
+            assert val == d1, (order, deg)
+        else:
+            assert val != d1, (order, deg)
+
+
+@pytest.mark.parametrize("shape,ndim,order", [((1, 1, 9), 1, 4), ((1, 4, 5), 2, 2), ((1, 4, 4), 2, 6),
+                                              ((3, 3, 4), 3, 2)])
+def test_model_h_exact_rational_brute_force(shape, ndim, order):
+    rng = np.random.default_rng(17)
+    fields = [rng.uniform(-0.4, 0.4, size=shape) for _ in range(1 + ndim)]
+    params, dt, nsteps = [0.9, 1.1, 0.5], 0.003, 3
+    got = oracle.run(MH, fields, ndim, 0.8, dt, order, params, nsteps)
+    ex = run_exact(MH, fields, ndim, 0.8, dt, order, params, nsteps)
+    assert len(got) == 1 + ndim
+    for g, e in zip(got, ex):
+        e = np.array([[[float(v) for v in row] for row in pl] for pl in e])
+        assert np.max(np.abs(g - e)) < 5e-15
+    # m is conserved exactly: a Laplacian and a centred divergence sum to zero
+    m0 = sum(Fraction(float(v)) for v in fields[0].ravel())
+    assert sum(v for pl in ex[0] for row in pl for v in row) == m0
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_model_h_without_coupling_is_cahn_hilliard_and_diffusion(order):
+    """c3 = 0: m evolves exactly as Cahn-Hilliard (bitwise) and every j_a as
+    the heat equation, whose single modes decay by (1 + dt lam)^n."""
+    shape, ndim, dx, dt, n = (1, 16, 20), 2, 1.0, 0.002, 20
+    rng = np.random.default_rng(18)
+    m = rng.uniform(-0.05, 0.05, size=shape)
+    jx, th = _mode(shape, ndim, (0, 3, 2))
+    jy, _ = _mode(shape, ndim, (0, 3, 2))
+    out = oracle.run(MH, [m, 0.1 * jx, -0.2 * jy], ndim, dx, dt, order, [1.0, 1.0, 0.0], n)
+    ch = oracle.run(CH, [m], ndim, dx, dt, order, [1.0, 1.0], n)[0]
+    assert np.array_equal(out[0], ch)
+    g = (1 + dt * _eig(order, th, dx)) ** n
+    assert np.max(np.abs(out[1] - 0.1 * g * jx)) <= 1e-15 * n * 8
+    assert np.max(np.abs(out[2] + 0.2 * g * jy)) <= 1e-15 * n * 8
+
+
+def test_model_h_coupling_one_step_closed_form():
+    """1D, order 2, c1 = c2 = 0, m = m0 + e cos(th x), j = j0: with
+    S = sin(th)/dx and lam = -4 sin^2(th/2)/dx^2 one step gives
+      m' = m0 + e cos(th x) (1 - dt lam^2) + dt c3 j0 e S sin(th x)
+      j' = j0 + dt c3 (m0 + e cos(th x)) lam e S sin(th x)
+    (advection of m by j, and the push of j along grad mu)."""
+    n, dx, dt, c3, m0, j0, e = 24, 0.7, 0.01, 0.5, 0.3, 0.8, 0.05
+    x = np.arange(n)
+    th = 2 * math.pi * 3 / n
+    m = m0 + e * np.cos(th * x)
+    j = np.full(n, j0)
+    out = oracle.run(MH, [m[None, None, :], j[None, None, :]], 1, dx, dt, 2, [0.0, 0.0, c3], 1)
+    S = math.sin(th) / dx
+    lam = -4 * math.sin(th / 2) ** 2 / dx ** 2
+    m1 = m0 + e * np.cos(th * x) * (1 - dt * lam * lam) + dt * c3 * j0 * e * S * np.sin(th * x)
+    j1 = j0 + dt * c3 * (m0 + e * np.cos(th * x)) * lam * e * S * np.sin(th * x)
+    assert np.max(np.abs(out[0][0, 0] - m1)) <= 1e-15
+    assert np.max(np.abs(out[1][0, 0] - j1)) <= 1e-15
+
+
+def test_model_h_dt_max_separates_growth_from_decay():
+    """Linearised about small fields, m is Cahn-Hilliard and j diffuses: the
+    checkerboard of m grows just above dt_max and decays just below it."""
+    shape, ndim = (1, 8, 8), 2
+    z, y, x = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    cb = ((-1.0) ** (x + y)) * 1e-3
+    zero = np.zeros(shape)
+    params = [0.0, 0.0, 0.5]
+    lim = oracle.dt_max(MH, ndim, 1.0, 4, params)
+    assert lim == oracle.dt_max(CH, ndim, 1.0, 4, params[:2])
+    up = oracle.run(MH, [cb, zero, zero], ndim, 1.0, lim * 1.02, 4, params, 200)[0]
+    dn = oracle.run(MH, [cb, zero, zero], ndim, 1.0, lim * 0.98, 4, params, 200)[0]
+    assert np.max(np.abs(up)) > 1e-3 and np.max(np.abs(dn)) < 1e-3
