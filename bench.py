@@ -211,6 +211,31 @@ def run_spectral(P, n, prec, steps, warmup, seed=202):
             "mass": hi + lo}
 
 
+def run_mh(P, n, prec, steps, warmup, seed=707):
+    """Model H (Eq. model-h, transverse projector one) 2D n^2, p = 4, dt =
+    0.005, c1 = c2 = 1, c3 = 0.5, m, j_x, j_y = U[-0.1, 0.1]: the per-site
+    kernels in two passes (mu, then the coupled update)."""
+    d = P.make_desc(P.PF_MH, (n, n), dx=1.0, dt=0.005, order=4, precision=prec,
+                    params=[1.0, 1.0, 0.5])
+    m = P.Model(d)
+    m.init(P.PF_IC_UNIFORM, seed, (-0.1, 0.1))
+    m.step(warmup)
+    m.sync()
+    m.timing(True)
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.sync()
+    wall = time.perf_counter() - t0
+    kernel_ms, launches, ksteps = m.timing_read()
+    m.close()
+    sites = float(n) * n
+    per = kernel_ms / ksteps
+    gbs = 2 * 3 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
+    return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
+            "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
+            "frac_of_peak": round(gbs / PEAK_GBS, 4)}
+
+
 def cpu_baseline(n=4096, seconds=10.0, batch=10):
     """The oracle as it stands on the host cores: CH 2D p4 FP64 on an n^2
     sample of the workload, stepped in batches until `seconds` have passed."""
@@ -269,7 +294,7 @@ def main():
     ap.add_argument("--skip-3d", action="store_true")
     ap.add_argument("--skip-mc", action="store_true", help="skip the Model C lines")
     ap.add_argument("--skip-next", action="store_true",
-                    help="skip the direct-biharmonic, 1D and spectral lines")
+                    help="skip the direct-biharmonic, 1D, spectral and Model H lines")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -318,6 +343,9 @@ def main():
             extra["spectral_ch2d_%d_%s" % (args.n // 2, tag)] = run_spectral(
                 P, args.n // 2, prec, max(10, args.steps // 10), 3)
         log("spectral done")
+        for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
+            extra["mh2d_%d_%s" % (args.n // 4, tag)] = run_mh(P, args.n // 4, prec, max(10, args.steps // 10), 2)
+        log("Model H done")
     extra["fp64_mass_drift"] = fp64["mass_drift"]
     extra["fp64_chunk"] = fp64["chunk"]
     extra["fp64_time_block"] = fp64["time_block"]

@@ -50,8 +50,8 @@ typedef enum {
 } pf_status;
 
 /* Model kinds: Allen-Cahn (Eq. model-a), Cahn-Hilliard (Eq. model-b),
- * Gray-Scott, Model C (Eq. model-c). */
-enum { PF_AC = 1, PF_CH = 2, PF_GS = 3, PF_MC = 4 };
+ * Gray-Scott, Model C (Eq. model-c), Model H (Eq. model-h). */
+enum { PF_AC = 1, PF_CH = 2, PF_GS = 3, PF_MC = 4, PF_MH = 5 };
 /* Storage / arithmetic precision of the bulk step. */
 enum { PF_FP64 = 0, PF_FP32 = 1 };
 /* Descriptor flags. */
@@ -70,9 +70,10 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
 
 /*
  * Model descriptor.  struct_size must be sizeof(pf_desc) (ABI check).
- *   kind      PF_AC, PF_CH, PF_GS or PF_MC
- *   nfields   1 for AC and CH, 2 for GS (u, v) and MC (phi, rho); anything
- *             else -> PF_ERR_ARG
+ *   kind      PF_AC, PF_CH, PF_GS, PF_MC or PF_MH
+ *   nfields   1 for AC and CH, 2 for GS (u, v) and MC (phi, rho), 1 + ndim
+ *             for MH (m, then the components of j); anything else ->
+ *             PF_ERR_ARG
  *   ndim      1, 2 or 3; n[ndim..2] must be 1 (1D grids run their own
  *             kernels, marching along x)
  *   n         grid extents (x, y, z), each >= 1, N = n0 n1 n2 < 2^40
@@ -83,7 +84,13 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
  *             reductions stay FP64 with compensation)
  *   params    AC, CH: {c1, c2};  GS: {Du, Dv, F, k};  MC: {c1, c2, c3} with
  *             phi_t = L phi + c1 phi - c2 phi^3 - 2 phi rho and
- *             rho_t = L(rho + c3 phi^2);  nparams must match
+ *             rho_t = L(rho + c3 phi^2);  MH: {c1, c2, c3} with the
+ *             transverse projector one: m_t = L mu - c3 div(m j), mu =
+ *             c2 m^3 - c1 m - L m, j_t = L j + c3 m grad(mu) (grad and div
+ *             by centred first-derivative stencils of accuracy `order`);
+ *             nparams must match.  MH runs the per-site kernels (one
+ *             field-sized temporary); its reductions cover m (mass,
+ *             non-finite count); the server does not take it.
  *   flags     PF_* flags above.  PF_BIHARMONIC_DIRECT (PF_CH only, else
  *             PF_ERR_ARG) replaces the Laplacian applied twice by the
  *             biharmonic's own stencil (Secs. "Advanced Derivative Support",
@@ -145,6 +152,14 @@ pf_status pf_weights(int32_t order, double *w);
  * order/2 + 2 doubles (caller-owned).  PF_ERR_ARG for a bad order or NULL.
  */
 pf_status pf_weights4(int32_t order, double *w4);
+
+/*
+ * Host FP64 centred first-derivative weights w1[0..order/2] (w1_{-j} =
+ * -w1_j, w1[0] = 0) of accuracy `order` (Model H's gradient and divergence),
+ * by the same recursion.  `w1` must hold order/2 + 1 doubles (caller-owned).
+ * PF_ERR_ARG for a bad order or NULL.
+ */
+pf_status pf_weights1(int32_t order, double *w1);
 
 /*
  * Explicit-stability limit of the descriptor's model: the largest dt for

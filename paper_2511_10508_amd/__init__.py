@@ -24,7 +24,7 @@ LIBPATH = os.path.join(_HERE, "libpfmi.so")
 
 PF_OK, PF_ERR_ARG, PF_ERR_UNSTABLE, PF_ERR_NOMEM, PF_ERR_DEVICE = 0, 1, 2, 3, 4
 PF_ERR_STATE, PF_ERR_UNSUPPORTED, PF_ERR_BUSY, PF_ERR_NOTFOUND = 5, 6, 7, 8
-PF_AC, PF_CH, PF_GS, PF_MC = 1, 2, 3, 4
+PF_AC, PF_CH, PF_GS, PF_MC, PF_MH = 1, 2, 3, 4, 5
 PF_FP64, PF_FP32 = 0, 1
 PF_ALLOW_UNSTABLE, PF_USE_GRAPH, PF_REDUCE_EACH_STEP, PF_FORCE_GENERIC = 1, 2, 4, 8
 PF_BIHARMONIC_DIRECT = 16
@@ -68,6 +68,7 @@ SIGNATURES = {
     "pf_status_str": (ctypes.c_char_p, [_i32]),
     "pf_weights": (_i32, [_i32, _pd]),
     "pf_weights4": (_i32, [_i32, _pd]),
+    "pf_weights1": (_i32, [_i32, _pd]),
     "pf_stability": (_i32, [_P(pf_desc), _pd]),
     "pf_footprint_bytes": (_u64, [_P(pf_desc)]),
     "pf_buffer_elems": (_i64, [_P(pf_desc)]),
@@ -153,11 +154,12 @@ def make_desc(kind, n, dx=1.0, dt=0.01, order=2, precision=PF_FP64, params=None,
     while len(n) < 3:
         n.append(1)
     if params is None:
-        params = {PF_GS: [0.2, 0.1, 0.04, 0.06], PF_MC: [1.0, 1.0, 0.5]}.get(kind, [1.0, 1.0])
+        params = {PF_GS: [0.2, 0.1, 0.04, 0.06], PF_MC: [1.0, 1.0, 0.5],
+                  PF_MH: [1.0, 1.0, 0.5]}.get(kind, [1.0, 1.0])
     d = pf_desc()
     d.struct_size = ctypes.sizeof(pf_desc)
     d.kind = kind
-    d.nfields = 2 if kind in (PF_GS, PF_MC) else 1
+    d.nfields = 1 + ndim if kind == PF_MH else 2 if kind in (PF_GS, PF_MC) else 1
     d.ndim = ndim
     for a in range(3):
         d.n[a] = int(n[a])
@@ -281,6 +283,12 @@ class Model:
 def weights(order):
     w = np.empty(order // 2 + 1)
     check(lib().pf_weights(order, _dp(w)))
+    return w
+
+
+def weights1(order):
+    w = np.empty(order // 2 + 1)
+    check(lib().pf_weights1(order, _dp(w)))
     return w
 
 

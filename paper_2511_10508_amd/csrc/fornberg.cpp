@@ -61,6 +61,25 @@ bool centered_d2_weights(int order, double *w)
     return true;
 }
 
+// Centred first-derivative weights w1[0..r] (w1_{-j} = -w1_j, w1_0 = 0) for
+// accuracy order p = 2r at unit spacing (Model H's gradient and divergence);
+// the weights of +j and -j are averaged with the sign flipped.
+bool centered_d1_weights(int order, double *w1)
+{
+    if (order < 2 || order % 2 != 0 || order > 16) return false;
+    const int r = order / 2;
+    std::vector<double> alpha;
+    alpha.push_back(0.0);
+    for (int j = 1; j <= r; ++j) {
+        alpha.push_back((double)j);
+        alpha.push_back((double)-j);
+    }
+    const auto d = fornberg(0.0, alpha, 1);
+    w1[0] = 0.0;
+    for (int j = 1; j <= r; ++j) w1[j] = 0.5 * (d[1][2 * j - 1] - d[1][2 * j]);
+    return true;
+}
+
 // Centred fourth-derivative weights w4[0..r+1] for accuracy order p = 2r at
 // unit spacing (the stencil of the direct biharmonic): 2(r+1)+1 = p+3 nodes,
 // the same node order and averaging.

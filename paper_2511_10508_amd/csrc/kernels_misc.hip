@@ -114,6 +114,37 @@ __global__ void __launch_bounds__(256) k_generic(StepArgs<T> a, T *scratch, int 
         mc_update<T, R>(a, p0, r0, Sp, Sg, p0 * ctrk, mc_g(a, p0, r0) * ctrk, pn, rn);
         a.buf[0][par ^ 1][off] = pn;
         a.buf[1][par ^ 1][off] = rn;
+    } else if constexpr (KIND == kMH && PASS == 2) {
+        // Model H (Eq. model-h, transverse projector one): k2 = dt c3, w1 =
+        // w1_j/dx; m' = m + dt L mu - dt c3 div(m j), j_a' = j_a + dt L j_a +
+        // dt c3 m grad_a mu, with mu from the first pass.
+        Field<T> fm{scratch, a.nx, a.ny, a.nz, a.pitch, a.plane};
+        const T m0 = f0.p[off], mu0 = scratch[off];
+        T Sm[R];
+        pair_sums<T, R>(fm, s, ndim, Sm);
+        T div = T(0);
+        for (int ax = 0; ax < ndim; ++ax) {
+            Field<T> fj{a.buf[1 + ax][par], a.nx, a.ny, a.nz, a.pitch, a.plane};
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                const Site p = shifted(s, ax, k), q = shifted(s, ax, -k);
+                div = fma(a.w1[k - 1], f0(p.x, p.y, p.z) * fj(p.x, p.y, p.z) - f0(q.x, q.y, q.z) * fj(q.x, q.y, q.z), div);
+            }
+        }
+        a.buf[0][par ^ 1][off] = fma(-a.k2, div, ch_update<T, R>(a, m0, Sm, mu0 * ctrk));
+        for (int ax = 0; ax < ndim; ++ax) {
+            Field<T> fj{a.buf[1 + ax][par], a.nx, a.ny, a.nz, a.pitch, a.plane};
+            T Sj[R];
+            pair_sums<T, R>(fj, s, ndim, Sj);
+            T grad = T(0);
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                const Site p = shifted(s, ax, k), q = shifted(s, ax, -k);
+                grad = fma(a.w1[k - 1], fm(p.x, p.y, p.z) - fm(q.x, q.y, q.z), grad);
+            }
+            const T j0 = fj.p[off];
+            a.buf[1 + ax][par ^ 1][off] = fma(a.k2 * m0, grad, ch_update<T, R>(a, j0, Sj, j0 * ctrk));
+        }
     } else if constexpr (KIND == kCHD && PASS == 1) {
         const int64_t fsize = a.plane * a.nz;
         for (int ax = 0; ax < ndim; ++ax) scratch[ax * fsize + off] = mu_axis<T, R>(a, f0, s, ax, ndim);
@@ -300,7 +331,7 @@ __global__ void __launch_bounds__(256) k_init(InitArgs a)
             val[0] = a.v0;
             val[1] = a.v1;
         }
-        for (int f = 0; f < a.nfields; ++f) {
+        for (int f = 0; f < a.nfields && f < 2; ++f) {
             void *p = f == 0 ? a.f0 : a.f1;
             if (a.fp32)
                 static_cast<float *>(p)[off] = (float)val[f];
@@ -328,12 +359,12 @@ hipError_t launch_generic(const Launch &L, const void *args, void *scratch, hipS
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
         const int64_t N = a.nx * a.ny * a.nz;
         const dim3 grid((unsigned)cdiv(N, 256)), block(256);
-        dispatch_kind_all(L.kind, [&](auto kc) {
+        dispatch_kind_generic(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             dispatch_r(L.r, GenericRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
                 T *sc = static_cast<T *>(scratch);
-                if constexpr (KIND == kCH || KIND == kCHD) {
+                if constexpr (KIND == kCH || KIND == kCHD || KIND == kMH) {
                     hipLaunchKernelGGL((k_generic<T, KIND, R, 1>), grid, block, 0, s, a, sc, L.ndim);
                     err = hipGetLastError();
                     if (err != hipSuccess) return;
@@ -361,7 +392,7 @@ hipError_t launch_reduce_state(const Launch &L, const void *args, hipStream_t s)
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
         const int64_t N = a.nx * a.ny * a.nz;
         const dim3 grid((unsigned)(reduce_partial_slots(N) / 4)), block(256);
-        dispatch_kind_all(L.kind, [&](auto kc) {
+        dispatch_kind_generic(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             dispatch_r(L.r, GenericRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;

@@ -47,6 +47,17 @@ bool dispatch_kind_all(int kind, F &&f)
     return dispatch_kind(kind, f);
 }
 
+// dispatch_kind_all plus Model H (the per-site generic kernels only).
+template <typename F>
+bool dispatch_kind_generic(int kind, F &&f)
+{
+    if (kind == kMH) {
+        f(std::integral_constant<int, kMH>{});
+        return true;
+    }
+    return dispatch_kind_all(kind, f);
+}
+
 template <typename F>
 void dispatch_prec(int fp32, F &&f)
 {

@@ -6,12 +6,15 @@
 
 namespace pf {
 
-constexpr int kAC = 1, kCH = 2, kGS = 3, kMC = 4;
+constexpr int kAC = 1, kCH = 2, kGS = 3, kMC = 4, kMH = 5;
 // Kernel kind of Cahn-Hilliard with the direct biharmonic stencil (a
 // descriptor flag on PF_CH; internal to the kernels and launchers).
-constexpr int kCHD = 5;
+constexpr int kCHD = 16;
+constexpr int kMaxFields = 4;       // Model H in 3D: m and three components of j
 
-// Fields of a model: Gray-Scott (u, v) and Model C (phi, rho) have two.
+// Fields a kernel family reduces and steps as a fixed set: Gray-Scott (u, v)
+// and Model C (phi, rho) have two.  Model H has 1 + ndim (m and j), stepped by
+// the per-site kernels only; its reductions cover m.
 constexpr int nfields_kind(int kind) { return (kind == kGS || kind == kMC) ? 2 : 1; }
 constexpr int kMaxR = 8;            // stencil radius r = order / 2 (order <= 16)
 constexpr int kNumQ = 3;            // reduction quantities per partial slot
@@ -28,7 +31,7 @@ constexpr int kWaves3D = 16;        // waves per workgroup of the 3D kernels (tw
 // precision T (rounded once from FP64 on the host).
 template <typename T>
 struct StepArgs {
-    T *buf[2][2];            // [field][parity]
+    T *buf[kMaxFields][2];   // [field][parity]
     int64_t nx, ny, nz;      // grid extents (nz = 1 in 2D)
     int64_t pitch;           // row stride
     int64_t plane;           // plane stride = pitch * ny
@@ -44,6 +47,7 @@ struct StepArgs {
     T wu[kMaxR];             // update weights of field 0 (dt-scaled)
     T wv[kMaxR];             // update weights of field 1 (GS, MC)
     T w4[kMaxR + 1];         // -dt w4_j/dx^4 (direct biharmonic, j = 1..r+1)
+    T w1[kMaxR];             // w1_j/dx (Model H: first derivatives, j = 1..r)
     T k0, k1, k2, k3;        // model constants (see kernels)
     double w64[kMaxR];       // w_j / dx^2 in FP64 (energy)
     double c1, c2;           // FP64 Landau constants (energy)
@@ -132,7 +136,7 @@ hipError_t launch_finalize(const double2 *part, int64_t pstride, int64_t slots, 
 struct InitArgs {
     void *f0, *f1;            // field buffers
     int64_t nx, ny, nz, pitch, plane;
-    int32_t fp32, nfields;
+    int32_t fp32, nfields;    // nfields: 1 or 2 (f0, f1)
     int32_t ic;               // 1 uniform, 2 GS cubes, 3 const
     uint64_t key0, key1;      // per-stream keys (SplitMix64 of seed, stream)
     double lo, span;          // x = lo + span * u01 (span = hi - lo rounded on the host)

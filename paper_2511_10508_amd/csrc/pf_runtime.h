@@ -21,7 +21,7 @@ struct Model {
     hipStream_t stream = nullptr;
     bool own_stream = false, own_bufs = true;
     bool async_alloc = false;     // stream-ordered allocations, no host syncs (server models)
-    void *buf[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    void *buf[kMaxFields][2] = {};   // [field][parity]
     int parity = 0;
     int64_t steps_done = 0;
 

@@ -21,6 +21,7 @@ namespace pf {
 
 bool centered_d2_weights(int order, double *w);
 bool centered_d4_weights(int order, double *w4);
+bool centered_d1_weights(int order, double *w1);
 
 static thread_local std::string g_err;
 
@@ -50,10 +51,11 @@ pf_status check_desc(const pf_desc *d)
     if (!d) return fail(PF_ERR_ARG, "descriptor is NULL");
     if (d->struct_size != sizeof(pf_desc))
         return fail(PF_ERR_ARG, "pf_desc.struct_size does not match this library");
-    if (d->kind != kAC && d->kind != kCH && d->kind != kGS && d->kind != kMC)
+    if (d->kind != kAC && d->kind != kCH && d->kind != kGS && d->kind != kMC && d->kind != kMH)
         return fail(PF_ERR_ARG, "unknown model kind");
-    if (d->nfields != nfields_of(d->kind))
-        return fail(PF_ERR_ARG, "nfields does not match the model (AC, CH: 1; GS, MC: 2)");
+    const int nf = d->kind == kMH ? 1 + d->ndim : nfields_of(d->kind);
+    if (d->nfields != nf)
+        return fail(PF_ERR_ARG, "nfields does not match the model (AC, CH: 1; GS, MC: 2; MH: 1 + ndim)");
     if (d->ndim < 1 || d->ndim > 3) return fail(PF_ERR_ARG, "ndim must be 1, 2 or 3");
     for (int a = 0; a < 3; ++a)
         if (d->n[a] < 1) return fail(PF_ERR_ARG, "grid extents must be >= 1");
@@ -69,8 +71,8 @@ pf_status check_desc(const pf_desc *d)
         return fail(PF_ERR_ARG, "order must be even, 2..16");
     if (d->precision != PF_FP64 && d->precision != PF_FP32)
         return fail(PF_ERR_ARG, "precision must be PF_FP64 or PF_FP32");
-    const int np = d->kind == kGS ? 4 : d->kind == kMC ? 3 : 2;
-    if (d->nparams != np) return fail(PF_ERR_ARG, "nparams must be 2 (AC, CH), 4 (GS) or 3 (MC)");
+    const int np = d->kind == kGS ? 4 : (d->kind == kMC || d->kind == kMH) ? 3 : 2;
+    if (d->nparams != np) return fail(PF_ERR_ARG, "nparams must be 2 (AC, CH), 4 (GS) or 3 (MC, MH)");
     for (int i = 0; i < np; ++i)
         if (!std::isfinite(d->params[i])) return fail(PF_ERR_ARG, "parameters must be finite");
     if ((d->flags & PF_BIHARMONIC_DIRECT) && d->kind != kCH)
@@ -109,6 +111,8 @@ double stability_limit(const pf_desc *d)
     double rho;
     if (d->kind == kAC || d->kind == kMC)  // MC: phi as AC about small fields, rho diffuses
         rho = lam + 2.0 * std::fabs(d->params[0]);
+    else if (d->kind == kMH)  // m as CH, each j_a diffuses; couplings are higher order
+        rho = std::max(lam * lam + 2.0 * std::fabs(d->params[0]) * lam, lam);
     else if (d->kind == kCH && (d->flags & PF_BIHARMONIC_DIRECT)) {
         // Nyquist symbol of the direct operator: ndim tau / dx^4 for the
         // fourth derivatives, ndim (ndim - 1) (sigma / dx^2)^2 for the mixed
@@ -172,7 +176,7 @@ static void fill_args(Model *m, StepArgs<T> &a)
 {
     const pf_desc &d = m->desc;
     std::memset(&a, 0, sizeof(a));
-    for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < kMaxFields; ++f)
         for (int p = 0; p < 2; ++p)
             a.buf[f][p] = static_cast<T *>(m->buf[f < m->nf ? f : 0][p]);
     a.nx = d.n[0];
@@ -198,6 +202,11 @@ static void fill_args(Model *m, StepArgs<T> &a)
             a.wu[j - 1] = (T)(d.dt * wl);
         }
     }
+    if (d.kind == kMH) {
+        double w1[kMaxR + 1];
+        centered_d1_weights(d.order, w1);
+        for (int j = 1; j <= r; ++j) a.w1[j - 1] = (T)(w1[j] / d.dx);
+    }
     if (m->L.kind == kCHD) {
         double w4[kMaxR + 2];
         centered_d4_weights(d.order, w4);
@@ -207,9 +216,10 @@ static void fill_args(Model *m, StepArgs<T> &a)
     if (d.kind == kAC) {
         a.k0 = (T)(d.dt * d.params[0]);
         a.k1 = (T)(d.dt * d.params[1]);
-    } else if (d.kind == kCH) {
+    } else if (d.kind == kCH || d.kind == kMH) {
         a.k0 = (T)d.params[0];
         a.k1 = (T)d.params[1];
+        a.k2 = (T)(d.dt * (d.kind == kMH ? d.params[2] : 0.0));
     } else if (d.kind == kMC) {
         a.k0 = (T)(d.dt * d.params[0]);
         a.k1 = (T)(d.dt * d.params[1]);
@@ -382,7 +392,8 @@ pf_status set_chunk(Model *m, int32_t chunk)
 
 static pf_status ensure_scratch(Model *m)
 {
-    if (m->family == 0 || (m->L.kind != kCH && m->L.kind != kCHD) || m->scratch) return PF_OK;
+    if (m->family == 0 || (m->L.kind != kCH && m->L.kind != kCHD && m->L.kind != kMH) || m->scratch)
+        return PF_OK;
     const size_t nbuf = m->L.kind == kCHD ? (size_t)m->desc.ndim : 1;
     PF_HIP(dev_alloc(m, &m->scratch, nbuf * tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
     return PF_OK;
@@ -619,7 +630,7 @@ pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double 
         *lo = q[1].y * vol;
         return PF_OK;
     case PF_RED_ENERGY:
-        if (d.kind == kGS || d.kind == kMC)
+        if (d.kind == kGS || d.kind == kMC || d.kind == kMH)
             return fail(PF_ERR_UNSUPPORTED, "free energy is reduced for Allen-Cahn and Cahn-Hilliard only");
         if (d.flags & PF_SPECTRAL)
             return fail(PF_ERR_UNSUPPORTED, "no free energy for the spectral scheme");
@@ -743,7 +754,7 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
 void model_release_async(Model *m)
 {
     if (!m) return;
-    for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < kMaxFields; ++f)
         for (int p = 0; p < 2; ++p)
             if (m->own_bufs) dev_free(m, m->buf[f][p]);
     dev_free(m, m->part);
@@ -771,7 +782,7 @@ void pf_destroy_model(Model *m)
     }
     destroy_graphs(m);
     if (m->own_bufs)
-        for (int f = 0; f < 2; ++f)
+        for (int f = 0; f < kMaxFields; ++f)
             for (int p = 0; p < 2; ++p)
                 if (m->buf[f][p]) hipFree(m->buf[f][p]);
     if (m->part) hipFree(m->part);
@@ -799,7 +810,7 @@ pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int3
     a.pitch = m->pitch;
     a.plane = m->pitch * d.n[1];
     a.fp32 = m->fp32;
-    a.nfields = m->nf;
+    a.nfields = std::min(2, m->nf);  // fields 0 and 1 here, the rest below
     a.ic = ic;
     a.key0 = stream_key(seed, 0);
     a.key1 = stream_key(seed, 1);
@@ -837,6 +848,20 @@ pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int3
         return fail(PF_ERR_ARG, "unknown initial condition");
     }
     hipError_t e = launch_init(a, m->stream);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    // Model H: fields 2 and 3 (j_y, j_z) from streams 2 and 3, as fields 0, 1
+    for (int f = 2; f < m->nf && e == hipSuccess; f += 2) {
+        a.f0 = m->buf[f][m->parity];
+        a.f1 = f + 1 < m->nf ? m->buf[f + 1][m->parity] : nullptr;
+        a.nfields = std::min(2, m->nf - f);
+        a.key0 = stream_key(seed, (uint64_t)f);
+        a.key1 = stream_key(seed, (uint64_t)f + 1);
+        if (ic == PF_IC_CONST) {
+            a.v0 = p[f];
+            a.v1 = f + 1 < m->nf ? p[f + 1] : 0.0;
+        }
+        e = launch_init(a, m->stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "init launch");
     m->steps_done = 0;
     return PF_OK;
@@ -949,6 +974,13 @@ PF_API pf_status pf_weights(int32_t order, double *w)
     return PF_OK;
 }
 
+PF_API pf_status pf_weights1(int32_t order, double *w1)
+{
+    if (!w1) return fail(PF_ERR_ARG, "w1 is NULL");
+    if (!centered_d1_weights(order, w1)) return fail(PF_ERR_ARG, "order must be even, 2..16");
+    return PF_OK;
+}
+
 PF_API pf_status pf_weights4(int32_t order, double *w4)
 {
     if (!w4) return fail(PF_ERR_ARG, "w4 is NULL");
@@ -976,6 +1008,7 @@ PF_API int64_t pf_buffer_elems(const pf_desc *desc)
 // cover the descriptor (1D and 2D: r <= 4; 3D: CH r <= 3, direct form r <= 2).
 static int generic_scratch_arrays(const pf_desc *d)
 {
+    if (d->kind == kMH) return 1;  // per-site kernels only: mu
     if (d->kind != kCH) return 0;
     const bool direct = (d->flags & PF_BIHARMONIC_DIRECT) != 0;
     const int r = d->order / 2;

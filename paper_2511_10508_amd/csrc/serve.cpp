@@ -569,7 +569,7 @@ PF_API pf_status pf_server_submit(pf_server *ss, const pf_desc *desc, int32_t ic
         return fail(PF_ERR_UNSTABLE, "dt exceeds the explicit-stability limit");
     if (desc->flags & (PF_USE_GRAPH | PF_REDUCE_EACH_STEP))
         return fail(PF_ERR_ARG, "served requests take no PF_USE_GRAPH / PF_REDUCE_EACH_STEP");
-    if (desc->ndim == 1 || (desc->flags & (PF_BIHARMONIC_DIRECT | PF_SPECTRAL)))
+    if (desc->ndim == 1 || desc->kind == PF_MH || (desc->flags & (PF_BIHARMONIC_DIRECT | PF_SPECTRAL)))
         return fail(PF_ERR_UNSUPPORTED, "the server batches 2D and 3D finite-difference grids "
                                         "with the composed biharmonic only");
     if (n_ic_params < 0 || n_ic_params > 8 || (n_ic_params && !ic_params))

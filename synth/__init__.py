@@ -142,8 +142,15 @@ def gray_scott_fields(seed, shape, ncubes=20, side=16, noise=0.01,
     return base_u + nu, base_v + nv
 
 
-def initial_fields(kind, shape, seed, ic=None, ic_params=None, origin=(0, 0, 0), wshape=None):
-    """Initial state for a model kind (1 AC, 2 CH, 3 GS, 4 MC) as FP64 arrays.
+def initial_fields(kind, shape, seed, ic=None, ic_params=None, origin=(0, 0, 0), wshape=None,
+                   ndim=None):
+    """Initial state for a model kind (1 AC, 2 CH, 3 GS, 4 MC, 5 MH) as FP64
+    arrays; Model H has 1 + ndim fields (ndim required)."""
+    return _initial_fields(kind, shape, seed, ic, ic_params, origin, wshape, ndim)
+
+
+def _initial_fields(kind, shape, seed, ic, ic_params, origin, wshape, ndim):
+    """Initial state for a model kind as FP64 arrays.
 
     ic / ic_params follow the library's pf_init convention:
       IC_UNIFORM  params (lo, hi): field f from stream f
@@ -152,7 +159,9 @@ def initial_fields(kind, shape, seed, ic=None, ic_params=None, origin=(0, 0, 0),
     """
     if ic is None:
         ic = IC_GS_CUBES if kind == 3 else IC_UNIFORM
-    nf = 2 if kind in (3, 4) else 1
+    if kind == 5 and ndim is None:
+        raise ValueError("Model H needs ndim (1 + ndim fields)")
+    nf = 1 + ndim if kind == 5 else 2 if kind in (3, 4) else 1
     if ic == IC_UNIFORM:
         lo, hi = (ic_params or (-0.05, 0.05))[:2]
         return [uniform_field(seed, f, shape, lo, hi, origin, wshape) for f in range(nf)]

@@ -221,3 +221,30 @@ def test_spectral_host_logic():
         h = ctypes.c_void_p()
         assert P.lib().pf_create(ctypes.byref(bad), None, ctypes.byref(h)) == P.PF_ERR_ARG
         assert b"PF_SPECTRAL" in P.lib().pf_last_error()
+
+
+def test_model_h_descriptor_and_host_logic():
+    for n in ((64,), (64, 64), (16, 16, 16)):
+        d = P.make_desc(P.PF_MH, n, dt=1e-3, order=4)
+        assert d.nfields == 1 + len(n) and d.nparams == 3
+        ref = oracle.dt_max(oracle.MH, len(n), 1.0, 4, [1.0, 1.0, 0.5])
+        assert math.isclose(P.stability(d), ref, rel_tol=1e-12)
+        per = P.buffer_elems(d) * 8
+        plain = P.footprint_bytes(P.make_desc(P.PF_AC, n, dt=1e-3))
+        # 2 (1 + ndim) field buffers and one temporary, against AC's 2
+        assert P.footprint_bytes(d) == plain + (2 * len(n) + 1) * per
+    bad = P.make_desc(P.PF_MH, (64, 64), dt=1e-3)
+    bad.nfields = 2
+    h = ctypes.c_void_p()
+    assert P.lib().pf_create(ctypes.byref(bad), None, ctypes.byref(h)) == P.PF_ERR_ARG
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 12, 16])
+def test_fornberg_first_derivative_matches_exact_weights(order):
+    """The library's first-derivative weights (Model H's gradient and
+    divergence) equal the oracle's exact ones to rounding."""
+    w = P.weights1(order)
+    exact = oracle.first_derivative_weights_exact(order)
+    assert len(w) == len(exact)
+    for a, e in zip(w, exact):
+        assert abs(Fraction(float(a)) - e) <= 8 * Fraction(math.ulp(float(e)) or 2.0 ** -1074) + Fraction(1, 10 ** 14) * abs(e)

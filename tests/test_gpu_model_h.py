@@ -1,0 +1,95 @@
+"""GPU parity of Model H (Eq. model-h, transverse projector one) against
+the CPU FP64 oracle: m and the ndim components of j after 100 steps of the
+per-site kernels, max |GPU - oracle| <= 1e-12 (FP64 storage) and <= 1e-4
+(FP32 storage); mass conservation of m, the counter-based initial fields of
+all 1 + ndim fields, and the refusals.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2511_10508_amd as P
+import paper_2511_10508_amd.serving as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = {P.PF_FP64: 1e-12, P.PF_FP32: 1e-4}
+PARAMS = [1.0, 1.0, 0.5]
+
+
+def _n(shape, ndim):
+    return {1: (shape[2],), 2: (shape[2], shape[1]), 3: (shape[2], shape[1], shape[0])}[ndim]
+
+
+def gpu_run(fields, ndim, order, prec, dt, nsteps, flags=0, dx=1.0):
+    d = P.make_desc(P.PF_MH, _n(fields[0].shape, ndim), dx=dx, dt=dt, order=order,
+                    precision=prec, params=PARAMS, flags=flags)
+    m = P.Model(d)
+    for f, a in enumerate(fields):
+        m.set_field(f, a)
+    m.step(nsteps)
+    return [m.get_field(f) for f in range(len(fields))], m
+
+
+CASES = [(1, (1, 1, 301), 2), (1, (1, 1, 256), 4), (2, (1, 75, 130), 2), (2, (1, 64, 90), 4),
+         (3, (13, 17, 30), 2), (3, (12, 14, 20), 4)]
+
+
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=["%dd-%s-p%d" % (c[0], "x".join(map(str, c[1])), c[2])
+                                              for c in CASES])
+def test_model_h_parity_100_steps(case, prec):
+    ndim, shape, order = case
+    dx = 0.9
+    dt = min(0.01, 0.8 * oracle.dt_max(oracle.MH, ndim, dx, order, PARAMS))
+    f0 = synth.initial_fields(5, shape, 61, synth.IC_UNIFORM, (-0.1, 0.1), ndim=ndim)
+    ref = oracle.run(oracle.MH, f0, ndim, dx, dt, order, PARAMS, 100)
+    got, m = gpu_run(f0, ndim, order, prec, dt, 100, dx=dx)
+    assert len(got) == 1 + ndim and m.tile()[1] == 1
+    for f, (g, r) in enumerate(zip(got, ref)):
+        err = float(np.max(np.abs(g - r)))
+        assert err <= TOL[prec], (f, err)
+
+
+@pytest.mark.parametrize("ndim,shape", [(2, (1, 96, 80)), (3, (16, 18, 20))])
+def test_model_h_mass_of_m_conserved(ndim, shape):
+    f0 = synth.initial_fields(5, shape, 62, synth.IC_UNIFORM, (-0.1, 0.1), ndim=ndim)
+    dt = 0.8 * oracle.dt_max(oracle.MH, ndim, 1.0, 4, PARAMS)
+    got, m = gpu_run(f0, ndim, 4, P.PF_FP64, dt, 50, flags=P.PF_REDUCE_EACH_STEP)
+    h, l = m.reduce_history(P.PF_RED_MASS0, 50)
+    m0 = oracle.exact_sum(f0[0])
+    assert float(np.max(np.abs((h + l) - m0))) <= 50 * f0[0].size * 2.2e-16 * 0.2
+    for which in (P.PF_RED_MASS1, P.PF_RED_ENERGY):
+        with pytest.raises(P.PfError) as e:
+            m.reduce(which)
+        assert e.value.status == P.PF_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+def test_model_h_device_init_matches_generator(prec):
+    """All four fields of a 3D model come from streams 0..3 of the generator."""
+    shape = (9, 10, 11)
+    d = P.make_desc(P.PF_MH, (11, 10, 9), dt=1e-3, precision=prec)
+    assert d.nfields == 4
+    m = P.Model(d)
+    m.init(P.PF_IC_UNIFORM, 63, (-0.2, 0.3))
+    ref = synth.initial_fields(5, shape, 63, synth.IC_UNIFORM, (-0.2, 0.3), ndim=3)
+    for f in range(4):
+        r = ref[f] if prec == P.PF_FP64 else ref[f].astype(np.float32).astype(np.float64)
+        assert np.array_equal(m.get_field(f), r), f
+    vals = (0.1, 0.2, 0.3, 0.4)
+    m.init(P.PF_IC_CONST, 0, vals)
+    for f in range(4):
+        v = vals[f] if prec == P.PF_FP64 else float(np.float32(vals[f]))
+        assert np.all(m.get_field(f) == v), f
+
+
+def test_model_h_refused_by_the_server():
+    srv = S.Server(hbm_budget=1 << 28)
+    try:
+        with pytest.raises(P.PfError) as e:
+            srv.submit(P.make_desc(P.PF_MH, (32, 32), dt=1e-3), P.PF_IC_UNIFORM, 1, (-0.1, 0.1), 10)
+        assert e.value.status == P.PF_ERR_UNSUPPORTED
+    finally:
+        srv.close()
