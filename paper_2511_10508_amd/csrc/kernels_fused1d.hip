@@ -8,7 +8,8 @@
 // of consecutive strips and walks it with PD strips of loads in flight.  Each
 // strip is read once from HBM; the halo columns that neighbouring strips
 // share come from L2.  Every stage uses the per-site functions of the 2D and
-// 3D kernels with the centre term 2 u0 of one axis.
+// 3D kernels with the centre term 2 u0 of one axis; Model H (m, j) runs here
+// fused as well.
 #include "pf_device.h"
 #include "pf_dispatch.h"
 
@@ -20,6 +21,19 @@ namespace {
 
 constexpr int kWaves1D = 4;  // waves per workgroup
 constexpr int kPrefetch1D = 2;  // strips of loads in flight per wave
+
+// Strip geometry of the 1D kernels: the common Shape, except Model H, which
+// steps two fields (m, j) with two radius-r stages per step (mu, then the
+// coupled update), like Cahn-Hilliard.
+template <typename T, int KIND, int R, int TB>
+struct Shape1D {
+    using S = Shape<T, KIND, R, TB>;
+    static constexpr int V = S::V, SW = S::SW;
+    static constexpr int NF = KIND == kMH ? 2 : S::NF;
+    static constexpr int H = KIND == kMH ? 2 * R * TB : S::H;
+    static constexpr int HV = (H + V - 1) / V * V;
+    static constexpr int OWMAX = SW - 2 * HV;
+};
 
 // Neighbour pair sums S[j-1] = e[v+j] + e[v-j] of a gathered neighbourhood
 // e of radius RE (>= R) at element v.
@@ -47,11 +61,11 @@ __device__ __forceinline__ void fwd1d64(const T (&e)[NE], int v, double x, doubl
 // output elements (om).
 template <typename T, int KIND, int R, bool RED>
 __device__ __forceinline__ void stage1d(const StepArgs<T> &a,
-                                        const T (&in)[nfields_kind(KIND)][Vec<T>::V],
-                                        T (&out)[nfields_kind(KIND)][Vec<T>::V],
+                                        const T (&in)[Shape1D<T, KIND, R, 1>::NF][Vec<T>::V],
+                                        T (&out)[Shape1D<T, KIND, R, 1>::NF][Vec<T>::V],
                                         const OutMask<Vec<T>::V> &om, RedState &red)
 {
-    constexpr int V = Vec<T>::V, NF = nfields_kind(KIND);
+    constexpr int V = Vec<T>::V, NF = Shape1D<T, KIND, R, 1>::NF;
     constexpr bool F64 = std::is_same<T, double>::value;
     double s0 = 0.0, s1 = 0.0;  // the strip's masked reduction sums
     if constexpr (KIND == kAC || KIND == kGS) {
@@ -139,6 +153,42 @@ __device__ __forceinline__ void stage1d(const StepArgs<T> &a,
                 }
             }
         }
+    } else if constexpr (KIND == kMH) {
+        // Model H in 1D (fields m, j): mu as Cahn-Hilliard; m' = m + dt L mu
+        // - dt c3 D1(m j), j' = j + dt L j + dt c3 m D1 mu (k2 = dt c3, w1 =
+        // w1_k/dx), each sum in the per-site kernel's order
+        T e[V + 2 * R], mu[V], em[V + 2 * R], mj[V], ep[V + 2 * R], ej[V + 2 * R];
+        gather_x<T, V, R>(in[0], e);
+        gather_x<T, V, R>(in[1], ej);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T S[R];
+            pairs1d<T, R, R>(e, v, S);
+            mu[v] = ch_mu<T, R>(a, in[0][v], S, in[0][v] * T(2));
+            mj[v] = in[0][v] * in[1][v];
+        }
+        gather_x<T, V, R>(mu, em);
+        gather_x<T, V, R>(mj, ep);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T Sm[R], Sj[R];
+            pairs1d<T, R, R>(em, v, Sm);
+            pairs1d<T, R, R>(ej, v, Sj);
+            T div = T(0), grad = T(0);
+            static_for<1, R + 1>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                div = fma(a.w1[k - 1], ep[R + v + k] - ep[R + v - k], div);
+            });
+            static_for<1, R + 1>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                grad = fma(a.w1[k - 1], em[R + v + k] - em[R + v - k], grad);
+            });
+            const T m0 = in[0][v], j0 = in[1][v];
+            out[0][v] = fma(-a.k2, div, ch_update<T, R>(a, m0, Sm, mu[v] * T(2)));
+            out[1][v] = fma(a.k2 * m0, grad, ch_update<T, R>(a, j0, Sj, j0 * T(2)));
+            if constexpr (RED)
+                if (om.ov[v]) s0 += (double)m0;
+        }
     } else {  // kCHD: in 1D mu_x = g, so c' = c + dt (D2 g - D4 c)
         constexpr int R4 = R + 1;
         T g[V], eg[V + 2 * R], ec[V + 2 * R4];
@@ -173,8 +223,10 @@ __device__ __forceinline__ void stage1d(const StepArgs<T> &a,
             }
         }
     }
+    // Model H reduces m only (mass, non-finite count)
+    constexpr bool TWO = NF == 2 && KIND != kMH;
     if constexpr (RED)
-        red_row_end<V, NF == 2>(red, om, s0, s1, [&](int f, int v) { return (double)in[f][v]; });
+        red_row_end<V, TWO>(red, om, s0, s1, [&](int f, int v) { return (double)in[f][v]; });
 }
 
 // Strip loads of one lane.  FAST: every strip of the segment lies inside
@@ -199,7 +251,7 @@ template <typename T, int KIND, int R, bool RED, int TB, bool FAST>
 __device__ __forceinline__ void march1d(const StepArgs<T> &a, int32_t s0, int32_t s1, int lane,
                                         int64_t pslot)
 {
-    using S = Shape<T, KIND, R, TB>;
+    using S = Shape1D<T, KIND, R, TB>;
     constexpr int V = S::V, HV = S::HV, NF = S::NF, PD = kPrefetch1D;
     const int64_t nx = a.nx, ow = a.ow;
     const int pl = lane * V;
@@ -260,7 +312,7 @@ __device__ __forceinline__ void march1d(const StepArgs<T> &a, int32_t s0, int32_
 template <typename T, int KIND, int R, bool RED, int TB>
 __global__ void __launch_bounds__(64 * kWaves1D) k_step1d(StepArgs<T> a)
 {
-    using S = Shape<T, KIND, R, TB>;
+    using S = Shape1D<T, KIND, R, TB>;
     const int32_t nwg = gridDim.x;
     const int32_t wg = xcd_item(blockIdx.x, nwg);
     const int32_t item = __builtin_amdgcn_readfirstlane(wg * kWaves1D + (int)(threadIdx.x >> 6));
@@ -284,12 +336,12 @@ bool plan_fused1d(const Launch &L, int64_t nx, int32_t clen, int tb, int32_t *st
     bool ok = false;
     dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
-        dispatch_kind_all(L.kind, [&](auto kc) {
+        dispatch_kind_generic(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             ok = dispatch_r(L.r, Fused1DRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
-                const int owmax = tb == 2 ? Shape<T, KIND, R, 2>::OWMAX : Shape<T, KIND, R, 1>::OWMAX;
-                constexpr int V = Shape<T, KIND, R>::V;
+                const int owmax = tb == 2 ? Shape1D<T, KIND, R, 2>::OWMAX : Shape1D<T, KIND, R, 1>::OWMAX;
+                constexpr int V = Shape1D<T, KIND, R, 1>::V;
                 const int64_t st = cdiv(nx, owmax);
                 *strips = (int32_t)st;
                 *ow = (int32_t)(cdiv(cdiv(nx, st), V) * V);
@@ -310,7 +362,7 @@ hipError_t launch_fused1d(const Launch &L, const void *args, int32_t blocks, int
     dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
-        dispatch_kind_all(L.kind, [&](auto kc) {
+        dispatch_kind_generic(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             dispatch_r(L.r, Fused1DRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;

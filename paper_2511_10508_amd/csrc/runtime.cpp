@@ -1008,7 +1008,8 @@ PF_API int64_t pf_buffer_elems(const pf_desc *desc)
 // cover the descriptor (1D and 2D: r <= 4; 3D: CH r <= 3, direct form r <= 2).
 static int generic_scratch_arrays(const pf_desc *d)
 {
-    if (d->kind == kMH) return 1;  // per-site kernels only: mu
+    if (d->kind == kMH)  // mu, except on 1D rows (fused, r <= 4)
+        return (d->ndim == 1 && !(d->flags & PF_FORCE_GENERIC) && d->order / 2 <= 4) ? 0 : 1;
     if (d->kind != kCH) return 0;
     const bool direct = (d->flags & PF_BIHARMONIC_DIRECT) != 0;
     const int r = d->order / 2;

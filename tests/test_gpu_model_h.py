@@ -46,13 +46,35 @@ def test_model_h_parity_100_steps(case, prec):
     f0 = synth.initial_fields(5, shape, 61, synth.IC_UNIFORM, (-0.1, 0.1), ndim=ndim)
     ref = oracle.run(oracle.MH, f0, ndim, dx, dt, order, PARAMS, 100)
     got, m = gpu_run(f0, ndim, order, prec, dt, 100, dx=dx)
-    assert len(got) == 1 + ndim and m.tile()[1] == 1
+    assert len(got) == 1 + ndim and m.tile()[1] == (0 if ndim == 1 else 1)
     for f, (g, r) in enumerate(zip(got, ref)):
         err = float(np.max(np.abs(g - r)))
         assert err <= TOL[prec], (f, err)
 
 
-@pytest.mark.parametrize("ndim,shape", [(2, (1, 96, 80)), (3, (16, 18, 20))])
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_model_h_1d_fused_equals_generic_bitwise(order, prec):
+    """1D rows run a fused strip kernel (one and two steps per sweep); it
+    gives bitwise the per-site kernel's fields."""
+    f0 = synth.initial_fields(5, (1, 1, 3001), 64, synth.IC_UNIFORM, (-0.1, 0.1), ndim=1)
+    dt = 0.8 * oracle.dt_max(oracle.MH, 1, 1.0, order, PARAMS)
+    a, ma = gpu_run(f0, 1, order, prec, dt, 25)
+    b, mb = gpu_run(f0, 1, order, prec, dt, 25, flags=P.PF_FORCE_GENERIC)
+    assert ma.tile()[1] == 0 and mb.tile()[1] == 1
+    d = P.make_desc(P.PF_MH, (3001,), dt=dt, order=order, precision=prec, params=PARAMS)
+    mc = P.Model(d)
+    mc.set_tile(3)
+    mc.set_time_block(2)
+    for f, x in enumerate(f0):
+        mc.set_field(f, x)
+    mc.step(25)
+    c = [mc.get_field(f) for f in range(2)]
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+@pytest.mark.parametrize("ndim,shape", [(1, (1, 1, 5000)), (2, (1, 96, 80)), (3, (16, 18, 20))])
 def test_model_h_mass_of_m_conserved(ndim, shape):
     f0 = synth.initial_fields(5, shape, 62, synth.IC_UNIFORM, (-0.1, 0.1), ndim=ndim)
     dt = 0.8 * oracle.dt_max(oracle.MH, ndim, 1.0, 4, PARAMS)
