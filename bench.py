@@ -211,14 +211,17 @@ def run_spectral(P, n, prec, steps, warmup, seed=202):
             "mass": hi + lo}
 
 
-def run_mh(P, n, prec, steps, warmup, seed=707):
-    """Model H (Eq. model-h, transverse projector one) 2D n^2, p = 4, dt =
-    0.005, c1 = c2 = 1, c3 = 0.5, m, j_x, j_y = U[-0.1, 0.1]: the per-site
-    kernels in two passes (mu, then the coupled update)."""
-    d = P.make_desc(P.PF_MH, (n, n), dx=1.0, dt=0.005, order=4, precision=prec,
+def run_mh(P, n, prec, steps, warmup, seed=707, ndim=2):
+    """Model H (Eq. model-h, transverse projector one) on a 2D n^2 grid (the
+    per-site kernels in two passes: mu, then the coupled update) or a 1D row
+    of n sites (the fused strip kernel, autotuned), p = 4, dt = 0.005,
+    c1 = c2 = 1, c3 = 0.5, m and j = U[-0.1, 0.1]."""
+    shape = (n, n) if ndim == 2 else (n,)
+    d = P.make_desc(P.PF_MH, shape, dx=1.0, dt=0.005, order=4, precision=prec,
                     params=[1.0, 1.0, 0.5])
     m = P.Model(d)
     m.init(P.PF_IC_UNIFORM, seed, (-0.1, 0.1))
+    m.autotune(2)
     m.step(warmup)
     m.sync()
     m.timing(True)
@@ -228,9 +231,9 @@ def run_mh(P, n, prec, steps, warmup, seed=707):
     wall = time.perf_counter() - t0
     kernel_ms, launches, ksteps = m.timing_read()
     m.close()
-    sites = float(n) * n
+    sites = float(n) ** ndim
     per = kernel_ms / ksteps
-    gbs = 2 * 3 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
+    gbs = 2 * (1 + ndim) * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
     return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
             "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
             "frac_of_peak": round(gbs / PEAK_GBS, 4)}
@@ -345,6 +348,8 @@ def main():
         log("spectral done")
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             extra["mh2d_%d_%s" % (args.n // 4, tag)] = run_mh(P, args.n // 4, prec, max(10, args.steps // 10), 2)
+            extra["mh1d_%d_%s" % (args.n * args.n // 16, tag)] = run_mh(
+                P, args.n * args.n // 16, prec, max(10, args.steps // 10), 2, ndim=1)
         log("Model H done")
     extra["fp64_mass_drift"] = fp64["mass_drift"]
     extra["fp64_chunk"] = fp64["chunk"]
