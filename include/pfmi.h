@@ -244,10 +244,14 @@ pf_status pf_step(pf_model *m, int64_t nsteps);
 /*
  * Reductions of the current state, compensated in FP64 on the device and
  * combined in a fixed order: value = hi + lo (double-double).
- *   PF_RED_MASS0 / PF_RED_MASS1: dx^d sum of field 0 / 1
+ *   PF_RED_MASS0 / PF_RED_MASS1: dx^d sum of field 0 / 1 (MASS1: GS and MC
+ *                  only, else PF_ERR_UNSUPPORTED)
  *   PF_RED_ENERGY: dx^d sum of -(1/2) x L x + (c2/4) x^4 - (c1/2) x^2 (AC, CH
- *                  only; GS, MC -> PF_ERR_UNSUPPORTED)
- *   PF_RED_NONFINITE: number of NaN / Inf values (hi = count, lo = 0)
+ *                  only, with the Laplacian of the descriptor's order, also
+ *                  for the direct biharmonic; GS, MC, MH and PF_SPECTRAL ->
+ *                  PF_ERR_UNSUPPORTED)
+ *   PF_RED_NONFINITE: number of NaN / Inf values (hi = count, lo = 0) of the
+ *                  reduced fields (MH: m only)
  * Synchronises the stream.
  */
 pf_status pf_reduce(pf_model *m, int32_t which, double *hi, double *lo);
