@@ -461,6 +461,11 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
             pf_status st = spectral_step(m, par, ap);
             if (st != PF_OK) return st;
             if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
+        } else if (mh2d_available(m->L) && !(d.flags & PF_FORCE_GENERIC)) {
+            if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
+            hipError_t e = launch_mh2d(m->L, ap, m->stream);
+            if (e != hipSuccess) return hip_fail(e, "Model H step launch");
+            if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
         } else {
             pf_status st = ensure_scratch(m);
             if (st != PF_OK) return st;
@@ -1008,8 +1013,12 @@ PF_API int64_t pf_buffer_elems(const pf_desc *desc)
 // cover the descriptor (1D and 2D: r <= 4; 3D: CH r <= 3, direct form r <= 2).
 static int generic_scratch_arrays(const pf_desc *d)
 {
-    if (d->kind == kMH)  // mu, except on 1D rows (fused, r <= 4)
-        return (d->ndim == 1 && !(d->flags & PF_FORCE_GENERIC) && d->order / 2 <= 4) ? 0 : 1;
+    if (d->kind == kMH) {  // mu, except on 1D rows (fused, r <= 4) and 2D tiles (r <= 2)
+        const int r = d->order / 2;
+        const bool one_pass = !(d->flags & PF_FORCE_GENERIC) &&
+                              ((d->ndim == 1 && r <= 4) || (d->ndim == 2 && r <= 2));
+        return one_pass ? 0 : 1;
+    }
     if (d->kind != kCH) return 0;
     const bool direct = (d->flags & PF_BIHARMONIC_DIRECT) != 0;
     const int r = d->order / 2;

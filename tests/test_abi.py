@@ -231,8 +231,8 @@ def test_model_h_descriptor_and_host_logic():
         assert math.isclose(P.stability(d), ref, rel_tol=1e-12)
         per = P.buffer_elems(d) * 8
         plain = P.footprint_bytes(P.make_desc(P.PF_AC, n, dt=1e-3))
-        # 2 (1 + ndim) field buffers and, off 1D rows, one temporary (mu)
-        tmp = 0 if len(n) == 1 else 1
+        # 2 (1 + ndim) field buffers and, in 3D, one temporary (mu)
+        tmp = 1 if len(n) == 3 else 0
         assert P.footprint_bytes(d) == plain + (2 * len(n) + tmp) * per
     bad = P.make_desc(P.PF_MH, (64, 64), dt=1e-3)
     bad.nfields = 2

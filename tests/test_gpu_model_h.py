@@ -74,6 +74,21 @@ def test_model_h_1d_fused_equals_generic_bitwise(order, prec):
         assert np.array_equal(x, y) and np.array_equal(x, z)
 
 
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("shape,order", [((1, 75, 130), 2), ((1, 64, 90), 4), ((1, 33, 31), 4),
+                                         ((1, 5, 7), 4), ((1, 130, 257), 2)])
+def test_model_h_2d_tiled_equals_generic_bitwise(shape, order, prec):
+    """2D grids with r <= 2 run one LDS-tiled pass (32 x 32 tiles, partial
+    and wrapping tiles included); it gives bitwise the two-pass per-site
+    kernel's fields."""
+    f0 = synth.initial_fields(5, shape, 65, synth.IC_UNIFORM, (-0.1, 0.1), ndim=2)
+    dt = 0.8 * oracle.dt_max(oracle.MH, 2, 1.0, order, PARAMS)
+    a, _ = gpu_run(f0, 2, order, prec, dt, 20)
+    b, _ = gpu_run(f0, 2, order, prec, dt, 20, flags=P.PF_FORCE_GENERIC)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("ndim,shape", [(1, (1, 1, 5000)), (2, (1, 96, 80)), (3, (16, 18, 20))])
 def test_model_h_mass_of_m_conserved(ndim, shape):
     f0 = synth.initial_fields(5, shape, 62, synth.IC_UNIFORM, (-0.1, 0.1), ndim=ndim)
