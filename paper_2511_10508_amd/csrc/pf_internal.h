@@ -108,11 +108,6 @@ hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k,
 // fields), ndim of them for the direct biharmonic.
 hipError_t launch_generic(const Launch &L, const void *args, void *scratch, hipStream_t s);
 
-// Model H on 2D grids (r <= 2) in one LDS-tiled pass, bitwise equal to the
-// two passes of the per-site kernels (which run it with PF_FORCE_GENERIC).
-bool mh2d_available(const Launch &L);
-hipError_t launch_mh2d(const Launch &L, const void *args, hipStream_t s);
-
 // Semi-implicit Fourier spectral step (Models A and B): the explicit term of
 // buf[0][parity] into g (pitched like the fields), and the implicit update of
 // the half spectrum uh from the explicit term's spectrum nh.

@@ -84,6 +84,12 @@ pf_status reduce_now(Model *m, double2 *host_out);
 pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double *hi, double *lo);
 int32_t default_chunk(const pf_desc *d);
 
+// Model H on 2D grids (r <= 2) in one LDS-tiled pass, bitwise equal to the
+// two passes of the per-site kernels (which run it with PF_FORCE_GENERIC);
+// kernels_mh2d.hip.
+bool mh2d_available(const Launch &L);
+hipError_t launch_mh2d(const Launch &L, const void *args, hipStream_t s);
+
 // Semi-implicit Fourier spectral scheme (spectral.cpp).
 pf_status spectral_setup(Model *m);
 pf_status spectral_step(Model *m, int par, const void *step_args);
