@@ -292,3 +292,19 @@ def test_direct_biharmonic_has_no_two_step_kernel_and_no_server():
             assert e.value.status == P.PF_ERR_UNSUPPORTED
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("n", [(5, 3), (2, 1), (9, 2), (3, 4, 2), (7, 6, 5), (33, 2, 3)])
+def test_direct_biharmonic_tiny_and_wrapping_grids(n):
+    """Extents smaller than the radius-(r+1) fourth-derivative stencil (true
+    periodic wrap), through the fused kernels and the per-site ones."""
+    ndim = len(n)
+    shape = (n[2] if ndim == 3 else 1, n[1], n[0])
+    order = 4
+    params = BASE[CHD][0]
+    dt = 0.5 * dt_for(CHD, ndim, order, params)
+    f0 = fields_for(CHD, shape, 3)
+    ref = oracle_run(CHD, f0, ndim, order, params, dt, 40)
+    for flags in (0, P.PF_FORCE_GENERIC):
+        got, _ = gpu_run(CHD, f0, ndim, order, P.PF_FP64, params, dt, 40, flags=flags)
+        assert float(np.max(np.abs(got[0] - ref[0]))) <= 1e-12, flags
