@@ -115,3 +115,14 @@ def test_spectral_descriptor_refusals():
         assert e.value.status == P.PF_ERR_UNSUPPORTED
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("ndim,shape", [(1, (1, 1, 2)), (1, (1, 1, 3)), (1, (1, 1, 5)), (2, (1, 2, 3)),
+                                        (2, (1, 7, 4)), (3, (2, 2, 3)), (3, (3, 5, 2))])
+def test_spectral_tiny_grids(ndim, shape):
+    """Grids of a few sites per axis, odd and even (the half spectrum of an
+    odd row has no Nyquist column)."""
+    f0 = _fields(P.PF_CH, shape, 44)[0]
+    ref = spectral.run(P.PF_CH, f0, ndim, 1.0, 0.25, [1.0, 1.0], 30)
+    got, _ = gpu_run(P.PF_CH, f0, ndim, P.PF_FP64, [1.0, 1.0], 1.0, 0.25, 30)
+    assert float(np.max(np.abs(got - ref))) <= 1e-12
