@@ -17,6 +17,7 @@
 // visible to pf_server_poll) once its event completes.  Requests submitted
 // while ticks run join at the next tick boundary.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>
@@ -113,14 +114,25 @@ struct Server {
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;  // (class, set, steps, grid) -> graph
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr;
-    int64_t tick = 0, launches = 0, captures = 0, replays = 0;
-    std::string fatal;
+    // written by the scheduler thread, read by pf_server_stats from any thread
+    std::atomic<int64_t> tick{0}, launches{0}, captures{0}, replays{0};
+    std::string fatal;  // guarded by mu (set_fatal)
 
     double now() const
     {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 };
+
+// Record a device failure of the scheduler (under the lock, so that submit,
+// poll and drain, which read it from other threads, see a whole string) and
+// wake drain, which would otherwise wait out its timeout.
+static void set_fatal(Server *s, const std::string &msg)
+{
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->fatal.empty()) s->fatal = msg;
+    s->done_cv.notify_all();
+}
 
 static int class_of(Server *s, const Model *m)
 {
@@ -340,14 +352,14 @@ static bool enqueue_tick(Server *s, std::vector<Req *> &run, int set)
             e = hipMemcpyAsync(static_cast<char *>(t.dev[set]) + t.args_bytes, ints,
                                sizeof(int32_t) * (2 * s->max_slots + 2), hipMemcpyHostToDevice, s->stream);
         if (e != hipSuccess) {
-            s->fatal = std::string("table upload: ") + hipGetErrorString(e);
+            set_fatal(s, std::string("table upload: ") + hipGetErrorString(e));
             return false;
         }
     }
     if (!cls.empty()) {
         hipError_t e = run_classes(s, cls, set, S);
         if (e != hipSuccess) {
-            s->fatal = std::string("batched launch: ") + hipGetErrorString(e);
+            set_fatal(s, std::string("batched launch: ") + hipGetErrorString(e));
             return false;
         }
     }
@@ -670,6 +682,7 @@ PF_API pf_status pf_server_cancel(pf_server *ss, uint64_t ticket)
     Req *r = it->second;
     if (r->state == QUEUED) {
         s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), r), s->queue.end());
+        r->footprint = 0;  // never admitted: nothing was charged to the budget
         r->status = PF_ERR_STATE;
         r->state = FINISHED;
         r->t_done = r->t_admit = s->now();
@@ -703,10 +716,10 @@ PF_API pf_status pf_server_stats(pf_server *ss, int64_t *ticks, int64_t *launche
     Server *s = SV(ss);
     if (!s) return fail(PF_ERR_ARG, "server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (ticks) *ticks = s->tick;
-    if (launches) *launches = s->launches;
-    if (captures) *captures = s->captures;
-    if (replays) *replays = s->replays;
+    if (ticks) *ticks = s->tick.load();
+    if (launches) *launches = s->launches.load();
+    if (captures) *captures = s->captures.load();
+    if (replays) *replays = s->replays.load();
     return PF_OK;
 }
 
@@ -721,10 +734,14 @@ PF_API void pf_server_destroy(pf_server *ss)
     }
     if (s->worker.joinable()) s->worker.join();
     (void)hipStreamSynchronize(s->stream);
+    // every request is in `all` (queued, running or finished) until released,
+    // then in to_free: each is freed and deleted exactly once
+    s->queue.clear();
+    s->active.clear();
     for (auto &kv : s->all) free_req(s, kv.second), delete kv.second;
+    s->all.clear();
     for (Req *r : s->to_free) free_req(s, r), delete r;
-    for (Req *r : s->queue)
-        if (s->all.find(r->ticket) == s->all.end()) delete r;
+    s->to_free.clear();
     (void)hipStreamSynchronize(s->stream);
     for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
     for (auto &t : s->classes) {
