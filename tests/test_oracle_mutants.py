@@ -99,3 +99,44 @@ def test_spectral_pins_catch_planted_mistake(name, tmp_path):
                           os.path.join(ROOT, "tests", "test_oracle_spectral.py")],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert res.returncode != 0, "spectral pins passed with planted mistake " + name
+
+
+STABILITY = os.path.join(ROOT, "oracle", "stability.py")
+STABILITY_MUTANTS = {
+    "dtmax_gs_min_for_max": ("rho = max(params[0], params[1]) * lam", "rho = min(params[0], params[1]) * lam"),
+    "dtmax_gs_drop_lam": ("rho = max(params[0], params[1]) * lam", "rho = max(params[0], params[1])"),
+    "dtmax_gs_drop_one": ("+ params[2] + params[3] + 1.0", "+ params[2] + params[3]"),
+    "dtmax_gs_lam_squared": ("rho = max(params[0], params[1]) * lam", "rho = max(params[0], params[1]) * lam * lam"),
+    "dtmax_ac_drop_c1": ("rho = lam + 2 * abs(params[0])", "rho = lam"),
+    "dtmax_ac_c1_factor": ("rho = lam + 2 * abs(params[0])", "rho = lam + abs(params[0])"),
+    "dtmax_ch_drop_c1": ("        rho = lam * lam + 2 * abs(params[0]) * lam\n    else:",
+                         "        rho = lam * lam\n    else:"),
+    "dtmax_ch_c1_factor": ("        rho = lam * lam + 2 * abs(params[0]) * lam\n    else:",
+                           "        rho = lam * lam + abs(params[0]) * lam\n    else:"),
+    "dtmax_ch_c1_without_lam": ("        rho = lam * lam + 2 * abs(params[0]) * lam\n    else:",
+                                "        rho = lam * lam + 2 * abs(params[0])\n    else:"),
+    "dtmax_mh_min_for_max": ("rho = max(lam * lam + 2 * abs(params[0]) * lam, lam)",
+                             "rho = min(lam * lam + 2 * abs(params[0]) * lam, lam)"),
+    "dtmax_mh_drop_c1": ("rho = max(lam * lam + 2 * abs(params[0]) * lam, lam)", "rho = max(lam * lam, lam)"),
+    "dtmax_mh_drop_diffusion": ("rho = max(lam * lam + 2 * abs(params[0]) * lam, lam)",
+                                "rho = lam * lam + 2 * abs(params[0]) * lam"),
+    "dtmax_mc_as_ch": ("    elif kind in (AC, MC):", "    elif kind == AC:"),
+    "dtmax_ndim_ignored": ("lam = abs(float(sigma)) * ndim / (dx * dx)", "lam = abs(float(sigma)) / (dx * dx)"),
+    "dtmax_dx_not_squared": ("lam = abs(float(sigma)) * ndim / (dx * dx)", "lam = abs(float(sigma)) * ndim / dx"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STABILITY_MUTANTS))
+def test_stability_pins_catch_planted_mistake(name, tmp_path):
+    """Mistakes planted in the explicit-stability limit (oracle/stability.py)
+    fail the dt_max pins of tests/test_oracle_pins.py."""
+    old, new = STABILITY_MUTANTS[name]
+    src = open(STABILITY).read()
+    assert src.count(old) == 1, "mutation anchor not found once: " + name
+    mut = tmp_path / "stability_mutant.py"
+    mut.write_text(src.replace(old, new))
+    env = dict(os.environ, PF_ORACLE_STABILITY_MUTANT=str(mut), OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          "-k", "dt_max or unstable", os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, "stability pins passed with planted mistake " + name

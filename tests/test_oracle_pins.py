@@ -412,6 +412,76 @@ def test_dt_max_config_values():
     assert oracle.dt_max(GS, 3, 1.0, 2, [0.2, 0.1, 0.04, 0.06]) < 1.0
 
 
+# The c1 terms of the limit are pinned about the separated homogeneous states
+# phi0^2 = c1/c2, where the linearised step is tightest: the checkerboard
+# perturbation of the oracle's own step grows just above dt_max and decays
+# just below it.  Model C (c3 = 0, rho = 0) and Model H (c3 = 0) reduce there
+# to Allen-Cahn and Cahn-Hilliard plus diffusion; large dx makes Model H's
+# diffusion branch (|lam*| > lam*^2 + 2 c1 |lam*|) the binding one.
+
+def _nyquist_ratio(kind, base, f, ndim, dx, order, params, dt, steps=300, amp=1e-9):
+    """Field f of the homogeneous state `base` perturbed by amp times the
+    checkerboard; max deviation of field f after `steps` oracle steps, over amp."""
+    shape = (1, 8, 8) if ndim == 2 else (4, 4, 4)
+    z, y, x = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    cb = (-1.0) ** (x + y + (z if ndim == 3 else 0))
+    init = [np.full(shape, float(b)) + (amp * cb if g == f else 0.0) for g, b in enumerate(base)]
+    out = oracle.run(kind, init, ndim, dx, dt, order, params, steps)
+    return float(np.max(np.abs(out[f] - base[f]))) / amp
+
+
+MH = 5
+
+
+@pytest.mark.parametrize("kind,base,f,ndim,dx,order,params", [
+    (AC, [math.sqrt(1.5 / 0.6)], 0, 2, 1.0, 2, [1.5, 0.6]),
+    (AC, [math.sqrt(2.0 / 0.5)], 0, 3, 0.8, 4, [2.0, 0.5]),
+    (CH, [2.0], 0, 2, 1.0, 4, [2.0, 0.5]),
+    (CH, [math.sqrt(3.0)], 0, 3, 1.2, 2, [3.0, 1.0]),
+    (MC, [2.0, 0.0], 0, 2, 1.0, 4, [1.2, 0.3, 0.0]),
+    (MH, [1.0, 0.0, 0.0], 0, 2, 1.0, 4, [1.5, 1.5, 0.0]),
+    (MH, [0.0, 0.0, 0.0], 1, 2, 4.0, 4, [0.05, 1.0, 0.0]),
+    (MH, [0.0, 0.0, 0.0, 0.0], 3, 3, 4.0, 2, [0.01, 1.0, 0.0]),
+])
+def test_dt_max_c1_terms_separate_growth_from_decay(kind, base, f, ndim, dx, order, params):
+    lim = oracle.dt_max(kind, ndim, dx, order, params)
+    assert _nyquist_ratio(kind, base, f, ndim, dx, order, params, 1.02 * lim) > 10.0
+    assert _nyquist_ratio(kind, base, f, ndim, dx, order, params, 0.98 * lim) < 0.1
+
+
+@pytest.mark.parametrize("ndim,order,dx,Du,Dv", [
+    (2, 2, 1.0, 0.2, 0.1), (3, 2, 1.0, 0.2, 0.1), (3, 2, 1.0, 0.4, 0.1),
+    (2, 4, 0.7, 0.1, 0.3), (3, 2, 1.3, 0.05, 0.4),
+])
+def test_gs_dt_max_bounds_the_nyquist_spectrum(ndim, order, dx, Du, Dv):
+    """Gray-Scott: the Jacobian of the oracle's right-hand side at the
+    checkerboard mode (central differences about homogeneous states), over u,
+    v in [0, 1]: dt_max keeps dt |eig| <= 2 everywhere, and its rate 2/dt_max
+    exceeds the largest |eig| by at most the reaction slack 1 + F + k."""
+    F, k = 0.04, 0.06
+    params = [Du, Dv, F, k]
+    lim = oracle.dt_max(GS, ndim, dx, order, params)
+    shape = (1, 8, 8) if ndim == 2 else (4, 4, 4)
+    z, y, x = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    cb = (-1.0) ** (x + y + (z if ndim == 3 else 0))
+    eps = 1e-6
+    worst = 0.0
+    for u0 in np.linspace(0.0, 1.0, 11):
+        for v0 in np.linspace(0.0, 1.0, 11):
+            J = np.zeros((2, 2))
+            for f in range(2):
+                d = [eps * cb if g == f else 0.0 for g in range(2)]
+                rp = oracle.rhs(GS, [np.full(shape, u0) + d[0], np.full(shape, v0) + d[1]], ndim, dx,
+                                order, params)
+                rm = oracle.rhs(GS, [np.full(shape, u0) - d[0], np.full(shape, v0) - d[1]], ndim, dx,
+                                order, params)
+                for g in range(2):
+                    J[g, f] = np.mean((rp[g] - rm[g]) * cb) / (2 * eps)
+            worst = max(worst, float(np.max(np.abs(np.linalg.eigvals(J)))))
+    assert lim * worst <= 2.0 * (1 + 1e-9)
+    assert 2.0 / lim <= worst + 1.0 + F + k + 1e-9
+
+
 def test_gray_scott_3d_dt1_is_unstable():
     """The Nyquist u-mode amplification at dt = 1 is 1 - dt (12 Du + F) = -1.44."""
     shape = (8, 8, 8)
