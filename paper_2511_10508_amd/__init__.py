@@ -242,6 +242,15 @@ class Model:
     def steps_done(self):
         return lib().pf_steps_done(self.h)
 
+    def set_steps_done(self, n):
+        check(lib().pf_set_steps_done(self.h, int(n)))
+
+    def field_device(self, f):
+        """(device pointer, pitch in elements, bytes per element) of field f's current buffer."""
+        p, pitch, eb = _vp(), _i64(), _i32()
+        check(lib().pf_field_device(self.h, f, ctypes.byref(p), ctypes.byref(pitch), ctypes.byref(eb)))
+        return p.value, pitch.value, eb.value
+
     def set_tile(self, chunk):
         check(lib().pf_set_tile(self.h, chunk))
 

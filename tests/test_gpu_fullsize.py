@@ -6,7 +6,8 @@ for AC/GS, 2r for CH), so the oracle runs on a periodic window of the seeded
 initial field of side W + 2 n H (generated directly by synth, whose
 counter-based values are the ones pf_init writes) and its central W x W (x W)
 block must match the GPU's window of the full grid.  Windows include the
-periodic seams.
+periodic seams.  The headline grids run 100 steps (2D CH 32768^2: windows of
+24^2 from 824^2 light cones; 3D GS 1024^3: 14^3 from 214^3).
 """
 import numpy as np
 import pytest
@@ -42,7 +43,7 @@ def _check_windows(m, kind, ndim, n, order, params, dt, steps, seed, ic, icp, ha
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
 def test_cahn_hilliard_32768_sampled(prec):
     """2D CH 32768^2, dx 1, dt 0.01, order 4 twice, c0 = U[-0.05, 0.05] seed 202."""
-    n, order, params, dt, steps, seed = (32768, 32768, 1), 4, [1.0, 1.0], 0.01, 20, 202
+    n, order, params, dt, steps, seed = (32768, 32768, 1), 4, [1.0, 1.0], 0.01, 100, 202
     d = P.make_desc(P.PF_CH, n[:2], dt=dt, order=order, precision=prec, params=params,
                     flags=P.PF_REDUCE_EACH_STEP)
     m = P.Model(d)
@@ -66,7 +67,7 @@ def test_cahn_hilliard_32768_sampled(prec):
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
 def test_gray_scott_1024_cubed_sampled(prec):
     """3D GS 1024^3, dt 0.5, order 2, 20 cubes of side 16 + 1 % noise, seed 303."""
-    n, order, params, dt, steps, seed = (1024, 1024, 1024), 2, [0.2, 0.1, 0.04, 0.06], 0.5, 10, 303
+    n, order, params, dt, steps, seed = (1024, 1024, 1024), 2, [0.2, 0.1, 0.04, 0.06], 0.5, 100, 303
     d = P.make_desc(P.PF_GS, n, dt=dt, order=order, precision=prec, params=params)
     m = P.Model(d)
     m.init(P.PF_IC_GS_CUBES, seed, (20, 16, 0.01))
@@ -76,7 +77,7 @@ def test_gray_scott_1024_cubed_sampled(prec):
     m.sync()
     corners = synth.cube_corners(seed, (1024, 1024, 1024), 20)
     cz, cy, cx = corners[0]
-    windows = [(0, 0, 0), (1024 - 7, 1024 - 9, 1024 - 5), (cz, cy, cx), (500, 3, 1000)]
+    windows = [(0, 0, 0), (1024 - 7, 1024 - 9, 1024 - 5), (cz, cy, cx)]
     _check_windows(m, P.PF_GS, 3, n, order, params, dt, steps, seed, synth.IC_GS_CUBES,
                    (20, 16, 0.01), 1, windows, 14, prec)
     m.close()

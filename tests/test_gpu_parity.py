@@ -301,8 +301,8 @@ def test_get_window_matches_full_field():
 @pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 @pytest.mark.parametrize("order", [2, 4])
 def test_two_step_blocking_is_bitwise_two_single_steps(kind, order, prec):
-    """Temporal blocking (two steps per sweep) against one step per sweep,
-    including an odd step count (the last step runs alone) and ragged tiles."""
+    """Temporal blocking (two steps per sweep) against one step per sweep over
+    101 steps (the last runs alone) with ragged tiles, and against the oracle."""
     shape, ndim = (1, 83, 301), 2
     params = BASE[kind][0]
     dt = dt_for(kind, ndim, order, params)
@@ -317,12 +317,12 @@ def test_two_step_blocking_is_bitwise_two_single_steps(kind, order, prec):
         assert m.time_block() == tb
         for f, a in enumerate(f0):
             m.set_field(f, a)
-        m.step(37)
-        assert m.steps_done() == 37
+        m.step(101)
+        assert m.steps_done() == 101
         outs.append([m.get_field(f) for f in range(len(f0))])
     for x, y in zip(*outs):
         assert np.array_equal(x, y)
-    ref = oracle_run(kind, shape, ndim, order, params, dt, 37, 31)[1]
+    ref = oracle_run(kind, shape, ndim, order, params, dt, 101, 31)[1]
     for g, r in zip(outs[1], ref):
         assert float(np.max(np.abs(g - r))) <= TOL[prec]
 
@@ -373,7 +373,8 @@ def test_time_block_refused_where_unavailable():
 @pytest.mark.parametrize("kind", [P.PF_AC, P.PF_CH, P.PF_GS, P.PF_MC])
 def test_two_step_blocking_3d(kind, prec):
     """3D two-step sweeps (order 2) against single steps, bitwise, with ragged
-    strips, y tiles and z chunks, an odd step count and fused reductions."""
+    strips, y tiles and z chunks, 101 steps and fused reductions, and against
+    the oracle."""
     shape, ndim, order = (29, 37, 150), 3, 2
     params = BASE[kind][0]
     dt = dt_for(kind, ndim, order, params)
@@ -388,13 +389,13 @@ def test_two_step_blocking_3d(kind, prec):
         m.set_time_block(tb)
         for f, a in enumerate(f0):
             m.set_field(f, a)
-        m.step(23)
+        m.step(101)
         outs.append([m.get_field(f) for f in range(len(f0))])
-        hist.append(sum(m.reduce_history(P.PF_RED_MASS0, 23)))
+        hist.append(sum(m.reduce_history(P.PF_RED_MASS0, 101)))
     for x, y in zip(*outs):
         assert np.array_equal(x, y)
     assert np.max(np.abs(hist[0] - hist[1])) <= 1e-13 * max(1.0, float(np.max(np.abs(hist[0]))))
-    ref = oracle_run(kind, shape, ndim, order, params, dt, 23, 51)[1]
+    ref = oracle_run(kind, shape, ndim, order, params, dt, 101, 51)[1]
     for g, r in zip(outs[1], ref):
         assert float(np.max(np.abs(g - r))) <= TOL[prec]
 
