@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -212,9 +214,9 @@ def run_spectral(P, n, prec, steps, warmup, seed=202):
 
 
 def run_mh(P, n, prec, steps, warmup, seed=707, ndim=2):
-    """Model H (Eq. model-h, transverse projector one) on a 2D n^2 grid (the
-    per-site kernels in two passes: mu, then the coupled update) or a 1D row
-    of n sites (the fused strip kernel, autotuned), p = 4, dt = 0.005,
+    """Model H (Eq. model-h, transverse projector one) on a 2D n^2 grid (one
+    LDS-tiled pass: m and j staged with their halo, mu in LDS) or a 1D row of
+    n sites (the fused strip kernel), autotuned, p = 4, dt = 0.005,
     c1 = c2 = 1, c3 = 0.5, m and j = U[-0.1, 0.1]."""
     shape = (n, n) if ndim == 2 else (n,)
     d = P.make_desc(P.PF_MH, shape, dx=1.0, dt=0.005, order=4, precision=prec,
@@ -237,6 +239,208 @@ def run_mh(P, n, prec, steps, warmup, seed=707, ndim=2):
     return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
             "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
             "frac_of_peak": round(gbs / PEAK_GBS, 4)}
+
+
+def run_ch3d(P, n, order, prec, steps, warmup, seed=404):
+    """Precision-study workload: 3D Cahn-Hilliard n^3, dt 0.005, c1 = c2 = 1,
+    c0 = U[-0.05, 0.05] (seed 404), order 2 / 4 / 6, fused mass / energy
+    reductions every step, autotuned."""
+    d = P.make_desc(P.PF_CH, (n, n, n), dx=1.0, dt=0.005, order=order, precision=prec,
+                    params=[1.0, 1.0], flags=P.PF_REDUCE_EACH_STEP)
+    m = P.Model(d)
+    m.init(P.PF_IC_UNIFORM, seed, (-0.05, 0.05))
+    m.autotune(2)
+    m.step(warmup)
+    m.sync()
+    m.timing(True)
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.sync()
+    wall = time.perf_counter() - t0
+    kernel_ms, launches, ksteps = m.timing_read()
+    hi, lo = m.reduce_history(P.PF_RED_MASS0, steps)
+    drift = float(abs((hi + lo) - (hi[0] + lo[0])).max())
+    chunk, family = m.tile()
+    tb, rows = m.time_block(), m.tile_rows()
+    m.close()
+    sites = float(n) ** 3
+    per = kernel_ms / ksteps
+    gbs = 2 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
+    return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
+            "kernel_ms": round(per, 4), "kernel_ms_per_launch": round(kernel_ms / launches, 4),
+            "achieved_gbs": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4),
+            "mass_drift": drift, "chunk": chunk, "family": family, "time_block": tb,
+            "tile_rows": rows}
+
+
+def run_ac128(P, steps=1000, seed=101):
+    """The small workload: 2D Allen-Cahn 128^2, dx 1, dt 0.05, order 2, FP64,
+    phi0 = U[-0.1, 0.1] (seed 101), 1000 steps, launch-bound: microseconds per
+    step with one launch per step (eager) and with replayed HIP graphs of 32
+    steps, plus the kernel time alone."""
+    out = {}
+    for name, flags in (("eager", 0), ("graph", P.PF_USE_GRAPH)):
+        d = P.make_desc(P.PF_AC, (128, 128), dx=1.0, dt=0.05, order=2, precision=P.PF_FP64,
+                        params=[1.0, 1.0], flags=flags)
+        m = P.Model(d)
+        m.init(P.PF_IC_UNIFORM, seed, (-0.1, 0.1))
+        m.step(steps)  # warm-up (captures the graphs)
+        m.sync()
+        best = 1e30
+        for _ in range(3):
+            t0 = time.perf_counter()
+            m.step(steps)
+            m.sync()
+            best = min(best, time.perf_counter() - t0)
+        out[name + "_us_per_step"] = round(best / steps * 1e6, 3)
+        if name == "eager":
+            m.timing(True)
+            m.step(steps)
+            kms, _, ks = m.timing_read()
+            out["kernel_us_per_step"] = round(kms / ks * 1e3, 3)
+        m.close()
+    out["site_updates_per_s_graph"] = 128 * 128 / (out["graph_us_per_step"] * 1e-6)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Serving workload: the batched server against a one-at-a-time loop on the
+# mixed request trace (synth.serving_trace: model uniform over AC / CH / GS,
+# 2D sides 64..2048 or 3D sides 32..256 log-uniform, 100..10000 steps, orders
+# 2 and 4, parameters jittered by +-20 %, FP32 storage, dt clamped to 0.9 of
+# the stability limit).
+
+def request_spec(req):
+    """(desc, ic, icp, sites) of a trace request; dt is clamped to 0.9 of the limit."""
+    import paper_2511_10508_amd as P
+    kind = req["kind"]
+    n = list(reversed(req["shape"]))[:req["ndim"]]
+    prec = P.PF_FP32 if req["fp32"] else P.PF_FP64
+    d = P.make_desc(kind, n, dx=1.0, dt=req["dt"], order=req["order"], precision=prec,
+                    params=req["params"])
+    lim = P.stability(d)
+    if d.dt > 0.9 * lim:
+        d.dt = 0.9 * lim
+    if kind == P.PF_GS:
+        ic, icp = P.PF_IC_GS_CUBES, (20, req["cube_side"], 0.01)
+    elif kind == P.PF_AC:
+        ic, icp = P.PF_IC_UNIFORM, (-0.1, 0.1)
+    else:
+        ic, icp = P.PF_IC_UNIFORM, (-0.05, 0.05)
+    return d, ic, icp, int(np.prod(req["shape"]))
+
+
+def _pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else float("nan")
+
+
+def _progress(every=30.0):
+    """log(msg) at most every `every` seconds."""
+    last = [time.perf_counter()]
+
+    def tick(msg):
+        now = time.perf_counter()
+        if now - last[0] >= every:
+            last[0] = now
+            log(msg)
+    return tick
+
+
+def run_batched(trace, max_slots=256, steps_per_tick=64, budget=0):
+    """The server: a submitter thread replays the arrivals, this thread polls
+    and releases; latency = completion seen by the poller minus arrival."""
+    import threading
+    from paper_2511_10508_amd.serving import Server
+    srv = Server(hbm_budget=budget, max_slots=max_slots, steps_per_tick=steps_per_tick)
+    progress = _progress()
+    specs = [request_spec(r) for r in trace]
+    work = sum(s[3] * r["steps"] for s, r in zip(specs, trace))
+    t_arr = {}
+    done = {}
+    start = time.perf_counter()
+
+    def submitter():
+        for r, (d, ic, icp, _) in zip(trace, specs):
+            wait = r["arrival"] - (time.perf_counter() - start)
+            if wait > 0:
+                time.sleep(wait)
+            tk = srv.submit(d, ic, r["seed"], icp, r["steps"])
+            t_arr[tk] = start + r["arrival"]
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat = []
+    while len(done) < len(trace):
+        for res in srv.poll():
+            now = time.perf_counter()
+            done[res["ticket"]] = res
+            srv.release(res["ticket"])
+            while res["ticket"] not in t_arr:
+                time.sleep(0.0005)
+            lat.append(now - t_arr[res["ticket"]])
+        progress("  batched: %d of %d requests done" % (len(done), len(trace)))
+        time.sleep(0.0005)
+    th.join()
+    makespan = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    bad = sum(1 for r in done.values() if r["status"] != 0)
+    return dict(p50_s=_pct(lat, 50), p99_s=_pct(lat, 99), makespan_s=makespan,
+                su_per_s=work / makespan, failed=bad, **st)
+
+
+def run_serial(trace):
+    """The one-at-a-time loop: for each request in arrival order, create,
+    initialise, one launch per step, reduce, destroy.  Its capacity is the
+    work over its busy time (the makespan less the time it waited for
+    arrivals), so one run on the Poisson trace gives both."""
+    import paper_2511_10508_amd as P
+    specs = [request_spec(r) for r in trace]
+    work = sum(s[3] * r["steps"] for s, r in zip(specs, trace))
+    lat = []
+    idle = 0.0
+    progress = _progress()
+    start = time.perf_counter()
+    for r, (d, ic, icp, _) in zip(trace, specs):
+        progress("  serial: %d of %d requests done" % (len(lat), len(trace)))
+        wait = r["arrival"] - (time.perf_counter() - start)
+        if wait > 0:
+            time.sleep(wait)
+            idle += wait
+        m = P.Model(d)
+        m.init(ic, r["seed"], icp)
+        m.step(r["steps"])
+        m.reduce(0)
+        m.close()
+        lat.append(time.perf_counter() - (start + r["arrival"]))
+    makespan = time.perf_counter() - start
+    return dict(p50_s=_pct(lat, 50), p99_s=_pct(lat, 99), makespan_s=makespan, idle_s=idle,
+                su_per_s=work / (makespan - idle))
+
+
+def serving_compare(nreq, seed=505, load=0.8, steps_per_tick=64):
+    """Throughput: the server's capacity with the whole trace submitted at
+    t = 0 (work over makespan); the one-at-a-time loop's capacity is its work
+    over busy time.  Latency: both on the same Poisson trace at `load` x the
+    server's capacity (requests/s); p50 and p99 of completion minus arrival."""
+    import synth
+    burst = synth.serving_trace(nreq, seed=seed, rate=None)
+    cap_b = run_batched(burst, steps_per_tick=steps_per_tick)
+    log("serving batched capacity: %.2f s" % cap_b["makespan_s"])
+    rate = load * nreq / cap_b["makespan_s"]
+    trace = synth.serving_trace(nreq, seed=seed, rate=rate)
+    lat_b = run_batched(trace, steps_per_tick=steps_per_tick)
+    log("serving batched at %.1f req/s: %.2f s" % (rate, lat_b["makespan_s"]))
+    lat_s = run_serial(trace)
+    log("serving serial at %.1f req/s: %.2f s (idle %.2f s)" % (rate, lat_s["makespan_s"],
+                                                                lat_s["idle_s"]))
+    return dict(requests=nreq, site_updates=sum(request_spec(r)[3] * r["steps"] for r in burst),
+                batched_su_per_s=cap_b["su_per_s"], serial_su_per_s=lat_s["su_per_s"],
+                throughput_speedup=cap_b["su_per_s"] / lat_s["su_per_s"],
+                load=load, rate_req_per_s=rate,
+                batched_p50_s=lat_b["p50_s"], batched_p99_s=lat_b["p99_s"],
+                serial_p50_s=lat_s["p50_s"], serial_p99_s=lat_s["p99_s"],
+                batched_capacity=cap_b, batched_load=lat_b, serial_load=lat_s)
 
 
 def cpu_baseline(n=4096, seconds=10.0, batch=10):
@@ -292,13 +496,20 @@ def main():
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
-    ap.add_argument("--serving", type=int, default=120,
+    ap.add_argument("--serving", type=int, default=2000,
                     help="requests in the serving comparison (0 skips it)")
     ap.add_argument("--skip-3d", action="store_true")
     ap.add_argument("--skip-mc", action="store_true", help="skip the Model C lines")
     ap.add_argument("--skip-next", action="store_true",
                     help="skip the direct-biharmonic, 1D, spectral and Model H lines")
+    ap.add_argument("--only", default="",
+                    help="comma-separated sections to run besides the headline: gs3d, ch3d, "
+                         "ac128, mc, next, serving, cpu (default: all)")
     args = ap.parse_args()
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(section, skipped=False):
+        return (section in only) if only else not skipped
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(requests would shard per GPU, a single model by slabs along its slowest "
@@ -316,7 +527,7 @@ def main():
     fp64 = run_ch(P, args.n, P.PF_FP64, args.steps, args.warmup)
     log("CH FP64: %.3f ms/step" % fp64["ms_per_step"])
     extra = {"copy_probe_gbs": round(attain, 1), "source_hash": src, "source_hash_3d": src3}
-    if not args.skip_fp32:
+    if not args.skip_fp32:  # the headline's FP32 twin always runs unless skipped
         fp32 = run_ch(P, args.n, P.PF_FP32, args.steps, args.warmup)
         extra["fp32"] = {
             "value": fp32["su_s"], "ms_per_step": round(fp32["ms_per_step"], 4),
@@ -325,17 +536,26 @@ def main():
             "mass_drift": fp32["mass_drift"], "chunk": fp32["chunk"],
             "time_block": fp32["time_block"]}
         log("CH FP32: %.3f ms/step" % fp32["ms_per_step"])
-    if not args.skip_3d:
+    if want("gs3d", args.skip_3d):
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             r = run_gs3d(P, 1024, prec, max(10, args.steps // 4), 5)
             r["hbm_bytes_per_launch"] = measured_traffic("gs3d_1024_" + tag, src3)
             extra["gs3d_1024_" + tag] = r
         log("GS 3D done")
-    if not args.skip_mc:
+    if want("ch3d", args.skip_3d):
+        for order in (2, 4, 6):
+            for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
+                extra["ch3d_512_p%d_%s" % (order, tag)] = run_ch3d(P, 512, order, prec,
+                                                                  max(20, args.steps // 2), 4)
+        log("CH 3D 512^3 done")
+    if want("ac128"):
+        extra["ac2d_128_fp64_1000_steps"] = run_ac128(P)
+        log("AC 128^2 done")
+    if want("mc", args.skip_mc):
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             extra["mc2d_%d_%s" % (args.n, tag)] = run_mc(P, args.n, prec, max(10, args.steps // 4), 4)
         log("Model C done")
-    if not args.skip_next:
+    if want("next", args.skip_next):
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             extra["chd2d_%d_%s" % (args.n, tag)] = run_ch_variant(
                 P, args.n, prec, max(10, args.steps // 4), 4, direct=True, ndim=2)
@@ -355,9 +575,8 @@ def main():
     extra["fp64_chunk"] = fp64["chunk"]
     extra["fp64_time_block"] = fp64["time_block"]
     extra["fp64_kernel_ms_per_launch"] = round(fp64["kernel_ms"], 4)
-    if args.serving:
-        from paper_2511_10508_amd import serving
-        extra["serving"] = serving.compare(args.serving, log=log)
+    if args.serving and want("serving"):
+        extra["serving"] = serving_compare(args.serving)
         log("serving done")
 
     traffic = measured_traffic("ch2d_%d_fp64" % args.n, src)
@@ -384,7 +603,7 @@ def main():
                      "traffic": traffic},
         "extra": extra,
     }
-    if not args.skip_cpu:
+    if want("cpu", args.skip_cpu):
         out["cpu_baseline"] = cpu_baseline()
         log("cpu baseline done")
     print(json.dumps(out))

@@ -13,7 +13,7 @@
  *   model; standard two-species form):
  *       du/dt = Du lap u - u v^2 + F (1 - u)
  *       dv/dt = Dv lap v + u v^2 - (F + k) v
- * on a uniform periodic 2D or 3D grid.  lap is the star-shaped sum of 1D
+ * on a uniform periodic 1D, 2D or 3D grid.  lap is the star-shaped sum of 1D
  * centred second-derivative stencils of any even accuracy order p
  * (Sec. "Compile-Time Stencil Generation": weights from polynomial
  * interpolation, symmetric unknowns); the Cahn-Hilliard biharmonic is that
@@ -88,9 +88,11 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
  *             transverse projector one: m_t = L mu - c3 div(m j), mu =
  *             c2 m^3 - c1 m - L m, j_t = L j + c3 m grad(mu) (grad and div
  *             by centred first-derivative stencils of accuracy `order`);
- *             nparams must match.  MH runs the per-site kernels (one
- *             field-sized temporary); its reductions cover m (mass,
- *             non-finite count); the server does not take it.
+ *             nparams must match.  MH runs one fused pass on 1D rows
+ *             (order <= 8) and 2D grids (order <= 4), and the per-site
+ *             kernels with one field-sized temporary (mu) otherwise; its
+ *             reductions cover m (mass, non-finite count); the server does
+ *             not take it.
  *   flags     PF_* flags above.  PF_BIHARMONIC_DIRECT (PF_CH only, else
  *             PF_ERR_ARG) replaces the Laplacian applied twice by the
  *             biharmonic's own stencil (Secs. "Advanced Derivative Support",

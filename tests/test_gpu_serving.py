@@ -9,7 +9,8 @@ import pytest
 import oracle
 import synth
 import paper_2511_10508_amd as P
-from paper_2511_10508_amd.serving import Server, request_spec
+from paper_2511_10508_amd.serving import Server
+from bench import request_spec
 
 pytestmark = pytest.mark.gpu
 
