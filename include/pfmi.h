@@ -244,6 +244,35 @@ pf_status pf_field_device(pf_model *m, int32_t field, void **ptr, int64_t *pitch
 pf_status pf_step(pf_model *m, int64_t nsteps);
 
 /*
+ * Allocation-free step, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Runs nsteps steps of the descriptor's model on caller-owned
+ * buffers in the layout of pf_create_on (2 * nfields buffers of
+ * pf_buffer_elems(desc) elements, 16-byte aligned; dev_bufs[2 f + p] is
+ * buffer p of field f), starting from buffer `parity` (0 or 1) of every
+ * field; the result is in buffer parity ^ (nsteps & 1).  The kernels and
+ * their plan are those of a pf_create_on model with pf_set_tile(m, 0), one
+ * step per launch and the default 3D tile layout, so fields and reductions
+ * are bitwise that model's.  With PF_REDUCE_EACH_STEP, dev_history
+ * (caller-owned device memory of 6 * nsteps doubles) receives for step k the
+ * reductions of the state at its start as three (hi, lo) pairs: the sum of
+ * field 0, the sum of field 1 (GS, MC) or of the energy density (AC, CH),
+ * and the non-finite count (hi), not multiplied by dx^ndim; without it
+ * dev_history may be NULL.  Enqueues on hip_stream (NULL = the null stream)
+ * of the current device and returns; no allocation.  The reduction partials
+ * live in one static 16 MiB device array per GPU, shared by every call on
+ * that GPU and keeping the last call's contents: calls that overlap on one
+ * GPU (other streams or threads) race and must be serialised by the caller.
+ * Errors, before anything is enqueued: PF_ERR_ARG (bad descriptor or
+ * arguments; PF_SPECTRAL, PF_FORCE_GENERIC or PF_USE_GRAPH; a grid whose
+ * partials need more than the 16 MiB), PF_ERR_UNSTABLE, PF_ERR_UNSUPPORTED
+ * (descriptors that need the per-site kernels and their field-sized
+ * temporary), PF_ERR_DEVICE.
+ */
+pf_status pf_step_noalloc(const pf_desc *desc, void *hip_stream, void *const *dev_bufs,
+                          int32_t nbufs, int32_t parity, int64_t nsteps, double *dev_history);
+
+/*
  * Reductions of the current state, compensated in FP64 on the device and
  * combined in a fixed order: value = hi + lo (double-double).
  *   PF_RED_MASS0 / PF_RED_MASS1: dx^d sum of field 0 / 1 (MASS1: GS and MC

@@ -81,6 +81,7 @@ SIGNATURES = {
     "pf_get_window": (_i32, [_vp, _i32, _pi64, _pi64, _pd]),
     "pf_field_device": (_i32, [_vp, _i32, _P(_vp), _pi64, _pi32]),
     "pf_step": (_i32, [_vp, _i64]),
+    "pf_step_noalloc": (_i32, [_P(pf_desc), _vp, _P(_vp), _i32, _i32, _i64, _vp]),
     "pf_reduce": (_i32, [_vp, _i32, _pd, _pd]),
     "pf_reduce_history": (_i32, [_vp, _i32, _pd, _pd, _i64]),
     "pf_sync": (_i32, [_vp]),
@@ -287,6 +288,15 @@ class Model:
         s = _vp()
         check(lib().pf_stream(self.h, ctypes.byref(s)))
         return s.value
+
+
+def step_noalloc(desc, stream, bufs, parity, nsteps, history=None):
+    """pf_step_noalloc: nsteps steps on caller-owned device buffers (device
+    pointers, pf_create_on layout) with no allocation; `history` is a device
+    pointer of 6 * nsteps doubles or None."""
+    arr = (_vp * len(bufs))(*bufs)
+    check(lib().pf_step_noalloc(ctypes.byref(desc), stream, arr, len(bufs), int(parity), int(nsteps),
+                                history))
 
 
 def weights(order):

@@ -84,6 +84,12 @@ pf_status reduce_now(Model *m, double2 *host_out);
 pf_status pick_quantity(const Model *m, int32_t which, const double2 *q, double *hi, double *lo);
 int32_t default_chunk(const pf_desc *d);
 
+// pf_step_noalloc (noalloc.hip): plan a borrowed model (all checks, no device
+// call, no allocation), then run it on the given reduction scratch.
+pf_status borrow_plan(Model *m, const pf_desc *d, void *stream, void *const *bufs, int32_t nbufs,
+                      int32_t parity, int64_t nsteps, const void *hist, int64_t *pairs_need);
+pf_status borrow_run(Model *m, double2 *scratch, int64_t nsteps, double2 *hist);
+
 // Model H on 2D grids (r <= 2) in one LDS-tiled pass, bitwise equal to the
 // two passes of the per-site kernels (which run it with PF_FORCE_GENERIC);
 // kernels_mh2d.hip.

@@ -586,6 +586,74 @@ pf_status do_steps(Model *m, int64_t nsteps)
     return PF_OK;
 }
 
+// pf_step_noalloc, host half: a model object that borrows the caller's
+// buffers and stream, planned as pf_create_on plans it with the default tile
+// (pf_set_tile(m, 0)), one step per launch and the default 3D tile layout.
+// Everything is checked here, before any device call; `pairs_need` returns
+// the reduction scratch (double2 pairs) the steps need (0 without
+// PF_REDUCE_EACH_STEP).  Allocates nothing.
+pf_status borrow_plan(Model *m, const pf_desc *d, void *stream, void *const *bufs, int32_t nbufs,
+                      int32_t parity, int64_t nsteps, const void *hist, int64_t *pairs_need)
+{
+    pf_status st = check_desc(d);
+    if (st != PF_OK) return st;
+    if (!(d->flags & PF_ALLOW_UNSTABLE) && d->dt > stability_limit(d))
+        return fail(PF_ERR_UNSTABLE, "dt exceeds the explicit-stability limit");
+    if (d->flags & (PF_SPECTRAL | PF_FORCE_GENERIC | PF_USE_GRAPH))
+        return fail(PF_ERR_ARG, "pf_step_noalloc takes no PF_SPECTRAL, PF_FORCE_GENERIC or PF_USE_GRAPH");
+    if (!bufs || nbufs != 2 * d->nfields) return fail(PF_ERR_ARG, "nbufs must be 2 * nfields");
+    if (parity != 0 && parity != 1) return fail(PF_ERR_ARG, "parity must be 0 or 1");
+    if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
+    const bool red = (d->flags & PF_REDUCE_EACH_STEP) != 0;
+    if (red && nsteps > 0 && !hist) return fail(PF_ERR_ARG, "PF_REDUCE_EACH_STEP needs a history buffer");
+    m->desc = *d;
+    m->nf = d->nfields;
+    m->fp32 = d->precision == PF_FP32;
+    m->L = Launch{(d->kind == kCH && (d->flags & PF_BIHARMONIC_DIRECT)) ? kCHD : d->kind, d->ndim,
+                  d->order / 2, m->fp32 ? 1 : 0};
+    m->pitch = pitch_of(d);
+    m->elems = buffer_elems(d);
+    m->stream = static_cast<hipStream_t>(stream);
+    m->own_stream = false;
+    m->own_bufs = false;
+    for (int f = 0; f < m->nf; ++f)
+        for (int p = 0; p < 2; ++p) {
+            void *b = bufs[2 * f + p];
+            if (!b || (reinterpret_cast<uintptr_t>(b) & 15))
+                return fail(PF_ERR_ARG, "device buffers must be non-NULL and 16-byte aligned");
+            m->buf[f][p] = b;
+        }
+    m->tb = 1;
+    m->rpw_req = 0;
+    m->clen = default_chunk(d);
+    plan(m);
+    if (m->family != 0)
+        return fail(PF_ERR_UNSUPPORTED, "this descriptor runs kernels that need a field-sized "
+                                        "temporary; pf_step_noalloc covers the fused kernels");
+    m->parity = parity;
+    *pairs_need = red ? (int64_t)kNumQ * (m->fused_slots + kFinSlots) : 0;
+    return PF_OK;
+}
+
+// pf_step_noalloc, device half: the reduction partials in `scratch` (every
+// pair a step reads is written earlier in the same step, so nothing needs
+// clearing), nsteps launches, the finalised reductions of step k (the state
+// at its start) to hist[kNumQ k .. kNumQ k + kNumQ).
+pf_status borrow_run(Model *m, double2 *scratch, int64_t nsteps, double2 *hist)
+{
+    const bool red = (m->desc.flags & PF_REDUCE_EACH_STEP) != 0;
+    m->part = red ? scratch : nullptr;
+    m->pstride = red ? m->fused_slots : 0;
+    m->part2 = red ? scratch + (int64_t)kNumQ * m->fused_slots : nullptr;
+    refresh_args(m);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        pf_status st = launch_step(m, m->parity, red, red ? hist + (int64_t)kNumQ * k : nullptr, false, 1);
+        if (st != PF_OK) return st;
+        m->parity ^= 1;
+    }
+    return PF_OK;
+}
+
 pf_status reduce_now(Model *m, double2 *host_out)
 {
     union {

@@ -249,3 +249,38 @@ def test_fornberg_first_derivative_matches_exact_weights(order):
     assert len(w) == len(exact)
     for a, e in zip(w, exact):
         assert abs(Fraction(float(a)) - e) <= 8 * Fraction(math.ulp(float(e)) or 2.0 ** -1074) + Fraction(1, 10 ** 14) * abs(e)
+
+
+def test_step_noalloc_refusals_precede_any_device_call():
+    """pf_step_noalloc checks its arguments and the reduction scratch it needs
+    (against the static 16 MiB) on the host before any HIP call; here, with
+    no GPU, each refusal is its own status rather than a device error.  The
+    pointers are never dereferenced: every case is refused first."""
+    ptrs = [16 * (i + 1) for i in range(4)]
+    red = P.PF_REDUCE_EACH_STEP
+    big = P.make_desc(P.PF_GS, (128, 4096, 6144), dt=0.5, order=2, precision=P.PF_FP32, flags=red)
+    with pytest.raises(P.PfError) as e:
+        P.step_noalloc(big, None, ptrs, 0, 1, 4096)
+    assert e.value.status == P.PF_ERR_ARG and "16 MiB" in str(e.value)
+    generic = P.make_desc(P.PF_CH, (20, 20, 20), dt=1e-4, order=10)
+    with pytest.raises(P.PfError) as e:
+        P.step_noalloc(generic, None, ptrs[:2], 0, 1, None)
+    assert e.value.status == P.PF_ERR_UNSUPPORTED
+    small = P.make_desc(P.PF_CH, (20, 20), dt=0.01, order=4, flags=red)
+    for args, status in (((ptrs[:2], 2, 1, 4096), P.PF_ERR_ARG),       # parity
+                         ((ptrs[:1], 0, 1, 4096), P.PF_ERR_ARG),       # nbufs
+                         ((ptrs[:2], 0, 1, None), P.PF_ERR_ARG),       # history
+                         ((ptrs[:2], 0, -1, 4096), P.PF_ERR_ARG),      # nsteps
+                         (([16, 40], 0, 1, 4096), P.PF_ERR_ARG)):      # alignment
+        with pytest.raises(P.PfError) as e:
+            P.step_noalloc(small, None, *args)
+        assert e.value.status == status
+    for flag in (P.PF_USE_GRAPH, P.PF_FORCE_GENERIC):
+        d = P.make_desc(P.PF_CH, (20, 20), dt=0.01, order=4, flags=flag)
+        with pytest.raises(P.PfError) as e:
+            P.step_noalloc(d, None, ptrs[:2], 0, 1, None)
+        assert e.value.status == P.PF_ERR_ARG
+    unstable = P.make_desc(P.PF_GS, (16, 16, 16), dt=1.0, order=2)
+    with pytest.raises(P.PfError) as e:
+        P.step_noalloc(unstable, None, ptrs, 0, 1, None)
+    assert e.value.status == P.PF_ERR_UNSTABLE
