@@ -115,7 +115,10 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
  *             about the separated states c^2 = c1/c2 (+inf for c1 = 0).  The
  *             mass reductions apply, the free energy is PF_ERR_UNSUPPORTED.
  *             The model holds two half spectra besides its fields (hipFFT
- *             plans allocate their own work space).  Not accepted by the server.
+ *             plans allocate their own work space) and keeps the updated
+ *             spectrum between steps, so a run of steps takes two transforms
+ *             per step; after pf_init, pf_set_field or pf_field_device the
+ *             next step transforms the state again.  Not accepted by the server.
  */
 typedef struct pf_desc {
     uint32_t struct_size;
@@ -399,8 +402,13 @@ typedef struct pf_result {
  * (0 = 90 % of free memory at creation); max_slots: most requests resident
  * at once, running or finished and not yet released (a finished request keeps
  * its memory and slot until pf_server_release); steps_per_tick: steps per
- * request per tick (0 = 64).  The environment variable PFMI_SERVER_MAX_GRAPHS
- * bounds the cache of captured tick graphs (default 256).
+ * request per tick (0 = 64).  Served requests run the batched kernels with
+ * two steps per launch where their class has a two-step kernel (2D orders 2
+ * and 4, 3D order 2), and the chunk length the server's autotuner picks per
+ * kernel class and size bucket on the first request of each bucket.
+ * Environment: PFMI_SERVER_MAX_GRAPHS bounds the cache of captured tick
+ * graphs (default 256); PFMI_SERVER_TWO_STEP=0 keeps one step per launch;
+ * PFMI_SERVER_TUNE=off keeps the library's default chunk.
  */
 pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t max_slots,
                            int32_t steps_per_tick, pf_server **out);

@@ -46,13 +46,13 @@ __device__ __forceinline__ void pairs1d(const T (&e)[NE], int v, T (&S)[R])
     });
 }
 
-// Forward differences x - x_{+j} in FP64 (energy by parts, FP32 storage).
+// Forward neighbours x_{+j} in FP64 (energy by parts, FP32 storage).
 template <typename T, int R, int RE, int NE>
-__device__ __forceinline__ void fwd1d64(const T (&e)[NE], int v, double x, double (&D)[R])
+__device__ __forceinline__ void fwd1d64(const T (&e)[NE], int v, double (&P)[R])
 {
     static_for<1, R + 1>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        D[j - 1] = x - (double)e[RE + v + j];
+        P[j - 1] = (double)e[RE + v + j];
     });
 }
 
@@ -96,9 +96,9 @@ __device__ __forceinline__ void stage1d(const StepArgs<T> &a,
                         for (int j = 0; j < R; ++j) S64[j] = S[0][j];
                         s1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, 2.0 * x);
                     } else {
-                        double D[R];
-                        fwd1d64<T, R, R>(e[0], v, x, D);
-                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                        double Pn[R];
+                        fwd1d64<T, R, R>(e[0], v, Pn);
+                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, a.w64sum, x, Pn);
                     }
                 }
             }
@@ -146,9 +146,9 @@ __device__ __forceinline__ void stage1d(const StepArgs<T> &a,
                     if constexpr (F64) {
                         s1 += energy_from_mu(a.c2, x, mu[v]);
                     } else {
-                        double D[R];
-                        fwd1d64<T, R, R>(e, v, x, D);
-                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                        double Pn[R];
+                        fwd1d64<T, R, R>(e, v, Pn);
+                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, a.w64sum, x, Pn);
                     }
                 }
             }
@@ -215,9 +215,9 @@ __device__ __forceinline__ void stage1d(const StepArgs<T> &a,
                         });
                         s1 += energy_density<R>(a.c1, a.c2, a.w64, x, S64, 2.0 * x);
                     } else {
-                        double D[R];
-                        fwd1d64<T, R, R4>(ec, v, x, D);
-                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                        double Pn[R];
+                        fwd1d64<T, R, R4>(ec, v, Pn);
+                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, a.w64sum, x, Pn);
                     }
                 }
             }

@@ -77,17 +77,28 @@ hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int
 }
 
 hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
-                                  hipStream_t s)
+                                  int tb, hipStream_t s)
 {
     hipError_t err = hipErrorInvalidValue;
+    if (tb == 2 && !time_block_available(L)) return err;
     dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
-        const BatchTable<T> &tb = *static_cast<const BatchTable<T> *>(table);
+        const BatchTable<T> &t = *static_cast<const BatchTable<T> *>(table);
         dispatch_kind(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
+            if (tb == 2) {
+                dispatch_r(L.r, TimeBlockRadii{}, [&](auto rc) {
+                    constexpr int R = decltype(rc)::value;
+                    hipLaunchKernelGGL((k_step2d_batched<T, KIND, R, 2>), dim3(blocks), dim3(64 * kWaves2D), 0,
+                                       s, t, k);
+                    err = hipGetLastError();
+                });
+                return;
+            }
             dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
-                hipLaunchKernelGGL((k_step2d_batched<T, KIND, R>), dim3(blocks), dim3(64 * kWaves2D), 0, s, tb, k);
+                hipLaunchKernelGGL((k_step2d_batched<T, KIND, R, 1>), dim3(blocks), dim3(64 * kWaves2D), 0, s,
+                                   t, k);
                 err = hipGetLastError();
             });
         });

@@ -1,0 +1,177 @@
+// Serving class for tiny grids: the whole grid of a request in one
+// workgroup's LDS.
+//
+// One workgroup of 1024 threads takes one request of the table at a time: it
+// loads the request's fields into LDS (dense, x fastest), runs the request's
+// steps of this tick there, ping-ponging between two copies of the fields,
+// and writes the final state into the other buffer of each field.  HBM is
+// touched once per tick instead of once per step, and a tick can run many
+// steps of a tiny request without lengthening the tick.  Cahn-Hilliard keeps
+// mu, Model C keeps g = rho + c3 phi^2 in a further LDS array.  Threads walk
+// the grid row by row (thread t holds column t mod nx of every
+// 1024 / nx-th row), so a site's coordinates cost no division.  Every site is
+// evaluated with the fused kernels' functions and neighbour order (x pair,
+// then y, then z), so the fields are bitwise those of the same request
+// stepped alone.
+#include "pf_device.h"
+#include "pf_dispatch.h"
+
+namespace pf {
+
+namespace {
+
+constexpr int kTinyThreads = 1024;
+
+// Neighbour pair sums of the LDS array u at site (x, y, z): x pair, then y,
+// then z, as the marching kernels form them.
+template <typename T, int R, int NDIM>
+__device__ __forceinline__ void tiny_pairs(const T *u, int32_t x, int32_t y, int32_t z, int32_t nx,
+                                           int32_t ny, int32_t nz, T (&S)[R])
+{
+    const int32_t row = (z * ny + y) * nx;
+#pragma unroll
+    for (int j = 1; j <= R; ++j) {
+        T acc = u[row + wrap32(x + j, nx)] + u[row + wrap32(x - j, nx)];
+        acc = acc + (u[(z * ny + wrap32(y + j, ny)) * nx + x] + u[(z * ny + wrap32(y - j, ny)) * nx + x]);
+        if constexpr (NDIM == 3)
+            acc = acc + (u[(wrap32(z + j, nz) * ny + y) * nx + x] + u[(wrap32(z - j, nz) * ny + y) * nx + x]);
+        S[j - 1] = acc;
+    }
+}
+
+// Calls f(i, x, y, z) for this thread's sites: column tid mod nx of rows
+// tid / nx, tid / nx + rpp, .. (rpp = 1024 / nx rows per pass; threads past
+// rpp nx idle).
+template <typename F>
+__device__ __forceinline__ void tiny_sweep(int32_t nx, int32_t ny, int32_t nz, F &&f)
+{
+    const int32_t rpp = kTinyThreads / nx;
+    const int32_t tid = threadIdx.x;
+    if (tid >= rpp * nx) return;
+    const int32_t x = tid % nx, r0 = tid / nx, rows = ny * nz;
+    int32_t y = r0 % ny, z = r0 / ny;
+    for (int32_t row = r0; row < rows; row += rpp) {
+        f(row * nx + x, x, y, z);
+        y += rpp;
+        while (y >= ny) {
+            y -= ny;
+            ++z;
+        }
+    }
+}
+
+template <typename T, int KIND, int R, int NDIM>
+__global__ void __launch_bounds__(kTinyThreads) k_tiny(BatchTable<T> tb)
+{
+    constexpr int NF = nfields_kind(KIND);
+    __shared__ T lds[kTinyLdsBytes / sizeof(T)];
+    const int32_t n = *tb.count;
+    for (int32_t e = blockIdx.x; e < n; e += gridDim.x) {
+        const int32_t steps = tb.steps[e];  // uniform over the workgroup
+        if (steps <= 0) continue;
+        const StepArgs<T> &a = tb.args[e];
+        const int32_t nx = (int32_t)a.nx, ny = (int32_t)a.ny, nz = (int32_t)a.nz;
+        const int32_t N = nx * ny * nz;
+        T *cur[NF], *nxt[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cur[f] = lds + f * N;
+            nxt[f] = lds + (NF + f) * N;
+        }
+        T *aux = lds + 2 * NF * N;
+        const int par = a.parity;
+        const T ctr = T(2 * NDIM);
+        tiny_sweep(nx, ny, nz, [&](int32_t i, int32_t x, int32_t y, int32_t z) {
+            const int64_t off = (int64_t)z * a.plane + (int64_t)y * a.pitch + x;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) cur[f][i] = a.buf[f][par][off];
+        });
+        __syncthreads();
+        for (int32_t s = 0; s < steps; ++s) {
+            if constexpr (KIND == kCH || KIND == kMC) {  // mu (CH) or g (MC) of every site
+                tiny_sweep(nx, ny, nz, [&](int32_t i, int32_t x, int32_t y, int32_t z) {
+                    if constexpr (KIND == kCH) {
+                        T S[R];
+                        tiny_pairs<T, R, NDIM>(cur[0], x, y, z, nx, ny, nz, S);
+                        aux[i] = ch_mu<T, R>(a, cur[0][i], S, cur[0][i] * ctr);
+                    } else {
+                        aux[i] = mc_g(a, cur[0][i], cur[NF - 1][i]);
+                    }
+                });
+                __syncthreads();
+            }
+            tiny_sweep(nx, ny, nz, [&](int32_t i, int32_t x, int32_t y, int32_t z) {
+                const T u0 = cur[0][i];
+                if constexpr (KIND == kAC) {
+                    T S[R];
+                    tiny_pairs<T, R, NDIM>(cur[0], x, y, z, nx, ny, nz, S);
+                    nxt[0][i] = ac_update<T, R>(a, u0, S, u0 * ctr);
+                } else if constexpr (KIND == kCH) {
+                    T Sm[R];
+                    tiny_pairs<T, R, NDIM>(aux, x, y, z, nx, ny, nz, Sm);
+                    nxt[0][i] = ch_update<T, R>(a, u0, Sm, aux[i] * ctr);
+                } else if constexpr (KIND == kGS) {
+                    T Su[R], Sv[R];
+                    tiny_pairs<T, R, NDIM>(cur[0], x, y, z, nx, ny, nz, Su);
+                    tiny_pairs<T, R, NDIM>(cur[NF - 1], x, y, z, nx, ny, nz, Sv);
+                    const T v0 = cur[NF - 1][i];
+                    gs_update<T, R>(a, u0, v0, Su, Sv, u0 * ctr, v0 * ctr, nxt[0][i], nxt[NF - 1][i]);
+                } else {
+                    T Sp[R], Sg[R];
+                    tiny_pairs<T, R, NDIM>(cur[0], x, y, z, nx, ny, nz, Sp);
+                    tiny_pairs<T, R, NDIM>(aux, x, y, z, nx, ny, nz, Sg);
+                    mc_update<T, R>(a, u0, cur[NF - 1][i], Sp, Sg, u0 * ctr, aux[i] * ctr, nxt[0][i],
+                                    nxt[NF - 1][i]);
+                }
+            });
+            __syncthreads();
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                T *t = cur[f];
+                cur[f] = nxt[f];
+                nxt[f] = t;
+            }
+        }
+        tiny_sweep(nx, ny, nz, [&](int32_t i, int32_t x, int32_t y, int32_t z) {
+            const int64_t off = (int64_t)z * a.plane + (int64_t)y * a.pitch + x;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) a.buf[f][par ^ 1][off] = cur[f][i];
+        });
+        __syncthreads();  // the next request reuses the LDS
+    }
+}
+
+}  // namespace
+
+bool tiny_available(const Launch &L, int64_t nx, int64_t ny, int64_t nz)
+{
+    if (L.ndim < 2 || L.r < 1 || L.r > 4) return false;
+    if (L.kind != kAC && L.kind != kCH && L.kind != kGS && L.kind != kMC) return false;
+    if (nx > kTinyThreads || ny > 1 << 20 || nz > 1 << 20) return false;
+    const int64_t N = nx * ny * nz;
+    const int nf = nfields_kind(L.kind), arrays = 2 * nf + ((L.kind == kCH || L.kind == kMC) ? 1 : 0);
+    return arrays * N * (L.fp32 ? 4 : 8) <= kTinyLdsBytes;
+}
+
+hipError_t launch_tiny(const Launch &L, const void *table, int32_t blocks, hipStream_t s)
+{
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_prec(L.fp32, [&](auto tz) {
+        using T = decltype(tz);
+        const BatchTable<T> &t = *static_cast<const BatchTable<T> *>(table);
+        dispatch_kind(L.kind, [&](auto kc) {
+            constexpr int KIND = decltype(kc)::value;
+            dispatch_r(L.r, RList<1, 2, 3, 4>{}, [&](auto rc) {
+                constexpr int R = decltype(rc)::value;
+                if (L.ndim == 2)
+                    hipLaunchKernelGGL((k_tiny<T, KIND, R, 2>), dim3(blocks), dim3(kTinyThreads), 0, s, t);
+                else
+                    hipLaunchKernelGGL((k_tiny<T, KIND, R, 3>), dim3(blocks), dim3(kTinyThreads), 0, s, t);
+                err = hipGetLastError();
+            });
+        });
+    });
+    return err;
+}
+
+}  // namespace pf

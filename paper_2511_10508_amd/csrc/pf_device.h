@@ -146,15 +146,15 @@ __device__ __forceinline__ T ac_update(const StepArgs<T> &a, T u0, const T (&S)[
     return acc;
 }
 
-// Cahn-Hilliard (Eq. model-b) chemical potential mu = c2 c^3 - c1 c - L c:
-// k0 = c1, k1 = c2, wi = w_j/dx^2.  Also returns L c.
+// Cahn-Hilliard (Eq. model-b) chemical potential mu = c2 c^3 - c1 c - L c =
+// c (c2 c^2 - c1) - L c: k0 = c1, k1 = c2, wi = w_j/dx^2.
 template <typename T, int R>
 __device__ __forceinline__ T ch_mu(const StepArgs<T> &a, T c0, const T (&S)[R], T ctr)
 {
     T lc = T(0);
 #pragma unroll
     for (int j = 0; j < R; ++j) lc = fma(a.wi[j], S[j] - ctr, lc);
-    return fma(a.k1 * c0, c0 * c0, -(a.k0 * c0)) - lc;
+    return fma(c0, fma(a.k1 * c0, c0, -a.k0), -lc);
 }
 // Cahn-Hilliard update c' = c + dt L mu: wu = dt w_j/dx^2, S from mu.
 template <typename T, int R>
@@ -174,7 +174,7 @@ __device__ __forceinline__ T ch_update(const StepArgs<T> &a, T c0, const T (&Sm)
 template <typename T>
 __device__ __forceinline__ T chd_g(const StepArgs<T> &a, T c0)
 {
-    return fma(a.k1 * c0, c0 * c0, -(a.k0 * c0));
+    return c0 * fma(a.k1 * c0, c0, -a.k0);
 }
 // Update from Sm (pairs of mu_a along axis a, summed over axes; ctrm = the
 // matching centre terms 2 sum_a mu_a) and S4 (fourth-derivative pairs of c,
@@ -259,19 +259,21 @@ __device__ __forceinline__ double energy_density(double c1, double c2, const dou
 
 // The same energy summed by parts, for FP32 storage (the state widened to
 // FP64): over the periodic grid, -(1/2) sum_i x_i (L x)_i equals
-// sum_i x_i sum_j w_j sum_axes (x_i - x_{i + j e_axis}), so each site takes
-// only its forward neighbours.  D[j-1] holds sum_axes (x - x_forward) at
-// distance j.  The per-site values differ from energy_density, the sum over
-// the grid (every reduction reports only sums) is the same up to rounding.
+// sum_i x_i sum_j w_j sum_axes (x_i - x_{i + j e_axis}) = sum_i x_i (wd x_i -
+// sum_j w_j P_j), where P[j-1] is the sum over the axes of the forward
+// neighbours at distance j and wd = ndim sum_j w_j; so each site takes only
+// its forward neighbours, and a multiply-add per distance.  The per-site
+// values differ from energy_density, the sum over the grid (every reduction
+// reports only sums) is the same up to rounding.
 template <int R>
-__device__ __forceinline__ double energy_by_parts(double c1, double c2, const double *w64, double x,
-                                                  const double (&D)[R])
+__device__ __forceinline__ double energy_by_parts(double c1, double c2, const double *w64, double wd,
+                                                  double x, const double (&P)[R])
 {
-    double g = 0.0;
+    double s = w64[0] * P[0];
 #pragma unroll
-    for (int j = 0; j < R; ++j) g = fma(w64[j], D[j], g);
+    for (int j = 1; j < R; ++j) s = fma(w64[j], P[j], s);
     const double x2 = x * x;
-    return fma(x, g, x2 * fma(0.25 * c2, x2, -0.5 * c1));
+    return fma(x, fma(wd, x, -s), x2 * fma(0.25 * c2, x2, -0.5 * c1));
 }
 
 // ---------------------------------------------------------------------------

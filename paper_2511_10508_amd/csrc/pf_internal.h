@@ -51,6 +51,7 @@ struct StepArgs {
     T w1[kMaxR];             // w1_j/dx (Model H: first derivatives, j = 1..r)
     T k0, k1, k2, k3;        // model constants (see kernels)
     double w64[kMaxR];       // w_j / dx^2 in FP64 (energy)
+    double w64sum;           // sum_j w64[j] (energy by parts)
     double c1, c2;           // FP64 Landau constants (energy)
     double2 *part;           // partial sums [q][slot]
     int64_t pstride;         // slots per quantity
@@ -99,10 +100,25 @@ hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int
                           int red, int tb, hipStream_t s);
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
                           int red, int tb, int rpw, hipStream_t s);
+// Batched (serving) launches: step k of the tick for every request of the
+// table.  tb = 2 (where time_block_available): the launch advances requests
+// with two or more steps left in the tick by a two-step sweep and those with
+// one left by a single step (their plan, made for two steps, covers the
+// single-step kernel); k counts steps, so the tick's launches are k = 0, 2, ..
 hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
-                                  hipStream_t s);
+                                  int tb, hipStream_t s);
 hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
-                                  hipStream_t s);
+                                  int tb, hipStream_t s);
+
+// Tiny-grid serving class: the whole grid of a request in one workgroup's LDS
+// (kTinyLdsBytes), all of a tick's steps of the request in one launch
+// (table steps[i] of them), the result written into the other buffer of
+// each field (one buffer flip per launch).  tiny_available: 2D / 3D AC, CH,
+// GS, Model C with r <= 4 and nx <= 1024 whose two copies of the fields
+// (plus mu or g) fit the LDS.
+constexpr int kTinyLdsBytes = 128 * 1024;
+bool tiny_available(const Launch &L, int64_t nx, int64_t ny, int64_t nz);
+hipError_t launch_tiny(const Launch &L, const void *table, int32_t blocks, hipStream_t s);
 
 // Generic per-site family (any r <= kMaxR, 1D, 2D and 3D).  CH runs two
 // passes through `scratch`: one field-sized buffer of T (same pitch as the
@@ -111,13 +127,14 @@ hipError_t launch_generic(const Launch &L, const void *args, void *scratch, hipS
 
 // Semi-implicit Fourier spectral step (Models A and B): the explicit term of
 // buf[0][parity] into g (pitched like the fields), and the implicit update of
-// the half spectrum uh from the explicit term's spectrum nh.
+// the half spectrum uh from the explicit term's spectrum nh (written to both).
 struct SpecArgs {
-    void *uh;              // half spectrum of the state, updated in place
-    const void *nh;        // half spectrum of the explicit term
+    void *uh;              // half spectrum of the state (u_scale uh), updated in place
+    void *nh;              // half spectrum of the explicit term; receives the update too
     int64_t nxh, ny, nz;   // nx/2 + 1, ny, nz
     double sx, sy, sz;     // 2 pi / (n_a dx)
     double dt, inv_n;      // time step, 1 / (nx ny nz)
+    double u_scale;        // 1 / (nx ny nz) for a fresh transform, 1 for the kept spectrum
 };
 hipError_t launch_spectral_nonlinear(const Launch &L, const void *args, void *g, hipStream_t s);
 hipError_t launch_spectral_update(const Launch &L, const SpecArgs &a, hipStream_t s);

@@ -33,16 +33,16 @@ __device__ __forceinline__ void pairs2d(const T (&rg)[K][V], const T (&e)[V + 2 
     });
 }
 
-// Forward differences sum_axes (x - x_forward) at distances 1..R of element
-// v, in FP64 from the widened values (x forward along +x, y along the ring).
+// Forward-neighbour sums over the axes at distances 1..R of element v, in
+// FP64 from the widened values (x forward along +x, y along the ring).
 template <typename T, int V, int R, int K, int CS>
 __device__ __forceinline__ void fwd2d64(const T (&rg)[K][V], const T (&e)[V + 2 * R], int v,
-                                        double x, double (&D)[R])
+                                        double (&P)[R])
 {
     static_for<1, R + 1>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         constexpr int sp = (CS + j) % K;
-        D[j - 1] = (x - (double)e[R + v + j]) + (x - (double)rg[sp][v]);
+        P[j - 1] = (double)e[R + v + j] + (double)rg[sp][v];
     });
 }
 
@@ -110,9 +110,9 @@ __device__ __forceinline__ void stage_acgs(const StepArgs<T> &a,
                     if constexpr (std::is_same<T, double>::value) {
                         s1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 4.0);
                     } else {
-                        double D[R];
-                        fwd2d64<T, V, R, K, CS>(rg[0], e[0], v, x, D);
-                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                        double Pn[R];
+                        fwd2d64<T, V, R, K, CS>(rg[0], e[0], v, Pn);
+                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, 2.0 * a.w64sum, x, Pn);
                     }
                 } else {
                     s1 += (double)rg[NF - 1][CS][v];
@@ -150,9 +150,9 @@ __device__ __forceinline__ void stage_mu(const StepArgs<T> &a, const T (&c)[K][V
                 if constexpr (std::is_same<T, double>::value) {
                     s1 += energy_from_mu(a.c2, x, mu[v]);
                 } else {
-                    double D[R];
-                    fwd2d64<T, V, R, K, CS>(c, e, v, x, D);
-                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                    double Pn[R];
+                    fwd2d64<T, V, R, K, CS>(c, e, v, Pn);
+                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, 2.0 * a.w64sum, x, Pn);
                 }
             }
         }
@@ -244,12 +244,12 @@ __device__ __forceinline__ void stage_chd(const StepArgs<T> &a, const T (&c)[K][
                     // the full chemical potential: mu_x + mu_y - g
                     s1 += energy_from_mu(a.c2, x, (mx[v] + my[CS][v]) - chd_g(a, c0));
                 } else {
-                    double D[R];
+                    double Pn[R];
                     static_for<1, R + 1>([&](auto jc) {
                         constexpr int j = decltype(jc)::value;
-                        D[j - 1] = (x - (double)ec[R4 + v + j]) + (x - (double)c[(CS + j) % K][v]);
+                        Pn[j - 1] = (double)ec[R4 + v + j] + (double)c[(CS + j) % K][v];
                     });
-                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, 2.0 * a.w64sum, x, Pn);
                 }
             }
         }
@@ -462,8 +462,11 @@ __global__ void __launch_bounds__(64 * kWaves2D)
 
 // Persistent batched 2D step: a fixed grid strides over the work items of
 // every request in the table (step k of the tick; requests with fewer steps
-// this tick skip).  Each request is stepped exactly as by k_step2d.
-template <typename T, int KIND, int R>
+// this tick skip).  Each request is stepped exactly as by k_step2d.  With
+// TB = 2, k is even and a request with two or more steps left in the tick
+// takes a two-step sweep, one with a single step left a single step; both
+// read buffer parity + k / 2 and write the other.
+template <typename T, int KIND, int R, int TB>
 __global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> tb, int32_t k)
 {
     const int32_t n = *tb.count;
@@ -472,10 +475,17 @@ __global__ void __launch_bounds__(64 * kWaves2D) k_step2d_batched(BatchTable<T> 
     for (int32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves2D + (int)(threadIdx.x >> 6));
          g < total; g += stride) {
         const int i = batch_request(tb, n, g);
-        if (k >= tb.steps[i]) continue;
+        const int32_t left = tb.steps[i] - k;  // uniform over the wave
+        if (left <= 0) continue;
         const StepArgs<T> &a = tb.args[i];
-        step2d_item<T, KIND, R, false, 1>(a, (a.parity + k) & 1, g - tb.item_start[i],
-                                          threadIdx.x & 63, 0);
+        const int par = (a.parity + k / TB) & 1;
+        if constexpr (TB == 2) {
+            if (left >= 2) {
+                step2d_item<T, KIND, R, false, 2>(a, par, g - tb.item_start[i], threadIdx.x & 63, 0);
+                continue;
+            }
+        }
+        step2d_item<T, KIND, R, false, 1>(a, par, g - tb.item_start[i], threadIdx.x & 63, 0);
     }
 }
 

@@ -73,19 +73,18 @@ __device__ __forceinline__ void pairs3d(const T (&rg)[K][V], const T (&e)[V + 2 
     });
 }
 
-// Forward differences sum_axes (x - x_forward) at distances 1..R of element
-// v, in FP64 from the widened values (+x from e, +y from the LDS rows, +z
-// along the ring).
+// Forward-neighbour sums over the axes at distances 1..R of element v, in
+// FP64 from the widened values (+x from e, +y from the LDS rows, +z along
+// the ring).
 template <typename T, int V, int R, int K, int CS, int NR, int RW>
 __device__ __forceinline__ void fwd3d64(const T (&rg)[K][V], const T (&e)[V + 2 * R],
-                                        const T (&L)[NR][RW], int rw, int pl, int v, double x,
-                                        double (&D)[R])
+                                        const T (&L)[NR][RW], int rw, int pl, int v,
+                                        double (&P)[R])
 {
     static_for<1, R + 1>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         constexpr int sp = (CS + j) % K;
-        D[j - 1] = ((x - (double)e[R + v + j]) + (x - (double)L[rw + j][pl + v])) +
-                   (x - (double)rg[sp][v]);
+        P[j - 1] = ((double)e[R + v + j] + (double)L[rw + j][pl + v]) + (double)rg[sp][v];
     });
 }
 
@@ -152,9 +151,9 @@ __device__ __forceinline__ void stage3_acgs(const StepArgs<T> &a,
                     if constexpr (std::is_same<T, double>::value) {
                         s1 += energy_density<R>(a.c1, a.c2, a.w64, x, Sf[0], x * 6.0);
                     } else {
-                        double D[R];
-                        fwd3d64<T, V, R, K, CS, NR, RW>(rg[0], e[0], L[0], rw, pl, v, x, D);
-                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                        double Pn[R];
+                        fwd3d64<T, V, R, K, CS, NR, RW>(rg[0], e[0], L[0], rw, pl, v, Pn);
+                        s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, 3.0 * a.w64sum, x, Pn);
                     }
                 } else {
                     s1 += (double)rg[NF - 1][CS][v];
@@ -191,9 +190,9 @@ __device__ __forceinline__ void stage3_mu(const StepArgs<T> &a, const T (&c)[K][
                 if constexpr (std::is_same<T, double>::value) {
                     s1 += energy_from_mu(a.c2, x, mu[v]);
                 } else {
-                    double D[R];
-                    fwd3d64<T, V, R, K, CS, NR, RW>(c, e, L, rw, pl, v, x, D);
-                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                    double Pn[R];
+                    fwd3d64<T, V, R, K, CS, NR, RW>(c, e, L, rw, pl, v, Pn);
+                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, 3.0 * a.w64sum, x, Pn);
                 }
             }
         }
@@ -223,10 +222,12 @@ __device__ __forceinline__ void stage3_chupd(const StepArgs<T> &a, const T (&m)[
 // the K-deep prefetch ring would not fit the 128 registers a lane of a
 // 16-wave workgroup can hold (wider stencils, and two-step sweeps with fused
 // reductions), where a plane's work is also long enough to hide one plane's
-// load latency.
+// load latency.  FP64 Cahn-Hilliard with r = 2 has room for the K = 5 ring
+// (about 120 registers with reductions).
 template <typename T, int KIND, int R, int TB, bool RED>
 constexpr int prefetch_depth()
 {
+    if (std::is_same<T, double>::value && KIND == kCH && R == 2 && TB == 1) return 2 * R + 1;
     return (R >= 2 || (TB == 2 && RED) || KIND == kCHD) ? 1 : 2 * R + 1;
 }
 
@@ -322,13 +323,13 @@ __device__ __forceinline__ void stage3_chd(const StepArgs<T> &a, const T (&c)[K]
                     // the full chemical potential: (mu_x + mu_y + mu_z - g) / 2
                     s1 += energy_from_mu(a.c2, x, 0.5 * (musum - chd_g(a, c0)));
                 } else {
-                    double D[R];
+                    double Pn[R];
                     static_for<1, R + 1>([&](auto jc) {
                         constexpr int j = decltype(jc)::value;
-                        D[j - 1] = ((x - (double)ec[R4 + v + j]) + (x - (double)Lc[rw + j][pl + v])) +
-                                   (x - (double)c[(CS + j) % K][v]);
+                        Pn[j - 1] = ((double)ec[R4 + v + j] + (double)Lc[rw + j][pl + v]) +
+                                    (double)c[(CS + j) % K][v];
                     });
-                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, x, D);
+                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, 3.0 * a.w64sum, x, Pn);
                 }
             }
         }
@@ -463,12 +464,13 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             // Model C keeps phi and g = rho + c3 phi^2 (the diffused field) in LDS
+                            // (the g branch is live only for Model C, NF = 2)
                             L[0][f][rw][pl + v] = (KIND == kMC && f == 1)
-                                                      ? mc_g(a, ring[0][s1][v], ring[1][s1][v])
+                                                      ? mc_g(a, ring[0][s1][v], ring[NF - 1][s1][v])
                                                       : ring[f][s1][v];
                             if constexpr (TB == 2)
                                 L[TB - 1][f][rw][pl + v] = (KIND == kMC && f == 1)
-                                                               ? mc_g(a, r1[0][s2][v], r1[1][s2][v])
+                                                               ? mc_g(a, r1[0][s2][v], r1[NF - 1][s2][v])
                                                                : r1[f][s2][v];
                         }
                 } else {
@@ -599,18 +601,26 @@ __global__ void __launch_bounds__(64 * kWaves3D) k_step3d(StepArgs<T> a)
 }
 
 // Persistent batched 3D step (see k_step2d_batched), two rows per wave; the
-// item loop is uniform over the workgroup, so every wave reaches the same
-// barriers.
-template <typename T, int KIND, int R>
+// item loop and the choice of a two-step sweep are uniform over the
+// workgroup, so every wave reaches the same barriers.
+template <typename T, int KIND, int R, int TB>
 __global__ void __launch_bounds__(64 * kWaves3D) k_step3d_batched(BatchTable<T> tb, int32_t k)
 {
     const int32_t n = *tb.count;
     const int32_t total = tb.item_start[n];
     for (int32_t g = blockIdx.x; g < total; g += gridDim.x) {
         const int i = batch_request(tb, n, g);
-        if (k >= tb.steps[i]) continue;
+        const int32_t left = tb.steps[i] - k;
+        if (left <= 0) continue;
         const StepArgs<T> &a = tb.args[i];
-        step3d_item<T, KIND, R, false, 1, 2>(a, (a.parity + k) & 1, g - tb.item_start[i], 0);
+        const int par = (a.parity + k / TB) & 1;
+        if constexpr (TB == 2) {
+            if (left >= 2) {
+                step3d_item<T, KIND, R, false, 2, 2>(a, par, g - tb.item_start[i], 0);
+                continue;
+            }
+        }
+        step3d_item<T, KIND, R, false, 1, 2>(a, par, g - tb.item_start[i], 0);
     }
 }
 

@@ -100,6 +100,8 @@ hipError_t launch_mh2d(const Launch &L, const void *args, hipStream_t s);
 pf_status spectral_setup(Model *m);
 pf_status spectral_step(Model *m, int par, const void *step_args);
 void spectral_release(Model *m);
+// The kept spectrum no longer matches the state (set from outside).
+void spectral_invalidate(Model *m);
 uint64_t spectral_bytes(const pf_desc *d);
 
 }  // namespace pf

@@ -188,9 +188,11 @@ static void fill_args(Model *m, StepArgs<T> &a)
     double w[kMaxR + 1];
     centered_d2_weights(d.order, w);
     const double idx2 = 1.0 / (d.dx * d.dx);
+    a.w64sum = 0.0;
     for (int j = 1; j <= r; ++j) {
         const double wl = w[j] * idx2;
         a.w64[j - 1] = wl;
+        a.w64sum += wl;
         a.wi[j - 1] = (T)wl;
         if (d.kind == kGS) {
             a.wu[j - 1] = (T)(d.dt * d.params[0] * wl);
@@ -497,8 +499,8 @@ static pf_status ensure_history(Model *m, int64_t n)
 static void destroy_graphs(Model *m)
 {
     for (auto &g : m->graphs) {
-        if (g.exec) hipGraphExecDestroy(g.exec);
-        if (g.graph) hipGraphDestroy(g.graph);
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
     }
     m->graphs.clear();
     m->graphs_valid = false;
@@ -523,7 +525,7 @@ static pf_status capture_graph(Model *m, int par, int k, bool red, Model::Graph 
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(m->stream, &graph);
     if (st != PF_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return st;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -795,9 +797,13 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
         return hip_fail(e, "hipMalloc(result)");
     }
     int32_t chunk = 0;
-    // served requests keep the default chunk and the batched kernels' layout
-    // (one step per launch, two tile rows per wave in 3D)
-    if (m->async_alloc) m->rpw_req = 2;
+    // served requests take the batched kernels' layout (two tile rows per
+    // wave in 3D, two-step sweeps where the class has them); the serving
+    // autotuner sets their chunk after admission
+    if (m->async_alloc) {
+        m->rpw_req = 2;
+        m->tb = time_block_available(m->L) ? 2 : 1;
+    }
     if (!m->async_alloc) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(tune_key(*desc));
@@ -857,16 +863,16 @@ void pf_destroy_model(Model *m)
     if (m->own_bufs)
         for (int f = 0; f < kMaxFields; ++f)
             for (int p = 0; p < 2; ++p)
-                if (m->buf[f][p]) hipFree(m->buf[f][p]);
-    if (m->part) hipFree(m->part);
-    if (m->res) hipFree(m->res);
-    if (m->part2) hipFree(m->part2);
-    if (m->hist) hipFree(m->hist);
-    if (m->stage) hipFree(m->stage);
-    if (m->scratch) hipFree(m->scratch);
+                if (m->buf[f][p]) (void)hipFree(m->buf[f][p]);
+    if (m->part) (void)hipFree(m->part);
+    if (m->res) (void)hipFree(m->res);
+    if (m->part2) (void)hipFree(m->part2);
+    if (m->hist) (void)hipFree(m->hist);
+    if (m->stage) (void)hipFree(m->stage);
+    if (m->scratch) (void)hipFree(m->scratch);
     spectral_release(m);
-    for (auto ev : m->events) hipEventDestroy(ev);
-    if (m->own_stream && m->stream) hipStreamDestroy(m->stream);
+    for (auto ev : m->events) (void)hipEventDestroy(ev);
+    if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
     delete m;
 }
 
@@ -937,6 +943,7 @@ pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int3
     }
     if (e != hipSuccess) return hip_fail(e, "init launch");
     m->steps_done = 0;
+    spectral_invalidate(m);
     return PF_OK;
 }
 
@@ -1156,6 +1163,7 @@ PF_API pf_status pf_set_field(pf_model *mm, int32_t field, const double *host, i
         for (int64_t i = 0; i < N; ++i) s[i] = (float)host[i];
         src = s;
     }
+    spectral_invalidate(m);
     PF_HIP(hipMemcpy2DAsync(m->buf[field][m->parity], ts * m->pitch, src, ts * d.n[0], ts * d.n[0],
                             d.n[1] * d.n[2], hipMemcpyHostToDevice, m->stream),
            "hipMemcpy2DAsync(set_field)");
@@ -1225,6 +1233,7 @@ PF_API pf_status pf_field_device(pf_model *mm, int32_t field, void **ptr, int64_
     if (!m) return fail(PF_ERR_ARG, "model is NULL");
     if (field < 0 || field >= m->nf) return fail(PF_ERR_ARG, "field index out of range");
     if (ptr) *ptr = m->buf[field][m->parity];
+    spectral_invalidate(m);  // the caller may write through the view
     if (pitch_elems) *pitch_elems = m->pitch;
     if (eb) *eb = (int32_t)tsize(m);
     return PF_OK;

@@ -7,15 +7,18 @@
 //   2. groups the running requests by kernel class (model, dimension,
 //      stencil radius, precision) and uploads one work-item table per class;
 //   3. launches, per class and on the class's own stream, a captured HIP
-//      graph of `steps_per_tick` chained persistent batched launches
-//      (captured once per class, table buffer and grid bucket); the class
-//      streams fork from and join back into the scheduler stream, so the
-//      classes run concurrently;
+//      graph of the tick's chained persistent batched launches (one per step,
+//      or one per two steps where the class has a two-step kernel; captured
+//      once per class, table buffer and grid bucket); the class streams fork
+//      from and join back into the scheduler stream, so the classes run
+//      concurrently;
 //   4. enqueues the final reductions of requests that finish in this tick.
 // Ticks are pipelined two deep: tick i+1 is enqueued before the host waits
 // for tick i, and requests that finished in tick i are retired (results
 // visible to pf_server_poll) once its event completes.  Requests submitted
-// while ticks run join at the next tick boundary.
+// while ticks run join at the next tick boundary.  The chunk length of each
+// request comes from the serving autotuner (tune_served), per kernel class
+// and size bucket.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -63,12 +66,17 @@ struct Req {
 };
 
 struct ClassKey {
-    int kind, ndim, r, fp32;
+    int kind, ndim, r, fp32, tiny;
     bool operator<(const ClassKey &o) const
     {
-        return std::tie(kind, ndim, r, fp32) < std::tie(o.kind, o.ndim, o.r, o.fp32);
+        return std::tie(kind, ndim, r, fp32, tiny) < std::tie(o.kind, o.ndim, o.r, o.fp32, o.tiny);
     }
 };
+
+// Steps a tiny-grid request may run per tick, in units of steps_per_tick: its
+// launch stays short (a few ms for the largest tiny grid) next to a tick of
+// the other classes, and it finishes in a few ticks.
+constexpr int kTinyTickFactor = 16;
 
 // Device and pinned host buffers of one class's work-item tables, double
 // buffered across pipelined ticks.
@@ -80,6 +88,9 @@ struct ClassTables {
     void *host[2] = {nullptr, nullptr};
     int32_t n[2] = {0, 0};
     int32_t blocks[2] = {1, 1};          // persistent grid of this tick (power of two)
+    int tb = 1;                          // steps per batched launch (2: two-step kernels)
+    bool tiny = false;                   // whole grid in LDS, one launch per tick
+    void *tune_dev = nullptr, *tune_host = nullptr;  // the autotuner's table (same layout)
     hipStream_t stream = nullptr;        // graph branch of this class
     hipEvent_t join = nullptr;
 };
@@ -92,6 +103,8 @@ struct Server {
     int max_slots = 0;
     int spt = 64;
     int max_graphs = kMaxGraphs;
+    bool two_step = true;  // two-step batched kernels where the class has them (PFMI_SERVER_TWO_STEP)
+    bool tune = true;      // serving autotuner (PFMI_SERVER_TUNE=off disables it)
     hipStream_t stream = nullptr, copy_stream = nullptr;
     std::chrono::steady_clock::time_point t0;
 
@@ -114,6 +127,9 @@ struct Server {
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;  // (class, set, steps, grid) -> graph
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr;
+    hipEvent_t tev[2] = {nullptr, nullptr};  // autotuner timing
+    // serving autotuner: chunk per (class, log2 of each extent)
+    std::map<std::tuple<int, int, int, int>, int32_t> tuned;
     // written by the scheduler thread, read by pf_server_stats from any thread
     std::atomic<int64_t> tick{0}, launches{0}, captures{0}, replays{0};
     std::string fatal;  // guarded by mu (set_fatal)
@@ -136,13 +152,16 @@ static void set_fatal(Server *s, const std::string &msg)
 
 static int class_of(Server *s, const Model *m)
 {
-    if (m->family != 0) return -1;
-    ClassKey k{m->L.kind, m->L.ndim, m->L.r, m->L.fp32};
+    const bool tiny = tiny_available(m->L, m->desc.n[0], m->desc.n[1], m->desc.n[2]);
+    if (m->family != 0 && !tiny) return -1;
+    ClassKey k{m->L.kind, m->L.ndim, m->L.r, m->L.fp32, tiny ? 1 : 0};
     auto it = s->class_index.find(k);
     if (it != s->class_index.end()) return it->second;
     ClassTables t;
     t.key = k;
     t.L = m->L;
+    t.tb = m->tb;  // served models are planned for two-step sweeps where the class has them
+    t.tiny = tiny;
     const size_t argsz = m->fp32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
     t.args_bytes = argsz * s->max_slots;
     const size_t total = t.args_bytes + sizeof(int32_t) * (2 * s->max_slots + 2);
@@ -198,29 +217,176 @@ static void fill_result(Req *r)
     }
 }
 
-// Launch the S batched steps of one class (buffer set `set`) on `st`.
+// Steps a request of class t runs in a tick of S steps (at most).
+static int64_t tick_steps(const ClassTables &t, int S) { return t.tiny ? (int64_t)kTinyTickFactor * S : S; }
+
+// One batched launch over the table at `dev` (layout [args | count |
+// item_start | steps], max_slots entries): step k of the tick.
+static hipError_t launch_table(const ClassTables &t, int max_slots, void *dev, int32_t k, int32_t blocks,
+                               hipStream_t st)
+{
+    char *d = static_cast<char *>(dev);
+    int32_t *ints = reinterpret_cast<int32_t *>(d + t.args_bytes);
+    if (t.tiny) {
+        if (t.L.fp32) {
+            BatchTable<float> tb{reinterpret_cast<StepArgs<float> *>(d), ints, ints + 1, ints + 1 + max_slots + 1};
+            return launch_tiny(t.L, &tb, blocks, st);
+        }
+        BatchTable<double> tb{reinterpret_cast<StepArgs<double> *>(d), ints, ints + 1, ints + 1 + max_slots + 1};
+        return launch_tiny(t.L, &tb, blocks, st);
+    }
+    if (t.L.fp32) {
+        BatchTable<float> tb{reinterpret_cast<StepArgs<float> *>(d), ints, ints + 1, ints + 1 + max_slots + 1};
+        return t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, blocks, t.tb, st)
+                             : launch_fused3d_batched(t.L, &tb, k, blocks, t.tb, st);
+    }
+    BatchTable<double> tb{reinterpret_cast<StepArgs<double> *>(d), ints, ints + 1, ints + 1 + max_slots + 1};
+    return t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, blocks, t.tb, st)
+                         : launch_fused3d_batched(t.L, &tb, k, blocks, t.tb, st);
+}
+
+// Launch the S batched steps of one class (buffer set `set`) on `st`: one
+// launch per step, or per two steps with the class's two-step kernels.
 static hipError_t launch_class(Server *s, int c, int set, int S, hipStream_t st)
 {
     ClassTables &t = s->classes[c];
-    char *dev = static_cast<char *>(t.dev[set]);
-    int32_t *ints = reinterpret_cast<int32_t *>(dev + t.args_bytes);
-    for (int k = 0; k < S; ++k) {
-        hipError_t e;
-        if (t.L.fp32) {
-            BatchTable<float> tb{reinterpret_cast<StepArgs<float> *>(dev), ints, ints + 1,
-                                 ints + 1 + s->max_slots + 1};
-            e = t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, t.blocks[set], st)
-                              : launch_fused3d_batched(t.L, &tb, k, t.blocks[set], st);
-        } else {
-            BatchTable<double> tb{reinterpret_cast<StepArgs<double> *>(dev), ints, ints + 1,
-                                  ints + 1 + s->max_slots + 1};
-            e = t.L.ndim == 2 ? launch_fused2d_batched(t.L, &tb, k, t.blocks[set], st)
-                              : launch_fused3d_batched(t.L, &tb, k, t.blocks[set], st);
-        }
+    if (t.tiny) {  // one launch runs every step of the tick
+        hipError_t e = launch_table(t, s->max_slots, t.dev[set], 0, t.blocks[set], st);
+        if (e == hipSuccess) s->launches++;
+        return e;
+    }
+    for (int k = 0; k < S; k += t.tb) {
+        hipError_t e = launch_table(t, s->max_slots, t.dev[set], k, t.blocks[set], st);
         if (e != hipSuccess) return e;
         s->launches++;
     }
     return hipSuccess;
+}
+
+// Fill a host table (layout of launch_table) with the given models, each
+// stepping steps[i] steps from its current parity; returns the work items.
+static int32_t fill_table(const ClassTables &t, int max_slots, void *host, const std::vector<Model *> &ms,
+                          const std::vector<int32_t> &steps)
+{
+    char *h = static_cast<char *>(host);
+    int32_t *ints = reinterpret_cast<int32_t *>(h + t.args_bytes);
+    ints[0] = (int32_t)ms.size();
+    int32_t *start = ints + 1;
+    int32_t *st = start + max_slots + 1;
+    int32_t acc = 0;
+    for (size_t i = 0; i < ms.size(); ++i) {
+        const Model *m = ms[i];
+        if (m->fp32) {
+            StepArgs<float> a = m->a32;
+            a.parity = m->parity;
+            reinterpret_cast<StepArgs<float> *>(host)[i] = a;
+        } else {
+            StepArgs<double> a = m->a64;
+            a.parity = m->parity;
+            reinterpret_cast<StepArgs<double> *>(host)[i] = a;
+        }
+        start[i] = acc;
+        acc += m->items;
+        st[i] = steps[i];
+    }
+    start[ms.size()] = acc;
+    return acc;
+}
+
+// Persistent grid for `items` work items: enough workgroups for every item,
+// rounded up to a power of two (so that few distinct graphs are needed).
+static int32_t persistent_blocks(const ClassTables &t, int64_t items)
+{
+    const int64_t need = t.L.ndim == 2 ? (items + kWaves2D - 1) / kWaves2D : items;
+    const int32_t cap = t.L.ndim == 2 ? kPersist2D : kPersist3D;
+    if (t.tiny) {  // one workgroup per request, at most one per CU
+        int32_t b = 1;
+        while (b < items && b < 256) b <<= 1;
+        return b;
+    }
+    int32_t b = 1;
+    while (b < need && b < cap) b <<= 1;
+    return b;
+}
+
+// Upload a filled host table of n entries to `dev` on the scheduler stream.
+static hipError_t upload_table(Server *s, const ClassTables &t, const void *host, void *dev, size_t n)
+{
+    const size_t argsz = t.L.fp32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
+    hipError_t e = hipMemcpyAsync(dev, host, argsz * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(static_cast<char *>(dev) + t.args_bytes, static_cast<const char *>(host) + t.args_bytes,
+                           sizeof(int32_t) * (2 * s->max_slots + 2), hipMemcpyHostToDevice, s->stream);
+    return e;
+}
+
+// Serving autotuner.  The chunk length (rows or planes marched per work item)
+// of each kernel class and size bucket (log2 of every extent) is chosen on
+// the first request of the bucket: for every candidate chunk the class's
+// batched kernel is timed on that request's table entry alone, and the chunk
+// with the least time per site and step is kept for the bucket (its later
+// requests take it at admission).  The timed launches read the request's
+// current buffer and write its other one, which holds no state, so the
+// request is unchanged.  A failure leaves the library's default chunk.
+// (Timing the request's entry replicated until the grid is full, as a busy
+// tick is, chose long chunks whose single work items outlast the rest of a
+// tick, and measured slower; PFMI_SERVER_TUNE=off keeps the default chunk.)
+static void tune_served(Server *s, Req *r)
+{
+    Model *m = r->m;
+    if (r->cls < 0 || !s->tune) return;
+    ClassTables &t = s->classes[r->cls];
+    if (t.tiny) return;
+    const pf_desc &d = m->desc;
+    auto lg = [](int64_t v) { int b = 0; while ((1ll << (b + 1)) <= v) ++b; return b; };
+    const auto key = std::make_tuple(r->cls, lg(d.n[0]), lg(d.n[1]), lg(d.n[2]));
+    auto it = s->tuned.find(key);
+    if (it != s->tuned.end()) {
+        if (it->second != m->clen) set_chunk(m, it->second);
+        return;
+    }
+    const int32_t keep = m->clen;
+    int32_t best = keep;
+    if (!t.tune_dev) {
+        const size_t total = t.args_bytes + sizeof(int32_t) * (2 * s->max_slots + 2);
+        if (hipMalloc(&t.tune_dev, total) != hipSuccess ||
+            hipHostMalloc(&t.tune_host, total, hipHostMallocDefault) != hipSuccess) {
+            s->tuned[key] = keep;
+            return;
+        }
+    }
+    const int64_t march = d.ndim == 2 ? d.n[1] : d.n[2];
+    const int64_t sites = d.n[0] * d.n[1] * d.n[2];
+    double best_t = 1e300;
+    int32_t prev = -1;
+    for (int32_t c : {8, 16, 32, 64, 128, 256, 512}) {
+        const int32_t cc = (int32_t)std::min<int64_t>(c, march);
+        if (cc == prev) continue;
+        prev = cc;
+        if (set_chunk(m, cc) != PF_OK || m->family != 0) break;
+        std::vector<Model *> ms(1, m);
+        std::vector<int32_t> st(1, (int32_t)t.tb);
+        const int32_t items = fill_table(t, s->max_slots, t.tune_host, ms, st);
+        const int32_t blocks = persistent_blocks(t, items);
+        hipError_t e = upload_table(s, t, t.tune_host, t.tune_dev, ms.size());
+        if (e == hipSuccess) e = launch_table(t, s->max_slots, t.tune_dev, 0, blocks, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(s->tev[0], s->stream);
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+            e = launch_table(t, s->max_slots, t.tune_dev, 0, blocks, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(s->tev[1], s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(s->tev[1]);
+        float ms_t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms_t, s->tev[0], s->tev[1]);
+        if (e != hipSuccess) break;
+        s->launches += 4;
+        const double per = (double)ms_t / ((double)sites * t.tb);
+        if (per < best_t) {
+            best_t = per;
+            best = cc;
+        }
+    }
+    if (set_chunk(m, best) != PF_OK) (void)set_chunk(m, keep);
+    s->tuned[key] = m->clen;
 }
 
 // The graph of S chained batched launches of class c for table buffer `set`
@@ -291,12 +457,6 @@ static hipError_t run_classes(Server *s, const std::vector<int> &cls, int set, i
     return e;
 }
 
-template <typename T>
-static void put_args(ClassTables &t, int set, int i, const StepArgs<T> &a)
-{
-    reinterpret_cast<StepArgs<T> *>(t.host[set])[i] = a;
-}
-
 // Enqueue one tick.  Returns false on a device error (recorded in fatal).
 static bool enqueue_tick(Server *s, std::vector<Req *> &run, int set)
 {
@@ -316,41 +476,15 @@ static bool enqueue_tick(Server *s, std::vector<Req *> &run, int set)
         t.n[set] = (int32_t)v.size();
         if (v.empty()) continue;
         cls.push_back((int)c);
-        char *h = static_cast<char *>(t.host[set]);
-        int32_t *ints = reinterpret_cast<int32_t *>(h + t.args_bytes);
-        ints[0] = (int32_t)v.size();
-        int32_t *start = ints + 1;
-        int32_t *steps = start + s->max_slots + 1;
-        int32_t acc = 0;
-        for (size_t i = 0; i < v.size(); ++i) {
-            Model *m = v[i]->m;
-            if (m->fp32) {
-                StepArgs<float> a = m->a32;
-                a.parity = m->parity;
-                put_args(t, set, (int)i, a);
-            } else {
-                StepArgs<double> a = m->a64;
-                a.parity = m->parity;
-                put_args(t, set, (int)i, a);
-            }
-            start[i] = acc;
-            acc += m->items;
-            steps[i] = (int32_t)std::min<int64_t>(S, v[i]->nsteps - v[i]->done);
+        std::vector<Model *> ms;
+        std::vector<int32_t> steps;
+        for (Req *r : v) {
+            ms.push_back(r->m);
+            steps.push_back((int32_t)std::min<int64_t>(tick_steps(t, S), r->nsteps - r->done));
         }
-        start[v.size()] = acc;
-        // persistent grid: enough workgroups for every item, rounded up to a
-        // power of two so that few distinct graphs are needed
-        const int64_t need = t.L.ndim == 2 ? (acc + kWaves2D - 1) / kWaves2D : acc;
-        const int32_t cap = t.L.ndim == 2 ? kPersist2D : kPersist3D;
-        int32_t b = 1;
-        while (b < need && b < cap) b <<= 1;
-        t.blocks[set] = b;
-        const size_t argsz = t.L.fp32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
-        hipError_t e = hipMemcpyAsync(t.dev[set], t.host[set], argsz * v.size(), hipMemcpyHostToDevice,
-                                      s->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(static_cast<char *>(t.dev[set]) + t.args_bytes, ints,
-                               sizeof(int32_t) * (2 * s->max_slots + 2), hipMemcpyHostToDevice, s->stream);
+        const int32_t items = fill_table(t, s->max_slots, t.host[set], ms, steps);
+        t.blocks[set] = persistent_blocks(t, t.tiny ? (int64_t)ms.size() : items);
+        hipError_t e = upload_table(s, t, t.host[set], t.dev[set], ms.size());
         if (e != hipSuccess) {
             set_fatal(s, std::string("table upload: ") + hipGetErrorString(e));
             return false;
@@ -372,10 +506,13 @@ static bool enqueue_tick(Server *s, std::vector<Req *> &run, int set)
         }
         r->done += n;  // do_steps advanced the model's parity and step count
     }
-    for (auto &v : by_class)
-        for (Req *r : v) {
-            const int64_t n = std::min<int64_t>(S, r->nsteps - r->done);
-            r->m->parity ^= (int)(n & 1);
+    for (size_t c = 0; c < by_class.size(); ++c)
+        for (Req *r : by_class[c]) {
+            // every launch that advanced the request flipped its buffers once
+            const ClassTables &t = s->classes[c];
+            const int64_t n = std::min<int64_t>(tick_steps(t, S), r->nsteps - r->done);
+            const int64_t flips = t.tiny ? (n > 0 ? 1 : 0) : (n + t.tb - 1) / t.tb;
+            r->m->parity ^= (int)(flips & 1);
             r->m->steps_done += n;
             r->done += n;
         }
@@ -478,9 +615,17 @@ static void worker_main(Server *s)
                 s->done_cv.notify_all();
                 continue;
             }
+            if (!s->two_step && m->tb == 2) {
+                m->tb = 1;
+                (void)set_chunk(m, m->clen);
+            }
             r->cls = class_of(s, m);
             r->state = RUNNING;
             s->active.push_back(r);  // a cancel during admission takes effect at the next tick
+        }
+        // tile of each newly admitted request (the scheduler thread owns its model)
+        for (Req *r : admitted) {
+            if (r->m && r->state == RUNNING) tune_served(s, r);
         }
         std::vector<Req *> run;
         {
@@ -539,6 +684,8 @@ PF_API pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t m
     s->max_slots = max_slots;
     s->spt = steps_per_tick ? steps_per_tick : 64;
     if (const char *g = std::getenv("PFMI_SERVER_MAX_GRAPHS")) s->max_graphs = std::max(1, std::atoi(g));
+    if (const char *g = std::getenv("PFMI_SERVER_TWO_STEP")) s->two_step = std::atoi(g) != 0;
+    if (const char *g = std::getenv("PFMI_SERVER_TUNE")) s->tune = std::string(g) != "off";
     s->t0 = std::chrono::steady_clock::now();
     if (hbm_budget == 0) {
         size_t fr = 0, tot = 0;
@@ -555,6 +702,8 @@ PF_API pf_status pf_server_create(int32_t device, uint64_t hbm_budget, int32_t m
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&s->tev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&s->tev[1]);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&s->pinned_pool, sizeof(double2) * kNumQ * (size_t)max_slots,
                           hipHostMallocDefault);
@@ -749,11 +898,15 @@ PF_API void pf_server_destroy(pf_server *ss)
             (void)hipFree(t.dev[b]);
             (void)hipHostFree(t.host[b]);
         }
+        if (t.tune_dev) (void)hipFree(t.tune_dev);
+        if (t.tune_host) (void)hipHostFree(t.tune_host);
         (void)hipStreamDestroy(t.stream);
         (void)hipEventDestroy(t.join);
     }
     (void)hipHostFree(s->pinned_pool);
     (void)hipEventDestroy(s->fork);
+    (void)hipEventDestroy(s->tev[0]);
+    (void)hipEventDestroy(s->tev[1]);
     (void)hipEventDestroy(s->ev[0]);
     (void)hipEventDestroy(s->ev[1]);
     (void)hipStreamDestroy(s->stream);

@@ -4,11 +4,15 @@
 // Fourier Spectral Scheme").  One step of the state buf[par]:
 //   1. g = explicit term of buf[par], written into buf[par ^ 1] (free until
 //      step 4 overwrites it);
-//   2. two real-to-complex transforms: buf[par] -> uh, g -> nh;
-//   3. uh <- implicit update (k_spec_update, scaled by 1/N);
-//   4. complex-to-real transform uh -> buf[par ^ 1].
-// The transforms are hipFFT plans on the library's pitched field layout
-// (rows of `pitch` elements), so no repacking pass is needed.
+//   2. real-to-complex transforms g -> nh and, only when the kept spectrum
+//      is not that of buf[par] (first step, or the state was set from
+//      outside), buf[par] -> uh;
+//   3. implicit update (k_spec_update): the next state's spectrum / N, kept
+//      in uh and also written over nh;
+//   4. complex-to-real transform nh -> buf[par ^ 1] (it may overwrite nh).
+// So a run of steps takes two transforms per step, not three.  The
+// transforms are hipFFT plans on the library's pitched field layout (rows of
+// `pitch` elements), so no repacking pass is needed.
 #include <hipfft/hipfft.h>
 
 #include <cmath>
@@ -22,7 +26,13 @@ struct Spectral {
     bool have_fwd = false, have_inv = false;
     void *uh = nullptr, *nh = nullptr;  // half spectra, nxh * ny * nz complex values
     SpecArgs args{};
+    int kept_par = -1;  // buffer whose state's spectrum / N is in uh (-1: none)
 };
+
+void spectral_invalidate(Model *m)
+{
+    if (m && m->spec) static_cast<Spectral *>(m->spec)->kept_par = -1;
+}
 
 static pf_status fft_fail(hipfftResult r, const char *what)
 {
@@ -115,29 +125,36 @@ pf_status spectral_step(Model *m, int par, const void *step_args)
     Spectral *sp = static_cast<Spectral *>(m->spec);
     if (!sp) return fail(PF_ERR_STATE, "spectral plans are missing");
     void *u = m->buf[0][par], *out = m->buf[0][par ^ 1];
+    const bool fresh = sp->kept_par != par;
+    sp->kept_par = -1;  // until this step completes
     hipError_t e = launch_spectral_nonlinear(m->L, step_args, out, m->stream);
     if (e != hipSuccess) return hip_fail(e, "spectral nonlinear launch");
-    hipfftResult r;
+    hipfftResult r = HIPFFT_SUCCESS;
     if (m->fp32) {
-        r = hipfftExecR2C(sp->fwd, static_cast<hipfftReal *>(u), static_cast<hipfftComplex *>(sp->uh));
+        if (fresh)
+            r = hipfftExecR2C(sp->fwd, static_cast<hipfftReal *>(u), static_cast<hipfftComplex *>(sp->uh));
         if (r == HIPFFT_SUCCESS)
             r = hipfftExecR2C(sp->fwd, static_cast<hipfftReal *>(out), static_cast<hipfftComplex *>(sp->nh));
     } else {
-        r = hipfftExecD2Z(sp->fwd, static_cast<hipfftDoubleReal *>(u),
-                          static_cast<hipfftDoubleComplex *>(sp->uh));
+        if (fresh)
+            r = hipfftExecD2Z(sp->fwd, static_cast<hipfftDoubleReal *>(u),
+                              static_cast<hipfftDoubleComplex *>(sp->uh));
         if (r == HIPFFT_SUCCESS)
             r = hipfftExecD2Z(sp->fwd, static_cast<hipfftDoubleReal *>(out),
                               static_cast<hipfftDoubleComplex *>(sp->nh));
     }
     if (r != HIPFFT_SUCCESS) return fft_fail(r, "forward transform");
-    e = launch_spectral_update(m->L, sp->args, m->stream);
+    SpecArgs a = sp->args;
+    a.u_scale = fresh ? a.inv_n : 1.0;
+    e = launch_spectral_update(m->L, a, m->stream);
     if (e != hipSuccess) return hip_fail(e, "spectral update launch");
     if (m->fp32)
-        r = hipfftExecC2R(sp->inv, static_cast<hipfftComplex *>(sp->uh), static_cast<hipfftReal *>(out));
+        r = hipfftExecC2R(sp->inv, static_cast<hipfftComplex *>(sp->nh), static_cast<hipfftReal *>(out));
     else
-        r = hipfftExecZ2D(sp->inv, static_cast<hipfftDoubleComplex *>(sp->uh),
+        r = hipfftExecZ2D(sp->inv, static_cast<hipfftDoubleComplex *>(sp->nh),
                           static_cast<hipfftDoubleReal *>(out));
     if (r != HIPFFT_SUCCESS) return fft_fail(r, "inverse transform");
+    sp->kept_par = par ^ 1;
     return PF_OK;
 }
 

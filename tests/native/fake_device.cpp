@@ -14,11 +14,13 @@
 // through the executable graph object, each re-reading its arguments from
 // memory when it runs, as a replayed kernel does.
 //
-// Fake kernels.  A batched step adds 1 to every site of every field of each
-// request whose step count in the tick exceeds k (reading buffer
-// parity + k, writing the other), so a request initialised to x0 holds
-// exactly x0 + nsteps after its steps: the harness checks every result
-// exactly.  Reductions sum field 0 (and field 1) in plain FP64 (the values
+// Fake kernels.  A batched launch advances each request whose step count in
+// the tick exceeds k by min(tb, steps left) steps, adding 1 per step to every
+// site of every field (reading buffer parity + k / tb, writing the other), so
+// a request initialised to x0 holds exactly x0 + nsteps after its steps: the
+// harness checks every result exactly.  Two-step launches exist for the same
+// classes as in the library; the tiny class (small grids) runs all of a
+// tick's steps in one launch.  Reductions sum field 0 (and field 1) in plain FP64 (the values
 // are small integers, so the sums are exact).
 //
 // Accounting.  Model memory is counted when model_create / the stream-ordered
@@ -27,6 +29,7 @@
 // compares with the server's budget.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <condition_variable>
 #include <cstdio>
@@ -226,6 +229,19 @@ hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned int)
     *e = reinterpret_cast<hipEvent_t>(new FakeEvent());
     return hipSuccess;
 }
+hipError_t hipEventCreate(hipEvent_t *e)
+{
+    *e = reinterpret_cast<hipEvent_t>(new FakeEvent());
+    return hipSuccess;
+}
+hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b)
+{
+    // a fixed figure per operation between the events: timing is not modelled
+    const uint64_t sa = reinterpret_cast<FakeEvent *>(a)->seq.load();
+    const uint64_t sb = reinterpret_cast<FakeEvent *>(b)->seq.load();
+    *ms = 0.01f * (float)(sb > sa ? sb - sa : 0);
+    return hipSuccess;
+}
 hipError_t hipEventDestroy(hipEvent_t e)
 {
     delete reinterpret_cast<FakeEvent *>(e);
@@ -351,6 +367,64 @@ double volume(const pf_desc &d)
 }
 int64_t reduce_partial_slots(int64_t) { return 1; }
 
+bool time_block_available(const Launch &L)
+{
+    return (L.ndim == 2 && (L.r == 1 || L.r == 2)) || (L.ndim == 3 && L.r == 1);
+}
+
+// The fake tiny class: grids of at most 200 sites, so the harness's mix has
+// both kinds of class.  A launch runs each request's steps of the tick.
+bool tiny_available(const Launch &L, int64_t nx, int64_t ny, int64_t nz)
+{
+    return L.ndim >= 2 && nx * ny * nz <= 200;
+}
+
+template <typename T>
+static void tiny_step(BatchTable<T> tb)
+{
+    const int32_t n = *tb.count;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t steps = tb.steps[i];
+        if (steps <= 0) continue;
+        const StepArgs<T> &a = tb.args[i];
+        const int nf = a.buf[1][0] != a.buf[0][0] ? 2 : 1;
+        const int64_t N = a.nx * a.ny * a.nz;
+        for (int f = 0; f < nf; ++f)
+            for (int64_t s = 0; s < N; ++s) a.buf[f][a.parity ^ 1][s] = a.buf[f][a.parity][s] + T(steps);
+    }
+}
+
+hipError_t launch_tiny(const Launch &L, const void *table, int32_t blocks, hipStream_t s)
+{
+    if (blocks < 1) return hipErrorInvalidValue;
+    if (L.fp32) {
+        const BatchTable<float> t = *static_cast<const BatchTable<float> *>(table);
+        enqueue(s, [t] { tiny_step<float>(t); });
+    } else {
+        const BatchTable<double> t = *static_cast<const BatchTable<double> *>(table);
+        enqueue(s, [t] { tiny_step<double>(t); });
+    }
+    return hipSuccess;
+}
+
+// Work items of the fake plan: one per `chunk` rows (planes in 3D) per 16
+// columns, so that the chunk changes the item count as in the real plans.
+static int32_t fake_items(const pf_desc &d, int32_t chunk)
+{
+    const int64_t march = d.ndim == 2 ? d.n[1] : d.n[2];
+    const int64_t chunks = (march + chunk - 1) / chunk;
+    return (int32_t)std::max<int64_t>(1, chunks * ((d.n[0] + 15) / 16));
+}
+
+pf_status set_chunk(Model *m, int32_t chunk)
+{
+    m->clen = chunk > 0 ? chunk : 8;
+    m->items = fake_items(m->desc, m->clen);
+    m->a64.items = m->items;
+    m->a32.items = m->items;
+    return PF_OK;
+}
+
 static int64_t sites(const pf_desc &d) { return d.n[0] * d.n[1] * d.n[2]; }
 static int64_t model_bytes(const pf_desc &d)
 {
@@ -383,8 +457,9 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *, int32_t
     m->res = static_cast<double2 *>(std::calloc(3, sizeof(double2)));
     charge(model_bytes(*desc));
     m->family = 0;
-    // work items: one per 64 sites, so that requests span several items
-    m->items = (int32_t)std::max<int64_t>(1, (m->elems + 63) / 64);
+    m->tb = async_alloc && time_block_available(m->L) ? 2 : 1;
+    m->clen = 8;
+    m->items = fake_items(*desc, m->clen);
     auto fill = [&](auto &a) {
         std::memset(&a, 0, sizeof(a));
         using T = std::remove_pointer_t<std::remove_reference_t<decltype(a.buf[0][0])>>;
@@ -454,41 +529,44 @@ pf_status init_fields(Model *m, int32_t, uint64_t seed, const double *, int32_t)
 pf_status do_steps(Model *, int64_t) { return fail(PF_ERR_STATE, "fake: no solo models"); }
 
 template <typename T>
-static void batched_step(BatchTable<T> tb, int32_t k)
+static void batched_step(BatchTable<T> tb, int32_t k, int steps_per_launch)
 {
     const int32_t n = *tb.count;
     for (int32_t i = 0; i < n; ++i) {
-        if (k >= tb.steps[i]) continue;
+        const int32_t left = tb.steps[i] - k;
+        if (left <= 0) continue;
+        const int adv = left < steps_per_launch ? left : steps_per_launch;
         const StepArgs<T> &a = tb.args[i];
-        const int par = (a.parity + k) & 1;
+        const int par = (a.parity + k / steps_per_launch) & 1;
         const int nf = a.buf[1][0] != a.buf[0][0] ? 2 : 1;
         const int64_t N = a.nx * a.ny * a.nz;
         for (int f = 0; f < nf; ++f) {
             const T *in = a.buf[f][par];
             T *out = a.buf[f][par ^ 1];
-            for (int64_t s = 0; s < N; ++s) out[s] = in[s] + T(1);
+            for (int64_t s = 0; s < N; ++s) out[s] = in[s] + T(adv);
         }
     }
 }
 
-hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
+hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks, int tb,
                                   hipStream_t s)
 {
-    if (blocks < 1) return hipErrorInvalidValue;
+    if (blocks < 1 || (tb != 1 && tb != 2) || (tb == 2 && !time_block_available(L)) || k % tb)
+        return hipErrorInvalidValue;
     if (L.fp32) {
-        const BatchTable<float> tb = *static_cast<const BatchTable<float> *>(table);
-        enqueue(s, [tb, k] { batched_step<float>(tb, k); });
+        const BatchTable<float> t = *static_cast<const BatchTable<float> *>(table);
+        enqueue(s, [t, k, tb] { batched_step<float>(t, k, tb); });
     } else {
-        const BatchTable<double> tb = *static_cast<const BatchTable<double> *>(table);
-        enqueue(s, [tb, k] { batched_step<double>(tb, k); });
+        const BatchTable<double> t = *static_cast<const BatchTable<double> *>(table);
+        enqueue(s, [t, k, tb] { batched_step<double>(t, k, tb); });
     }
     return hipSuccess;
 }
 
-hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks,
+hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k, int32_t blocks, int tb,
                                   hipStream_t s)
 {
-    return launch_fused2d_batched(L, table, k, blocks, s);
+    return launch_fused2d_batched(L, table, k, blocks, tb, s);
 }
 
 template <typename T>

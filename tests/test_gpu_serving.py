@@ -1,6 +1,8 @@
 """Serving engine on the GPU: continuous batching returns, for every request,
 bitwise the field that the same request gives when stepped alone; admission
-respects the HBM budget; cancellation and late arrivals work."""
+respects the HBM budget; cancellation and late arrivals work.  The mix holds
+grids small enough for the whole-grid-in-LDS class (every kind, 2D and 3D, r
+up to 4) beside ones served by the batched tile kernels."""
 import time
 
 import numpy as np
@@ -28,12 +30,14 @@ def _mixed_requests():
         (3, 3, (16, 30, 20), 4, False, [0.2, 0.1, 0.035, 0.065], 0.3),
         (1, 2, (1, 33, 45), 4, False, [0.8, 1.2], 0.04),
         (2, 2, (1, 40, 40), 8, True, [1.0, 1.0], 0.005),   # r = 4
-        (2, 3, (12, 12, 12), 8, False, [1.0, 1.0], 0.001),  # 3D CH r = 4: stepped on its own
+        (2, 3, (12, 12, 12), 8, False, [1.0, 1.0], 0.001),  # 3D CH r = 4
         (3, 2, (1, 128, 128), 4, True, [0.2, 0.1, 0.04, 0.06], 0.4),
         (1, 3, (20, 26, 70), 2, False, [1.0, 1.0], 0.05),   # FP64 3D AC / GS order 2: the
         (3, 3, (14, 40, 66), 2, False, [0.2, 0.1, 0.04, 0.06], 0.5),  # batched tile layout
         (4, 2, (1, 90, 110), 4, True, [1.0, 1.0, 0.5], 0.01),   # Model C
         (4, 3, (16, 20, 70), 2, False, [0.9, 1.1, 0.5], 0.01),
+        (4, 2, (1, 40, 50), 6, False, [1.0, 1.0, 0.5], 0.002),  # tiny Model C, r = 3
+        (3, 3, (12, 14, 16), 2, True, [0.2, 0.1, 0.04, 0.06], 0.5),  # tiny 3D Gray-Scott
     ]
     for i, (kind, ndim, shape, order, fp32, params, dt) in enumerate(specs):
         reqs.append(dict(id=i, kind=kind, ndim=ndim, shape=shape, steps=37 + 11 * i, order=order,
