@@ -73,6 +73,17 @@ def measured_traffic(tag, src_hash):
         return None
 
 
+def attach_traffic(r, tag, src_hash):
+    """Add the HBM bytes per launch measured by the counters (committed
+    summary profiles/traffic_<tag>.txt, taken on the current kernel sources)
+    and the fraction of peak they make at the measured launch time."""
+    t = measured_traffic(tag, src_hash)
+    r["hbm_bytes_per_launch"] = t
+    per = r.get("kernel_ms_per_launch")
+    r["frac_hbm_measured"] = None if (t is None or not per) else round(t / (per * 1e-3) / 1e9 / PEAK_GBS, 4)
+    return r
+
+
 def copy_probe(P, torch, nbytes=2 ** 31, reps=10):
     x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     y = torch.empty_like(x)
@@ -140,9 +151,9 @@ def run_mc(P, n, prec, steps, warmup, seed=606):
     per = kernel_ms / ksteps
     gbs = 2 * 2 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
     return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
-            "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
-            "frac_of_peak": round(gbs / PEAK_GBS, 4), "rho_mass_drift": drift,
-            "chunk": chunk, "time_block": tb}
+            "kernel_ms": round(per, 4), "kernel_ms_per_launch": round(kernel_ms / launches, 4),
+            "achieved_gbs": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4),
+            "rho_mass_drift": drift, "chunk": chunk, "time_block": tb}
 
 
 def run_ch_variant(P, n, prec, steps, warmup, direct, ndim, seed=202):
@@ -181,10 +192,11 @@ def run_ch_variant(P, n, prec, steps, warmup, direct, ndim, seed=202):
 def run_spectral(P, n, prec, steps, warmup, seed=202):
     """Semi-implicit Fourier spectral Cahn-Hilliard (Eq. model-b) on a 2D n^2
     grid, dx = 1, dt = 0.5 (far above the explicit limit), c1 = c2 = 1, c0 =
-    U[-0.05, 0.05]: three hipFFT transforms and two element-wise kernels per
-    step.  `per_site_bytes` is the scheme's minimum HBM traffic per site and
-    step with these transforms (each transform reads and writes its data
-    once, the element-wise kernels likewise)."""
+    U[-0.05, 0.05]: two hipFFT transforms (the updated spectrum is kept
+    between steps) and two element-wise kernels per step.  `per_site_bytes`
+    is the scheme's minimum HBM traffic per site and step with these
+    transforms (each transform reads and writes its data once, the
+    element-wise kernels likewise)."""
     d = P.make_desc(P.PF_CH, (n, n), dx=1.0, dt=0.5, order=2, precision=prec,
                     params=[1.0, 1.0], flags=P.PF_SPECTRAL)
     m = P.Model(d)
@@ -200,10 +212,10 @@ def run_spectral(P, n, prec, steps, warmup, seed=202):
     hi, lo = m.reduce(P.PF_RED_MASS0)
     m.close()
     Pb = 8 if prec == P.PF_FP64 else 4
-    # nonlinear: read u, write g (2P); two forward transforms: read P, write ~P
-    # each (half spectrum of 2P-byte complex values); update: read 2 spectra,
-    # write one (3P); inverse: read P, write P
-    per_site = 2 * Pb + 2 * (2 * Pb) + 3 * Pb + 2 * Pb
+    # nonlinear: read u, write g (2P); forward transform of g: read P, write
+    # ~P (half spectrum of 2P-byte complex values); update: read 2 spectra,
+    # write 2 (4P); inverse: read P, write P
+    per_site = 2 * Pb + 2 * Pb + 4 * Pb + 2 * Pb
     sites = float(n) * n
     per = kernel_ms / ksteps
     gbs = per_site * sites / (per * 1e-3) / 1e9
@@ -483,9 +495,9 @@ def run_gs3d(P, n, prec, steps, warmup, seed=303):
     per = kernel_ms / ksteps
     gbs = 2 * 2 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
     return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
-            "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
-            "frac_of_peak": round(gbs / PEAK_GBS, 4), "chunk": chunk, "time_block": tb,
-            "tile_rows": rows}
+            "kernel_ms": round(per, 4), "kernel_ms_per_launch": round(kernel_ms / launches, 4),
+            "achieved_gbs": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4),
+            "chunk": chunk, "time_block": tb, "tile_rows": rows}
 
 
 def main():
@@ -534,26 +546,28 @@ def main():
             "kernel_ms": round(fp32["kernel_ms"], 4), "achieved_gbs": round(fp32["achieved_gbs"], 1),
             "frac_of_peak": round(fp32["achieved_gbs"] / PEAK_GBS, 4),
             "mass_drift": fp32["mass_drift"], "chunk": fp32["chunk"],
-            "time_block": fp32["time_block"]}
+            "time_block": fp32["time_block"], "kernel_ms_per_launch": round(fp32["kernel_ms"], 4)}
+        attach_traffic(extra["fp32"], "ch2d_%d_fp32" % args.n, src)
         log("CH FP32: %.3f ms/step" % fp32["ms_per_step"])
     if want("gs3d", args.skip_3d):
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             r = run_gs3d(P, 1024, prec, max(10, args.steps // 4), 5)
-            r["hbm_bytes_per_launch"] = measured_traffic("gs3d_1024_" + tag, src3)
-            extra["gs3d_1024_" + tag] = r
+            extra["gs3d_1024_" + tag] = attach_traffic(r, "gs3d_1024_" + tag, src3)
         log("GS 3D done")
     if want("ch3d", args.skip_3d):
         for order in (2, 4, 6):
             for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
-                extra["ch3d_512_p%d_%s" % (order, tag)] = run_ch3d(P, 512, order, prec,
-                                                                  max(20, args.steps // 2), 4)
+                key = "ch3d_512_p%d_%s" % (order, tag)
+                extra[key] = attach_traffic(run_ch3d(P, 512, order, prec, max(20, args.steps // 2), 4),
+                                            key, src3)
         log("CH 3D 512^3 done")
     if want("ac128"):
         extra["ac2d_128_fp64_1000_steps"] = run_ac128(P)
         log("AC 128^2 done")
     if want("mc", args.skip_mc):
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
-            extra["mc2d_%d_%s" % (args.n, tag)] = run_mc(P, args.n, prec, max(10, args.steps // 4), 4)
+            key = "mc2d_%d_%s" % (args.n, tag)
+            extra[key] = attach_traffic(run_mc(P, args.n, prec, max(10, args.steps // 4), 4), key, src)
         log("Model C done")
     if want("next", args.skip_next):
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
@@ -600,7 +614,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(fp64["achieved_gbs"], 1),
                      "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(fp64["achieved_gbs"] / PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     # HBM bytes the counters measured per launch over the launch time
+                     "traffic_frac": None if traffic is None else
+                     round(traffic / (fp64["kernel_ms"] * 1e-3) / 1e9 / PEAK_GBS, 4)},
         "extra": extra,
     }
     if want("cpu", args.skip_cpu):
