@@ -273,7 +273,7 @@ def run_ch3d(P, n, order, prec, steps, warmup, seed=404):
     hi, lo = m.reduce_history(P.PF_RED_MASS0, steps)
     drift = float(abs((hi + lo) - (hi[0] + lo[0])).max())
     chunk, family = m.tile()
-    tb, rows = m.time_block(), m.tile_rows()
+    tb, rows, passes = m.time_block(), m.tile_rows(), m.passes()
     m.close()
     sites = float(n) ** 3
     per = kernel_ms / ksteps
@@ -282,7 +282,7 @@ def run_ch3d(P, n, order, prec, steps, warmup, seed=404):
             "kernel_ms": round(per, 4), "kernel_ms_per_launch": round(kernel_ms / launches, 4),
             "achieved_gbs": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4),
             "mass_drift": drift, "chunk": chunk, "family": family, "time_block": tb,
-            "tile_rows": rows}
+            "tile_rows": rows, "passes": passes}
 
 
 def run_ac128(P, steps=1000, seed=101):
@@ -558,8 +558,9 @@ def main():
         for order in (2, 4, 6):
             for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
                 key = "ch3d_512_p%d_%s" % (order, tag)
-                extra[key] = attach_traffic(run_ch3d(P, 512, order, prec, max(20, args.steps // 2), 4),
-                                            key, src3)
+                r = run_ch3d(P, 512, order, prec, max(20, args.steps // 2), 4)
+                # a two-pass plan's traffic covers both of its kernels
+                extra[key] = attach_traffic(r, key + ("_2pass" if r["passes"] == 2 else ""), src3)
         log("CH 3D 512^3 done")
     if want("ac128"):
         extra["ac2d_128_fp64_1000_steps"] = run_ac128(P)

@@ -341,8 +341,27 @@ pf_status pf_set_tile_rows(pf_model *m, int32_t rows);
 int32_t pf_get_tile_rows(const pf_model *m);
 
 /*
+ * Passes of a 3D Cahn-Hilliard step (composed form, order <= 6) on the fused
+ * kernels.  1 (default): mu = f'(c) - L c stays in registers and LDS, and
+ * the update is the second of two chained radius-r stencils in the same
+ * sweep (halo 2r).  2: a first pass writes mu into a field-sized buffer (the
+ * model allocates it, one more field of HBM) and reduces c, a second reads
+ * mu and c and writes the stepped c; each pass has the halo of one stencil
+ * and a single register ring, at the price of writing and reading mu and
+ * reading c twice (the three-array layout of the paper, Sec. Benchmarks,
+ * memory-footprint table).  Fields are bitwise those of one pass; fused
+ * reductions agree to their compensated accuracy.  Two passes run one step
+ * per launch (pf_set_time_block(m, 2) is then PF_ERR_UNSUPPORTED).
+ * PF_ERR_UNSUPPORTED for other models, orders, the per-site or spectral
+ * family.  pf_get_passes returns the passes in use (0 outside the fused
+ * family, -1 for NULL).  The autotuner considers both.
+ */
+pf_status pf_set_passes(pf_model *m, int32_t passes);
+int32_t pf_get_passes(const pf_model *m);
+
+/*
  * Autotuner: times each candidate (chunk length, time-block factor, 3D tile
- * layout) on the model's own buffers by re-running steps from the current
+ * layout, passes of a 3D Cahn-Hilliard step) on the model's own buffers by re-running steps from the current
  * state (whose buffer is never written, so the state is unchanged), keeps the
  * fastest per step and records it in an in-process cache keyed by (kind,
  * ndim, order, precision, per-step reductions, size class) that later models
@@ -406,6 +425,11 @@ typedef struct pf_result {
  * two steps per launch where their class has a two-step kernel (2D orders 2
  * and 4, 3D order 2), and the chunk length the server's autotuner picks per
  * kernel class and size bucket on the first request of each bucket.
+ * Requests whose grid fits one workgroup's LDS (2D or 3D Allen-Cahn,
+ * Cahn-Hilliard, Gray-Scott or Model C, order <= 8, x extent <= 1024, both
+ * copies of the fields plus mu or g within 128 KiB) form a tiny class: one
+ * workgroup per request keeps the whole grid in LDS and runs up to
+ * 16 x steps_per_tick of its steps per tick, touching HBM once per tick.
  * Environment: PFMI_SERVER_MAX_GRAPHS bounds the cache of captured tick
  * graphs (default 256); PFMI_SERVER_TWO_STEP=0 keeps one step per launch;
  * PFMI_SERVER_TUNE=off keeps the library's default chunk.

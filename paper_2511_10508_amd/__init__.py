@@ -94,6 +94,8 @@ SIGNATURES = {
     "pf_get_time_block": (_i32, [_vp]),
     "pf_set_tile_rows": (_i32, [_vp, _i32]),
     "pf_get_tile_rows": (_i32, [_vp]),
+    "pf_set_passes": (_i32, [_vp, _i32]),
+    "pf_get_passes": (_i32, [_vp]),
     "pf_autotune": (_i32, [_vp, _i32]),
     "pf_timing_enable": (_i32, [_vp, _i32]),
     "pf_timing_read": (_i32, [_vp, _pd, _pi64, _pi64]),
@@ -283,6 +285,12 @@ class Model:
 
     def tile_rows(self):
         return lib().pf_get_tile_rows(self.h)
+
+    def set_passes(self, passes):
+        check(lib().pf_set_passes(self.h, passes))
+
+    def passes(self):
+        return lib().pf_get_passes(self.h)
 
     def stream(self):
         s = _vp()

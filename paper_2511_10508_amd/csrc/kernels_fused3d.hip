@@ -66,10 +66,16 @@ bool rows_per_wave_available(const Launch &L, int tb, int rpw)
 
 int rows_per_wave_default(const Launch &L, int tb) { return rows_per_wave_available(L, tb, 1) ? 1 : 2; }
 
-bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
-                  int rpw, int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks,
-                  int32_t *items, int32_t *blocks, int32_t *threads)
+bool two_pass_available(const Launch &L)
 {
+    return L.ndim == 3 && L.kind == kCH && L.r >= 1 && L.r <= 3;
+}
+
+bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
+                  int rpw, int passes, int32_t *strips, int32_t *ow, int32_t *ytiles,
+                  int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads)
+{
+    if (passes == 2 && !(two_pass_available(L) && tb == 1 && rpw == 2)) return false;
     if (!rows_per_wave_available(L, tb, rpw)) return false;
     return dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
         using T = decltype(tz);
@@ -93,6 +99,12 @@ bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t c
                 return;
             }
         }
+        if constexpr (KIND == kCH && TB == 1) {
+            if (passes == 2) {  // both passes share the tiles of one radius-r stage
+                plan(Tile3D<T, kCHMU, R, 1, 2>{});
+                return;
+            }
+        }
         plan(Tile3D<T, KIND, R, TB, 2>{});
     });
 }
@@ -108,16 +120,43 @@ static hipError_t launch3d(const StepArgs<T> &a, int32_t blocks, int32_t threads
     return hipGetLastError();
 }
 
+// Two-pass step: the mu pass writes mu into the mu buffer through the output
+// slot of field 0 (and reduces c); the update pass reads mu as field 0 and c
+// as field 1 and writes c through the output slot of field 0.
+template <typename T, int R>
+static hipError_t launch3d_two_pass(const StepArgs<T> &a, T *mu, int32_t blocks, int32_t threads,
+                                    int red, hipStream_t s)
+{
+    const int p = a.parity;
+    StepArgs<T> a1 = a;
+    a1.buf[0][p ^ 1] = mu;
+    hipError_t err = launch3d<T, kCHMU, R, 1, 2>(a1, blocks, threads, red, s);
+    if (err != hipSuccess) return err;
+    StepArgs<T> a2 = a;
+    a2.buf[0][p] = mu;
+    a2.buf[1][p] = a.buf[0][p];
+    a2.red = 0;
+    hipLaunchKernelGGL((k_step3d<T, kCHUP, R, false, 1, 2>), dim3(blocks), dim3(threads), 0, s, a2);
+    return hipGetLastError();
+}
+
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
-                          int red, int tb, int rpw, hipStream_t s)
+                          int red, int tb, int rpw, void *mu, hipStream_t s)
 {
     hipError_t err = hipErrorInvalidValue;
     if (!rows_per_wave_available(L, tb, rpw)) return err;
+    if (mu && !(two_pass_available(L) && tb == 1 && rpw == 2)) return err;
     dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
         using T = decltype(tz);
         constexpr int KIND = decltype(kc)::value, R = decltype(rc)::value;
         constexpr int TB = decltype(tbc)::value;
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
+        if constexpr (KIND == kCH && TB == 1) {
+            if (mu) {
+                err = launch3d_two_pass<T, R>(a, static_cast<T *>(mu), blocks, threads, red, s);
+                return;
+            }
+        }
         if constexpr (has_one_row_per_wave<T, KIND, R>()) {
             if (rpw == 1) {
                 err = launch3d<T, KIND, R, TB, 1>(a, blocks, threads, red, s);

@@ -10,13 +10,17 @@ constexpr int kAC = 1, kCH = 2, kGS = 3, kMC = 4, kMH = 5;
 // Kernel kind of Cahn-Hilliard with the direct biharmonic stencil (a
 // descriptor flag on PF_CH; internal to the kernels and launchers).
 constexpr int kCHD = 16;
+// The two passes of Cahn-Hilliard with mu through a field-sized buffer (3D):
+// kCHMU takes c and writes mu (and reduces c); kCHUP takes mu (stencil) and c
+// (centre values only) and writes the stepped c.
+constexpr int kCHMU = 17, kCHUP = 18;
 constexpr int kMaxFields = 4;       // Model H in 3D: m and three components of j
 
 // Fields a kernel family reduces and steps as a fixed set: Gray-Scott (u, v)
 // and Model C (phi, rho) have two.  Model H has 1 + ndim (m and j), stepped by
 // its own kernels (the 1D strip kernel, the 2D tiled kernel, the per-site
 // kernels elsewhere); its reductions cover m.
-constexpr int nfields_kind(int kind) { return (kind == kGS || kind == kMC) ? 2 : 1; }
+constexpr int nfields_kind(int kind) { return (kind == kGS || kind == kMC || kind == kCHUP) ? 2 : 1; }
 constexpr int kMaxR = 8;            // stencil radius r = order / 2 (order <= 16)
 constexpr int kNumQ = 3;            // reduction quantities per partial slot
 constexpr int kWaves2D = 4;         // waves per workgroup, 2D kernels
@@ -88,9 +92,14 @@ bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int tb,
 // layout used until one is set or tuned.
 bool rows_per_wave_available(const Launch &L, int tb, int rpw);
 int rows_per_wave_default(const Launch &L, int tb);
+// Two passes (3D Cahn-Hilliard, composed form, one step per launch, two rows
+// per wave): mu goes through a field-sized buffer instead of staying in
+// registers, and both passes have the halo of one radius-r stencil instead
+// of two.  plan_fused3d with passes = 2 plans the tiles of both passes.
+bool two_pass_available(const Launch &L);
 bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
-                  int rpw, int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks,
-                  int32_t *items, int32_t *blocks, int32_t *threads);
+                  int rpw, int passes, int32_t *strips, int32_t *ow, int32_t *ytiles,
+                  int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads);
 // 1D: strips of one row, `clen` strips per wave (chunks = items = waves).
 bool plan_fused1d(const Launch &L, int64_t nx, int32_t clen, int tb, int32_t *strips, int32_t *ow,
                   int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads);
@@ -98,8 +107,10 @@ hipError_t launch_fused1d(const Launch &L, const void *args, int32_t blocks, int
                           int red, int tb, hipStream_t s);
 hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
                           int red, int tb, hipStream_t s);
+// mu: the field-sized mu buffer of a two-pass plan (same pitch and plane
+// stride as the fields), nullptr for the fused single pass.
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
-                          int red, int tb, int rpw, hipStream_t s);
+                          int red, int tb, int rpw, void *mu, hipStream_t s);
 // Batched (serving) launches: step k of the tick for every request of the
 // table.  tb = 2 (where time_block_available): the launch advances requests
 // with two or more steps left in the tick by a two-step sweep and those with

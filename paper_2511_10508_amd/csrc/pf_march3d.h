@@ -38,7 +38,8 @@ struct Tile3D {
     // LDS planes: the centre plane of every stage's input stream; the direct
     // biharmonic keeps c of the newest plane, c and mu_y of the centre plane
     static constexpr int NST = KIND == kCHD ? 3 : (KIND == kCH ? 2 : 1) * TB;
-    static constexpr int NFS = (KIND == kCH || KIND == kCHD) ? 1 : S::NF;  // fields per plane
+    // fields per plane (the mu pass of a two-pass CH step stages mu only)
+    static constexpr int NFS = (KIND == kCH || KIND == kCHD || KIND == kCHMU || KIND == kCHUP) ? 1 : S::NF;
     static constexpr int NB = (NST * NFS <= 2 || KIND == kCHD) ? 2 : 1;  // LDS buffers (double when it fits)
     using lds_type = T[NB][NST][NFS][NR][RW];
     static_assert(RPW == 1 || RPW == 2, "one or two rows per wave");
@@ -218,6 +219,15 @@ __device__ __forceinline__ void stage3_chupd(const StepArgs<T> &a, const T (&m)[
     }
 }
 
+// Prefetch depth of the two passes of a two-pass Cahn-Hilliard step: each
+// holds one ring of K planes (the mu pass) or one ring plus c's centre planes
+// (the update pass), which leaves room for K planes in flight up to r = 2;
+// at r = 3 the update pass (two fields in flight) and the FP32 mu pass with
+// reductions (the FP64 energy) prefetch one plane.
+template <typename T, int KIND, int R, bool RED>
+constexpr int kTwoPassPD =
+    (R == 3 && (KIND == kCHUP || (RED && std::is_same<T, float>::value))) ? 1 : 2 * R + 1;
+
 // Prefetch depth PD of the input planes: K planes ahead, or one plane where
 // the K-deep prefetch ring would not fit the 128 registers a lane of a
 // 16-wave workgroup can hold (wider stencils, and two-step sweeps with fused
@@ -228,6 +238,7 @@ template <typename T, int KIND, int R, int TB, bool RED>
 constexpr int prefetch_depth()
 {
     if (std::is_same<T, double>::value && KIND == kCH && R == 2 && TB == 1) return 2 * R + 1;
+    if (KIND == kCHMU || KIND == kCHUP) return kTwoPassPD<T, KIND, R, RED>;
     return (R >= 2 || (TB == 2 && RED) || KIND == kCHD) ? 1 : 2 * R + 1;
 }
 
@@ -426,7 +437,26 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
 #pragma unroll
                 for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph % PD]);
             }
-            if constexpr (KIND == kCHD) {
+            if constexpr (KIND == kCHMU || KIND == kCHUP) {
+                // one radius-r stage: mu of c (with the reductions of c), or
+                // the update of c from the mu stream and c's centre plane
+                constexpr int s1 = Slot<K, R>::template at<ph>;
+                if constexpr (TL::NB == 1) __syncthreads();
+#pragma unroll
+                for (int v = 0; v < V; ++v) L[0][0][rw][pl + v] = ring[0][s1][v];
+                __syncthreads();
+                if (age >= 2 * R && rows_ok(1)) {
+                    const int32_t pz = t - R;
+                    T res[V];
+                    if constexpr (KIND == kCHMU)
+                        stage3_mu<T, R, K, s1, NR, RW, RED>(a, ring[0], L[0][0], rw, pl, res, om,
+                                                            pz >= z0 && pz < z1, red[0]);
+                    else
+                        stage3_chupd<T, R, K, s1, NR, RW>(a, ring[0], L[0][0], rw, pl, ring[NF - 1][s1], res);
+                    if (out_row)
+                        store_row<T, V>(out[0] + (int64_t)wrap32(pz, nz) * plane + rowoff, xl, om, res);
+                }
+            } else if constexpr (KIND == kCHD) {
                 // centre plane z = t - (R+1); its inputs are complete once age >= 2 (R+1)
                 constexpr int sz = Slot<K, R + 1>::template at<ph>;
                 const bool live = age >= 2 * (R + 1);  // uniform over the workgroup

@@ -30,6 +30,7 @@ struct Model {
     int family = 1;
     int tb = 1;                   // time steps fused per launch (2D, r <= 2)
     int rpw_req = 0, rpw = 2;     // 3D tile rows per wave: requested (0: default), in use
+    int passes_req = 1, passes = 1;  // 3D CH: mu in registers (1) or through `scratch` (2)
     int32_t clen = 0, strips = 0, ow = 0, ytiles = 1, chunks = 0, items = 0, blocks = 0,
             threads = 0;
     int64_t fused_slots = 0;
@@ -43,7 +44,7 @@ struct Model {
     double2 *hist = nullptr;     // per-step reductions [hist_cap][kNumQ]
     int64_t hist_cap = 0, hist_len = 0;
     double2 *stage = nullptr;    // graph staging rows [kGraphSteps][kNumQ]
-    void *scratch = nullptr;     // CH mu buffer(s) of the per-site family
+    void *scratch = nullptr;     // CH mu buffer(s) of the per-site family or of a two-pass plan
     void *spec = nullptr;        // spectral scheme state (family 2): plans and half spectra
 
     struct Graph {

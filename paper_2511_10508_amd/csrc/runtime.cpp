@@ -2,6 +2,7 @@
 // loop (eager or replayed HIP graphs), reductions, initial conditions,
 // kernel timing and the tile autotuner.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -263,14 +264,21 @@ static bool plan(Model *m)
         ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, m->tb, &strips, &ow, &chunks, &items,
                           &blocks, &threads);
     else {
-        m->rpw = m->rpw_req && rows_per_wave_available(L, m->tb, m->rpw_req)
-                     ? m->rpw_req
-                     : rows_per_wave_default(L, m->tb);
-        ok = plan_fused3d(L, d.n[0], d.n[1], d.n[2], m->clen, m->tb, m->rpw, &strips, &ow,
-                          &ytiles, &chunks, &items, &blocks, &threads);
+        m->passes = m->passes_req == 2 && two_pass_available(L) ? 2 : 1;
+        if (m->passes == 2) {
+            m->tb = 1;
+            m->rpw = 2;
+        } else {
+            m->rpw = m->rpw_req && rows_per_wave_available(L, m->tb, m->rpw_req)
+                         ? m->rpw_req
+                         : rows_per_wave_default(L, m->tb);
+        }
+        ok = plan_fused3d(L, d.n[0], d.n[1], d.n[2], m->clen, m->tb, m->rpw, m->passes, &strips,
+                          &ow, &ytiles, &chunks, &items, &blocks, &threads);
     }
     if (!ok) {
         m->tb = 1;
+        m->passes = 1;
         return true;
     }
     m->family = 0;
@@ -317,7 +325,7 @@ int32_t default_chunk(const pf_desc *d)
 // ride on every step, and the log2 of each extent.
 struct TuneChoice {
     int32_t chunk;
-    int tb, rpw;
+    int tb, rpw, passes;
 };
 using TuneKey = std::tuple<int, int, int, int, int, int, int, int>;
 static std::mutex g_tune_mu;
@@ -382,23 +390,28 @@ static void refresh_args(Model *m)
     }
 }
 
+// Field-sized mu buffer(s): the per-site family's CH, direct-biharmonic and
+// Model H temporaries, or the mu buffer of a two-pass fused plan.
+static pf_status ensure_scratch(Model *m)
+{
+    const bool need = m->family == 0 ? m->passes == 2
+                                     : (m->L.kind == kCH || m->L.kind == kCHD || m->L.kind == kMH);
+    if (!need || m->scratch) return PF_OK;
+    const size_t nbuf = m->L.kind == kCHD ? (size_t)m->desc.ndim : 1;
+    PF_HIP(dev_alloc(m, &m->scratch, nbuf * tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
+    return PF_OK;
+}
+
 pf_status set_chunk(Model *m, int32_t chunk)
 {
     m->clen = chunk > 0 ? chunk : default_chunk(&m->desc);
     plan(m);
     m->graphs_valid = false;
     pf_status st = ensure_partials(m);
+    // a two-pass plan gets its mu buffer now, not inside a graph capture
+    if (st == PF_OK && m->family == 0 && m->passes == 2) st = ensure_scratch(m);
     refresh_args(m);
     return st;
-}
-
-static pf_status ensure_scratch(Model *m)
-{
-    if (m->family == 0 || (m->L.kind != kCH && m->L.kind != kCHD && m->L.kind != kMH) || m->scratch)
-        return PF_OK;
-    const size_t nbuf = m->L.kind == kCHD ? (size_t)m->desc.ndim : 1;
-    PF_HIP(dev_alloc(m, &m->scratch, nbuf * tsize(m) * (size_t)m->elems), "hipMalloc(scratch)");
-    return PF_OK;
 }
 
 // Launch `tb` fused steps from parity `par` (writes 1 - par).  red: fuse the
@@ -437,10 +450,15 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
         m->ev_used += 2;
     }
     if (m->family == 0) {
+        if (m->passes == 2) {
+            pf_status st = ensure_scratch(m);
+            if (st != PF_OK) return st;
+        }
         if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
         hipError_t e = d.ndim == 1   ? launch_fused1d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
                        : d.ndim == 2 ? launch_fused2d(m->L, ap, m->blocks, m->threads, red, tb, m->stream)
-                                     : launch_fused3d(m->L, ap, m->blocks, m->threads, red, tb, m->rpw, m->stream);
+                                     : launch_fused3d(m->L, ap, m->blocks, m->threads, red, tb, m->rpw,
+                                                      m->passes == 2 ? m->scratch : nullptr, m->stream);
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
         if (red) {
@@ -811,6 +829,7 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
             chunk = it->second.chunk;
             m->tb = it->second.tb;
             m->rpw_req = it->second.rpw;
+            m->passes_req = it->second.passes;
         }
     }
     st = set_chunk(m, chunk);
@@ -968,23 +987,31 @@ pf_status autotune(Model *m, int32_t trials)
     if (time_block_available(m->L)) tbs.push_back(2);
     if (trials < 1) trials = 3;
     const int32_t keep_c = m->clen;
-    const int keep_tb = m->tb, keep_rpw = m->rpw_req;
+    const int keep_tb = m->tb, keep_rpw = m->rpw_req, keep_passes = m->passes_req;
     hipEvent_t a, b;
     PF_HIP(hipEventCreate(&a), "hipEventCreate");
     PF_HIP(hipEventCreate(&b), "hipEventCreate");
     double2 *scratch = nullptr;
     if (red) PF_HIP(hipMalloc((void **)&scratch, sizeof(double2) * kNumQ * 2), "hipMalloc(tune)");
     float best = 1e30f;
-    TuneChoice bestc{keep_c, keep_tb, keep_rpw};
+    TuneChoice bestc{keep_c, keep_tb, keep_rpw, keep_passes};
     pf_status st = PF_OK;
-    for (int tb : tbs) {
-        for (int rpw : {2, 1}) {
-            if (d.ndim != 3 ? rpw != 2 : !rows_per_wave_available(m->L, tb, rpw)) continue;
+    // (tb, rpw, passes): every time block and 3D tile layout in one pass, and
+    // the two-pass form where it exists
+    std::vector<std::array<int, 3>> forms;
+    for (int tb : tbs)
+        for (int rpw : {2, 1})
+            if (d.ndim != 3 ? rpw == 2 : rows_per_wave_available(m->L, tb, rpw)) forms.push_back({tb, rpw, 1});
+    if (two_pass_available(m->L) && !(d.flags & PF_FORCE_GENERIC)) forms.push_back({1, 2, 2});
+    for (const auto &fm : forms) {
+        const int tb = fm[0], rpw = fm[1], passes = fm[2];
+        {
             for (int32_t c : cand) {
                 m->tb = tb;
                 m->rpw_req = d.ndim == 3 ? rpw : 0;
+                m->passes_req = passes;
                 st = set_chunk(m, c);
-                if (st != PF_OK || m->family != 0 || m->tb != tb) break;
+                if (st != PF_OK || m->family != 0 || m->tb != tb || m->passes != passes) break;
                 st = launch_step(m, m->parity, red, scratch, false, tb);
                 if (st != PF_OK) break;
                 (void)hipEventRecord(a, m->stream);
@@ -997,7 +1024,7 @@ pf_status autotune(Model *m, int32_t trials)
                 ms /= tb;
                 if (st == PF_OK && ms < best) {
                     best = ms;
-                    bestc = {c, tb, m->rpw_req};
+                    bestc = {c, tb, m->rpw_req, passes};
                 }
             }
             if (st != PF_OK) break;
@@ -1010,6 +1037,11 @@ pf_status autotune(Model *m, int32_t trials)
     if (st != PF_OK) return st;
     m->tb = bestc.tb;
     m->rpw_req = bestc.rpw;
+    m->passes_req = bestc.passes;
+    if (m->passes_req != 2 && m->scratch && m->family == 0) {  // the mu buffer of a tried two-pass plan
+        dev_free(m, m->scratch);
+        m->scratch = nullptr;
+    }
     st = set_chunk(m, bestc.chunk);
     if (st != PF_OK) return st;
     m->launches = 0;
@@ -1351,6 +1383,31 @@ PF_API int32_t pf_get_tile_rows(const pf_model *m)
     if (!m) return -1;
     const Model *mm = reinterpret_cast<const Model *>(m);
     return (mm->desc.ndim == 3 && mm->family == 0) ? mm->rpw : 0;
+}
+
+PF_API pf_status pf_set_passes(pf_model *m, int32_t passes)
+{
+    if (!m || (passes != 1 && passes != 2)) return fail(PF_ERR_ARG, "passes must be 1 or 2");
+    Model *mm = M(m);
+    PF_HIP(hipStreamSynchronize(mm->stream), "hipStreamSynchronize");
+    if (passes == 2 && (mm->desc.flags & (PF_FORCE_GENERIC | PF_SPECTRAL) || !two_pass_available(mm->L)))
+        return fail(PF_ERR_UNSUPPORTED, "two passes exist for 3D Cahn-Hilliard (composed form, order <= 6)");
+    mm->passes_req = passes;
+    if (passes == 2) mm->tb = 1;
+    pf_status st = set_chunk(mm, mm->clen);
+    if (st == PF_OK && passes == 1 && mm->scratch && mm->family == 0) {
+        dev_free(mm, mm->scratch);
+        mm->scratch = nullptr;
+    }
+    if (st == PF_OK && mm->passes != passes) return fail(PF_ERR_UNSUPPORTED, "two-pass kernels not available");
+    return st;
+}
+
+PF_API int32_t pf_get_passes(const pf_model *m)
+{
+    if (!m) return -1;
+    const Model *mm = reinterpret_cast<const Model *>(m);
+    return mm->family == 0 ? mm->passes : 0;
 }
 
 PF_API pf_status pf_autotune(pf_model *m, int32_t trials)
