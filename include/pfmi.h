@@ -89,8 +89,9 @@ enum { PF_RED_MASS0 = 0, PF_RED_MASS1 = 1, PF_RED_ENERGY = 2, PF_RED_NONFINITE =
  *             c2 m^3 - c1 m - L m, j_t = L j + c3 m grad(mu) (grad and div
  *             by centred first-derivative stencils of accuracy `order`);
  *             nparams must match.  MH runs one fused pass on 1D rows
- *             (order <= 8) and 2D grids (order <= 4), and the per-site
- *             kernels with one field-sized temporary (mu) otherwise; its
+ *             (order <= 8) and on 2D and 3D grids (order <= 4), and the
+ *             per-site kernels with one field-sized temporary (mu)
+ *             otherwise; its
  *             reductions cover m (mass, non-finite count); the server does
  *             not take it.
  *   flags     PF_* flags above.  PF_BIHARMONIC_DIRECT (PF_CH only, else
@@ -176,8 +177,10 @@ pf_status pf_stability(const pf_desc *desc, double *dt_max);
 
 /* Device bytes a model of this descriptor holds (2 buffers per field, padded
  * pitch, plus reduction scratch, plus the field-sized temporaries of the
- * per-site kernels where the fused ones do not apply: one for Cahn-Hilliard,
- * ndim for the direct biharmonic).  0 for an invalid descriptor. */
+ * per-site kernels where the fused ones do not apply: one for Cahn-Hilliard
+ * and Model H, ndim for the direct biharmonic).  A 3D Cahn-Hilliard model
+ * switched to two passes (pf_set_passes, or the autotuner's choice) holds
+ * one field more.  0 for an invalid descriptor. */
 uint64_t pf_footprint_bytes(const pf_desc *desc);
 
 /* Elements of one device field buffer (pitch * n1 * n2).  -1 if invalid. */

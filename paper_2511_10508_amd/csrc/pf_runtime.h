@@ -96,6 +96,10 @@ pf_status borrow_run(Model *m, double2 *scratch, int64_t nsteps, double2 *hist);
 // kernels_mh2d.hip.
 bool mh2d_available(const Launch &L);
 hipError_t launch_mh2d(const Launch &L, const void *args, hipStream_t s);
+// Model H on 3D grids (r <= 2) in one z-marching pass, bitwise equal to the
+// per-site kernels' two passes; kernels_mh3d.hip.
+bool mh3d_available(const Launch &L);
+hipError_t launch_mh3d(const Launch &L, const void *args, hipStream_t s);
 
 // Semi-implicit Fourier spectral scheme (spectral.cpp).
 pf_status spectral_setup(Model *m);

@@ -481,9 +481,9 @@ static pf_status launch_step(Model *m, int par, bool red, double2 *res, bool tim
             pf_status st = spectral_step(m, par, ap);
             if (st != PF_OK) return st;
             if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
-        } else if (mh2d_available(m->L) && !(d.flags & PF_FORCE_GENERIC)) {
+        } else if ((mh2d_available(m->L) || mh3d_available(m->L)) && !(d.flags & PF_FORCE_GENERIC)) {
             if (timed) PF_HIP(hipEventRecord(e0, m->stream), "hipEventRecord");
-            hipError_t e = launch_mh2d(m->L, ap, m->stream);
+            hipError_t e = d.ndim == 2 ? launch_mh2d(m->L, ap, m->stream) : launch_mh3d(m->L, ap, m->stream);
             if (e != hipSuccess) return hip_fail(e, "Model H step launch");
             if (timed) PF_HIP(hipEventRecord(e1, m->stream), "hipEventRecord");
         } else {
@@ -1120,10 +1120,10 @@ PF_API int64_t pf_buffer_elems(const pf_desc *desc)
 // cover the descriptor (1D and 2D: r <= 4; 3D: CH r <= 3, direct form r <= 2).
 static int generic_scratch_arrays(const pf_desc *d)
 {
-    if (d->kind == kMH) {  // mu, except on 1D rows (fused, r <= 4) and 2D tiles (r <= 2)
+    if (d->kind == kMH) {  // mu, except on 1D rows (fused, r <= 4), 2D tiles and 3D marches (r <= 2)
         const int r = d->order / 2;
         const bool one_pass = !(d->flags & PF_FORCE_GENERIC) &&
-                              ((d->ndim == 1 && r <= 4) || (d->ndim == 2 && r <= 2));
+                              ((d->ndim == 1 && r <= 4) || (d->ndim >= 2 && r <= 2));
         return one_pass ? 0 : 1;
     }
     if (d->kind != kCH) return 0;

@@ -1,7 +1,8 @@
 """GPU parity of Model H (Eq. model-h, transverse projector one) against
 the CPU FP64 oracle: m and the ndim components of j after 100 steps of the
-per-site kernels, max |GPU - oracle| <= 1e-12 (FP64 storage) and <= 1e-4
-(FP32 storage); mass conservation of m, the counter-based initial fields of
+fused kernels (1D strips, 2D tiles, 3D z-marching), max |GPU - oracle| <=
+1e-12 (FP64 storage) and <= 1e-4 (FP32 storage), each bitwise equal to the
+per-site kernels; mass conservation of m, the counter-based initial fields of
 all 1 + ndim fields, and the refusals.
 """
 import numpy as np
@@ -85,6 +86,21 @@ def test_model_h_2d_tiled_equals_generic_bitwise(shape, order, prec):
     dt = 0.8 * oracle.dt_max(oracle.MH, 2, 1.0, order, PARAMS)
     a, _ = gpu_run(f0, 2, order, prec, dt, 20)
     b, _ = gpu_run(f0, 2, order, prec, dt, 20, flags=P.PF_FORCE_GENERIC)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("shape,order", [((13, 17, 30), 2), ((12, 14, 20), 4), ((40, 37, 70), 2),
+                                         ((35, 20, 33), 4), ((5, 6, 7), 4), ((3, 40, 36), 2)])
+def test_model_h_3d_marched_equals_generic_bitwise(shape, order, prec):
+    """3D grids with r <= 2 run one z-marching pass (32 x 16 column tiles,
+    z chunks, partial and wrapping tiles, grids thinner than the halo); it
+    gives bitwise the two-pass per-site kernel's fields."""
+    f0 = synth.initial_fields(5, shape, 66, synth.IC_UNIFORM, (-0.1, 0.1), ndim=3)
+    dt = 0.8 * oracle.dt_max(oracle.MH, 3, 1.0, order, PARAMS)
+    a, _ = gpu_run(f0, 3, order, prec, dt, 21)
+    b, _ = gpu_run(f0, 3, order, prec, dt, 21, flags=P.PF_FORCE_GENERIC)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
 
