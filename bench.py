@@ -39,14 +39,18 @@ def log(msg):
 T0 = time.perf_counter()
 
 
+FAMILY_SOURCES = {"2d": ("pf_march2d.h", "kernels_fused2d.hip"),
+                  "3d": ("pf_march3d.h", "kernels_fused3d.hip"),
+                  "mh3d": ("kernels_mh3d.hip",)}
+
+
 def source_hash(family="2d"):
-    """Hash of the device code of one kernel family ("2d" or "3d"): its
-    marching header and instantiation file plus the shared headers, with
+    """Hash of the device code of one kernel family ("2d", "3d" or "mh3d"):
+    its marching header and instantiation file plus the shared headers, with
     comments and whitespace removed (they do not change the kernels)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_10508_amd", "csrc")
-    for f in ("pf_device.h", "pf_internal.h", "pf_dispatch.h", "pf_march%s.h" % family,
-              "kernels_fused%s.hip" % family):
+    for f in ("pf_device.h", "pf_internal.h", "pf_dispatch.h") + FAMILY_SOURCES[family]:
         with open(os.path.join(csrc, f)) as fh:
             code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
         code = re.sub(r"//[^\n]*", " ", code)
@@ -157,13 +161,13 @@ def run_mc(P, n, prec, steps, warmup, seed=606):
 
 
 def run_ch_variant(P, n, prec, steps, warmup, direct, ndim, seed=202):
-    """Cahn-Hilliard (Eq. model-b) p = 4, dt = 0.01, c1 = c2 = 1, c0 =
-    U[-0.05, 0.05], fused mass / energy reductions every step: either the 2D
-    n^2 grid with the direct biharmonic stencil (direct=True), or a 1D row of
-    n sites with the composed operator."""
+    """Cahn-Hilliard (Eq. model-b) p = 4, c1 = c2 = 1, c0 = U[-0.05, 0.05],
+    fused mass / energy reductions every step: the 2D n^2 grid (dt = 0.01) or
+    the 3D n^3 grid (dt = 0.005) with the direct biharmonic stencil
+    (direct=True), or a 1D row of n sites with the composed operator."""
     flags = P.PF_REDUCE_EACH_STEP | (P.PF_BIHARMONIC_DIRECT if direct else 0)
-    shape = (n, n) if ndim == 2 else (n,)
-    d = P.make_desc(P.PF_CH, shape, dx=1.0, dt=0.01, order=4, precision=prec,
+    shape = {1: (n,), 2: (n, n), 3: (n, n, n)}[ndim]
+    d = P.make_desc(P.PF_CH, shape, dx=1.0, dt=0.005 if ndim == 3 else 0.01, order=4, precision=prec,
                     params=[1.0, 1.0], flags=flags)
     m = P.Model(d)
     m.init(P.PF_IC_UNIFORM, seed, (-0.05, 0.05))
@@ -250,8 +254,8 @@ def run_mh(P, n, prec, steps, warmup, seed=707, ndim=2):
     per = kernel_ms / ksteps
     gbs = 2 * (1 + ndim) * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
     return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
-            "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
-            "frac_of_peak": round(gbs / PEAK_GBS, 4)}
+            "kernel_ms": round(per, 4), "kernel_ms_per_launch": round(kernel_ms / launches, 4),
+            "achieved_gbs": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4)}
 
 
 def run_ch3d(P, n, order, prec, steps, warmup, seed=404):
@@ -577,6 +581,8 @@ def main():
                 P, args.n, prec, max(10, args.steps // 4), 4, direct=True, ndim=2)
             extra["ch1d_%d_%s" % (args.n * args.n // 4, tag)] = run_ch_variant(
                 P, args.n * args.n // 4, prec, max(10, args.steps // 4), 4, direct=False, ndim=1)
+            extra["chd3d_512_%s" % tag] = run_ch_variant(P, 512, prec, max(10, args.steps // 4), 4,
+                                                         direct=True, ndim=3)
         log("direct biharmonic and 1D done")
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             extra["spectral_ch2d_%d_%s" % (args.n // 2, tag)] = run_spectral(
@@ -586,7 +592,9 @@ def main():
             extra["mh2d_%d_%s" % (args.n // 4, tag)] = run_mh(P, args.n // 4, prec, max(10, args.steps // 10), 2)
             extra["mh1d_%d_%s" % (args.n * args.n // 16, tag)] = run_mh(
                 P, args.n * args.n // 16, prec, max(10, args.steps // 10), 2, ndim=1)
-            extra["mh3d_512_%s" % tag] = run_mh(P, 512, prec, max(10, args.steps // 10), 2, ndim=3)
+            extra["mh3d_512_%s" % tag] = attach_traffic(
+                run_mh(P, 512, prec, max(10, args.steps // 10), 2, ndim=3), "mh3d_512_" + tag,
+                source_hash("mh3d"))
         log("Model H done")
     extra["fp64_mass_drift"] = fp64["mass_drift"]
     extra["fp64_chunk"] = fp64["chunk"]

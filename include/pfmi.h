@@ -357,7 +357,9 @@ int32_t pf_get_tile_rows(const pf_model *m);
  * per launch (pf_set_time_block(m, 2) is then PF_ERR_UNSUPPORTED).
  * PF_ERR_UNSUPPORTED for other models, orders, the per-site or spectral
  * family.  pf_get_passes returns the passes in use (0 outside the fused
- * family, -1 for NULL).  The autotuner considers both.
+ * family, -1 for NULL).  Until set, FP32 order 6 with PF_REDUCE_EACH_STEP
+ * runs two passes (its one-pass kernel spills registers and is slower),
+ * everything else one.  The autotuner considers both.
  */
 pf_status pf_set_passes(pf_model *m, int32_t passes);
 int32_t pf_get_passes(const pf_model *m);

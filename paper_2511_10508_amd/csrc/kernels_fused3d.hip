@@ -4,19 +4,16 @@
 
 namespace pf {
 
-// Gray-Scott and Allen-Cahn: r <= 4; Cahn-Hilliard (halo 2r): r <= 3; the
-// direct biharmonic (two rings of 2r+3 planes in 128 registers): r <= 2.
+// Gray-Scott and Allen-Cahn: r <= 4; Cahn-Hilliard (halo 2r): r <= 3.  The
+// direct biharmonic runs its own column-tile kernel (kernels_chd3d.hip).
 using Fused3DRadii = RList<1, 2, 3, 4>;
 using Fused3DRadiiCH = RList<1, 2, 3>;
-using Fused3DRadiiCHD = RList<1, 2>;
 
 template <int KIND, typename F>
 bool dispatch_r3d(int r, F &&f)
 {
     if constexpr (KIND == kCH)
         return dispatch_r(r, Fused3DRadiiCH{}, f);
-    else if constexpr (KIND == kCHD)
-        return dispatch_r(r, Fused3DRadiiCHD{}, f);
     else
         return dispatch_r(r, Fused3DRadii{}, f);
 }
@@ -37,13 +34,12 @@ bool dispatch3d(const Launch &L, int tb, F &&f)
 {
     bool ok = false;
     dispatch_prec(L.fp32, [&](auto tz) {
-        dispatch_kind_all(L.kind, [&](auto kc) {
+        dispatch_kind(L.kind, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             if (tb == 2) {
-                if constexpr (KIND != kCHD)  // no two-step direct-biharmonic kernel
-                    ok = dispatch_r(L.r, TimeBlockRadii3D{}, [&](auto rc) {
-                        f(tz, kc, rc, std::integral_constant<int, 2>{});
-                    });
+                ok = dispatch_r(L.r, TimeBlockRadii3D{}, [&](auto rc) {
+                    f(tz, kc, rc, std::integral_constant<int, 2>{});
+                });
             }
             else if (tb == 1)
                 ok = dispatch_r3d<KIND>(L.r, [&](auto rc) {
@@ -56,6 +52,7 @@ bool dispatch3d(const Launch &L, int tb, F &&f)
 
 bool rows_per_wave_available(const Launch &L, int tb, int rpw)
 {
+    if (L.kind == kCHD) return chd3d_available(L) && tb == 1 && rpw == 2;  // the column-tile kernel
     bool has1 = false;
     if (!dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto) {
             has1 = has_one_row_per_wave<decltype(tz), decltype(kc)::value, decltype(rc)::value>();
@@ -71,12 +68,19 @@ bool two_pass_available(const Launch &L)
     return L.ndim == 3 && L.kind == kCH && L.r >= 1 && L.r <= 3;
 }
 
+bool two_pass_default(const Launch &L, bool reduce_each_step)
+{
+    return two_pass_available(L) && L.fp32 && L.r == 3 && reduce_each_step;
+}
+
 bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
                   int rpw, int passes, int32_t *strips, int32_t *ow, int32_t *ytiles,
                   int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads)
 {
     if (passes == 2 && !(two_pass_available(L) && tb == 1 && rpw == 2)) return false;
     if (!rows_per_wave_available(L, tb, rpw)) return false;
+    if (L.kind == kCHD)
+        return passes == 1 && plan_chd3d(L, nx, ny, nz, clen, strips, ow, ytiles, chunks, items, blocks, threads);
     return dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
         using T = decltype(tz);
         constexpr int KIND = decltype(kc)::value, R = decltype(rc)::value;
@@ -146,6 +150,7 @@ hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int
     hipError_t err = hipErrorInvalidValue;
     if (!rows_per_wave_available(L, tb, rpw)) return err;
     if (mu && !(two_pass_available(L) && tb == 1 && rpw == 2)) return err;
+    if (L.kind == kCHD) return launch_chd3d(L, args, blocks, red, s);
     dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
         using T = decltype(tz);
         constexpr int KIND = decltype(kc)::value, R = decltype(rc)::value;

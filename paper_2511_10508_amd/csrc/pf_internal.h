@@ -97,6 +97,10 @@ int rows_per_wave_default(const Launch &L, int tb);
 // registers, and both passes have the halo of one radius-r stencil instead
 // of two.  plan_fused3d with passes = 2 plans the tiles of both passes.
 bool two_pass_available(const Launch &L);
+// The plan without a request: two passes for FP32 order 6 with reductions
+// every step, whose one-pass kernel exceeds the register budget (and is the
+// slower of the two).
+bool two_pass_default(const Launch &L, bool reduce_each_step);
 bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
                   int rpw, int passes, int32_t *strips, int32_t *ow, int32_t *ytiles,
                   int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads);
@@ -107,6 +111,14 @@ hipError_t launch_fused1d(const Launch &L, const void *args, int32_t blocks, int
                           int red, int tb, hipStream_t s);
 hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
                           int red, int tb, hipStream_t s);
+// 3D Cahn-Hilliard with the direct biharmonic (r <= 3): one z-marching pass
+// over column tiles (kernels_chd3d.hip); plan_fused3d and launch_fused3d
+// route kCHD here.
+bool chd3d_available(const Launch &L);
+bool plan_chd3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int32_t *strips,
+                int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items, int32_t *blocks,
+                int32_t *threads);
+hipError_t launch_chd3d(const Launch &L, const void *args, int32_t blocks, int red, hipStream_t s);
 // mu: the field-sized mu buffer of a two-pass plan (same pitch and plane
 // stride as the fields), nullptr for the fused single pass.
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,

@@ -35,12 +35,11 @@ struct Tile3D {
     static constexpr int NR = RPW * kWaves3D;                // tile rows
     static constexpr int RW = LPR * V;                       // loaded columns per row
     static constexpr int OWMAX = RW - 2 * HV;                // most outputs per row
-    // LDS planes: the centre plane of every stage's input stream; the direct
-    // biharmonic keeps c of the newest plane, c and mu_y of the centre plane
-    static constexpr int NST = KIND == kCHD ? 3 : (KIND == kCH ? 2 : 1) * TB;
-    // fields per plane (the mu pass of a two-pass CH step stages mu only)
-    static constexpr int NFS = (KIND == kCH || KIND == kCHD || KIND == kCHMU || KIND == kCHUP) ? 1 : S::NF;
-    static constexpr int NB = (NST * NFS <= 2 || KIND == kCHD) ? 2 : 1;  // LDS buffers (double when it fits)
+    // LDS planes: the centre plane of every stage's input stream
+    static constexpr int NST = (KIND == kCH ? 2 : 1) * TB;
+    // fields per plane (the passes of a two-pass CH step stage one stream)
+    static constexpr int NFS = (KIND == kCH || KIND == kCHMU || KIND == kCHUP) ? 1 : S::NF;
+    static constexpr int NB = NST * NFS <= 2 ? 2 : 1;  // LDS buffers (double when it fits)
     using lds_type = T[NB][NST][NFS][NR][RW];
     static_assert(RPW == 1 || RPW == 2, "one or two rows per wave");
     static_assert(2 * H < NR && OWMAX > 0, "halo too wide for the 3D tile");
@@ -239,115 +238,7 @@ constexpr int prefetch_depth()
 {
     if (std::is_same<T, double>::value && KIND == kCH && R == 2 && TB == 1) return 2 * R + 1;
     if (KIND == kCHMU || KIND == kCHUP) return kTwoPassPD<T, KIND, R, RED>;
-    return (R >= 2 || (TB == 2 && RED) || KIND == kCHD) ? 1 : 2 * R + 1;
-}
-
-// Direct-biharmonic Cahn-Hilliard in 3D (see the 2D form in pf_march2d.h):
-// c' = c + dt (sum_a D2_a mu_a - sum_a D4_a c), mu_a = g - sum_{b != a} D2_b c.
-// mu_z of the newest plane PH (x from lane shifts, y from its LDS plane Lc)
-// goes into the ring mz; mu_y of the centre plane CS (x and z only) goes to
-// LDS before the barrier; the update of the centre plane then takes mu_x
-// (y from LDS, z from the ring), the y-pairs of mu_y from LDS, the z-pairs
-// of mz and the fourth-derivative pairs of c along the three axes.  Every
-// sum is formed in the per-site generic kernel's order (x, then y, then z).
-template <typename T, int R, int K, int PH, int NR, int RW>
-__device__ __forceinline__ void chd3_mu_z(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
-                                          const T (&Lc)[NR][RW], int rw, int pl,
-                                          T (&mz)[Vec<T>::V])
-{
-    constexpr int V = Vec<T>::V;
-    T e[V + 2 * R];
-    gather_x<T, V, R>(c[PH], e);
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        T S[R];
-        static_for<1, R + 1>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            S[j - 1] = (e[R + v + j] + e[R + v - j]) + (Lc[rw + j][pl + v] + Lc[rw - j][pl + v]);
-        });
-        mz[v] = ch_mu<T, R>(a, c[PH][v], S, c[PH][v] * T(4));
-    }
-}
-
-template <typename T, int R, int K, int CS>
-__device__ __forceinline__ void chd3_mu_y(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
-                                          T (&my)[Vec<T>::V])
-{
-    constexpr int V = Vec<T>::V;
-    T e[V + 2 * R];
-    gather_x<T, V, R>(c[CS], e);
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        T S[R];
-        static_for<1, R + 1>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            S[j - 1] = (e[R + v + j] + e[R + v - j]) + (c[(CS + j) % K][v] + c[(CS - j + K) % K][v]);
-        });
-        my[v] = ch_mu<T, R>(a, c[CS][v], S, c[CS][v] * T(4));
-    }
-}
-
-template <typename T, int R, int K, int CS, int NR, int RW, bool RED>
-__device__ __forceinline__ void stage3_chd(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
-                                           const T (&mz)[K][Vec<T>::V], const T (&Lc)[NR][RW],
-                                           const T (&Lmy)[NR][RW], int rw, int pl,
-                                           T (&res)[Vec<T>::V], const OutMask<Vec<T>::V> &om,
-                                           bool red_row, RedState &red)
-{
-    constexpr int V = Vec<T>::V, R4 = R + 1;
-    T mx[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        T S[R];
-        static_for<1, R + 1>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            S[j - 1] = (Lc[rw + j][pl + v] + Lc[rw - j][pl + v]) +
-                       (c[(CS + j) % K][v] + c[(CS - j + K) % K][v]);
-        });
-        mx[v] = ch_mu<T, R>(a, c[CS][v], S, c[CS][v] * T(4));
-    }
-    T em[V + 2 * R], ec[V + 2 * R4];
-    gather_x<T, V, R>(mx, em);
-    gather_x<T, V, R4>(c[CS], ec);
-    double s0 = 0.0, s1 = 0.0;  // the row's masked reduction sums
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        T Sm[R], S4[R4];
-        static_for<1, R + 1>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            Sm[j - 1] = ((em[R + v + j] + em[R + v - j]) + (Lmy[rw + j][pl + v] + Lmy[rw - j][pl + v])) +
-                        (mz[(CS + j) % K][v] + mz[(CS - j + K) % K][v]);
-        });
-        static_for<1, R4 + 1>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            S4[j - 1] = ((ec[R4 + v + j] + ec[R4 + v - j]) + (Lc[rw + j][pl + v] + Lc[rw - j][pl + v])) +
-                        (c[(CS + j) % K][v] + c[(CS - j + K) % K][v]);
-        });
-        const T c0 = c[CS][v];
-        const T musum = (mx[v] + Lmy[rw][pl + v]) + mz[CS][v];
-        res[v] = chd_update<T, R>(a, c0, Sm, musum * T(2), S4, c0 * T(6));
-        if constexpr (RED) {
-            if (om.ov[v]) {
-                const double x = (double)c0;
-                s0 += x;
-                if constexpr (std::is_same<T, double>::value) {
-                    // the full chemical potential: (mu_x + mu_y + mu_z - g) / 2
-                    s1 += energy_from_mu(a.c2, x, 0.5 * (musum - chd_g(a, c0)));
-                } else {
-                    double Pn[R];
-                    static_for<1, R + 1>([&](auto jc) {
-                        constexpr int j = decltype(jc)::value;
-                        Pn[j - 1] = ((double)ec[R4 + v + j] + (double)Lc[rw + j][pl + v]) +
-                                    (double)c[(CS + j) % K][v];
-                    });
-                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, 3.0 * a.w64sum, x, Pn);
-                }
-            }
-        }
-    }
-    if constexpr (RED)
-        if (red_row)
-            red_row_end<V, false>(red, om, s0, s1, [&](int, int v) { return (double)c[CS][v]; });
+    return (R >= 2 || (TB == 2 && RED)) ? 1 : 2 * R + 1;
 }
 
 template <typename T, int KIND, int R, bool RED, bool FAST, int TB, int RPW>
@@ -385,14 +276,12 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
     T r1[TB == 2 ? NF : 1][K][V];
     T m0[KIND == kCH ? K : 1][V];
     T m1[(KIND == kCH && TB == 2) ? K : 1][V];
-    T mz[KIND == kCHD ? K : 1][V];  // direct biharmonic: mu_z planes
     static_assert(K % PD == 0, "plane t is prefetched into slot t mod PD of a K-phase loop");
     // rings that feed LDS rows or later stages before first being computed hold zeros
 #pragma unroll
     for (int i = 0; i < K; ++i)
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            if constexpr (KIND == kCHD) mz[i][v] = T(0);
             if constexpr (KIND == kCH) {
                 m0[i][v] = T(0);
                 if constexpr (TB == 2) m1[i][v] = T(0);
@@ -453,31 +342,6 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                                                             pz >= z0 && pz < z1, red[0]);
                     else
                         stage3_chupd<T, R, K, s1, NR, RW>(a, ring[0], L[0][0], rw, pl, ring[NF - 1][s1], res);
-                    if (out_row)
-                        store_row<T, V>(out[0] + (int64_t)wrap32(pz, nz) * plane + rowoff, xl, om, res);
-                }
-            } else if constexpr (KIND == kCHD) {
-                // centre plane z = t - (R+1); its inputs are complete once age >= 2 (R+1)
-                constexpr int sz = Slot<K, R + 1>::template at<ph>;
-                const bool live = age >= 2 * (R + 1);  // uniform over the workgroup
-#pragma unroll
-                for (int v = 0; v < V; ++v) L[0][0][rw][pl + v] = ring[0][ph][v];
-                if (live) {
-                    T my[V];
-                    chd3_mu_y<T, R, K, sz>(a, ring[0], my);
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        L[1][0][rw][pl + v] = ring[0][sz][v];
-                        L[2][0][rw][pl + v] = my[v];
-                    }
-                }
-                __syncthreads();
-                if (rows_ok(1)) chd3_mu_z<T, R, K, ph, NR, RW>(a, ring[0], L[0][0], rw, pl, mz[ph]);
-                if (live && rw >= R + 1 && rw < NR - R - 1) {
-                    const int32_t pz = t - (R + 1);
-                    T res[V];
-                    stage3_chd<T, R, K, sz, NR, RW, RED>(a, ring[0], mz, L[1][0], L[2][0], rw, pl,
-                                                         res, om, pz >= z0 && pz < z1, red[0]);
                     if (out_row)
                         store_row<T, V>(out[0] + (int64_t)wrap32(pz, nz) * plane + rowoff, xl, om, res);
                 }

@@ -30,7 +30,9 @@ struct Model {
     int family = 1;
     int tb = 1;                   // time steps fused per launch (2D, r <= 2)
     int rpw_req = 0, rpw = 2;     // 3D tile rows per wave: requested (0: default), in use
-    int passes_req = 1, passes = 1;  // 3D CH: mu in registers (1) or through `scratch` (2)
+    // 3D CH: mu in registers (1) or through `scratch` (2); requested (0: the
+    // library's choice), in use
+    int passes_req = 0, passes = 1;
     int32_t clen = 0, strips = 0, ow = 0, ytiles = 1, chunks = 0, items = 0, blocks = 0,
             threads = 0;
     int64_t fused_slots = 0;

@@ -264,7 +264,9 @@ static bool plan(Model *m)
         ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, m->tb, &strips, &ow, &chunks, &items,
                           &blocks, &threads);
     else {
-        m->passes = m->passes_req == 2 && two_pass_available(L) ? 2 : 1;
+        const bool two = m->passes_req == 2 ||
+                         (m->passes_req == 0 && two_pass_default(L, (d.flags & PF_REDUCE_EACH_STEP) != 0));
+        m->passes = two && two_pass_available(L) ? 2 : 1;
         if (m->passes == 2) {
             m->tb = 1;
             m->rpw = 2;
@@ -645,6 +647,7 @@ pf_status borrow_plan(Model *m, const pf_desc *d, void *stream, void *const *buf
         }
     m->tb = 1;
     m->rpw_req = 0;
+    m->passes_req = 1;  // the mu buffer of two passes would be an allocation
     m->clen = default_chunk(d);
     plan(m);
     if (m->family != 0)
@@ -820,6 +823,7 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
     // autotuner sets their chunk after admission
     if (m->async_alloc) {
         m->rpw_req = 2;
+        m->passes_req = 1;
         m->tb = time_block_available(m->L) ? 2 : 1;
     }
     if (!m->async_alloc) {
@@ -1130,7 +1134,7 @@ static int generic_scratch_arrays(const pf_desc *d)
     const bool direct = (d->flags & PF_BIHARMONIC_DIRECT) != 0;
     const int r = d->order / 2;
     bool fused = !(d->flags & PF_FORCE_GENERIC) && r <= 4;
-    if (d->ndim == 3) fused = fused && r <= (direct ? 2 : 3);
+    if (d->ndim == 3) fused = fused && r <= 3;
     if (fused) return 0;
     return direct ? d->ndim : 1;
 }
@@ -1395,7 +1399,7 @@ PF_API pf_status pf_set_passes(pf_model *m, int32_t passes)
     mm->passes_req = passes;
     if (passes == 2) mm->tb = 1;
     pf_status st = set_chunk(mm, mm->clen);
-    if (st == PF_OK && passes == 1 && mm->scratch && mm->family == 0) {
+    if (st == PF_OK && mm->passes == 1 && mm->scratch && mm->family == 0) {
         dev_free(mm, mm->scratch);
         mm->scratch = nullptr;
     }

@@ -185,10 +185,12 @@ def test_footprint_counts_generic_temporaries():
     n3, n2 = (64, 64, 64), (256, 256)
     base3 = P.footprint_bytes(P.make_desc(P.PF_CH, n3, dt=1e-3, order=4))
     per3 = P.buffer_elems(P.make_desc(P.PF_CH, n3)) * 8
-    d = P.make_desc(P.PF_CH, n3, dt=1e-4, order=6, flags=P.PF_BIHARMONIC_DIRECT)
-    assert P.footprint_bytes(d) == base3 + 3 * per3  # radius 3: no fused 3D direct kernel
-    d = P.make_desc(P.PF_CH, n3, dt=1e-3, order=4, flags=P.PF_BIHARMONIC_DIRECT)
-    assert P.footprint_bytes(d) == base3
+    d = P.make_desc(P.PF_CH, n3, dt=1e-5, order=8, flags=P.PF_BIHARMONIC_DIRECT)
+    base3_8 = P.footprint_bytes(P.make_desc(P.PF_CH, n3, dt=1e-5, order=8))
+    assert P.footprint_bytes(d) == base3_8 + 2 * per3  # radius 4: no fused 3D direct kernel
+    for order in (4, 6):  # the fused 3D direct kernel covers r <= 3
+        d = P.make_desc(P.PF_CH, n3, dt=1e-4, order=order, flags=P.PF_BIHARMONIC_DIRECT)
+        assert P.footprint_bytes(d) == base3
     d = P.make_desc(P.PF_CH, n3, dt=1e-3, order=8)  # radius 4: no fused 3D CH kernel
     assert P.footprint_bytes(d) == base3 + per3
     base2 = P.footprint_bytes(P.make_desc(P.PF_CH, n2, dt=1e-3, order=4))
@@ -231,9 +233,14 @@ def test_model_h_descriptor_and_host_logic():
         assert math.isclose(P.stability(d), ref, rel_tol=1e-12)
         per = P.buffer_elems(d) * 8
         plain = P.footprint_bytes(P.make_desc(P.PF_AC, n, dt=1e-3))
-        # 2 (1 + ndim) field buffers and, in 3D, one temporary (mu)
-        tmp = 1 if len(n) == 3 else 0
-        assert P.footprint_bytes(d) == plain + (2 * len(n) + tmp) * per
+        # 2 (1 + ndim) field buffers; no temporary (one fused pass in 1D, 2D
+        # and 3D at order 4), one (mu) for the per-site kernels
+        assert P.footprint_bytes(d) == plain + 2 * len(n) * per
+        g = P.make_desc(P.PF_MH, n, dt=1e-3, order=4, flags=P.PF_FORCE_GENERIC)
+        assert P.footprint_bytes(g) == P.footprint_bytes(d) + per
+    d8 = P.make_desc(P.PF_MH, (16, 16, 16), dt=1e-4, order=8)
+    assert P.footprint_bytes(d8) == (P.footprint_bytes(P.make_desc(P.PF_AC, (16, 16, 16), dt=1e-4, order=8))
+                                     + 7 * P.buffer_elems(d8) * 8)
     bad = P.make_desc(P.PF_MH, (64, 64), dt=1e-3)
     bad.nfields = 2
     h = ctypes.c_void_p()
