@@ -231,10 +231,10 @@ def run_spectral(P, n, prec, steps, warmup, seed=202):
 
 def run_mh(P, n, prec, steps, warmup, seed=707, ndim=2):
     """Model H (Eq. model-h, transverse projector one) on a 2D n^2 grid (one
-    LDS-tiled pass: m and j staged with their halo, mu in LDS), a 3D n^3 grid
-    (one z-marching pass, mu in registers and LDS) or a 1D row of n sites
-    (the fused strip kernel), autotuned, p = 4, dt = 0.005, c1 = c2 = 1,
-    c3 = 0.5, m and j = U[-0.1, 0.1]."""
+    y-marching pass over column strips), a 3D n^3 grid (one z-marching pass
+    over column tiles; mu in registers and LDS in both) or a 1D row of n
+    sites (the fused strip kernel), autotuned, p = 4, dt = 0.005, c1 = c2 =
+    1, c3 = 0.5, m and j = U[-0.1, 0.1]."""
     shape = {1: (n,), 2: (n, n), 3: (n, n, n)}[ndim]
     d = P.make_desc(P.PF_MH, shape, dx=1.0, dt=0.005, order=4, precision=prec,
                     params=[1.0, 1.0, 0.5])

@@ -18,7 +18,7 @@ constexpr int kMaxFields = 4;       // Model H in 3D: m and three components of 
 
 // Fields a kernel family reduces and steps as a fixed set: Gray-Scott (u, v)
 // and Model C (phi, rho) have two.  Model H has 1 + ndim (m and j), stepped by
-// its own kernels (the 1D strip kernel, the 2D tiled kernel, the per-site
+// its own kernels (the 1D strip kernel, the 2D and 3D marching kernels, the per-site
 // kernels elsewhere); its reductions cover m.
 constexpr int nfields_kind(int kind) { return (kind == kGS || kind == kMC || kind == kCHUP) ? 2 : 1; }
 constexpr int kMaxR = 8;            // stencil radius r = order / 2 (order <= 16)

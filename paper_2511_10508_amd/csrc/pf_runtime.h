@@ -93,7 +93,7 @@ pf_status borrow_plan(Model *m, const pf_desc *d, void *stream, void *const *buf
                       int32_t parity, int64_t nsteps, const void *hist, int64_t *pairs_need);
 pf_status borrow_run(Model *m, double2 *scratch, int64_t nsteps, double2 *hist);
 
-// Model H on 2D grids (r <= 2) in one LDS-tiled pass, bitwise equal to the
+// Model H on 2D grids (r <= 2) in one y-marching pass, bitwise equal to the
 // two passes of the per-site kernels (which run it with PF_FORCE_GENERIC);
 // kernels_mh2d.hip.
 bool mh2d_available(const Launch &L);

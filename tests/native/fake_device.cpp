@@ -157,6 +157,14 @@ void charge(int64_t b)
 
 }  // namespace
 
+// Failure injection: with every = k > 0, every k-th model creation fails as
+// an allocation failure would (PF_ERR_NOMEM, nothing allocated).
+static std::atomic<int> g_fail_every{0}, g_creates{0};
+extern "C" void fake_fail_creates(int every)
+{
+    g_fail_every.store(every);
+    g_creates.store(0);
+}
 extern "C" int64_t fake_model_bytes_peak(void) { return g_model_peak.load(); }
 extern "C" int64_t fake_model_bytes_live(void) { return g_model_bytes.load(); }
 extern "C" void fake_reset_peak(void) { g_model_peak.store(g_model_bytes.load()); }
@@ -439,6 +447,9 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *, int32_t
 {
     pf_status st = check_desc(desc);
     if (st != PF_OK) return st;
+    const int every = g_fail_every.load();
+    if (every > 0 && (g_creates.fetch_add(1) + 1) % every == 0)
+        return fail(PF_ERR_NOMEM, "fake: injected allocation failure");
     Model *m = new Model();
     m->desc = *desc;
     m->nf = desc->nfields;

@@ -26,6 +26,7 @@ extern "C" int64_t fake_model_bytes_peak(void);
 extern "C" int64_t fake_model_bytes_live(void);
 extern "C" void fake_device_idle(void);
 extern "C" void fake_reset_peak(void);
+extern "C" void fake_fail_creates(int every);
 
 namespace {
 
@@ -264,6 +265,61 @@ int run_cancel_queued(uint64_t seed)
     return 0;
 }
 
+// Allocation failures at admission: every third model creation fails.  Those
+// requests come back with PF_ERR_NOMEM and no steps, every other one is
+// exact, and no memory or budget leaks.
+int run_alloc_failures(uint64_t seed)
+{
+    std::mt19937_64 rng(seed + 11);
+    pf_server *srv = nullptr;
+    const uint64_t budget = 400000;
+    fake_device_idle();
+    fake_reset_peak();
+    check(pf_server_create(0, budget, 8, 16, &srv) == PF_OK, "create");
+    fake_fail_creates(3);
+    const int nreq = 90;
+    std::map<uint64_t, Spec> specs;
+    for (int i = 0; i < nreq; ++i) {
+        Spec s = make_spec(rng, i);
+        uint64_t t = 0;
+        check(pf_server_submit(srv, &s.d, PF_IC_UNIFORM, s.seed, nullptr, 0, s.nsteps, &t) == PF_OK, "submit");
+        specs[t] = s;
+    }
+    std::vector<pf_result> buf(32);
+    int seen = 0, nomem = 0;
+    const auto t_end = std::chrono::steady_clock::now() + std::chrono::seconds(60);
+    while (seen < nreq && std::chrono::steady_clock::now() < t_end) {
+        int32_t n = 0;
+        check(pf_server_poll(srv, buf.data(), (int32_t)buf.size(), &n) == PF_OK, "poll");
+        for (int k = 0; k < n; ++k) {
+            const pf_result &r = buf[k];
+            const Spec &s = specs[r.ticket];
+            if (r.status == PF_ERR_NOMEM) {
+                nomem++;
+                check(r.steps_done == 0, "failed request advanced", r.ticket);
+            } else {
+                check(r.status == PF_OK, "status", r.ticket, (unsigned long long)r.status);
+                check(r.steps_done == s.nsteps && r.mass[0] == expect_mass(s, 0), "result of a healthy request",
+                      r.ticket);
+            }
+            check(pf_server_release(srv, r.ticket) == PF_OK, "release", r.ticket);
+            seen++;
+        }
+        if (n == 0) std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+    check(seen == nreq && nomem == nreq / 3, "injected failures", (unsigned long long)seen,
+          (unsigned long long)nomem);
+    check(pf_server_drain(srv, 10.0) == PF_OK, "drain");
+    pf_server_destroy(srv);
+    fake_fail_creates(0);
+    fake_device_idle();
+    check(fake_model_bytes_peak() <= (int64_t)budget, "admitted memory above the budget",
+          (unsigned long long)fake_model_bytes_peak(), budget);
+    check(fake_model_bytes_live() == 0, "model memory leaked after failures",
+          (unsigned long long)fake_model_bytes_live());
+    return 0;
+}
+
 // Destroy with a backlog: requests queued, running and finished-unreleased.
 int run_destroy_backlog(uint64_t seed)
 {
@@ -295,6 +351,7 @@ int main(int argc, char **argv)
     const uint64_t seed = argc > 2 ? std::strtoull(argv[2], nullptr, 10) : 1;
     run_mix(nreq, seed);
     run_cancel_queued(seed);
+    run_alloc_failures(seed);
     run_destroy_backlog(seed);
     if (g_fail.load()) {
         std::fprintf(stderr, "serve_stress: %d failures\n", g_fail.load());

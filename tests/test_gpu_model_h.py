@@ -77,11 +77,12 @@ def test_model_h_1d_fused_equals_generic_bitwise(order, prec):
 
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("shape,order", [((1, 75, 130), 2), ((1, 64, 90), 4), ((1, 33, 31), 4),
-                                         ((1, 5, 7), 4), ((1, 130, 257), 2)])
-def test_model_h_2d_tiled_equals_generic_bitwise(shape, order, prec):
-    """2D grids with r <= 2 run one LDS-tiled pass (32 x 32 tiles, partial
-    and wrapping tiles included); it gives bitwise the two-pass per-site
-    kernel's fields."""
+                                         ((1, 5, 7), 4), ((1, 130, 257), 2), ((1, 300, 700), 4),
+                                         ((1, 41, 253), 4)])
+def test_model_h_2d_marched_equals_generic_bitwise(shape, order, prec):
+    """2D grids with r <= 2 run one y-marching pass (strips of 256 - 4r
+    columns, y chunks, partial and wrapping strips, grids narrower than the
+    halo); it gives bitwise the two-pass per-site kernel's fields."""
     f0 = synth.initial_fields(5, shape, 65, synth.IC_UNIFORM, (-0.1, 0.1), ndim=2)
     dt = 0.8 * oracle.dt_max(oracle.MH, 2, 1.0, order, PARAMS)
     a, _ = gpu_run(f0, 2, order, prec, dt, 20)

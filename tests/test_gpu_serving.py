@@ -197,6 +197,44 @@ def test_unstable_request_is_refused():
     srv.close()
 
 
+def test_nonfinite_request_is_isolated_from_its_batch():
+    """A request whose state is NaN shares its class's launches (tiny and
+    batched tile classes) with finite requests: it finishes with its
+    non-finite sites counted, and every other request is bitwise the same as
+    alone."""
+    reqs = []
+    for i, shape in enumerate([(1, 40, 40), (1, 40, 44), (1, 200, 300), (1, 210, 290)]):
+        reqs.append(dict(id=i, kind=1, ndim=2, shape=shape, steps=90, order=2, params=[1.0, 1.0],
+                         dt=0.05, seed=300 + i, arrival=0.0, fp32=True, cube_side=3))
+    srv = Server(max_slots=16, steps_per_tick=16)
+    tickets = {}
+    for r in reqs:
+        d, ic, icp, _ = request_spec(r)
+        if r["id"] % 2 == 1:  # one NaN request per class
+            ic, icp = P.PF_IC_CONST, (float("nan"),)
+        tickets[srv.submit(d, ic, r["seed"], icp, r["steps"])] = r
+    got = {}
+    t_end = time.time() + 60
+    while len(got) < len(reqs):
+        assert time.time() < t_end
+        for res in srv.poll(64):
+            r = tickets[res["ticket"]]
+            got[r["id"]] = (res, srv.fetch(res["ticket"], 0, r["shape"]))
+            srv.release(res["ticket"])
+        time.sleep(0.001)
+    srv.close()
+    for r in reqs:
+        res, field = got[r["id"]]
+        assert res["status"] == 0 and res["steps_done"] == r["steps"]
+        sites = r["shape"][1] * r["shape"][2]
+        if r["id"] % 2 == 1:
+            assert res["nonfinite"] == sites and np.all(np.isnan(field))
+        else:
+            assert res["nonfinite"] == 0
+            alone, _ = _alone(r)
+            assert np.array_equal(alone[0], field)
+
+
 def test_graph_cache_turnover_keeps_results(monkeypatch):
     """With a one-entry graph cache every new class set destroys the cached
     executable graphs; the server waits for the graph in flight first, and

@@ -6,7 +6,9 @@ memory, with a device thread that runs the enqueued work asynchronously) and
 driven by tests/native/serve_stress.cpp: concurrent submitters, a poller that
 checks every result exactly and releases it, fetches, a canceller and a
 statistics reader race with the scheduler thread; then a cancel-while-queued
-budget check and destroys with requests queued, running and unreleased.
+budget check, injected allocation failures at admission (every third model
+creation fails: those requests return PF_ERR_NOMEM, the others stay exact,
+nothing leaks), and destroys with requests queued, running and unreleased.
 
 Builds: g++ with AddressSanitizer + UndefinedBehaviorSanitizer, and clang++
 (ROCm's LLVM) with ThreadSanitizer -- GCC 11's ThreadSanitizer runtime does
