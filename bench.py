@@ -41,7 +41,11 @@ T0 = time.perf_counter()
 
 FAMILY_SOURCES = {"2d": ("pf_march2d.h", "kernels_fused2d.hip"),
                   "3d": ("pf_march3d.h", "kernels_fused3d.hip"),
-                  "mh3d": ("kernels_mh3d.hip",)}
+                  "1d": ("kernels_fused1d.hip",),
+                  "mh2d": ("kernels_mh2d.hip",),
+                  "mh3d": ("kernels_mh3d.hip",),
+                  "chd3d": ("kernels_chd3d.hip",),
+                  "spectral": ("kernels_spectral.hip", "spectral.cpp")}
 
 
 def source_hash(family="2d"):
@@ -479,6 +483,62 @@ def cpu_baseline(n=4096, seconds=10.0, batch=10):
                 sample="2D Cahn-Hilliard %d^2 p4 FP64, %d steps in %.1f s (OpenMP)" % (n, steps, dt))
 
 
+def run_generic(P, kind, n, order, prec, dt, params, flags, ic, icp, steps=20, warmup=4, seed=808):
+    """One autotuned model on synthetic input: kernel milliseconds per step
+    (HIP events around every step launch) and the fraction of the 8 TB/s
+    HBM peak that its algorithmic bytes (every field read and written once
+    per step) make; the spectral step is priced at its 10 P per site."""
+    d = P.make_desc(kind, n, dx=1.0, dt=dt, order=order, precision=prec, params=params, flags=flags)
+    m = P.Model(d)
+    m.init(ic, seed, icp)
+    m.autotune(2)
+    m.step(warmup)
+    m.sync()
+    m.timing(True)
+    m.step(steps)
+    kms, launches, ks = m.timing_read()
+    chunk, family = m.tile()
+    tb = m.time_block()
+    m.close()
+    per = kms / ks
+    sites = 1.0
+    for e in n:
+        sites *= e
+    Pb = 8 if prec == P.PF_FP64 else 4
+    nf = {P.PF_GS: 2, P.PF_MC: 2, P.PF_MH: 1 + len(n)}.get(kind, 1)
+    per_site = 10 * Pb if flags & P.PF_SPECTRAL else 2 * nf * Pb
+    return {"kernel_ms": round(per, 4), "frac_of_peak": round(per_site * sites / (per * 1e-3) / 1e9 / PEAK_GBS, 4),
+            "chunk": chunk, "family": family, "time_block": tb}
+
+
+def run_extra(P):
+    """Workloads beside the bench lines, for the kernel tables: 2D CH without
+    per-step reductions, 2D AC and GS, 3D AC, Model C in 3D, the spectral
+    step in 3D and 1D, Model H and the direct biharmonic at order 2."""
+    R = P.PF_REDUCE_EACH_STEP
+    U = P.PF_IC_UNIFORM
+    cases = {
+        "ch2d_32768_p4_noreduce": (P.PF_CH, (32768, 32768), 4, 0.01, [1.0, 1.0], 0, U, (-0.05, 0.05)),
+        "ac2d_32768_p2": (P.PF_AC, (32768, 32768), 2, 0.05, [1.0, 1.0], R, U, (-0.1, 0.1)),
+        "gs2d_16384_p2": (P.PF_GS, (16384, 16384), 2, 0.5, [0.2, 0.1, 0.04, 0.06], R, P.PF_IC_GS_CUBES, (20, 64, 0.01)),
+        "ac3d_1024_p2": (P.PF_AC, (1024, 1024, 1024), 2, 0.05, [1.0, 1.0], 0, U, (-0.1, 0.1)),
+        "mc3d_512_p2": (P.PF_MC, (512, 512, 512), 2, 0.01, [1.0, 1.0, 0.5], R, U, (-0.1, 0.1)),
+        "spectral_ch3d_512": (P.PF_CH, (512, 512, 512), 2, 0.5, [1.0, 1.0], P.PF_SPECTRAL, U, (-0.05, 0.05)),
+        "spectral_ch1d_67108864": (P.PF_CH, (1 << 26,), 2, 0.5, [1.0, 1.0], P.PF_SPECTRAL, U, (-0.05, 0.05)),
+        "mh3d_512_p2": (P.PF_MH, (512, 512, 512), 2, 0.005, [1.0, 1.0, 0.5], 0, U, (-0.1, 0.1)),
+        "mh2d_8192_p2": (P.PF_MH, (8192, 8192), 2, 0.005, [1.0, 1.0, 0.5], 0, U, (-0.1, 0.1)),
+        "chd3d_512_p2": (P.PF_CH, (512, 512, 512), 2, 0.005, [1.0, 1.0], R | P.PF_BIHARMONIC_DIRECT, U,
+                         (-0.05, 0.05)),
+        "chd3d_512_p6": (P.PF_CH, (512, 512, 512), 6, 0.002, [1.0, 1.0], R | P.PF_BIHARMONIC_DIRECT, U,
+                         (-0.05, 0.05)),
+    }
+    out = {}
+    for key, (kind, n, order, dt, params, flags, ic, icp) in cases.items():
+        for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
+            out["%s_%s" % (key, tag)] = run_generic(P, kind, n, order, prec, dt, params, flags, ic, icp)
+    return out
+
+
 def run_gs3d(P, n, prec, steps, warmup, seed=303):
     """3D Gray-Scott n^3, p = 2, dt = 0.5, 20 cubes of side 16 plus 1 % noise."""
     d = P.make_desc(P.PF_GS, (n, n, n), dx=1.0, dt=0.5, order=2, precision=prec,
@@ -521,7 +581,8 @@ def main():
                     help="skip the direct-biharmonic, 1D, spectral and Model H lines")
     ap.add_argument("--only", default="",
                     help="comma-separated sections to run besides the headline: gs3d, ch3d, "
-                         "ac128, mc, next, serving, cpu (default: all)")
+                         "ac128, mc, next, serving, cpu (default: all), and the opt-in extra "
+                         "(the kernel tables' other workloads)")
     args = ap.parse_args()
     only = set(x for x in args.only.split(",") if x)
 
@@ -567,6 +628,9 @@ def main():
                 # a two-pass plan's traffic covers both of its kernels
                 extra[key] = attach_traffic(r, key + ("_2pass" if r["passes"] == 2 else ""), src3)
         log("CH 3D 512^3 done")
+    if "extra" in only:  # opt-in: the kernel tables' other workloads
+        extra["extra"] = run_extra(P)
+        log("extra workloads done")
     if want("ac128"):
         extra["ac2d_128_fp64_1000_steps"] = run_ac128(P)
         log("AC 128^2 done")
