@@ -21,11 +21,18 @@ bool dispatch_r3d(int r, F &&f)
 using TimeBlockRadii3D = RList<1>;  // radii with a two-step (TB = 2) 3D kernel
 
 // One row per wave is built besides two for FP64 Allen-Cahn with r <= 2 and
-// FP64 Gray-Scott with r = 1, where it measures faster (and is the default).
+// FP64 Gray-Scott with r = 1, where it measures faster (and is the default);
+// four rows per wave (8-wave workgroups, two per CU) for Cahn-Hilliard, an
+// autotuner candidate.
 template <typename T, int KIND, int R>
 constexpr bool has_one_row_per_wave()
 {
     return std::is_same<T, double>::value && ((KIND == kAC && R <= 2) || (KIND == kGS && R == 1));
+}
+template <typename T, int KIND, int R>
+constexpr bool has_four_rows_per_wave()
+{
+    return KIND == kCH;
 }
 
 // Calls f(T, KIND, R, TB) for the instantiated 3D kernel of L and tb.
@@ -53,12 +60,13 @@ bool dispatch3d(const Launch &L, int tb, F &&f)
 bool rows_per_wave_available(const Launch &L, int tb, int rpw)
 {
     if (L.kind == kCHD) return chd3d_available(L) && tb == 1 && rpw == 2;  // the column-tile kernel
-    bool has1 = false;
+    bool has1 = false, has4 = false;
     if (!dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto) {
             has1 = has_one_row_per_wave<decltype(tz), decltype(kc)::value, decltype(rc)::value>();
+            has4 = has_four_rows_per_wave<decltype(tz), decltype(kc)::value, decltype(rc)::value>();
         }))
         return false;
-    return rpw == 2 || (rpw == 1 && has1);
+    return rpw == 2 || (rpw == 1 && has1) || (rpw == 4 && has4);
 }
 
 int rows_per_wave_default(const Launch &L, int tb) { return rows_per_wave_available(L, tb, 1) ? 1 : 2; }
@@ -95,11 +103,17 @@ bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t c
             const int64_t it = st * (int64_t)*ytiles * *chunks;
             *items = (int32_t)it;
             *blocks = (int32_t)it;
-            *threads = 64 * kWaves3D;
+            *threads = 64 * TL::NW;
         };
         if constexpr (has_one_row_per_wave<T, KIND, R>()) {
             if (rpw == 1) {
                 plan(Tile3D<T, KIND, R, TB, 1>{});
+                return;
+            }
+        }
+        if constexpr (has_four_rows_per_wave<T, KIND, R>()) {
+            if (rpw == 4) {
+                plan(Tile3D<T, KIND, R, TB, 4>{});
                 return;
             }
         }
@@ -165,6 +179,12 @@ hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int
         if constexpr (has_one_row_per_wave<T, KIND, R>()) {
             if (rpw == 1) {
                 err = launch3d<T, KIND, R, TB, 1>(a, blocks, threads, red, s);
+                return;
+            }
+        }
+        if constexpr (has_four_rows_per_wave<T, KIND, R>()) {
+            if (rpw == 4) {
+                err = launch3d<T, KIND, R, TB, 4>(a, blocks, threads, red, s);
                 return;
             }
         }

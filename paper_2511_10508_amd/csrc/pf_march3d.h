@@ -14,12 +14,15 @@ namespace pf {
 // columns, 512 contiguous bytes each).  Two rows per wave double the tile
 // height for the same registers per lane, which halves the share of the tile
 // lost to the y-halo (2H of NR rows) at the price of a wider share lost to
-// the x-halo (2HV of RW columns); the layout is chosen per kernel.
+// the x-halo (2HV of RW columns); the layout is chosen per kernel.  With
+// RPW = 4 (Cahn-Hilliard) rows of 16 lanes make the same 32-row tile with 8
+// waves, so two workgroups share a CU and one's barrier wait is covered by
+// the other's work, for a still wider x-halo share.
 // As in 2D the step is a chain of radius-r stages (two per CH step, one per
 // AC/GS step; TB steps per sweep); each stage keeps a z-window of K = 2r+1
 // planes of its input stream in registers, takes x-neighbours by lane
 // shifts and y-neighbours from the other rows of its centre plane in LDS.
-// With two rows per wave a shift across the middle of the wave brings the
+// With two or four rows per wave a shift across a row boundary brings the
 // other row's edge value into a halo column, on which no valid output
 // depends.  Stage k's centre plane was produced r iterations earlier, so
 // every stage's LDS row is written before one barrier per plane; a stage at
@@ -30,9 +33,12 @@ template <typename T, int KIND, int R, int TB, int RPW_ = 2>
 struct Tile3D {
     using S = Shape<T, KIND, R, TB>;
     static constexpr int V = S::V, H = S::H, HV = S::HV;
-    static constexpr int RPW = RPW_;                         // rows per wave (1 or 2)
+    static constexpr int RPW = RPW_;                         // rows per wave (1, 2 or 4)
     static constexpr int LPR = 64 / RPW;                     // lanes per row
-    static constexpr int NR = RPW * kWaves3D;                // tile rows
+    // waves per workgroup: 16, or 8 with four rows per wave (the same 32-row
+    // tile in half the lanes, so that two workgroups share a CU)
+    static constexpr int NW = RPW == 4 ? kWaves3D / 2 : kWaves3D;
+    static constexpr int NR = RPW * NW;                      // tile rows
     static constexpr int RW = LPR * V;                       // loaded columns per row
     static constexpr int OWMAX = RW - 2 * HV;                // most outputs per row
     // LDS planes: the centre plane of every stage's input stream
@@ -41,7 +47,7 @@ struct Tile3D {
     static constexpr int NFS = (KIND == kCH || KIND == kCHMU || KIND == kCHUP) ? 1 : S::NF;
     static constexpr int NB = NST * NFS <= 2 ? 2 : 1;  // LDS buffers (double when it fits)
     using lds_type = T[NB][NST][NFS][NR][RW];
-    static_assert(RPW == 1 || RPW == 2, "one or two rows per wave");
+    static_assert(RPW == 1 || RPW == 2 || RPW == 4, "one, two or four rows per wave");
     static_assert(2 * H < NR && OWMAX > 0, "halo too wide for the 3D tile");
 };
 
@@ -459,6 +465,18 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
         red_flush(red[0], a.part, a.pstride, pslot, lane);
         if constexpr (TB == 2)
             red_flush(red[TB - 1], a.part, a.pstride, pslot + (int64_t)a.items * kWaves3D, lane);
+        if constexpr (TL::NW < kWaves3D) {
+            // an 8-wave workgroup clears the partial slots of the waves it does
+            // not have (each item owns kWaves3D slots per time step)
+            constexpr int M = kWaves3D - TL::NW;
+            const int tid = threadIdx.x;
+            const int64_t base = pslot - __builtin_amdgcn_readfirstlane(tid >> 6) + TL::NW;
+            if (tid < kNumQ * M * TB) {
+                const int q = tid / (M * TB), rest = tid % (M * TB), s = rest % M, step = rest / M;
+                a.part[(int64_t)q * a.pstride + base + s + step * (int64_t)a.items * kWaves3D] =
+                    make_double2(0.0, 0.0);
+            }
+        }
     }
 }
 
@@ -487,7 +505,7 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
 }
 
 template <typename T, int KIND, int R, bool RED, int TB, int RPW>
-__global__ void __launch_bounds__(64 * kWaves3D) k_step3d(StepArgs<T> a)
+__global__ void __launch_bounds__(64 * (RPW == 4 ? kWaves3D / 2 : kWaves3D)) k_step3d(StepArgs<T> a)
 {
     const int32_t item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.items) return;  // uniform over the workgroup

@@ -1004,7 +1004,7 @@ pf_status autotune(Model *m, int32_t trials)
     // the two-pass form where it exists
     std::vector<std::array<int, 3>> forms;
     for (int tb : tbs)
-        for (int rpw : {2, 1})
+        for (int rpw : {2, 1, 4})
             if (d.ndim != 3 ? rpw == 2 : rows_per_wave_available(m->L, tb, rpw)) forms.push_back({tb, rpw, 1});
     if (two_pass_available(m->L) && !(d.flags & PF_FORCE_GENERIC)) forms.push_back({1, 2, 2});
     for (const auto &fm : forms) {
@@ -1371,13 +1371,14 @@ PF_API int32_t pf_get_time_block(const pf_model *m) { return m ? reinterpret_cas
 
 PF_API pf_status pf_set_tile_rows(pf_model *m, int32_t rows)
 {
-    if (!m || rows < 0 || rows > 2) return fail(PF_ERR_ARG, "tile rows must be 0, 1 or 2");
+    if (!m || rows < 0 || rows > 4 || rows == 3) return fail(PF_ERR_ARG, "tile rows must be 0, 1, 2 or 4");
     Model *mm = M(m);
     PF_HIP(hipStreamSynchronize(mm->stream), "hipStreamSynchronize");
     if (mm->desc.ndim != 3 || mm->family != 0)
         return fail(PF_ERR_UNSUPPORTED, "tile rows apply to the fused 3D kernels");
     if (rows && !rows_per_wave_available(mm->L, mm->tb, rows))
-        return fail(PF_ERR_UNSUPPORTED, "one row per wave is built for FP64 AC (order <= 4) and GS (order 2)");
+        return fail(PF_ERR_UNSUPPORTED, "one row per wave is built for FP64 AC (order <= 4) and GS (order 2), "
+                                        "four for Cahn-Hilliard");
     mm->rpw_req = rows;
     return set_chunk(mm, mm->clen);
 }

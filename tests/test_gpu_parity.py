@@ -434,6 +434,40 @@ def test_3d_tile_rows_bitwise(kind, order, tb):
         assert float(np.max(np.abs(g - r))) <= TOL[P.PF_FP64]
 
 
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("order,tb", [(2, 1), (2, 2), (4, 1), (6, 1)])
+def test_3d_cahn_hilliard_four_rows_per_wave_bitwise(order, tb, prec):
+    """3D Cahn-Hilliard with four 16-lane rows per wave (8-wave workgroups):
+    bitwise the fields of two rows per wave (ragged strips, y tiles and z
+    chunks, an odd step count), reductions equal to their compensated
+    accuracy (the 8-wave items clear their unused partial slots), and the
+    oracle."""
+    shape, ndim, steps = (23, 45, 150), 3, 17
+    params = BASE[P.PF_CH][0]
+    dt = dt_for(P.PF_CH, ndim, order, params)
+    f0 = fields_for(P.PF_CH, shape, 62)
+    n = (shape[2], shape[1], shape[0])
+    outs, hist = [], []
+    for rows in (2, 4):
+        d = P.make_desc(P.PF_CH, n, dt=dt, order=order, precision=prec, params=params,
+                        flags=P.PF_REDUCE_EACH_STEP)
+        m = P.Model(d)
+        m.set_passes(1)
+        m.set_tile(8)
+        m.set_time_block(tb)
+        m.set_tile_rows(rows)
+        assert m.tile_rows() == rows
+        m.set_field(0, f0[0])
+        m.step(steps)
+        outs.append(m.get_field(0))
+        hist.append([sum(m.reduce_history(q, steps)) for q in (P.PF_RED_MASS0, P.PF_RED_ENERGY)])
+    assert np.array_equal(outs[0], outs[1])
+    for a, b in zip(hist[0], hist[1]):
+        assert np.max(np.abs(a - b)) <= 1e-13 * max(1.0, float(np.max(np.abs(a))))
+    ref = oracle_run(P.PF_CH, shape, ndim, order, params, dt, steps, 62)[1]
+    assert float(np.max(np.abs(outs[1] - ref[0]))) <= TOL[prec]
+
+
 def test_tile_rows_defaults_and_refusals():
     gs = P.Model(P.make_desc(P.PF_GS, (40, 30, 20), dt=0.3, order=2))
     assert gs.tile_rows() == 1            # FP64 Gray-Scott default
@@ -444,11 +478,16 @@ def test_tile_rows_defaults_and_refusals():
     with pytest.raises(P.PfError) as e:
         gs.set_tile_rows(3)
     assert e.value.status == P.PF_ERR_ARG
+    with pytest.raises(P.PfError) as e:
+        gs.set_tile_rows(4)               # four rows per wave: Cahn-Hilliard only
+    assert e.value.status == P.PF_ERR_UNSUPPORTED
     ch = P.Model(P.make_desc(P.PF_CH, (40, 30, 20), dt=0.001, order=2))
     assert ch.tile_rows() == 2
     with pytest.raises(P.PfError) as e:
         ch.set_tile_rows(1)
     assert e.value.status == P.PF_ERR_UNSUPPORTED
+    ch.set_tile_rows(4)
+    assert ch.tile_rows() == 4
     ac32 = P.Model(P.make_desc(P.PF_AC, (40, 30, 20), dt=0.01, order=2, precision=P.PF_FP32))
     assert ac32.tile_rows() == 2
     with pytest.raises(P.PfError):
