@@ -335,8 +335,10 @@ int32_t pf_get_time_block(const pf_model *m);
  * segments; built for every 3D kernel).  1: one row of 64 lanes (16-row
  * tiles, 1 KiB segments; built for FP64 Allen-Cahn with order <= 4 and
  * FP64 Gray-Scott with order 2, where it is the default).  4: four rows of
- * 16 lanes (32-row tiles of 8 waves, two workgroups per CU; built for
- * Cahn-Hilliard).  0 restores the default.  Fields
+ * 16 lanes (32-row tiles of 8 waves, two workgroups per CU, or one with up
+ * to 256 registers a lane; built for Cahn-Hilliard, Model C, Gray-Scott with
+ * order >= 4 and Allen-Cahn with order 8; the default for Gray-Scott and
+ * Model C with order >= 6).  0 restores the default.  Fields
  * are bitwise independent of it.  PF_ERR_UNSUPPORTED for a 2D model, the
  * per-site family, or a layout not built for this model.  pf_get_tile_rows
  * returns the layout in use (0 for 2D models and the per-site family, -1 for

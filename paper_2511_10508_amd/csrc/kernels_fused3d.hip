@@ -21,9 +21,11 @@ bool dispatch_r3d(int r, F &&f)
 using TimeBlockRadii3D = RList<1>;  // radii with a two-step (TB = 2) 3D kernel
 
 // One row per wave is built besides two for FP64 Allen-Cahn with r <= 2 and
-// FP64 Gray-Scott with r = 1, where it measures faster (and is the default);
-// four rows per wave (8-wave workgroups, two per CU) for Cahn-Hilliard, an
-// autotuner candidate.
+// FP64 Gray-Scott with r = 1, where it measures faster (and is the default).
+// Four rows per wave (8-wave workgroups: two per CU at up to 128 registers,
+// up to 256 registers with one) for Cahn-Hilliard and Model C, Gray-Scott
+// with r >= 2 and Allen-Cahn with r = 4: an autotuner candidate, and the
+// default where two rows per wave would spill hundreds of bytes a lane.
 template <typename T, int KIND, int R>
 constexpr bool has_one_row_per_wave()
 {
@@ -32,7 +34,7 @@ constexpr bool has_one_row_per_wave()
 template <typename T, int KIND, int R>
 constexpr bool has_four_rows_per_wave()
 {
-    return KIND == kCH;
+    return KIND == kCH || KIND == kMC || (KIND == kGS && R >= 2) || (KIND == kAC && R == 4);
 }
 
 // Calls f(T, KIND, R, TB) for the instantiated 3D kernel of L and tb.
@@ -69,7 +71,25 @@ bool rows_per_wave_available(const Launch &L, int tb, int rpw)
     return rpw == 2 || (rpw == 1 && has1) || (rpw == 4 && has4);
 }
 
-int rows_per_wave_default(const Launch &L, int tb) { return rows_per_wave_available(L, tb, 1) ? 1 : 2; }
+int rows_per_wave_batched(const Launch &L)
+{
+    int rpw = 2;
+    dispatch_kind(L.kind, [&](auto kc) {
+        dispatch_r3d<decltype(kc)::value>(L.r, [&](auto rc) {
+            rpw = batched_rpw<decltype(kc)::value, decltype(rc)::value>();
+        });
+    });
+    return rpw;
+}
+
+int rows_per_wave_default(const Launch &L, int tb)
+{
+    if (rows_per_wave_available(L, tb, 1)) return 1;
+    // four rows where two would spill hundreds of bytes a lane (Gray-Scott and
+    // Model C with r >= 3: 3-6x faster on 512^3)
+    const bool heavy = (L.kind == kGS || L.kind == kMC) && L.r >= 3;
+    return heavy && rows_per_wave_available(L, tb, 4) ? 4 : 2;
+}
 
 bool two_pass_available(const Launch &L)
 {
@@ -206,16 +226,17 @@ hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k,
             if (tb == 2) {
                 dispatch_r(L.r, TimeBlockRadii3D{}, [&](auto rc) {
                     constexpr int R = decltype(rc)::value;
-                    hipLaunchKernelGGL((k_step3d_batched<T, KIND, R, 2>), dim3(blocks), dim3(64 * kWaves3D), 0,
-                                       s, t, k);
+                    constexpr int NW = Tile3D<T, KIND, R, 2, batched_rpw<KIND, R>()>::NW;
+                    hipLaunchKernelGGL((k_step3d_batched<T, KIND, R, 2>), dim3(blocks), dim3(64 * NW), 0, s, t,
+                                       k);
                     err = hipGetLastError();
                 });
                 return;
             }
             dispatch_r3d<KIND>(L.r, [&](auto rc) {
                 constexpr int R = decltype(rc)::value;
-                hipLaunchKernelGGL((k_step3d_batched<T, KIND, R, 1>), dim3(blocks), dim3(64 * kWaves3D), 0, s,
-                                   t, k);
+                constexpr int NW = Tile3D<T, KIND, R, 1, batched_rpw<KIND, R>()>::NW;
+                hipLaunchKernelGGL((k_step3d_batched<T, KIND, R, 1>), dim3(blocks), dim3(64 * NW), 0, s, t, k);
                 err = hipGetLastError();
             });
         });

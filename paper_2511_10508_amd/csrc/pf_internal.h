@@ -92,6 +92,8 @@ bool plan_fused2d(const Launch &L, int64_t nx, int64_t ny, int32_t clen, int tb,
 // layout used until one is set or tuned.
 bool rows_per_wave_available(const Launch &L, int tb, int rpw);
 int rows_per_wave_default(const Launch &L, int tb);
+// the layout of the batched (serving) 3D kernel of L's class: 2 or 4
+int rows_per_wave_batched(const Launch &L);
 // Two passes (3D Cahn-Hilliard, composed form, one step per launch, two rows
 // per wave): mu goes through a field-sized buffer instead of staying in
 // registers, and both passes have the halo of one radius-r stencil instead

@@ -512,12 +512,23 @@ __global__ void __launch_bounds__(64 * (RPW == 4 ? kWaves3D / 2 : kWaves3D)) k_s
     step3d_item<T, KIND, R, RED, TB, RPW>(a, a.parity, item, (int64_t)item * kWaves3D);
 }
 
-// Persistent batched 3D step (see k_step2d_batched), two rows per wave; the
-// item loop and the choice of a two-step sweep are uniform over the
-// workgroup, so every wave reaches the same barriers.
-template <typename T, int KIND, int R, int TB>
-__global__ void __launch_bounds__(64 * kWaves3D) k_step3d_batched(BatchTable<T> tb, int32_t k)
+// Rows per wave of the batched (serving) 3D kernels: two, or four (8-wave
+// workgroups, up to 256 registers a lane) for the classes whose two-row
+// kernel would spill (Model C, Gray-Scott with r >= 3).
+template <int KIND, int R>
+constexpr int batched_rpw()
 {
+    return (KIND == kMC || (KIND == kGS && R >= 3)) ? 4 : 2;
+}
+
+// Persistent batched 3D step (see k_step2d_batched); the item loop and the
+// choice of a two-step sweep are uniform over the workgroup, so every wave
+// reaches the same barriers.
+template <typename T, int KIND, int R, int TB>
+__global__ void __launch_bounds__(64 * (batched_rpw<KIND, R>() == 4 ? kWaves3D / 2 : kWaves3D))
+    k_step3d_batched(BatchTable<T> tb, int32_t k)
+{
+    constexpr int RPW = batched_rpw<KIND, R>();
     const int32_t n = *tb.count;
     const int32_t total = tb.item_start[n];
     for (int32_t g = blockIdx.x; g < total; g += gridDim.x) {
@@ -528,11 +539,11 @@ __global__ void __launch_bounds__(64 * kWaves3D) k_step3d_batched(BatchTable<T> 
         const int par = (a.parity + k / TB) & 1;
         if constexpr (TB == 2) {
             if (left >= 2) {
-                step3d_item<T, KIND, R, false, 2, 2>(a, par, g - tb.item_start[i], 0);
+                step3d_item<T, KIND, R, false, 2, RPW>(a, par, g - tb.item_start[i], 0);
                 continue;
             }
         }
-        step3d_item<T, KIND, R, false, 1, 2>(a, par, g - tb.item_start[i], 0);
+        step3d_item<T, KIND, R, false, 1, RPW>(a, par, g - tb.item_start[i], 0);
     }
 }
 

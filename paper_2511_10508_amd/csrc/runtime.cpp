@@ -822,7 +822,7 @@ pf_status model_create(const pf_desc *desc, void *stream, void *const *bufs, int
     // wave in 3D, two-step sweeps where the class has them); the serving
     // autotuner sets their chunk after admission
     if (m->async_alloc) {
-        m->rpw_req = 2;
+        m->rpw_req = desc->ndim == 3 ? rows_per_wave_batched(m->L) : 2;
         m->passes_req = 1;
         m->tb = time_block_available(m->L) ? 2 : 1;
     }
@@ -1378,7 +1378,7 @@ PF_API pf_status pf_set_tile_rows(pf_model *m, int32_t rows)
         return fail(PF_ERR_UNSUPPORTED, "tile rows apply to the fused 3D kernels");
     if (rows && !rows_per_wave_available(mm->L, mm->tb, rows))
         return fail(PF_ERR_UNSUPPORTED, "one row per wave is built for FP64 AC (order <= 4) and GS (order 2), "
-                                        "four for Cahn-Hilliard");
+                                        "four for CH, Model C, GS (order >= 4) and AC (order 8)");
     mm->rpw_req = rows;
     return set_chunk(mm, mm->clen);
 }

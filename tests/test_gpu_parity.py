@@ -434,22 +434,28 @@ def test_3d_tile_rows_bitwise(kind, order, tb):
         assert float(np.max(np.abs(g - r))) <= TOL[P.PF_FP64]
 
 
+FOUR_ROWS = [(P.PF_CH, 2, 1), (P.PF_CH, 2, 2), (P.PF_CH, 4, 1), (P.PF_CH, 6, 1), (P.PF_MC, 2, 1),
+             (P.PF_MC, 2, 2), (P.PF_MC, 6, 1), (P.PF_GS, 4, 1), (P.PF_GS, 6, 1), (P.PF_GS, 8, 1),
+             (P.PF_AC, 8, 1)]
+
+
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("order,tb", [(2, 1), (2, 2), (4, 1), (6, 1)])
-def test_3d_cahn_hilliard_four_rows_per_wave_bitwise(order, tb, prec):
-    """3D Cahn-Hilliard with four 16-lane rows per wave (8-wave workgroups):
+@pytest.mark.parametrize("kind,order,tb", FOUR_ROWS, ids=["k%d-p%d-tb%d" % c for c in FOUR_ROWS])
+def test_3d_four_rows_per_wave_bitwise(kind, order, tb, prec):
+    """3D kernels with four 16-lane rows per wave (8-wave workgroups):
     bitwise the fields of two rows per wave (ragged strips, y tiles and z
     chunks, an odd step count), reductions equal to their compensated
     accuracy (the 8-wave items clear their unused partial slots), and the
     oracle."""
     shape, ndim, steps = (23, 45, 150), 3, 17
-    params = BASE[P.PF_CH][0]
-    dt = dt_for(P.PF_CH, ndim, order, params)
-    f0 = fields_for(P.PF_CH, shape, 62)
+    params = BASE[kind][0]
+    dt = dt_for(kind, ndim, order, params)
+    f0 = fields_for(kind, shape, 62)
     n = (shape[2], shape[1], shape[0])
+    second = P.PF_RED_MASS1 if kind in (P.PF_GS, P.PF_MC) else P.PF_RED_ENERGY
     outs, hist = [], []
     for rows in (2, 4):
-        d = P.make_desc(P.PF_CH, n, dt=dt, order=order, precision=prec, params=params,
+        d = P.make_desc(kind, n, dt=dt, order=order, precision=prec, params=params,
                         flags=P.PF_REDUCE_EACH_STEP)
         m = P.Model(d)
         m.set_passes(1)
@@ -457,15 +463,18 @@ def test_3d_cahn_hilliard_four_rows_per_wave_bitwise(order, tb, prec):
         m.set_time_block(tb)
         m.set_tile_rows(rows)
         assert m.tile_rows() == rows
-        m.set_field(0, f0[0])
+        for f, a in enumerate(f0):
+            m.set_field(f, a)
         m.step(steps)
-        outs.append(m.get_field(0))
-        hist.append([sum(m.reduce_history(q, steps)) for q in (P.PF_RED_MASS0, P.PF_RED_ENERGY)])
-    assert np.array_equal(outs[0], outs[1])
+        outs.append([m.get_field(f) for f in range(len(f0))])
+        hist.append([sum(m.reduce_history(q, steps)) for q in (P.PF_RED_MASS0, second)])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
     for a, b in zip(hist[0], hist[1]):
         assert np.max(np.abs(a - b)) <= 1e-13 * max(1.0, float(np.max(np.abs(a))))
-    ref = oracle_run(P.PF_CH, shape, ndim, order, params, dt, steps, 62)[1]
-    assert float(np.max(np.abs(outs[1] - ref[0]))) <= TOL[prec]
+    ref = oracle_run(kind, shape, ndim, order, params, dt, steps, 62)[1]
+    for g, r in zip(outs[1], ref):
+        assert float(np.max(np.abs(g - r))) <= TOL[prec]
 
 
 def test_tile_rows_defaults_and_refusals():
@@ -479,8 +488,10 @@ def test_tile_rows_defaults_and_refusals():
         gs.set_tile_rows(3)
     assert e.value.status == P.PF_ERR_ARG
     with pytest.raises(P.PfError) as e:
-        gs.set_tile_rows(4)               # four rows per wave: Cahn-Hilliard only
+        gs.set_tile_rows(4)               # four rows per wave: not Gray-Scott at r = 1
     assert e.value.status == P.PF_ERR_UNSUPPORTED
+    gs6 = P.Model(P.make_desc(P.PF_GS, (40, 30, 20), dt=0.1, order=6))
+    assert gs6.tile_rows() == 4           # the default where two rows per wave would spill
     ch = P.Model(P.make_desc(P.PF_CH, (40, 30, 20), dt=0.001, order=2))
     assert ch.tile_rows() == 2
     with pytest.raises(P.PfError) as e:

@@ -37,6 +37,8 @@ def _mixed_requests():
         (4, 2, (1, 90, 110), 4, True, [1.0, 1.0, 0.5], 0.01),   # Model C
         (4, 3, (16, 20, 70), 2, False, [0.9, 1.1, 0.5], 0.01),
         (4, 2, (1, 40, 50), 6, False, [1.0, 1.0, 0.5], 0.002),  # tiny Model C, r = 3
+        (3, 3, (20, 26, 40), 6, True, [0.2, 0.1, 0.04, 0.06], 0.3),  # batched 3D kernels with
+        (4, 3, (16, 24, 30), 6, False, [1.0, 1.0, 0.5], 0.002),     # four rows per wave
         (3, 3, (12, 14, 16), 2, True, [0.2, 0.1, 0.04, 0.06], 0.5),  # tiny 3D Gray-Scott
     ]
     for i, (kind, ndim, shape, order, fp32, params, dt) in enumerate(specs):
