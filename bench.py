@@ -62,9 +62,11 @@ def source_hash(family="2d"):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tag, src_hash):
+def measured_traffic(tag, src_hash, layout=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
+    was taken on the current kernel sources and (given `layout`, a dict of
+    time_block / tile_rows) on the same layout as the timed kernel (else
+    None)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % tag)
     if not os.path.exists(path):
         return None
@@ -75,6 +77,9 @@ def measured_traffic(tag, src_hash):
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != src_hash:
         return None
+    for key, field in (("time_block", "layout_tb"), ("tile_rows", "layout_rpw")):
+        if layout and layout.get(key) is not None and field in vals and int(vals[field]) != int(layout[key]):
+            return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -85,7 +90,7 @@ def attach_traffic(r, tag, src_hash):
     """Add the HBM bytes per launch measured by the counters (committed
     summary profiles/traffic_<tag>.txt, taken on the current kernel sources)
     and the fraction of peak they make at the measured launch time."""
-    t = measured_traffic(tag, src_hash)
+    t = measured_traffic(tag, src_hash, r)
     r["hbm_bytes_per_launch"] = t
     per = r.get("kernel_ms_per_launch")
     r["frac_hbm_measured"] = None if (t is None or not per) else round(t / (per * 1e-3) / 1e9 / PEAK_GBS, 4)
@@ -668,7 +673,7 @@ def main():
         extra["serving"] = serving_compare(args.serving)
         log("serving done")
 
-    traffic = measured_traffic("ch2d_%d_fp64" % args.n, src)
+    traffic = measured_traffic("ch2d_%d_fp64" % args.n, src, {"time_block": fp64["time_block"]})
     out = {
         "metric": "site-updates/s & % HBM peak (FP64 vs FP32); serving p50/p99 vs serial",
         "value": fp64["su_s"],
