@@ -423,7 +423,7 @@ def run_serial(trace):
     import paper_2511_10508_amd as P
     specs = [request_spec(r) for r in trace]
     work = sum(s[3] * r["steps"] for s, r in zip(specs, trace))
-    lat = []
+    lat, svc = [], []
     idle = 0.0
     progress = _progress()
     start = time.perf_counter()
@@ -433,22 +433,40 @@ def run_serial(trace):
         if wait > 0:
             time.sleep(wait)
             idle += wait
+        t_begin = time.perf_counter()
         m = P.Model(d)
         m.init(ic, r["seed"], icp)
         m.step(r["steps"])
         m.reduce(0)
         m.close()
-        lat.append(time.perf_counter() - (start + r["arrival"]))
+        t_end = time.perf_counter()
+        svc.append(t_end - t_begin)
+        lat.append(t_end - (start + r["arrival"]))
     makespan = time.perf_counter() - start
     return dict(p50_s=_pct(lat, 50), p99_s=_pct(lat, 99), makespan_s=makespan, idle_s=idle,
-                su_per_s=work / (makespan - idle))
+                su_per_s=work / (makespan - idle), service_s=svc)
 
 
-def serving_compare(nreq, seed=505, load=0.8, steps_per_tick=64):
+def fifo_replay(arrivals, service):
+    """Latencies of a single FIFO server with the given per-request service
+    times (the one-at-a-time loop, whose service time does not depend on the
+    load) for other arrival times: completion_i = max(arrival_i,
+    completion_{i-1}) + service_i."""
+    done, lat = 0.0, []
+    for a, s in zip(arrivals, service):
+        done = max(a, done) + s
+        lat.append(done - a)
+    return lat
+
+
+def serving_compare(nreq, seed=505, load=0.8, load2=0.5, steps_per_tick=64):
     """Throughput: the server's capacity with the whole trace submitted at
     t = 0 (work over makespan); the one-at-a-time loop's capacity is its work
     over busy time.  Latency: both on the same Poisson trace at `load` x the
-    server's capacity (requests/s); p50 and p99 of completion minus arrival."""
+    server's capacity (requests/s); p50 and p99 of completion minus arrival.
+    A second load point (`load2`): the server measured again, the loop's
+    latencies from a FIFO replay of its measured per-request service times.
+    The traces hold the same requests at every rate."""
     import synth
     burst = synth.serving_trace(nreq, seed=seed, rate=None)
     cap_b = run_batched(burst, steps_per_tick=steps_per_tick)
@@ -460,13 +478,26 @@ def serving_compare(nreq, seed=505, load=0.8, steps_per_tick=64):
     lat_s = run_serial(trace)
     log("serving serial at %.1f req/s: %.2f s (idle %.2f s)" % (rate, lat_s["makespan_s"],
                                                                 lat_s["idle_s"]))
+    rate2 = load2 * nreq / cap_b["makespan_s"]
+    trace2 = synth.serving_trace(nreq, seed=seed, rate=rate2)
+    lat_b2 = run_batched(trace2, steps_per_tick=steps_per_tick)
+    log("serving batched at %.1f req/s: %.2f s" % (rate2, lat_b2["makespan_s"]))
+    lat_s2 = fifo_replay([r["arrival"] for r in trace2], lat_s["service_s"])
+    # the replay at the measured load, beside the measured loop: how well it models the loop
+    lat_s1 = fifo_replay([r["arrival"] for r in trace], lat_s["service_s"])
+    svc = lat_s.pop("service_s")
     return dict(requests=nreq, site_updates=sum(request_spec(r)[3] * r["steps"] for r in burst),
                 batched_su_per_s=cap_b["su_per_s"], serial_su_per_s=lat_s["su_per_s"],
                 throughput_speedup=cap_b["su_per_s"] / lat_s["su_per_s"],
                 load=load, rate_req_per_s=rate,
                 batched_p50_s=lat_b["p50_s"], batched_p99_s=lat_b["p99_s"],
                 serial_p50_s=lat_s["p50_s"], serial_p99_s=lat_s["p99_s"],
-                batched_capacity=cap_b, batched_load=lat_b, serial_load=lat_s)
+                load2=load2, rate2_req_per_s=rate2,
+                batched_p50_s_at_load2=lat_b2["p50_s"], batched_p99_s_at_load2=lat_b2["p99_s"],
+                serial_p50_s_at_load2=_pct(lat_s2, 50), serial_p99_s_at_load2=_pct(lat_s2, 99),
+                serial_p50_s_replayed=_pct(lat_s1, 50), serial_p99_s_replayed=_pct(lat_s1, 99),
+                serial_service_total_s=sum(svc),
+                batched_capacity=cap_b, batched_load=lat_b, batched_load2=lat_b2, serial_load=lat_s)
 
 
 def cpu_baseline(n=4096, seconds=10.0, batch=10):

@@ -184,8 +184,11 @@ def serving_trace(nreq, seed=505, rate=None, dims=(2, 3), fp32=True):
     order uniform over {2, 4}; parameters jittered by U[0.8, 1.2] around the
     base workloads (AC c1=c2=1 dt=0.05; CH c1=c2=1 dt=0.01; GS Du=0.2 Dv=0.1
     F=0.04 k=0.06 dt=0.5).  Arrival times are Poisson with the given rate
-    (requests/s); rate None gives all arrivals at t = 0.  The time-step limit
-    is not applied here: the caller redraws dt against its own limit.
+    (requests/s); rate None gives all arrivals at t = 0.  The requests
+    themselves do not depend on the rate (every request draws its
+    inter-arrival gap, used or not), so traces at different rates hold the
+    same requests.  The time-step limit is not applied here: the caller
+    redraws dt against its own limit.
     """
     rng = np.random.default_rng(seed)
     out = []
@@ -208,8 +211,9 @@ def serving_trace(nreq, seed=505, rate=None, dims=(2, 3), fp32=True):
             params, dt = [1.0 * jit[0], 1.0 * jit[1]], 0.01 * jit[4]
         else:
             params, dt = [0.2 * jit[0], 0.1 * jit[1], 0.04 * jit[2], 0.06 * jit[3]], 0.5 * jit[4]
+        gap = float(rng.exponential(1.0))
         if rate:
-            t += float(rng.exponential(1.0 / rate))
+            t += gap / rate
         out.append(dict(id=i, kind=kind, ndim=ndim, shape=shape, steps=steps, order=order,
                         params=params, dt=float(dt), seed=int(mix_int(seed * 1000003 + i) >> 1),
                         arrival=t, fp32=fp32,

@@ -56,3 +56,10 @@ def test_serving_trace_shapes():
     t = [r["arrival"] for r in tr]
     assert all(b >= a for a, b in zip(t, t[1:]))
     assert {r["kind"] for r in tr} == {1, 2, 3}
+    # the same requests at any rate: only the arrivals change (and scale)
+    for other in (synth.serving_trace(200, seed=505, rate=None), synth.serving_trace(200, seed=505, rate=5.0)):
+        for a, b in zip(tr, other):
+            assert {k: v for k, v in a.items() if k != "arrival"} == {k: v for k, v in b.items() if k != "arrival"}
+    slow = synth.serving_trace(200, seed=505, rate=5.0)
+    assert all(abs(b["arrival"] - 2.0 * a["arrival"]) <= 1e-9 * max(1.0, b["arrival"]) for a, b in zip(tr, slow))
+    assert all(r["arrival"] == 0.0 for r in synth.serving_trace(20, seed=505))
