@@ -108,15 +108,17 @@ def copy_probe(P, torch, nbytes=2 ** 31, reps=10):
     return 2.0 * nbytes / (ms.value * 1e-3) / 1e9
 
 
-def run_ch(P, n, prec, steps, warmup, seed=202):
+def run_ch(P, n, prec, steps, warmup, seed=202, flags=0):
     d = P.make_desc(P.PF_CH, (n, n), dx=1.0, dt=0.01, order=4, precision=prec,
-                    params=[1.0, 1.0], flags=P.PF_REDUCE_EACH_STEP)
+                    params=[1.0, 1.0], flags=P.PF_REDUCE_EACH_STEP | flags)
     m = P.Model(d)
     m.init(P.PF_IC_UNIFORM, seed, (-0.05, 0.05))
     m.autotune(2)
     m.step(warmup)
     m.sync()
-    m.timing(True)
+    # per-launch events replace the graph, so a graph run is timed by wall only
+    graph = (flags & P.PF_USE_GRAPH) != 0
+    m.timing(not graph)
     t0 = time.perf_counter()
     m.step(steps)
     m.sync()
@@ -130,6 +132,8 @@ def run_ch(P, n, prec, steps, warmup, seed=202):
     m.close()
     sites = float(n) * n
     wall = t1 - t0
+    if graph:
+        kernel_ms, launches, ksteps = wall * 1e3, 1, steps
     per_launch = kernel_ms / launches
     # algorithmic bytes of one launch: every field read and written once per
     # time step it advances (a two-step launch counts two steps)
@@ -617,8 +621,8 @@ def main():
                     help="skip the direct-biharmonic, 1D, spectral and Model H lines")
     ap.add_argument("--only", default="",
                     help="comma-separated sections to run besides the headline: gs3d, ch3d, "
-                         "ac128, mc, next, serving, cpu (default: all), and the opt-in extra "
-                         "(the kernel tables' other workloads)")
+                         "sizes, ac128, mc, next, serving, cpu (default: all), and the opt-in "
+                         "extra (the kernel tables' other workloads)")
     args = ap.parse_args()
     only = set(x for x in args.only.split(",") if x)
 
@@ -655,7 +659,23 @@ def main():
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             r = run_gs3d(P, 1024, prec, max(10, args.steps // 4), 5)
             extra["gs3d_1024_" + tag] = attach_traffic(r, "gs3d_1024_" + tag, src3)
+            extra["gs3d_512_" + tag] = run_gs3d(P, 512, prec, max(20, args.steps // 2), 5)
         log("GS 3D done")
+    if want("sizes"):
+        # the 2D Cahn-Hilliard workload at its smaller sizes (4096^2 FP32 fits
+        # the 256 MB last-level cache: not a roofline point)
+        # (at 4096^2 the host's launch gaps show: the graph line replays the
+        # step batch as one HIP graph)
+        for n, gname, gflag in ((4096, "", 0), (4096, "_graph", P.PF_USE_GRAPH), (16384, "", 0)):
+            for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
+                r = run_ch(P, n, prec, max(20, args.steps), 10, flags=gflag)
+                line = {"value": r["su_s"], "ms_per_step": round(r["ms_per_step"], 4),
+                        "chunk": r["chunk"], "time_block": r["time_block"]}
+                if not gflag:
+                    line["kernel_ms_per_launch"] = round(r["kernel_ms"], 4)
+                    line["frac_of_peak"] = round(r["achieved_gbs"] / PEAK_GBS, 4)
+                extra["ch2d_%d_%s%s" % (n, tag, gname)] = line
+        log("CH 2D sizes done")
     if want("ch3d", args.skip_3d):
         for order in (2, 4, 6):
             for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):

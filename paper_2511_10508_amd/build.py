@@ -65,6 +65,7 @@ def build(jobs=None, verbose=False, force=True):
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + \
           [o for o, _ in results] + ["-L" + os.path.join(ROCM, "lib"), "-lhipfft",
+                                     "-lrocprofiler-sdk-roctx",
                                      "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

@@ -93,6 +93,16 @@ pf_status borrow_plan(Model *m, const pf_desc *d, void *stream, void *const *buf
                       int32_t parity, int64_t nsteps, const void *hist, int64_t *pairs_need);
 pf_status borrow_run(Model *m, double2 *scratch, int64_t nsteps, double2 *hist);
 
+// roctx ranges (trace.cpp): TraceRange opens one for its lifetime.
+void trace_push(const char *msg);
+void trace_pop();
+struct TraceRange {
+    explicit TraceRange(const char *msg) { trace_push(msg); }
+    ~TraceRange() { trace_pop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
 // Model H on 2D grids (r <= 2) in one y-marching pass, bitwise equal to the
 // two passes of the per-site kernels (which run it with PF_FORCE_GENERIC);
 // kernels_mh2d.hip.

@@ -559,6 +559,7 @@ static pf_status capture_graph(Model *m, int par, int k, bool red, Model::Graph 
 pf_status do_steps(Model *m, int64_t nsteps)
 {
     if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
+    TraceRange range("pf_step");
     const bool each = (m->desc.flags & PF_REDUCE_EACH_STEP) != 0;
     if (each) {
         pf_status st = ensure_history(m, nsteps);
@@ -976,6 +977,7 @@ pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int3
 pf_status autotune(Model *m, int32_t trials)
 {
     if (m->family != 0) return PF_OK;
+    TraceRange range("pf_autotune");
     const pf_desc &d = m->desc;
     const bool red = (d.flags & PF_REDUCE_EACH_STEP) != 0;
     // chunk candidates up to the marching extent (1D: strips per wave)

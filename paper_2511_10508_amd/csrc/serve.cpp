@@ -642,6 +642,7 @@ static void worker_main(Server *s)
         }
         const int set = (int)(s->tick & 1);
         if (!run.empty()) {
+            TraceRange range("pf_server tick");
             if (!enqueue_tick(s, run, set)) break;
         }
         (void)hipEventRecord(s->ev[set], s->stream);
