@@ -336,7 +336,8 @@ int32_t pf_get_time_block(const pf_model *m);
  * tiles, 1 KiB segments; built for FP64 Allen-Cahn with order <= 4 and
  * FP64 Gray-Scott with order 2, where it is the default).  4: four rows of
  * 16 lanes (32-row tiles of 8 waves, two workgroups per CU, or one with up
- * to 256 registers a lane; built for Cahn-Hilliard, Model C, Gray-Scott with
+ * to 256 registers a lane; 48-row tiles of 12 waves for Cahn-Hilliard with
+ * order 6; built for Cahn-Hilliard, Model C, Gray-Scott with
  * order >= 4 and Allen-Cahn with order 8; the default for Gray-Scott and
  * Model C with order >= 6).  0 restores the default.  Fields
  * are bitwise independent of it.  PF_ERR_UNSUPPORTED for a 2D model, the
@@ -361,9 +362,7 @@ int32_t pf_get_tile_rows(const pf_model *m);
  * per launch (pf_set_time_block(m, 2) is then PF_ERR_UNSUPPORTED).
  * PF_ERR_UNSUPPORTED for other models, orders, the per-site or spectral
  * family.  pf_get_passes returns the passes in use (0 outside the fused
- * family, -1 for NULL).  Until set, FP32 order 6 with PF_REDUCE_EACH_STEP
- * runs two passes (its one-pass kernel spills registers and is slower),
- * everything else one.  The autotuner considers both.
+ * family, -1 for NULL).  Until set, one pass; the autotuner considers both.
  */
 pf_status pf_set_passes(pf_model *m, int32_t passes);
 int32_t pf_get_passes(const pf_model *m);
@@ -375,7 +374,9 @@ int32_t pf_get_passes(const pf_model *m);
  * fastest per step and records it in an in-process cache keyed by (kind,
  * ndim, order, precision, per-step reductions, size class) that later models
  * of the same class reuse.
- * trials = timed launches per candidate.
+ * trials = timed launches per candidate (<= 0: 3); where they take less
+ * than 2 ms, the candidate is timed again with as many launches as fill
+ * 2 ms (at most 64).
  */
 pf_status pf_autotune(pf_model *m, int32_t trials);
 

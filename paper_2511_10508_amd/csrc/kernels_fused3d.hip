@@ -23,7 +23,8 @@ using TimeBlockRadii3D = RList<1>;  // radii with a two-step (TB = 2) 3D kernel
 // One row per wave is built besides two for FP64 Allen-Cahn with r <= 2 and
 // FP64 Gray-Scott with r = 1, where it measures faster (and is the default).
 // Four rows per wave (8-wave workgroups: two per CU at up to 128 registers,
-// up to 256 registers with one) for Cahn-Hilliard and Model C, Gray-Scott
+// up to 256 registers with one; 12 waves for Cahn-Hilliard with r = 3) for
+// Cahn-Hilliard and Model C, Gray-Scott
 // with r >= 2 and Allen-Cahn with r = 4: an autotuner candidate, and the
 // default where two rows per wave would spill hundreds of bytes a lane.
 template <typename T, int KIND, int R>
@@ -86,19 +87,15 @@ int rows_per_wave_default(const Launch &L, int tb)
 {
     if (rows_per_wave_available(L, tb, 1)) return 1;
     // four rows where two would spill hundreds of bytes a lane (Gray-Scott and
-    // Model C with r >= 3: 3-6x faster on 512^3)
-    const bool heavy = (L.kind == kGS || L.kind == kMC) && L.r >= 3;
+    // Model C with r >= 3: 3-6x faster on 512^3) or 88 (FP32 Cahn-Hilliard
+    // with r = 3, whose 48-row tiles of 12 waves run 1.5x faster on 512^3)
+    const bool heavy = ((L.kind == kGS || L.kind == kMC) && L.r >= 3) || (L.kind == kCH && L.r == 3 && L.fp32);
     return heavy && rows_per_wave_available(L, tb, 4) ? 4 : 2;
 }
 
 bool two_pass_available(const Launch &L)
 {
     return L.ndim == 3 && L.kind == kCH && L.r >= 1 && L.r <= 3;
-}
-
-bool two_pass_default(const Launch &L, bool reduce_each_step)
-{
-    return two_pass_available(L) && L.fp32 && L.r == 3 && reduce_each_step;
 }
 
 bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,

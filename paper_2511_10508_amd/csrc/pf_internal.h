@@ -99,10 +99,6 @@ int rows_per_wave_batched(const Launch &L);
 // registers, and both passes have the halo of one radius-r stencil instead
 // of two.  plan_fused3d with passes = 2 plans the tiles of both passes.
 bool two_pass_available(const Launch &L);
-// The plan without a request: two passes for FP32 order 6 with reductions
-// every step, whose one-pass kernel exceeds the register budget (and is the
-// slower of the two).
-bool two_pass_default(const Launch &L, bool reduce_each_step);
 bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int tb,
                   int rpw, int passes, int32_t *strips, int32_t *ow, int32_t *ytiles,
                   int32_t *chunks, int32_t *items, int32_t *blocks, int32_t *threads);

@@ -15,9 +15,10 @@ namespace pf {
 // height for the same registers per lane, which halves the share of the tile
 // lost to the y-halo (2H of NR rows) at the price of a wider share lost to
 // the x-halo (2HV of RW columns); the layout is chosen per kernel.  With
-// RPW = 4 (Cahn-Hilliard) rows of 16 lanes make the same 32-row tile with 8
-// waves, so two workgroups share a CU and one's barrier wait is covered by
-// the other's work, for a still wider x-halo share.
+// RPW = 4 rows of 16 lanes make the same 32-row tile with 8 waves, so two
+// workgroups share a CU and one's barrier wait is covered by the other's
+// work, for a still wider x-halo share (Cahn-Hilliard with r = 3: a 48-row
+// tile of 12 waves, see Tile3D).
 // As in 2D the step is a chain of radius-r stages (two per CH step, one per
 // AC/GS step; TB steps per sweep); each stage keeps a z-window of K = 2r+1
 // planes of its input stream in registers, takes x-neighbours by lane
@@ -35,9 +36,13 @@ struct Tile3D {
     static constexpr int V = S::V, H = S::H, HV = S::HV;
     static constexpr int RPW = RPW_;                         // rows per wave (1, 2 or 4)
     static constexpr int LPR = 64 / RPW;                     // lanes per row
-    // waves per workgroup: 16, or 8 with four rows per wave (the same 32-row
-    // tile in half the lanes, so that two workgroups share a CU)
-    static constexpr int NW = RPW == 4 ? kWaves3D / 2 : kWaves3D;
+    // waves per workgroup: 16; with four rows per wave 8 (the same 32-row
+    // tile in half the lanes, so that two workgroups share a CU at up to 128
+    // registers a lane), or 12 for Cahn-Hilliard with r = 3, whose kernels
+    // need 129-168 registers: one workgroup per CU either way, and twelve
+    // waves make three per SIMD and a 48-row tile (36 rows written of 48
+    // instead of 20 of 32)
+    static constexpr int NW = RPW == 4 ? ((KIND == kCH && R == 3) ? 12 : 8) : kWaves3D;
     static constexpr int NR = RPW * NW;                      // tile rows
     static constexpr int RW = LPR * V;                       // loaded columns per row
     static constexpr int OWMAX = RW - 2 * HV;                // most outputs per row
@@ -239,10 +244,11 @@ constexpr int kTwoPassPD =
 // reductions), where a plane's work is also long enough to hide one plane's
 // load latency.  FP64 Cahn-Hilliard with r = 2 has room for the K = 5 ring
 // (about 120 registers with reductions).
-template <typename T, int KIND, int R, int TB, bool RED>
+template <typename T, int KIND, int R, int TB, bool RED, int RPW>
 constexpr int prefetch_depth()
 {
     if (std::is_same<T, double>::value && KIND == kCH && R == 2 && TB == 1) return 2 * R + 1;
+    if (KIND == kCH && R == 3 && TB == 1 && RPW == 4) return 2;
     if (KIND == kCHMU || KIND == kCHUP) return kTwoPassPD<T, KIND, R, RED>;
     return (R >= 2 || (TB == 2 && RED)) ? 1 : 2 * R + 1;
 }
@@ -277,12 +283,15 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
     T *out[2] = {a.buf[0][par ^ 1], a.buf[NF - 1][par ^ 1]};
 
     T ring[NF][K][V];
-    constexpr int PD = prefetch_depth<T, KIND, R, TB, RED>();
+    constexpr int PD = prefetch_depth<T, KIND, R, TB, RED, RPW>();
     T pre[NF][PD][V];                                // planes t+1 .. t+PD
     T r1[TB == 2 ? NF : 1][K][V];
     T m0[KIND == kCH ? K : 1][V];
     T m1[(KIND == kCH && TB == 2) ? K : 1][V];
-    static_assert(K % PD == 0, "plane t is prefetched into slot t mod PD of a K-phase loop");
+    // phases per loop iteration: a multiple of the ring depth and of the
+    // prefetch depth, so that plane t sits in ring slot t mod K and prefetch
+    // slot t mod PD at compile time
+    constexpr int NP = K % PD == 0 ? K : K * PD;
     // rings that feed LDS rows or later stages before first being computed hold zeros
 #pragma unroll
     for (int i = 0; i < K; ++i)
@@ -326,7 +335,7 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int v = 0; v < V; ++v) ring[f][ph][v] = pre[f][ph % PD][v];
+                for (int v = 0; v < V; ++v) ring[f][ph % K][v] = pre[f][ph % PD][v];
             if (!G || t + PD < tend) {
                 const int64_t off = (int64_t)wrap32(t + PD, nz) * plane + rowoff;
 #pragma unroll
@@ -457,17 +466,17 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
         }
     };
     int32_t tb = tb0;
-    for (; tb + K + PD <= tend; tb += K)
-        static_for<0, K>([&](auto phc) { phase(phc, std::false_type{}, tb); });
-    for (; tb < tend; tb += K)
-        static_for<0, K>([&](auto phc) { phase(phc, std::true_type{}, tb); });
+    for (; tb + NP + PD <= tend; tb += NP)
+        static_for<0, NP>([&](auto phc) { phase(phc, std::false_type{}, tb); });
+    for (; tb < tend; tb += NP)
+        static_for<0, NP>([&](auto phc) { phase(phc, std::true_type{}, tb); });
     if constexpr (RED) {
         red_flush(red[0], a.part, a.pstride, pslot, lane);
         if constexpr (TB == 2)
             red_flush(red[TB - 1], a.part, a.pstride, pslot + (int64_t)a.items * kWaves3D, lane);
         if constexpr (TL::NW < kWaves3D) {
-            // an 8-wave workgroup clears the partial slots of the waves it does
-            // not have (each item owns kWaves3D slots per time step)
+            // an 8- or 12-wave workgroup clears the partial slots of the waves
+            // it does not have (each item owns kWaves3D slots per time step)
             constexpr int M = kWaves3D - TL::NW;
             const int tid = threadIdx.x;
             const int64_t base = pslot - __builtin_amdgcn_readfirstlane(tid >> 6) + TL::NW;
@@ -505,7 +514,7 @@ __device__ __forceinline__ void step3d_item(const StepArgs<T> &a, int par, int32
 }
 
 template <typename T, int KIND, int R, bool RED, int TB, int RPW>
-__global__ void __launch_bounds__(64 * (RPW == 4 ? kWaves3D / 2 : kWaves3D)) k_step3d(StepArgs<T> a)
+__global__ void __launch_bounds__((64 * Tile3D<T, KIND, R, TB, RPW>::NW)) k_step3d(StepArgs<T> a)
 {
     const int32_t item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.items) return;  // uniform over the workgroup
@@ -525,7 +534,7 @@ constexpr int batched_rpw()
 // choice of a two-step sweep are uniform over the workgroup, so every wave
 // reaches the same barriers.
 template <typename T, int KIND, int R, int TB>
-__global__ void __launch_bounds__(64 * (batched_rpw<KIND, R>() == 4 ? kWaves3D / 2 : kWaves3D))
+__global__ void __launch_bounds__((64 * Tile3D<T, KIND, R, 1, batched_rpw<KIND, R>()>::NW))
     k_step3d_batched(BatchTable<T> tb, int32_t k)
 {
     constexpr int RPW = batched_rpw<KIND, R>();

@@ -264,9 +264,7 @@ static bool plan(Model *m)
         ok = plan_fused2d(L, d.n[0], d.n[1], m->clen, m->tb, &strips, &ow, &chunks, &items,
                           &blocks, &threads);
     else {
-        const bool two = m->passes_req == 2 ||
-                         (m->passes_req == 0 && two_pass_default(L, (d.flags & PF_REDUCE_EACH_STEP) != 0));
-        m->passes = two && two_pass_available(L) ? 2 : 1;
+        m->passes = m->passes_req == 2 && two_pass_available(L) ? 2 : 1;
         if (m->passes == 2) {
             m->tb = 1;
             m->rpw = 2;
@@ -974,6 +972,8 @@ pf_status init_fields(Model *m, int32_t ic, uint64_t seed, const double *p, int3
 // Times every candidate (chunk length, time-block factor) on the model's own
 // buffers: each trial re-runs steps from the current parity, whose buffer is
 // never written, so the state is untouched.  Keeps the fastest per step.
+constexpr float kTuneMinMs = 2.0f;  // least timed span per autotuner candidate
+
 pf_status autotune(Model *m, int32_t trials)
 {
     if (m->family != 0) return PF_OK;
@@ -1020,14 +1020,22 @@ pf_status autotune(Model *m, int32_t trials)
                 if (st != PF_OK || m->family != 0 || m->tb != tb || m->passes != passes) break;
                 st = launch_step(m, m->parity, red, scratch, false, tb);
                 if (st != PF_OK) break;
-                (void)hipEventRecord(a, m->stream);
-                for (int t = 0; t < trials && st == PF_OK; ++t)
-                    st = launch_step(m, m->parity, red, scratch, false, tb);
-                (void)hipEventRecord(b, m->stream);
-                (void)hipEventSynchronize(b);
+                // time `trials` launches; where they take less than kTuneMinMs,
+                // time again with enough launches to fill it (short launches
+                // differ by a few percent from one to the next)
+                int reps = trials;
                 float ms = 0;
-                (void)hipEventElapsedTime(&ms, a, b);
-                ms /= tb;
+                for (int pass = 0; pass < 2 && st == PF_OK; ++pass) {
+                    (void)hipEventRecord(a, m->stream);
+                    for (int t = 0; t < reps && st == PF_OK; ++t)
+                        st = launch_step(m, m->parity, red, scratch, false, tb);
+                    (void)hipEventRecord(b, m->stream);
+                    (void)hipEventSynchronize(b);
+                    (void)hipEventElapsedTime(&ms, a, b);
+                    if (pass > 0 || ms >= kTuneMinMs || !(ms > 0.f)) break;
+                    reps = std::min(64, (int)std::ceil(reps * kTuneMinMs / ms));
+                }
+                ms /= (float)reps * tb;
                 if (st == PF_OK && ms < best) {
                     best = ms;
                     bestc = {c, tb, m->rpw_req, passes};

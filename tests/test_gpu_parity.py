@@ -442,11 +442,11 @@ FOUR_ROWS = [(P.PF_CH, 2, 1), (P.PF_CH, 2, 2), (P.PF_CH, 4, 1), (P.PF_CH, 6, 1),
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("kind,order,tb", FOUR_ROWS, ids=["k%d-p%d-tb%d" % c for c in FOUR_ROWS])
 def test_3d_four_rows_per_wave_bitwise(kind, order, tb, prec):
-    """3D kernels with four 16-lane rows per wave (8-wave workgroups):
-    bitwise the fields of two rows per wave (ragged strips, y tiles and z
-    chunks, an odd step count), reductions equal to their compensated
-    accuracy (the 8-wave items clear their unused partial slots), and the
-    oracle."""
+    """3D kernels with four 16-lane rows per wave (8-wave workgroups; 12
+    waves and 48-row tiles for CH order 6): bitwise the fields of two rows
+    per wave (ragged strips, y tiles and z chunks, an odd step count),
+    reductions equal to their compensated accuracy (the 8- and 12-wave items
+    clear their unused partial slots), and the oracle."""
     shape, ndim, steps = (23, 45, 150), 3, 17
     params = BASE[kind][0]
     dt = dt_for(kind, ndim, order, params)

@@ -113,9 +113,11 @@ def test_set_passes_refusals():
     assert e.value.status == P.PF_ERR_ARG
     ch6 = P.Model(P.make_desc(P.PF_CH, (40, 30, 20), dt=1e-4, order=6, precision=P.PF_FP32,
                               flags=P.PF_REDUCE_EACH_STEP))
-    assert ch6.passes() == 2  # the default where the one-pass kernel spills
+    assert ch6.passes() == 1 and ch6.tile_rows() == 4  # the 48-row tiles of 12 waves
+    ch6.set_passes(2)
+    assert ch6.passes() == 2 and ch6.tile_rows() == 2
     ch6.set_passes(1)
-    assert ch6.passes() == 1
+    assert ch6.passes() == 1 and ch6.tile_rows() == 4
     assert P.Model(P.make_desc(P.PF_CH, (40, 30, 20), dt=1e-4, order=6, precision=P.PF_FP32)).passes() == 1
     for d in (P.make_desc(P.PF_CH, (40, 30), dt=0.001, order=4),
               P.make_desc(P.PF_AC, (40, 30, 20), dt=0.01, order=2),
