@@ -44,7 +44,7 @@ FAMILY_SOURCES = {"2d": ("pf_march2d.h", "kernels_fused2d.hip"),
                   "1d": ("kernels_fused1d.hip",),
                   "mh2d": ("kernels_mh2d.hip",),
                   "mh3d": ("kernels_mh3d.hip",),
-                  "chd3d": ("kernels_chd3d.hip",),
+                  "chd3d": ("pf_march3d.h", "kernels_chd3d.hip"),
                   "spectral": ("kernels_spectral.hip", "spectral.cpp")}
 
 

@@ -337,9 +337,12 @@ int32_t pf_get_time_block(const pf_model *m);
  * FP64 Gray-Scott with order 2, where it is the default).  4: four rows of
  * 16 lanes (32-row tiles of 8 waves, two workgroups per CU, or one with up
  * to 256 registers a lane; 48-row tiles of 12 waves for Cahn-Hilliard with
- * order 6; built for Cahn-Hilliard, Model C, Gray-Scott with
- * order >= 4 and Allen-Cahn with order 8; the default for Gray-Scott and
- * Model C with order >= 6).  0 restores the default.  Fields
+ * order 6 and the direct biharmonic with order 2; built for Cahn-Hilliard,
+ * Model C, Gray-Scott with order >= 4, Allen-Cahn with order 8 and the
+ * direct biharmonic; the default for Gray-Scott and Model C with order >= 6,
+ * FP32 Cahn-Hilliard with order 6 and the direct biharmonic).  The direct
+ * biharmonic has one other 3D layout, 2: one thread per column of an x-y
+ * tile (plus its halo) marching along z.  0 restores the default.  Fields
  * are bitwise independent of it.  PF_ERR_UNSUPPORTED for a 2D model, the
  * per-site family, or a layout not built for this model.  pf_get_tile_rows
  * returns the layout in use (0 for 2D models and the per-site family, -1 for

@@ -1,8 +1,11 @@
 // Cahn-Hilliard with the direct biharmonic stencil on 3D grids, one z-marching
-// pass (the fused family's 3D kernel for PF_BIHARMONIC_DIRECT).
+// pass (the fused family's 3D kernels for PF_BIHARMONIC_DIRECT), in two tile
+// layouts: the 3D march of the other models with four rows per wave
+// (k_step3d<T, kCHD, r, RED, 1, 4>, pf_march3d.h: halo r + 1, x-neighbours
+// by lane shifts, the default) and the column tiles below (layout 2).
 //
 // c' = c + dt (sum_a D2_a mu_a - sum_a D4_a c), mu_a = g - sum_{b != a} D2_b c,
-// g = c2 c^3 - c1 c.  A workgroup owns an x-y tile of output columns plus a
+// g = c2 c^3 - c1 c.  Column tiles: a workgroup owns an x-y tile of output columns plus a
 // halo of 2r and marches along z over a chunk of planes, one column per
 // thread.  When plane t of c arrives:
 //   mu_x, mu_y and mu_z at plane t - r (tile + r halo): x-y neighbours of c
@@ -18,8 +21,8 @@
 // kernel.  The fused reductions (mass, energy, non-finite count of the state
 // at the start of the step) follow the other fused kernels: one compensated
 // partial per wave, in the slots of 16 waves per work item.
-#include "pf_device.h"
 #include "pf_dispatch.h"
+#include "pf_march3d.h"
 
 namespace pf {
 
@@ -207,15 +210,36 @@ hipError_t launch_chd3d_r(const StepArgs<T> &a, int32_t blocks, int red, hipStre
 
 bool chd3d_available(const Launch &L) { return L.kind == kCHD && L.ndim == 3 && L.r >= 1 && L.r <= 3; }
 
-bool plan_chd3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int32_t *strips,
-                int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items, int32_t *blocks,
-                int32_t *threads)
+bool plan_chd3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int rpw,
+                int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items,
+                int32_t *blocks, int32_t *threads)
 {
     if (!chd3d_available(L) || clen < 1) return false;
     bool ok = false;
     dispatch_prec(L.fp32, [&](auto tz) {
         dispatch_r(L.r, RList<1, 2, 3>{}, [&](auto rc) {
-            using TL = CHD3Tile<decltype(tz), decltype(rc)::value>;
+            using T = decltype(tz);
+            constexpr int R = decltype(rc)::value;
+            auto plan = [&](auto tl) {  // the 3D march's tiles
+                using TS = decltype(tl);
+                const int64_t st = cdiv(nx, TS::OWMAX);
+                const int64_t it = st * cdiv(ny, TS::NR - 2 * TS::H) * cdiv(nz, clen);
+                if (it > (int64_t)INT32_MAX) return;
+                *strips = (int32_t)st;
+                *ow = (int32_t)(cdiv(cdiv(nx, st), TS::V) * TS::V);
+                *ytiles = (int32_t)cdiv(ny, TS::NR - 2 * TS::H);
+                *chunks = (int32_t)cdiv(nz, clen);
+                *items = (int32_t)it;
+                *blocks = (int32_t)it;
+                *threads = 64 * TS::NW;
+                ok = true;
+            };
+            if (rpw == 4) {
+                plan(Tile3D<T, kCHD, R, 1, 4>{});
+                return;
+            }
+            if (rpw != 2) return;
+            using TL = CHD3Tile<T, R>;
             const int64_t tx = cdiv(nx, TL::TX), ty = cdiv(ny, TL::TY), ch = cdiv(nz, clen);
             const int64_t it = tx * ty * ch;
             if (it > (int64_t)INT32_MAX) return;
@@ -232,7 +256,19 @@ bool plan_chd3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t cle
     return ok;
 }
 
-hipError_t launch_chd3d(const Launch &L, const void *args, int32_t blocks, int red, hipStream_t s)
+template <typename T, int R, int RPW>
+hipError_t launch_chd3d_march(const StepArgs<T> &a, int32_t blocks, int32_t threads, int red, hipStream_t s)
+{
+    if (threads != 64 * Tile3D<T, kCHD, R, 1, RPW>::NW) return hipErrorInvalidValue;
+    if (red)
+        hipLaunchKernelGGL((k_step3d<T, kCHD, R, true, 1, RPW>), dim3(blocks), dim3(threads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step3d<T, kCHD, R, false, 1, RPW>), dim3(blocks), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_chd3d(const Launch &L, const void *args, int32_t blocks, int32_t threads, int red,
+                        int rpw, hipStream_t s)
 {
     hipError_t err = hipErrorInvalidValue;
     if (!chd3d_available(L)) return err;
@@ -240,7 +276,11 @@ hipError_t launch_chd3d(const Launch &L, const void *args, int32_t blocks, int r
         using T = decltype(tz);
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
         dispatch_r(L.r, RList<1, 2, 3>{}, [&](auto rc) {
-            err = launch_chd3d_r<T, decltype(rc)::value>(a, blocks, red, s);
+            constexpr int R = decltype(rc)::value;
+            if (rpw == 4)
+                err = launch_chd3d_march<T, R, 4>(a, blocks, threads, red, s);
+            else if (rpw == 2 && threads == CHD3Tile<T, R>::THREADS)
+                err = launch_chd3d_r<T, R>(a, blocks, red, s);
         });
     });
     return err;

@@ -62,7 +62,7 @@ bool dispatch3d(const Launch &L, int tb, F &&f)
 
 bool rows_per_wave_available(const Launch &L, int tb, int rpw)
 {
-    if (L.kind == kCHD) return chd3d_available(L) && tb == 1 && rpw == 2;  // the column-tile kernel
+    if (L.kind == kCHD) return chd3d_available(L) && tb == 1 && (rpw == 2 || rpw == 4);
     bool has1 = false, has4 = false;
     if (!dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto) {
             has1 = has_one_row_per_wave<decltype(tz), decltype(kc)::value, decltype(rc)::value>();
@@ -88,8 +88,11 @@ int rows_per_wave_default(const Launch &L, int tb)
     if (rows_per_wave_available(L, tb, 1)) return 1;
     // four rows where two would spill hundreds of bytes a lane (Gray-Scott and
     // Model C with r >= 3: 3-6x faster on 512^3) or 88 (FP32 Cahn-Hilliard
-    // with r = 3, whose 48-row tiles of 12 waves run 1.5x faster on 512^3)
-    const bool heavy = ((L.kind == kGS || L.kind == kMC) && L.r >= 3) || (L.kind == kCH && L.r == 3 && L.fp32);
+    // with r = 3, whose 48-row tiles of 12 waves run 1.5x faster on 512^3);
+    // the direct biharmonic's march (its other layout is the column tiles:
+    // 1.0-2.8x slower on 512^3)
+    const bool heavy = ((L.kind == kGS || L.kind == kMC) && L.r >= 3) || (L.kind == kCH && L.r == 3 && L.fp32) ||
+                       L.kind == kCHD;
     return heavy && rows_per_wave_available(L, tb, 4) ? 4 : 2;
 }
 
@@ -105,7 +108,8 @@ bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t c
     if (passes == 2 && !(two_pass_available(L) && tb == 1 && rpw == 2)) return false;
     if (!rows_per_wave_available(L, tb, rpw)) return false;
     if (L.kind == kCHD)
-        return passes == 1 && plan_chd3d(L, nx, ny, nz, clen, strips, ow, ytiles, chunks, items, blocks, threads);
+        return passes == 1 &&
+               plan_chd3d(L, nx, ny, nz, clen, rpw, strips, ow, ytiles, chunks, items, blocks, threads);
     return dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
         using T = decltype(tz);
         constexpr int KIND = decltype(kc)::value, R = decltype(rc)::value;
@@ -181,7 +185,7 @@ hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int
     hipError_t err = hipErrorInvalidValue;
     if (!rows_per_wave_available(L, tb, rpw)) return err;
     if (mu && !(two_pass_available(L) && tb == 1 && rpw == 2)) return err;
-    if (L.kind == kCHD) return launch_chd3d(L, args, blocks, red, s);
+    if (L.kind == kCHD) return launch_chd3d(L, args, blocks, threads, red, rpw, s);
     dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
         using T = decltype(tz);
         constexpr int KIND = decltype(kc)::value, R = decltype(rc)::value;

@@ -110,13 +110,15 @@ hipError_t launch_fused1d(const Launch &L, const void *args, int32_t blocks, int
 hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
                           int red, int tb, hipStream_t s);
 // 3D Cahn-Hilliard with the direct biharmonic (r <= 3): one z-marching pass
-// over column tiles (kernels_chd3d.hip); plan_fused3d and launch_fused3d
-// route kCHD here.
+// (kernels_chd3d.hip), the 3D march with four rows per wave (rpw 4, the
+// default) or one column per thread over column tiles (rpw 2);
+// plan_fused3d and launch_fused3d route kCHD here.
 bool chd3d_available(const Launch &L);
-bool plan_chd3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int32_t *strips,
-                int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items, int32_t *blocks,
-                int32_t *threads);
-hipError_t launch_chd3d(const Launch &L, const void *args, int32_t blocks, int red, hipStream_t s);
+bool plan_chd3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t clen, int rpw,
+                int32_t *strips, int32_t *ow, int32_t *ytiles, int32_t *chunks, int32_t *items,
+                int32_t *blocks, int32_t *threads);
+hipError_t launch_chd3d(const Launch &L, const void *args, int32_t blocks, int32_t threads, int red,
+                        int rpw, hipStream_t s);
 // mu: the field-sized mu buffer of a two-pass plan (same pitch and plane
 // stride as the fields), nullptr for the fused single pass.
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,

@@ -38,19 +38,23 @@ struct Tile3D {
     static constexpr int LPR = 64 / RPW;                     // lanes per row
     // waves per workgroup: 16; with four rows per wave 8 (the same 32-row
     // tile in half the lanes, so that two workgroups share a CU at up to 128
-    // registers a lane), or 12 for Cahn-Hilliard with r = 3, whose kernels
-    // need 129-168 registers: one workgroup per CU either way, and twelve
-    // waves make three per SIMD and a 48-row tile (36 rows written of 48
-    // instead of 20 of 32)
-    static constexpr int NW = RPW == 4 ? ((KIND == kCH && R == 3) ? 12 : 8) : kWaves3D;
+    // registers a lane), or 12 for Cahn-Hilliard with r = 3 and the direct
+    // biharmonic with r = 1, whose kernels need 129-168 registers: one
+    // workgroup per CU either way, and twelve waves make three per SIMD and a
+    // 48-row tile (CH r = 3: 36 rows written of 48 instead of 20 of 32).  The
+    // direct biharmonic with r >= 2 needs up to 256 registers and stays at 8.
+    static constexpr int NW = RPW == 4 ? (((KIND == kCH && R == 3) || (KIND == kCHD && R == 1)) ? 12 : 8)
+                                       : kWaves3D;
     static constexpr int NR = RPW * NW;                      // tile rows
     static constexpr int RW = LPR * V;                       // loaded columns per row
     static constexpr int OWMAX = RW - 2 * HV;                // most outputs per row
     // LDS planes: the centre plane of every stage's input stream
-    static constexpr int NST = (KIND == kCH ? 2 : 1) * TB;
+    // (the direct biharmonic: c at the arriving plane, c and mu_y at the
+    // centre plane)
+    static constexpr int NST = (KIND == kCH ? 2 : KIND == kCHD ? 3 : 1) * TB;
     // fields per plane (the passes of a two-pass CH step stage one stream)
     static constexpr int NFS = (KIND == kCH || KIND == kCHMU || KIND == kCHUP) ? 1 : S::NF;
-    static constexpr int NB = NST * NFS <= 2 ? 2 : 1;  // LDS buffers (double when it fits)
+    static constexpr int NB = (NST * NFS <= 2 || KIND == kCHD) ? 2 : 1;  // LDS buffers (double when it fits)
     using lds_type = T[NB][NST][NFS][NR][RW];
     static_assert(RPW == 1 || RPW == 2 || RPW == 4, "one, two or four rows per wave");
     static_assert(2 * H < NR && OWMAX > 0, "halo too wide for the 3D tile");
@@ -229,6 +233,124 @@ __device__ __forceinline__ void stage3_chupd(const StepArgs<T> &a, const T (&m)[
     }
 }
 
+// Direct-biharmonic Cahn-Hilliard in 3D: c' = c + dt (sum_a D2_a mu_a -
+// sum_a D4_a c), mu_a = g - sum_{b != a} D2_b c (the chemical potential
+// without the a-axis term).  The ring holds K = 2r + 3 planes of c; the
+// update runs on the centre plane CS, r + 1 planes behind the newest, so the
+// halo is r + 1 instead of the composed form's 2r.  Every sum is formed in
+// the per-site kernel's order (pairs x, then y, then z), so the fields are
+// bitwise those of the per-site kernels.
+//
+// mu_y of the centre plane from its x-neighbourhood (lane shifts) and the
+// z-ring (no y term: computed before the plane's barrier).
+template <typename T, int R, int K, int CS>
+__device__ __forceinline__ void stage3_chd_mu_y(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                                T (&my)[Vec<T>::V])
+{
+    constexpr int V = Vec<T>::V;
+    T e[V + 2 * R];
+    gather_x<T, V, R>(c[CS], e);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T S[R];
+        static_for<1, R + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            S[j - 1] = (e[R + v + j] + e[R + v - j]) + (c[(CS + j) % K][v] + c[(CS - j + K) % K][v]);
+        });
+        const T c0 = c[CS][v];
+        my[v] = ch_mu<T, R>(a, c0, S, c0 * T(4));
+    }
+}
+
+// mu_z of the arriving plane SA (x by lane shifts, y from its plane in LDS)
+// into slot SA of the mu_z ring.
+template <typename T, int R, int K, int SA, int NR, int RW>
+__device__ __forceinline__ void stage3_chd_mu_z(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                                const T (&L)[NR][RW], int rw, int pl,
+                                                T (&mz)[K][Vec<T>::V])
+{
+    constexpr int V = Vec<T>::V;
+    T e[V + 2 * R];
+    gather_x<T, V, R>(c[SA], e);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T S[R];
+        static_for<1, R + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            S[j - 1] = (e[R + v + j] + e[R + v - j]) + (L[rw + j][pl + v] + L[rw - j][pl + v]);
+        });
+        const T c0 = c[SA][v];
+        mz[SA][v] = ch_mu<T, R>(a, c0, S, c0 * T(4));
+    }
+}
+
+// The update of the centre plane CS: mu_x (y-pairs from the centre plane of
+// c in LDS Lc, z-pairs from the ring), then the D2 pairs of mu_x (x, lane
+// shifts), mu_y (y, its plane in LDS Lm) and mu_z (z, its ring) and the D4
+// pairs of c (lane shifts, Lc, ring); with RED the state at CS is reduced.
+template <typename T, int R, int K, int CS, int NR, int RW, bool RED>
+__device__ __forceinline__ void stage3_chd_update(const StepArgs<T> &a, const T (&c)[K][Vec<T>::V],
+                                                  const T (&my)[Vec<T>::V], const T (&mz)[K][Vec<T>::V],
+                                                  const T (&Lc)[NR][RW], const T (&Lm)[NR][RW], int rw,
+                                                  int pl, T (&res)[Vec<T>::V], const OutMask<Vec<T>::V> &om,
+                                                  bool red_row, RedState &red)
+{
+    constexpr int V = Vec<T>::V, R4 = R + 1;
+    T mx[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T S[R];
+        static_for<1, R + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            S[j - 1] = (Lc[rw + j][pl + v] + Lc[rw - j][pl + v]) + (c[(CS + j) % K][v] + c[(CS - j + K) % K][v]);
+        });
+        const T c0 = c[CS][v];
+        mx[v] = ch_mu<T, R>(a, c0, S, c0 * T(4));
+    }
+    T em[V + 2 * R], ec[V + 2 * R4];
+    gather_x<T, V, R>(mx, em);
+    gather_x<T, V, R4>(c[CS], ec);
+    double s0 = 0.0, s1 = 0.0;  // the row's masked reduction sums
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        T Sm[R], S4[R4];
+        static_for<1, R + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            Sm[j - 1] = ((em[R + v + j] + em[R + v - j]) + (Lm[rw + j][pl + v] + Lm[rw - j][pl + v])) +
+                        (mz[(CS + j) % K][v] + mz[(CS - j + K) % K][v]);
+        });
+        static_for<1, R4 + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            S4[j - 1] = ((ec[R4 + v + j] + ec[R4 + v - j]) + (Lc[rw + j][pl + v] + Lc[rw - j][pl + v])) +
+                        (c[(CS + j) % K][v] + c[(CS - j + K) % K][v]);
+        });
+        const T c0 = c[CS][v];
+        const T musum = (mx[v] + my[v]) + mz[CS][v];
+        res[v] = chd_update<T, R>(a, c0, Sm, musum * T(2), S4, c0 * T(6));
+        if constexpr (RED) {
+            if (om.ov[v]) {
+                const double x = (double)c0;
+                s0 += x;
+                if constexpr (std::is_same<T, double>::value) {
+                    // the full chemical potential: (mu_x + mu_y + mu_z - g) / 2
+                    s1 += energy_from_mu(a.c2, x, 0.5 * (musum - chd_g(a, c0)));
+                } else {
+                    double Pn[R];
+                    static_for<1, R + 1>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        Pn[j - 1] = ((double)ec[R4 + v + j] + (double)Lc[rw + j][pl + v]) +
+                                    (double)c[(CS + j) % K][v];
+                    });
+                    s1 += energy_by_parts<R>(a.c1, a.c2, a.w64, 3.0 * a.w64sum, x, Pn);
+                }
+            }
+        }
+    }
+    if constexpr (RED)
+        if (red_row)
+            red_row_end<V, false>(red, om, s0, s1, [&](int, int v) { return (double)c[CS][v]; });
+}
+
 // Prefetch depth of the two passes of a two-pass Cahn-Hilliard step: each
 // holds one ring of K planes (the mu pass) or one ring plus c's centre planes
 // (the update pass), which leaves room for K planes in flight up to r = 2;
@@ -249,6 +371,7 @@ constexpr int prefetch_depth()
 {
     if (std::is_same<T, double>::value && KIND == kCH && R == 2 && TB == 1) return 2 * R + 1;
     if (KIND == kCH && R == 3 && TB == 1 && RPW == 4) return 2;
+    if (KIND == kCHD) return 1;
     if (KIND == kCHMU || KIND == kCHUP) return kTwoPassPD<T, KIND, R, RED>;
     return (R >= 2 || (TB == 2 && RED)) ? 1 : 2 * R + 1;
 }
@@ -288,6 +411,7 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
     T r1[TB == 2 ? NF : 1][K][V];
     T m0[KIND == kCH ? K : 1][V];
     T m1[(KIND == kCH && TB == 2) ? K : 1][V];
+    T mz[KIND == kCHD ? K : 1][V];                   // direct biharmonic: mu_z ring
     // phases per loop iteration: a multiple of the ring depth and of the
     // prefetch depth, so that plane t sits in ring slot t mod K and prefetch
     // slot t mod PD at compile time
@@ -301,6 +425,7 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
                 m0[i][v] = T(0);
                 if constexpr (TB == 2) m1[i][v] = T(0);
             }
+            if constexpr (KIND == kCHD) mz[i][v] = T(0);
             if constexpr (TB == 2)
 #pragma unroll
                 for (int f = 0; f < NF; ++f) r1[f][i][v] = T(0);
@@ -341,7 +466,30 @@ __device__ __forceinline__ void march3d(const StepArgs<T> &a, int par, int64_t x
 #pragma unroll
                 for (int f = 0; f < NF; ++f) io.load(in[f] + off, pre[f][ph % PD]);
             }
-            if constexpr (KIND == kCHMU || KIND == kCHUP) {
+            if constexpr (KIND == kCHD) {
+                // the direct biharmonic: mu_z of the arriving plane t, and the
+                // update of the centre plane t - (r + 1)
+                constexpr int sa = ph % K, sc = Slot<K, R + 1>::template at<ph>;
+                T my[V];
+                stage3_chd_mu_y<T, R, K, sc>(a, ring[0], my);
+                if constexpr (TL::NB == 1) __syncthreads();
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    L[0][0][rw][pl + v] = ring[0][sa][v];
+                    L[1][0][rw][pl + v] = ring[0][sc][v];
+                    L[2][0][rw][pl + v] = my[v];
+                }
+                __syncthreads();
+                if (rows_ok(1)) stage3_chd_mu_z<T, R, K, sa, NR, RW>(a, ring[0], L[0][0], rw, pl, mz);
+                if (age >= 2 * H && rw >= H && rw < NR - H) {
+                    const int32_t pz = t - H;
+                    T res[V];
+                    stage3_chd_update<T, R, K, sc, NR, RW, RED>(a, ring[0], my, mz, L[1][0], L[2][0], rw, pl,
+                                                                res, om, pz >= z0 && pz < z1, red[0]);
+                    if (out_row)
+                        store_row<T, V>(out[0] + (int64_t)wrap32(pz, nz) * plane + rowoff, xl, om, res);
+                }
+            } else if constexpr (KIND == kCHMU || KIND == kCHUP) {
                 // one radius-r stage: mu of c (with the reductions of c), or
                 // the update of c from the mu stream and c's centre plane
                 constexpr int s1 = Slot<K, R>::template at<ph>;

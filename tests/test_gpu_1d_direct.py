@@ -218,7 +218,7 @@ def test_direct_biharmonic_parity_100_steps(case, prec):
                                               (3, (19, 35, 140), 4), (3, (23, 30, 41), 6),
                                               (3, (5, 40, 37), 2), (3, (6, 7, 9), 4)])
 def test_direct_biharmonic_fused_equals_generic_bitwise(ndim, shape, order, prec):
-    """The fused kernels (2D march; 3D column tiles with z chunks, partial,
+    """The fused kernels (2D march; 3D march with z chunks, partial,
     wrapping and thin grids) give bitwise the per-site kernel's fields."""
     params = BASE[CHD][0]
     dt = dt_for(CHD, ndim, order, params)
@@ -227,6 +227,35 @@ def test_direct_biharmonic_fused_equals_generic_bitwise(ndim, shape, order, prec
     b, mb = gpu_run(CHD, f0, ndim, order, prec, params, dt, 30, flags=P.PF_FORCE_GENERIC)
     assert ma.tile()[1] == 0 and mb.tile()[1] == 1
     assert np.array_equal(a[0], b[0])
+
+
+@pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("order,shape", [(2, (21, 45, 150)), (4, (23, 45, 150)), (6, (19, 53, 140))])
+def test_direct_biharmonic_3d_layouts_bitwise(order, shape, prec):
+    """3D direct biharmonic in both tile layouts (column tiles; the 3D march
+    with four rows per wave, ragged strips, y tiles and z chunks):
+    fields bitwise those of the per-site kernel, fused reductions of every
+    step equal to their compensated accuracy."""
+    params = BASE[CHD][0]
+    dt = dt_for(CHD, 3, order, params)
+    f0 = fields_for(CHD, shape, 29)
+    n = (shape[2], shape[1], shape[0])
+    steps = 13
+    ref, mg = gpu_run(CHD, f0, 3, order, prec, params, dt, steps,
+                      flags=P.PF_FORCE_GENERIC | P.PF_REDUCE_EACH_STEP)
+    hist_ref = [sum(mg.reduce_history(q, steps)) for q in (P.PF_RED_MASS0, P.PF_RED_ENERGY)]
+    for rows in (2, 4):
+        d = P.make_desc(P.PF_CH, n, dt=dt, order=order, precision=prec, params=params,
+                        flags=P.PF_BIHARMONIC_DIRECT | P.PF_REDUCE_EACH_STEP)
+        m = P.Model(d)
+        m.set_tile(8)
+        m.set_tile_rows(rows)
+        assert m.tile_rows() == rows and m.tile()[1] == 0
+        m.set_field(0, f0[0])
+        m.step(steps)
+        assert np.array_equal(m.get_field(0), ref[0]), rows
+        for a, b in zip(hist_ref, [sum(m.reduce_history(q, steps)) for q in (P.PF_RED_MASS0, P.PF_RED_ENERGY)]):
+            assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, float(np.max(np.abs(a)))), rows
 
 
 def test_direct_biharmonic_strip_chunk_invariance_and_graphs_bitwise():
