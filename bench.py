@@ -43,7 +43,7 @@ FAMILY_SOURCES = {"2d": ("pf_march2d.h", "kernels_fused2d.hip"),
                   "3d": ("pf_march3d.h", "kernels_fused3d.hip"),
                   "1d": ("kernels_fused1d.hip",),
                   "mh2d": ("kernels_mh2d.hip",),
-                  "mh3d": ("kernels_mh3d.hip",),
+                  "mh3d": ("pf_march3d.h", "kernels_mh3d.hip"),
                   "chd3d": ("pf_march3d.h", "kernels_chd3d.hip"),
                   "spectral": ("kernels_spectral.hip", "spectral.cpp")}
 
@@ -244,8 +244,9 @@ def run_spectral(P, n, prec, steps, warmup, seed=202):
 
 def run_mh(P, n, prec, steps, warmup, seed=707, ndim=2):
     """Model H (Eq. model-h, transverse projector one) on a 2D n^2 grid (one
-    y-marching pass over column strips), a 3D n^3 grid (one z-marching pass
-    over column tiles; mu in registers and LDS in both) or a 1D row of n
+    y-marching pass over column strips), a 3D n^3 grid (one z-marching pass,
+    the 3D march with four rows per wave at p = 4; mu in registers and LDS in
+    both) or a 1D row of n
     sites (the fused strip kernel), autotuned, p = 4, dt = 0.005, c1 = c2 =
     1, c3 = 0.5, m and j = U[-0.1, 0.1]."""
     shape = {1: (n,), 2: (n, n), 3: (n, n, n)}[ndim]

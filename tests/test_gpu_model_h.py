@@ -95,9 +95,10 @@ def test_model_h_2d_marched_equals_generic_bitwise(shape, order, prec):
 @pytest.mark.parametrize("shape,order", [((13, 17, 30), 2), ((12, 14, 20), 4), ((40, 37, 70), 2),
                                          ((35, 20, 33), 4), ((5, 6, 7), 4), ((3, 40, 36), 2)])
 def test_model_h_3d_marched_equals_generic_bitwise(shape, order, prec):
-    """3D grids with r <= 2 run one z-marching pass (32 x 16 column tiles,
-    z chunks, partial and wrapping tiles, grids thinner than the halo); it
-    gives bitwise the two-pass per-site kernel's fields."""
+    """3D grids with r <= 2 run one z-marching pass (r = 1: 32 x 16 column
+    tiles; r = 2: the 3D march with four rows per wave; z chunks, partial and
+    wrapping tiles, grids thinner than the halo); it gives bitwise the
+    two-pass per-site kernel's fields."""
     f0 = synth.initial_fields(5, shape, 66, synth.IC_UNIFORM, (-0.1, 0.1), ndim=3)
     dt = 0.8 * oracle.dt_max(oracle.MH, 3, 1.0, order, PARAMS)
     a, _ = gpu_run(f0, 3, order, prec, dt, 21)
