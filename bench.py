@@ -40,7 +40,7 @@ T0 = time.perf_counter()
 
 
 FAMILY_SOURCES = {"2d": ("pf_march2d.h", "kernels_fused2d.hip"),
-                  "3d": ("pf_march3d.h", "kernels_fused3d.hip"),
+                  "3d": ("pf_march3d.h", "pf_fused3d.h", "pf_fused3d_kind.h", "kernels_fused3d.hip"),
                   "1d": ("kernels_fused1d.hip",),
                   "mh2d": ("kernels_mh2d.hip",),
                   "mh3d": ("pf_march3d.h", "kernels_mh3d.hip"),

@@ -1,0 +1,12 @@
+// 3D fused kernels of Cahn-Hilliard, FP64 storage: one (precision, kind) pair of
+// the launchers in pf_fused3d_kind.h, instantiated in a file of its own.
+#include "pf_fused3d_kind.h"
+
+namespace pf {
+
+template hipError_t launch_fused3d_kind<double, kCH>(const Launch &, const StepArgs<double> &, int32_t, int32_t, int,
+                                                 int, int, double *, hipStream_t);
+template hipError_t launch_fused3d_batched_kind<double, kCH>(const Launch &, const BatchTable<double> &, int32_t,
+                                                         int32_t, int, hipStream_t);
+
+}  // namespace pf

@@ -1,42 +1,8 @@
-// Instantiations and launchers of the 3D fused marching kernels.
-#include "pf_march3d.h"
-#include "pf_dispatch.h"
+// Planning and dispatch of the 3D fused marching kernels (their launchers
+// are instantiated per precision and kind in kernels_f3d_*.hip).
+#include "pf_fused3d.h"
 
 namespace pf {
-
-// Gray-Scott and Allen-Cahn: r <= 4; Cahn-Hilliard (halo 2r): r <= 3.  The
-// direct biharmonic runs its own column-tile kernel (kernels_chd3d.hip).
-using Fused3DRadii = RList<1, 2, 3, 4>;
-using Fused3DRadiiCH = RList<1, 2, 3>;
-
-template <int KIND, typename F>
-bool dispatch_r3d(int r, F &&f)
-{
-    if constexpr (KIND == kCH)
-        return dispatch_r(r, Fused3DRadiiCH{}, f);
-    else
-        return dispatch_r(r, Fused3DRadii{}, f);
-}
-
-using TimeBlockRadii3D = RList<1>;  // radii with a two-step (TB = 2) 3D kernel
-
-// One row per wave is built besides two for FP64 Allen-Cahn with r <= 2 and
-// FP64 Gray-Scott with r = 1, where it measures faster (and is the default).
-// Four rows per wave (8-wave workgroups: two per CU at up to 128 registers,
-// up to 256 registers with one; 12 waves for Cahn-Hilliard with r = 3) for
-// Cahn-Hilliard and Model C, Gray-Scott
-// with r >= 2 and Allen-Cahn with r = 4: an autotuner candidate, and the
-// default where two rows per wave would spill hundreds of bytes a lane.
-template <typename T, int KIND, int R>
-constexpr bool has_one_row_per_wave()
-{
-    return std::is_same<T, double>::value && ((KIND == kAC && R <= 2) || (KIND == kGS && R == 1));
-}
-template <typename T, int KIND, int R>
-constexpr bool has_four_rows_per_wave()
-{
-    return KIND == kCH || KIND == kMC || (KIND == kGS && R >= 2) || (KIND == kAC && R == 4);
-}
 
 // Calls f(T, KIND, R, TB) for the instantiated 3D kernel of L and tb.
 template <typename F>
@@ -148,37 +114,6 @@ bool plan_fused3d(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int32_t c
     });
 }
 
-template <typename T, int KIND, int R, int TB, int RPW>
-static hipError_t launch3d(const StepArgs<T> &a, int32_t blocks, int32_t threads, int red,
-                           hipStream_t s)
-{
-    if (red)
-        hipLaunchKernelGGL((k_step3d<T, KIND, R, true, TB, RPW>), dim3(blocks), dim3(threads), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_step3d<T, KIND, R, false, TB, RPW>), dim3(blocks), dim3(threads), 0, s, a);
-    return hipGetLastError();
-}
-
-// Two-pass step: the mu pass writes mu into the mu buffer through the output
-// slot of field 0 (and reduces c); the update pass reads mu as field 0 and c
-// as field 1 and writes c through the output slot of field 0.
-template <typename T, int R>
-static hipError_t launch3d_two_pass(const StepArgs<T> &a, T *mu, int32_t blocks, int32_t threads,
-                                    int red, hipStream_t s)
-{
-    const int p = a.parity;
-    StepArgs<T> a1 = a;
-    a1.buf[0][p ^ 1] = mu;
-    hipError_t err = launch3d<T, kCHMU, R, 1, 2>(a1, blocks, threads, red, s);
-    if (err != hipSuccess) return err;
-    StepArgs<T> a2 = a;
-    a2.buf[0][p] = mu;
-    a2.buf[1][p] = a.buf[0][p];
-    a2.red = 0;
-    hipLaunchKernelGGL((k_step3d<T, kCHUP, R, false, 1, 2>), dim3(blocks), dim3(threads), 0, s, a2);
-    return hipGetLastError();
-}
-
 hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int32_t threads,
                           int red, int tb, int rpw, void *mu, hipStream_t s)
 {
@@ -186,30 +121,12 @@ hipError_t launch_fused3d(const Launch &L, const void *args, int32_t blocks, int
     if (!rows_per_wave_available(L, tb, rpw)) return err;
     if (mu && !(two_pass_available(L) && tb == 1 && rpw == 2)) return err;
     if (L.kind == kCHD) return launch_chd3d(L, args, blocks, threads, red, rpw, s);
-    dispatch3d(L, tb, [&](auto tz, auto kc, auto rc, auto tbc) {
+    dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
-        constexpr int KIND = decltype(kc)::value, R = decltype(rc)::value;
-        constexpr int TB = decltype(tbc)::value;
-        const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
-        if constexpr (KIND == kCH && TB == 1) {
-            if (mu) {
-                err = launch3d_two_pass<T, R>(a, static_cast<T *>(mu), blocks, threads, red, s);
-                return;
-            }
-        }
-        if constexpr (has_one_row_per_wave<T, KIND, R>()) {
-            if (rpw == 1) {
-                err = launch3d<T, KIND, R, TB, 1>(a, blocks, threads, red, s);
-                return;
-            }
-        }
-        if constexpr (has_four_rows_per_wave<T, KIND, R>()) {
-            if (rpw == 4) {
-                err = launch3d<T, KIND, R, TB, 4>(a, blocks, threads, red, s);
-                return;
-            }
-        }
-        err = launch3d<T, KIND, R, TB, 2>(a, blocks, threads, red, s);
+        dispatch_kind(L.kind, [&](auto kc) {
+            err = launch_fused3d_kind<T, decltype(kc)::value>(L, *static_cast<const StepArgs<T> *>(args), blocks,
+                                                              threads, red, tb, rpw, static_cast<T *>(mu), s);
+        });
     });
     return err;
 }
@@ -221,25 +138,9 @@ hipError_t launch_fused3d_batched(const Launch &L, const void *table, int32_t k,
     if (tb == 2 && !time_block_available(L)) return err;
     dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
-        const BatchTable<T> &t = *static_cast<const BatchTable<T> *>(table);
         dispatch_kind(L.kind, [&](auto kc) {
-            constexpr int KIND = decltype(kc)::value;
-            if (tb == 2) {
-                dispatch_r(L.r, TimeBlockRadii3D{}, [&](auto rc) {
-                    constexpr int R = decltype(rc)::value;
-                    constexpr int NW = Tile3D<T, KIND, R, 2, batched_rpw<KIND, R>()>::NW;
-                    hipLaunchKernelGGL((k_step3d_batched<T, KIND, R, 2>), dim3(blocks), dim3(64 * NW), 0, s, t,
-                                       k);
-                    err = hipGetLastError();
-                });
-                return;
-            }
-            dispatch_r3d<KIND>(L.r, [&](auto rc) {
-                constexpr int R = decltype(rc)::value;
-                constexpr int NW = Tile3D<T, KIND, R, 1, batched_rpw<KIND, R>()>::NW;
-                hipLaunchKernelGGL((k_step3d_batched<T, KIND, R, 1>), dim3(blocks), dim3(64 * NW), 0, s, t, k);
-                err = hipGetLastError();
-            });
+            err = launch_fused3d_batched_kind<T, decltype(kc)::value>(
+                L, *static_cast<const BatchTable<T> *>(table), k, blocks, tb, s);
         });
     });
     return err;
