@@ -39,7 +39,7 @@ def log(msg):
 T0 = time.perf_counter()
 
 
-FAMILY_SOURCES = {"2d": ("pf_march2d.h", "kernels_fused2d.hip"),
+FAMILY_SOURCES = {"2d": ("pf_march2d.h", "pf_fused2d.h", "pf_fused2d_kind.h", "kernels_fused2d.hip"),
                   "3d": ("pf_march3d.h", "pf_fused3d.h", "pf_fused3d_kind.h", "kernels_fused3d.hip"),
                   "1d": ("kernels_fused1d.hip",),
                   "mh2d": ("kernels_mh2d.hip",),

@@ -1,0 +1,13 @@
+// 2D fused kernels of Allen-Cahn, FP64 storage: one
+// (precision, kind) pair of the launchers in pf_fused2d_kind.h, instantiated in
+// a file of its own.
+#include "pf_fused2d_kind.h"
+
+namespace pf {
+
+template hipError_t launch_fused2d_kind<double, kAC>(const Launch &, const StepArgs<double> &, int32_t, int32_t, int,
+                                                 int, hipStream_t);
+template hipError_t launch_fused2d_batched_kind<double, kAC>(const Launch &, const BatchTable<double> &, int32_t,
+                                                         int32_t, int, hipStream_t);
+
+}  // namespace pf

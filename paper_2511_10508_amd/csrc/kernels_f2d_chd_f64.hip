@@ -1,0 +1,11 @@
+// 2D fused kernels of Cahn-Hilliard with the direct biharmonic, FP64 storage: one
+// (precision, kind) pair of the launchers in pf_fused2d_kind.h, instantiated in
+// a file of its own.
+#include "pf_fused2d_kind.h"
+
+namespace pf {
+
+template hipError_t launch_fused2d_kind<double, kCHD>(const Launch &, const StepArgs<double> &, int32_t, int32_t, int,
+                                                 int, hipStream_t);
+
+}  // namespace pf

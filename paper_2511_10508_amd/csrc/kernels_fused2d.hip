@@ -1,11 +1,9 @@
-// Instantiations and launchers of the 2D fused marching kernels.
-#include "pf_march2d.h"
-#include "pf_dispatch.h"
+// Planning and dispatch of the 2D fused marching kernels (their launchers
+// are instantiated per precision and kind in kernels_f2d_*.hip).
+#include "pf_device.h"
+#include "pf_fused2d.h"
 
 namespace pf {
-
-using Fused2DRadii = RList<1, 2, 3, 4>;
-using TimeBlockRadii = RList<1, 2>;  // radii with a two-step (TB = 2) kernel
 
 bool time_block_available(const Launch &L)
 {
@@ -47,30 +45,9 @@ hipError_t launch_fused2d(const Launch &L, const void *args, int32_t blocks, int
     hipError_t err = hipErrorInvalidValue;
     dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
-        const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
         dispatch_kind_all(L.kind, [&](auto kc) {
-            constexpr int KIND = decltype(kc)::value;
-            if (tb == 2) {
-                if constexpr (KIND != kCHD) {  // the direct biharmonic has no two-step kernel
-                    dispatch_r(L.r, TimeBlockRadii{}, [&](auto rc) {
-                        constexpr int R = decltype(rc)::value;
-                        if (red)
-                            hipLaunchKernelGGL((k_step2d<T, KIND, R, true, 2>), dim3(blocks), dim3(threads), 0, s, a);
-                        else
-                            hipLaunchKernelGGL((k_step2d<T, KIND, R, false, 2>), dim3(blocks), dim3(threads), 0, s, a);
-                        err = hipGetLastError();
-                    });
-                }
-                return;
-            }
-            dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
-                constexpr int R = decltype(rc)::value;
-                if (red)
-                    hipLaunchKernelGGL((k_step2d<T, KIND, R, true, 1>), dim3(blocks), dim3(threads), 0, s, a);
-                else
-                    hipLaunchKernelGGL((k_step2d<T, KIND, R, false, 1>), dim3(blocks), dim3(threads), 0, s, a);
-                err = hipGetLastError();
-            });
+            err = launch_fused2d_kind<T, decltype(kc)::value>(L, *static_cast<const StepArgs<T> *>(args), blocks,
+                                                              threads, red, tb, s);
         });
     });
     return err;
@@ -83,24 +60,9 @@ hipError_t launch_fused2d_batched(const Launch &L, const void *table, int32_t k,
     if (tb == 2 && !time_block_available(L)) return err;
     dispatch_prec(L.fp32, [&](auto tz) {
         using T = decltype(tz);
-        const BatchTable<T> &t = *static_cast<const BatchTable<T> *>(table);
         dispatch_kind(L.kind, [&](auto kc) {
-            constexpr int KIND = decltype(kc)::value;
-            if (tb == 2) {
-                dispatch_r(L.r, TimeBlockRadii{}, [&](auto rc) {
-                    constexpr int R = decltype(rc)::value;
-                    hipLaunchKernelGGL((k_step2d_batched<T, KIND, R, 2>), dim3(blocks), dim3(64 * kWaves2D), 0,
-                                       s, t, k);
-                    err = hipGetLastError();
-                });
-                return;
-            }
-            dispatch_r(L.r, Fused2DRadii{}, [&](auto rc) {
-                constexpr int R = decltype(rc)::value;
-                hipLaunchKernelGGL((k_step2d_batched<T, KIND, R, 1>), dim3(blocks), dim3(64 * kWaves2D), 0, s,
-                                   t, k);
-                err = hipGetLastError();
-            });
+            err = launch_fused2d_batched_kind<T, decltype(kc)::value>(
+                L, *static_cast<const BatchTable<T> *>(table), k, blocks, tb, s);
         });
     });
     return err;
