@@ -266,9 +266,9 @@ __device__ __forceinline__ void mh3d_march(const StepArgs<T> &a, int64_t xb, int
         }
     const int32_t tb0 = z0 - H, tend = z1 + H;
     auto load = [&](int32_t t, T (&vm)[V], T (&vj)[3][V]) {
-        const int64_t om_ = (int64_t)wrap32(t, nz) * plane + rowoff;
+        const int64_t offm = (int64_t)wrap32(t, nz) * plane + rowoff;
         const int64_t oj = (int64_t)wrap32(t - R, nz) * plane + rowoff;
-        io.load(in[0] + om_, vm);
+        io.load(in[0] + offm, vm);
 #pragma unroll
         for (int c = 0; c < 3; ++c) io.load(in[1 + c] + oj, vj[c]);
     };
