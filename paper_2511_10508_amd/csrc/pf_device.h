@@ -262,9 +262,10 @@ __device__ __forceinline__ double energy_density(double c1, double c2, const dou
 // sum_i x_i sum_j w_j sum_axes (x_i - x_{i + j e_axis}) = sum_i x_i (wd x_i -
 // sum_j w_j P_j), where P[j-1] is the sum over the axes of the forward
 // neighbours at distance j and wd = ndim sum_j w_j; so each site takes only
-// its forward neighbours, and a multiply-add per distance.  The per-site
-// values differ from energy_density, the sum over the grid (every reduction
-// reports only sums) is the same up to rounding.
+// its forward neighbours, and a multiply-add per distance.  With the local
+// terms the density is x^2 ((c2/4) x^2 + wd - c1/2) - x sum_j w_j P_j.  The
+// per-site values differ from energy_density, the sum over the grid (every
+// reduction reports only sums) is the same up to rounding.
 template <int R>
 __device__ __forceinline__ double energy_by_parts(double c1, double c2, const double *w64, double wd,
                                                   double x, const double (&P)[R])
@@ -273,7 +274,7 @@ __device__ __forceinline__ double energy_by_parts(double c1, double c2, const do
 #pragma unroll
     for (int j = 1; j < R; ++j) s = fma(w64[j], P[j], s);
     const double x2 = x * x;
-    return fma(x, fma(wd, x, -s), x2 * fma(0.25 * c2, x2, -0.5 * c1));
+    return fma(x2, fma(0.25 * c2, x2, wd - 0.5 * c1), -(x * s));
 }
 
 // ---------------------------------------------------------------------------
