@@ -245,7 +245,11 @@ pf_status pf_field_device(pf_model *m, int32_t field, void **ptr, int64_t *pitch
  * (asynchronous).  With PF_REDUCE_EACH_STEP the reductions of the state at
  * the start of every step are fused into the step kernel and kept in a
  * device history (pf_reduce_history).  With PF_USE_GRAPH the launches are
- * replayed from captured HIP graphs.
+ * replayed from captured HIP graphs.  A small 2D Allen-Cahn model (order <=
+ * 4, ny a multiple of 16 with (ny / 16) * nx <= 1024, one copy of the grid
+ * within 128 KiB) stepped without PF_REDUCE_EACH_STEP or kernel timing runs
+ * up to 4096 steps per launch in one workgroup's LDS; the fields are bitwise
+ * the same.
  */
 pf_status pf_step(pf_model *m, int64_t nsteps);
 
@@ -385,7 +389,8 @@ pf_status pf_autotune(pf_model *m, int32_t trials);
 
 /*
  * Kernel timing on the model's stream: while enabled, pf_step records a HIP
- * event pair around every step-kernel launch (graph replay is off);
+ * event pair around every step-kernel launch (graph replay and the
+ * whole-grid LDS launches of small models are off);
  * pf_timing_read synchronises and returns the summed kernel milliseconds,
  * the number of launches and the number of time steps they advanced since
  * the last enable (any output pointer may be NULL).

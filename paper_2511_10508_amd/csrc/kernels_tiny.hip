@@ -141,7 +141,117 @@ __global__ void __launch_bounds__(kTinyThreads) k_tiny(BatchTable<T> tb)
     }
 }
 
+// ---------------------------------------------------------------------------
+// A single small 2D Allen-Cahn model stepped many times per launch: one copy
+// of the grid in LDS (so FP64 grids up to 128^2 fit).  Thread t owns a
+// segment of column t mod nx, rows [s L, (s + 1) L), s = t / nx, held in
+// registers; per step it takes its sites' x-neighbours (and the r rows
+// beyond its segment) from LDS and the rest from its registers, computes the
+// segment's new values, and after a barrier writes them to LDS.  Same
+// per-site functions and neighbour order as every other kernel, so the
+// fields are bitwise those of steps taken one launch each.
+constexpr int kLdsSegment = 16;  // rows per segment (128^2: 8 segments of 16 rows per column)
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kTinyThreads) k_lds_steps(StepArgs<T> a, int32_t steps)
+{
+    constexpr int L = kLdsSegment;
+    __shared__ T u[kTinyLdsBytes / sizeof(T)];
+    const int32_t nx = (int32_t)a.nx, ny = (int32_t)a.ny;
+    const int32_t tid = threadIdx.x;
+    const int32_t x = tid % nx, y0 = (tid / nx) * L;
+    const bool owner = y0 < ny;  // the host checks ny = L * segments with segments * nx <= 1024
+    int32_t xm[R], xp[R], ym[R], yp[R];  // wrapped x-neighbours; LDS index of the rows beyond the segment
+#pragma unroll
+    for (int j = 1; j <= R; ++j) {
+        xp[j - 1] = wrap32(x + j, nx);
+        xm[j - 1] = wrap32(x - j, nx);
+        yp[j - 1] = wrap32(y0 + L - 1 + j, ny) * nx + x;
+        ym[j - 1] = wrap32(y0 - j, ny) * nx + x;
+    }
+    const T ctr = T(4);
+    const int par = a.parity;
+    // c: the segment's values; the new value of row k replaces c[k - r] once
+    // row k is computed (later rows need only rows from k + 1 - r on), so
+    // r + 1 new values wait in nv
+    T c[L], nv[R + 1];
+    if (owner) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            c[k] = a.buf[0][par][(int64_t)(y0 + k) * a.pitch + x];
+            u[(y0 + k) * nx + x] = c[k];
+        }
+    }
+    __syncthreads();
+    for (int32_t s = 0; s < steps; ++s) {
+        if (owner) {
+            static_for<0, L>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const int32_t row = (y0 + k) * nx;
+                T S[R];
+                static_for<1, R + 1>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    T p, m;
+                    if constexpr (k + j < L)
+                        p = c[k + j];
+                    else
+                        p = u[yp[k + j - L]];
+                    if constexpr (k - j >= 0)
+                        m = c[k - j];
+                    else
+                        m = u[ym[j - k - 1]];
+                    S[j - 1] = (u[row + xp[j - 1]] + u[row + xm[j - 1]]) + (p + m);
+                });
+                const T u0 = c[k];
+                if constexpr (k >= R) c[k - R] = nv[(k - R) % (R + 1)];
+                nv[k % (R + 1)] = ac_update<T, R>(a, u0, S, u0 * ctr);
+            });
+            static_for<L - R, L>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                c[k] = nv[k % (R + 1)];
+            });
+        }
+        __syncthreads();
+        if (owner) {
+#pragma unroll
+            for (int k = 0; k < L; ++k) u[(y0 + k) * nx + x] = c[k];
+        }
+        __syncthreads();
+    }
+    if (owner) {
+        T *out = a.buf[0][par ^ (steps & 1)];
+#pragma unroll
+        for (int k = 0; k < L; ++k) out[(int64_t)(y0 + k) * a.pitch + x] = c[k];
+    }
+}
+
 }  // namespace
+
+bool lds_steps_available(const Launch &L, int64_t nx, int64_t ny, int64_t nz)
+{
+    // 2D, r <= 2, ny a multiple of the segment length with every segment of
+    // every column a thread of one workgroup
+    if (L.kind != kAC || L.ndim != 2 || L.r < 1 || L.r > 2 || nz != 1) return false;
+    if (nx < 1 || ny < kLdsSegment || ny % kLdsSegment != 0) return false;
+    if ((ny / kLdsSegment) * nx > kTinyThreads) return false;
+    return nx * ny * (L.fp32 ? 4 : 8) <= kTinyLdsBytes;
+}
+
+hipError_t launch_lds_steps(const Launch &L, const void *args, int32_t steps, hipStream_t s)
+{
+    hipError_t err = hipErrorInvalidValue;
+    if (steps < 1) return err;
+    dispatch_prec(L.fp32, [&](auto tz) {
+        using T = decltype(tz);
+        const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
+        if (!lds_steps_available(L, a.nx, a.ny, a.nz)) return;
+        dispatch_r(L.r, RList<1, 2>{}, [&](auto rc) {
+            hipLaunchKernelGGL((k_lds_steps<T, decltype(rc)::value>), dim3(1), dim3(kTinyThreads), 0, s, a, steps);
+            err = hipGetLastError();
+        });
+    });
+    return err;
+}
 
 bool tiny_available(const Launch &L, int64_t nx, int64_t ny, int64_t nz)
 {

@@ -143,6 +143,15 @@ constexpr int kTinyLdsBytes = 128 * 1024;
 bool tiny_available(const Launch &L, int64_t nx, int64_t ny, int64_t nz);
 hipError_t launch_tiny(const Launch &L, const void *table, int32_t blocks, hipStream_t s);
 
+// Many steps of one small Allen-Cahn model in one launch: 2D, r <= 2, ny a
+// multiple of 16 with (ny / 16) * nx <= 1024, the grid (one copy) in
+// kTinyLdsBytes of LDS; each thread holds a 16-row segment of one column in
+// registers between two barriers.  `args` is the
+// model's StepArgs; the launch reads buf[parity] and leaves the state after
+// `steps` steps in buf[parity ^ (steps & 1)].
+bool lds_steps_available(const Launch &L, int64_t nx, int64_t ny, int64_t nz);
+hipError_t launch_lds_steps(const Launch &L, const void *args, int32_t steps, hipStream_t s);
+
 // Generic per-site family (any r <= kMaxR, 1D, 2D and 3D).  CH runs two
 // passes through `scratch`: one field-sized buffer of T (same pitch as the
 // fields), ndim of them for the direct biharmonic.

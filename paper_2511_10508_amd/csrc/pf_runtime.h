@@ -33,6 +33,9 @@ struct Model {
     // 3D CH: mu in registers (1) or through `scratch` (2); requested (0: the
     // library's choice), in use
     int passes_req = 0, passes = 1;
+    // small Allen-Cahn grids of the fused family: step calls without per-step
+    // reductions or kernel timing run every step in one workgroup's LDS
+    bool lds_steps = false;
     int32_t clen = 0, strips = 0, ow = 0, ytiles = 1, chunks = 0, items = 0, blocks = 0,
             threads = 0;
     int64_t fused_slots = 0;

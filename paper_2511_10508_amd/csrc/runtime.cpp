@@ -245,6 +245,7 @@ static bool plan(Model *m)
     Launch L = m->L;
     const pf_desc &d = m->desc;
     m->family = 1;
+    m->lds_steps = false;
     if (d.flags & PF_SPECTRAL) {
         m->family = 2;
         m->tb = 1;
@@ -282,6 +283,7 @@ static bool plan(Model *m)
         return true;
     }
     m->family = 0;
+    m->lds_steps = lds_steps_available(L, d.n[0], d.n[1], d.n[2]);
     m->strips = strips;
     m->ow = ow;
     m->ytiles = ytiles;
@@ -554,6 +556,8 @@ static pf_status capture_graph(Model *m, int par, int k, bool red, Model::Graph 
     return PF_OK;
 }
 
+constexpr int32_t kLdsLaunchSteps = 4096;  // steps per launch of the whole-grid LDS kernel
+
 pf_status do_steps(Model *m, int64_t nsteps)
 {
     if (nsteps < 0) return fail(PF_ERR_ARG, "nsteps must be >= 0");
@@ -566,6 +570,22 @@ pf_status do_steps(Model *m, int64_t nsteps)
     }
     const bool use_graph = (m->desc.flags & PF_USE_GRAPH) != 0 && !m->timing;
     int64_t done = 0;
+    if (m->lds_steps && !each && !m->timing) {
+        // the whole grid in one workgroup's LDS, up to kLdsLaunchSteps steps per launch
+        while (done < nsteps) {
+            const int32_t k = (int32_t)std::min<int64_t>(nsteps - done, kLdsLaunchSteps);
+            StepArgs<double> a64 = m->a64;
+            StepArgs<float> a32 = m->a32;
+            a64.parity = a32.parity = m->parity;
+            const hipError_t e = launch_lds_steps(m->L, m->fp32 ? (const void *)&a32 : (const void *)&a64, k,
+                                                  m->stream);
+            if (e != hipSuccess) return hip_fail(e, "LDS step kernel launch");
+            m->parity ^= (k & 1);
+            m->steps_done += k;
+            done += k;
+        }
+        return PF_OK;
+    }
     if (use_graph && nsteps >= 2 * kGraphSteps) {
         if (!m->stage) PF_HIP(hipMalloc((void **)&m->stage, sizeof(double2) * kNumQ * kGraphSteps),
                               "hipMalloc(stage)");

@@ -140,6 +140,40 @@ def test_config_allen_cahn_128_1000_steps():
         assert float(np.max(np.abs(got[0] - ref[0]))) <= 1e-12
 
 
+# the first six fit the whole-grid kernel (2D, ny a multiple of 16, every
+# 16-row segment of every column a thread of one 1024-thread workgroup), the
+# last two take the per-launch path
+LDS_CASES = [((1, 128, 128), 2, P.PF_FP64, 37), ((1, 128, 128), 2, P.PF_FP32, 4100),
+             ((1, 32, 70), 4, P.PF_FP32, 64), ((1, 16, 1000), 2, P.PF_FP64, 21),
+             ((1, 64, 64), 4, P.PF_FP64, 13), ((1, 48, 20), 2, P.PF_FP32, 31),
+             ((1, 5, 7), 4, P.PF_FP64, 13), ((9, 10, 11), 2, P.PF_FP64, 30)]
+
+
+@pytest.mark.parametrize("shape,order,prec,steps", LDS_CASES,
+                         ids=["%s-p%d-%s-%d" % ("x".join(map(str, c[0])), c[1], "fp64" if c[2] == P.PF_FP64
+                                                else "fp32", c[3]) for c in LDS_CASES])
+def test_allen_cahn_whole_grid_in_lds_bitwise(shape, order, prec, steps):
+    """Small 2D Allen-Cahn grids run all the steps of a call in one
+    workgroup's LDS (up to 4096 per launch): fields bitwise those of the per-site
+    kernels, for odd and even step counts, calls split in two, graphs, and
+    per-step reductions (which take the one-launch-per-step path)."""
+    ndim = 3 if shape[0] > 1 else 2
+    params = BASE[P.PF_AC][0]
+    dt = dt_for(P.PF_AC, ndim, order, params)
+    f0 = fields_for(P.PF_AC, shape, 44)
+    ref, _ = gpu_run(P.PF_AC, f0, ndim, order, prec, params, dt, steps, flags=P.PF_FORCE_GENERIC)
+    for flags in (0, P.PF_USE_GRAPH, P.PF_REDUCE_EACH_STEP):
+        got, m = gpu_run(P.PF_AC, f0, ndim, order, prec, params, dt, steps, flags=flags)
+        assert m.tile()[1] == 0 and m.steps_done() == steps
+        assert np.array_equal(got[0], ref[0]), flags
+    n = {2: (shape[2], shape[1]), 3: (shape[2], shape[1], shape[0])}[ndim]
+    m = P.Model(P.make_desc(P.PF_AC, n, dt=dt, order=order, precision=prec, params=params))
+    m.set_field(0, f0[0])
+    m.step(steps // 3)
+    m.step(steps - steps // 3)
+    assert np.array_equal(m.get_field(0), ref[0])
+
+
 @pytest.mark.parametrize("prec", [P.PF_FP64, P.PF_FP32], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("kind,ndim,shape,ic,icp", [
     (P.PF_AC, 2, (1, 33, 70), P.PF_IC_UNIFORM, (-0.1, 0.1)),
