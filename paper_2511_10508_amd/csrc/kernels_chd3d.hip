@@ -170,7 +170,7 @@ __global__ void __launch_bounds__((CHD3Tile<T, R>::THREADS)) k_chd3d(StepArgs<T>
                         Pn[j - 1] = ((double)B[kCq][ly][lx + j] + (double)B[kCq][ly + j][lx]) + (double)cw[C + j];
                     e = energy_by_parts<R>(a.c1, a.c2, a.w64, 3.0 * a.w64sum, x, Pn);
                 }
-                if (!(finite_val(x) && finite_val(e))) red.bad += finite_val(x) ? 0.0 : 1.0;
+                if (!(finite_val(x) && finite_val(e))) red.bad += finite_val(x) ? 0u : 1u;
                 acc_add(red.q0, x);
                 acc_add(red.q1, e);
             }

@@ -204,11 +204,11 @@ __global__ void __launch_bounds__(256) k_reduce_state(StepArgs<T> a, int ndim)
         const int64_t off = s.z * a.plane + s.y * a.pitch + s.x;
         const double x = (double)f0.p[off];
         acc_add(red.q0, x);
-        red.bad += finite_val(x) ? 0.0 : 1.0;
+        red.bad += finite_val(x) ? 0u : 1u;
         if constexpr (nfields_kind(KIND) == 2) {
             const double y = (double)f1.p[off];
             acc_add(red.q1, y);
-            red.bad += finite_val(y) ? 0.0 : 1.0;
+            red.bad += finite_val(y) ? 0u : 1u;
         } else {
             double S64[R];
             auto at = [&](int64_t xx, int64_t yy, int64_t zz) { return (double)f0(xx, yy, zz); };

@@ -111,7 +111,7 @@ __device__ __forceinline__ double wave_sum_exact(double c)
 
 struct RedState {
     Acc q0{0.0, 0.0}, q1{0.0, 0.0};
-    double bad = 0.0;
+    uint32_t bad = 0;  // non-finite sites this lane reduced
 };
 
 __device__ __forceinline__ void red_flush(const RedState &r, double2 *part, int64_t pstride,
@@ -119,7 +119,7 @@ __device__ __forceinline__ void red_flush(const RedState &r, double2 *part, int6
 {
     const Acc a = wave_reduce(r.q0);
     const Acc b = wave_reduce(r.q1);
-    const double c = wave_sum_exact(r.bad);
+    const double c = wave_sum_exact((double)r.bad);
     if (lane == 0) {
         part[slot] = make_double2(a.hi, a.lo);
         part[pstride + slot] = make_double2(b.hi, b.lo);
@@ -421,12 +421,12 @@ __device__ __forceinline__ void red_row_end(RedState &red, const OutMask<V> &om,
                                             double s1, F &&value)
 {
     if (!(finite_val(s0) && finite_val(s1))) {
-        double bad = 0.0;
+        uint32_t bad = 0;
 #pragma unroll
         for (int v = 0; v < V; ++v)
             if (om.ov[v]) {
-                bad += finite_val(value(0, v)) ? 0.0 : 1.0;
-                if constexpr (TWO) bad += finite_val(value(1, v)) ? 0.0 : 1.0;
+                bad += finite_val(value(0, v)) ? 0u : 1u;
+                if constexpr (TWO) bad += finite_val(value(1, v)) ? 0u : 1u;
             }
         red.bad += bad;
     }
