@@ -225,6 +225,134 @@ __global__ void __launch_bounds__(kTinyThreads) k_lds_steps(StepArgs<T> a, int32
     }
 }
 
+// Whole-wave lane rotations by DPP: lane i receives lane i + 1 (wave_rol:1)
+// or lane i - 1 (wave_ror:1), lane 63 and lane 0 wrapping round.
+__device__ __forceinline__ int rot_from_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xF, 0xF, false); }
+__device__ __forceinline__ int rot_from_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xF, 0xF, false); }
+template <bool NEXT>
+__device__ __forceinline__ float rot_lane(float x)
+{
+    const int v = __builtin_bit_cast(int, x);
+    return __builtin_bit_cast(float, NEXT ? rot_from_next(v) : rot_from_prev(v));
+}
+template <bool NEXT>
+__device__ __forceinline__ double rot_lane(double x)
+{
+    const long long b = __builtin_bit_cast(long long, x);
+    int lo = (int)b, hi = (int)(b >> 32);
+    lo = NEXT ? rot_from_next(lo) : rot_from_prev(lo);
+    hi = NEXT ? rot_from_next(hi) : rot_from_prev(hi);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Whole-grid steps for 2D Allen-Cahn with r = 1 on nx = 64 W columns and
+// ny = 16 LR rows: wave w of the 16 holds rows [w LR, (w + 1) LR) in
+// registers, lane l columns [l W, (l + 1) W), so that one wave spans a whole
+// periodic row and x-neighbours across lanes are lane rotations.  Only the
+// first and last row of each wave cross waves: they go through an LDS array
+// of 16 x 2 rows, double-buffered by step parity, so one barrier per step.
+// The site arithmetic is that of every other kernel (same order).
+constexpr int kRowWaves = 16;
+
+template <typename T, int W, int LR>
+__global__ void __launch_bounds__(64 * kRowWaves) k_lds_rows(StepArgs<T> a, int32_t steps)
+{
+    constexpr int NX = 64 * W;
+    __shared__ T bnd[2][kRowWaves][2][NX];  // [step parity][wave][first / last row][x]
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    const int wu = (w + kRowWaves - 1) % kRowWaves, wd = (w + 1) % kRowWaves;
+    const int32_t y0 = w * LR, x0 = l * W;
+    const T ctr = T(4);
+    const int par = a.parity;
+    T c[2][W][LR];  // ping-pong: the state and the next state
+#pragma unroll
+    for (int k = 0; k < LR; ++k)
+#pragma unroll
+        for (int i = 0; i < W; ++i) c[0][i][k] = a.buf[0][par][(int64_t)(y0 + k) * a.pitch + x0 + i];
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        bnd[0][w][0][x0 + i] = c[0][i][0];
+        bnd[0][w][1][x0 + i] = c[0][i][LR - 1];
+    }
+    __syncthreads();
+    // one step from c[S] into c[S ^ 1], reading the boundary rows of parity b
+    auto step = [&](auto sc, int b) {
+        constexpr int S = decltype(sc)::value;
+        T up[W], dn[W];  // the row above the wave's first and below its last
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            up[i] = bnd[b][wu][1][x0 + i];
+            dn[i] = bnd[b][wd][0][x0 + i];
+        }
+        static_for<0, LR>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const T left = rot_lane<false>(c[S][W - 1][k]);  // column x0 - 1
+            const T right = rot_lane<true>(c[S][0][k]);      // column x0 + W
+            static_for<0, W>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                T xp, xm, p, m;
+                if constexpr (i + 1 < W)
+                    xp = c[S][i + 1][k];
+                else
+                    xp = right;
+                if constexpr (i >= 1)
+                    xm = c[S][i - 1][k];
+                else
+                    xm = left;
+                if constexpr (k + 1 < LR)
+                    p = c[S][i][k + 1];
+                else
+                    p = dn[i];
+                if constexpr (k >= 1)
+                    m = c[S][i][k - 1];
+                else
+                    m = up[i];
+                const T Sx[1] = {(xp + xm) + (p + m)};
+                const T u0 = c[S][i][k];
+                c[S ^ 1][i][k] = ac_update<T, 1>(a, u0, Sx, u0 * ctr);
+            });
+        });
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            bnd[b ^ 1][w][0][x0 + i] = c[S ^ 1][i][0];
+            bnd[b ^ 1][w][1][x0 + i] = c[S ^ 1][i][LR - 1];
+        }
+        __syncthreads();
+    };
+    // an odd step count takes its extra step first, so that the state ends in
+    // c[0] (indices known at compile time keep c in registers)
+    int b = 0;
+    if (steps & 1) {
+        step(std::integral_constant<int, 0>{}, b);
+        b ^= 1;
+#pragma unroll
+        for (int k = 0; k < LR; ++k)
+#pragma unroll
+            for (int i = 0; i < W; ++i) c[0][i][k] = c[1][i][k];
+    }
+    for (int32_t s = steps & 1; s < steps; s += 2) {
+        step(std::integral_constant<int, 0>{}, b);
+        step(std::integral_constant<int, 1>{}, b ^ 1);
+    }
+    T *out = a.buf[0][par ^ (steps & 1)];
+#pragma unroll
+    for (int k = 0; k < LR; ++k)
+#pragma unroll
+        for (int i = 0; i < W; ++i) out[(int64_t)(y0 + k) * a.pitch + x0 + i] = c[0][i][k];
+}
+
+// (W, LR) of the row kernel for a grid, or W = 0
+static void lds_rows_shape(const Launch &L, int64_t nx, int64_t ny, int64_t nz, int *W, int *LR)
+{
+    *W = 0;
+    *LR = 0;
+    if (L.kind != kAC || L.ndim != 2 || L.r != 1 || nz != 1) return;
+    if ((nx != 64 && nx != 128) || (ny != 16 * 4 && ny != 16 * 8)) return;
+    *W = (int)(nx / 64);
+    *LR = (int)(ny / 16);
+}
+
 }  // namespace
 
 bool lds_steps_available(const Launch &L, int64_t nx, int64_t ny, int64_t nz)
@@ -245,6 +373,19 @@ hipError_t launch_lds_steps(const Launch &L, const void *args, int32_t steps, hi
         using T = decltype(tz);
         const StepArgs<T> &a = *static_cast<const StepArgs<T> *>(args);
         if (!lds_steps_available(L, a.nx, a.ny, a.nz)) return;
+        int W, LR;
+        lds_rows_shape(L, a.nx, a.ny, a.nz, &W, &LR);
+        if (W) {
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(1), dim3(64 * kRowWaves), 0, s, a, steps);
+                err = hipGetLastError();
+            };
+            if (W == 1 && LR == 4) go(k_lds_rows<T, 1, 4>);
+            if (W == 1 && LR == 8) go(k_lds_rows<T, 1, 8>);
+            if (W == 2 && LR == 4) go(k_lds_rows<T, 2, 4>);
+            if (W == 2 && LR == 8) go(k_lds_rows<T, 2, 8>);
+            return;
+        }
         dispatch_r(L.r, RList<1, 2>{}, [&](auto rc) {
             hipLaunchKernelGGL((k_lds_steps<T, decltype(rc)::value>), dim3(1), dim3(kTinyThreads), 0, s, a, steps);
             err = hipGetLastError();
