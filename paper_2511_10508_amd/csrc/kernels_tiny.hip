@@ -245,20 +245,23 @@ __device__ __forceinline__ double rot_lane(double x)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Whole-grid steps for 2D Allen-Cahn with r = 1 on nx = 64 W columns and
+// Whole-grid steps for 2D Allen-Cahn with r <= W on nx = 64 W columns and
 // ny = 16 LR rows: wave w of the 16 holds rows [w LR, (w + 1) LR) in
 // registers, lane l columns [l W, (l + 1) W), so that one wave spans a whole
-// periodic row and x-neighbours across lanes are lane rotations.  Only the
-// first and last row of each wave cross waves: they go through an LDS array
-// of 16 x 2 rows, double-buffered by step parity, so one barrier per step.
-// The site arithmetic is that of every other kernel (same order).
+// periodic row and x-neighbours across lanes are lane rotations (r <= W keeps
+// them within the next lane).  Only the first and last r rows of each wave
+// cross waves: they go through an LDS array of 16 x 2r rows, double-buffered
+// by step parity, so one barrier per step.  The site arithmetic is that of
+// every other kernel (same order).
 constexpr int kRowWaves = 16;
 
-template <typename T, int W, int LR>
+template <typename T, int R, int W, int LR>
 __global__ void __launch_bounds__(64 * kRowWaves) k_lds_rows(StepArgs<T> a, int32_t steps)
 {
+    static_assert(R <= W && R <= LR, "neighbours within the next lane and the next wave");
     constexpr int NX = 64 * W;
-    __shared__ T bnd[2][kRowWaves][2][NX];  // [step parity][wave][first / last row][x]
+    // [step parity][wave][first r rows, then last r rows][x]
+    __shared__ T bnd[2][kRowWaves][2 * R][NX];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
     const int wu = (w + kRowWaves - 1) % kRowWaves, wd = (w + 1) % kRowWaves;
@@ -270,54 +273,70 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_lds_rows(StepArgs<T> a, int3
     for (int k = 0; k < LR; ++k)
 #pragma unroll
         for (int i = 0; i < W; ++i) c[0][i][k] = a.buf[0][par][(int64_t)(y0 + k) * a.pitch + x0 + i];
+    auto put_edges = [&](auto sc, int b) {
+        constexpr int S = decltype(sc)::value;
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-        bnd[0][w][0][x0 + i] = c[0][i][0];
-        bnd[0][w][1][x0 + i] = c[0][i][LR - 1];
-    }
+        for (int t = 0; t < R; ++t)
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                bnd[b][w][t][x0 + i] = c[S][i][t];
+                bnd[b][w][R + t][x0 + i] = c[S][i][LR - R + t];
+            }
+    };
+    put_edges(std::integral_constant<int, 0>{}, 0);
     __syncthreads();
-    // one step from c[S] into c[S ^ 1], reading the boundary rows of parity b
+    // one step from c[S] into c[S ^ 1], reading the edge rows of parity b
     auto step = [&](auto sc, int b) {
         constexpr int S = decltype(sc)::value;
-        T up[W], dn[W];  // the row above the wave's first and below its last
+        T up[R][W], dn[R][W];  // up[m]: row y0 - 1 - m; dn[m]: row y0 + LR + m
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            up[i] = bnd[b][wu][1][x0 + i];
-            dn[i] = bnd[b][wd][0][x0 + i];
-        }
+        for (int m = 0; m < R; ++m)
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                up[m][i] = bnd[b][wu][2 * R - 1 - m][x0 + i];
+                dn[m][i] = bnd[b][wd][m][x0 + i];
+            }
         static_for<0, LR>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const T left = rot_lane<false>(c[S][W - 1][k]);  // column x0 - 1
-            const T right = rot_lane<true>(c[S][0][k]);      // column x0 + W
+            // columns x0 - W + q (q >= W - r) of lane l - 1, x0 + W + q (q < r) of lane l + 1
+            T left[W], right[W];
+            static_for<W - R, W>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                left[q] = rot_lane<false>(c[S][q][k]);
+            });
+            static_for<0, R>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                right[q] = rot_lane<true>(c[S][q][k]);
+            });
             static_for<0, W>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                T xp, xm, p, m;
-                if constexpr (i + 1 < W)
-                    xp = c[S][i + 1][k];
-                else
-                    xp = right;
-                if constexpr (i >= 1)
-                    xm = c[S][i - 1][k];
-                else
-                    xm = left;
-                if constexpr (k + 1 < LR)
-                    p = c[S][i][k + 1];
-                else
-                    p = dn[i];
-                if constexpr (k >= 1)
-                    m = c[S][i][k - 1];
-                else
-                    m = up[i];
-                const T Sx[1] = {(xp + xm) + (p + m)};
+                T Sx[R];
+                static_for<1, R + 1>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    T xp, xm, p, m;
+                    if constexpr (i + j < W)
+                        xp = c[S][i + j][k];
+                    else
+                        xp = right[i + j - W];
+                    if constexpr (i - j >= 0)
+                        xm = c[S][i - j][k];
+                    else
+                        xm = left[i - j + W];
+                    if constexpr (k + j < LR)
+                        p = c[S][i][k + j];
+                    else
+                        p = dn[k + j - LR][i];
+                    if constexpr (k - j >= 0)
+                        m = c[S][i][k - j];
+                    else
+                        m = up[j - k - 1][i];
+                    Sx[j - 1] = (xp + xm) + (p + m);
+                });
                 const T u0 = c[S][i][k];
-                c[S ^ 1][i][k] = ac_update<T, 1>(a, u0, Sx, u0 * ctr);
+                c[S ^ 1][i][k] = ac_update<T, R>(a, u0, Sx, u0 * ctr);
             });
         });
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-            bnd[b ^ 1][w][0][x0 + i] = c[S ^ 1][i][0];
-            bnd[b ^ 1][w][1][x0 + i] = c[S ^ 1][i][LR - 1];
-        }
+        put_edges(std::integral_constant<int, S ^ 1>{}, b ^ 1);
         __syncthreads();
     };
     // an odd step count takes its extra step first, so that the state ends in
@@ -347,8 +366,9 @@ static void lds_rows_shape(const Launch &L, int64_t nx, int64_t ny, int64_t nz, 
 {
     *W = 0;
     *LR = 0;
-    if (L.kind != kAC || L.ndim != 2 || L.r != 1 || nz != 1) return;
+    if (L.kind != kAC || L.ndim != 2 || L.r < 1 || L.r > 2 || nz != 1) return;
     if ((nx != 64 && nx != 128) || (ny != 16 * 4 && ny != 16 * 8)) return;
+    if (L.r > nx / 64) return;  // r <= W
     *W = (int)(nx / 64);
     *LR = (int)(ny / 16);
 }
@@ -380,10 +400,12 @@ hipError_t launch_lds_steps(const Launch &L, const void *args, int32_t steps, hi
                 hipLaunchKernelGGL(kern, dim3(1), dim3(64 * kRowWaves), 0, s, a, steps);
                 err = hipGetLastError();
             };
-            if (W == 1 && LR == 4) go(k_lds_rows<T, 1, 4>);
-            if (W == 1 && LR == 8) go(k_lds_rows<T, 1, 8>);
-            if (W == 2 && LR == 4) go(k_lds_rows<T, 2, 4>);
-            if (W == 2 && LR == 8) go(k_lds_rows<T, 2, 8>);
+            if (L.r == 1 && W == 1 && LR == 4) go(k_lds_rows<T, 1, 1, 4>);
+            if (L.r == 1 && W == 1 && LR == 8) go(k_lds_rows<T, 1, 1, 8>);
+            if (L.r == 1 && W == 2 && LR == 4) go(k_lds_rows<T, 1, 2, 4>);
+            if (L.r == 1 && W == 2 && LR == 8) go(k_lds_rows<T, 1, 2, 8>);
+            if (L.r == 2 && W == 2 && LR == 4) go(k_lds_rows<T, 2, 2, 4>);
+            if (L.r == 2 && W == 2 && LR == 8) go(k_lds_rows<T, 2, 2, 8>);
             return;
         }
         dispatch_r(L.r, RList<1, 2>{}, [&](auto rc) {

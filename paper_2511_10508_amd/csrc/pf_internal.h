@@ -146,9 +146,10 @@ hipError_t launch_tiny(const Launch &L, const void *table, int32_t blocks, hipSt
 // Many steps of one small Allen-Cahn model in one launch: 2D, r <= 2, ny a
 // multiple of 16 with (ny / 16) * nx <= 1024, the grid (one copy) in
 // kTinyLdsBytes of LDS; each thread holds a 16-row segment of one column in
-// registers between two barriers.  With r = 1 on 64 or 128 columns and 64 or
-// 128 rows one wave holds a band of whole rows instead (x-neighbours by lane
-// rotation, only the bands' edge rows through LDS, one barrier per step).
+// registers between two barriers.  On 64 or 128 columns (r <= columns / 64)
+// and 64 or 128 rows one wave holds a band of whole rows instead
+// (x-neighbours by lane rotation, only the bands' edge rows through LDS, one
+// barrier per step).
 // `args` is the
 // model's StepArgs; the launch reads buf[parity] and leaves the state after
 // `steps` steps in buf[parity ^ (steps & 1)].

@@ -147,10 +147,12 @@ LDS_CASES = [((1, 128, 128), 2, P.PF_FP64, 37), ((1, 128, 128), 2, P.PF_FP32, 41
              ((1, 32, 70), 4, P.PF_FP32, 64), ((1, 16, 1000), 2, P.PF_FP64, 21),
              ((1, 64, 64), 4, P.PF_FP64, 13), ((1, 48, 20), 2, P.PF_FP32, 31),
              ((1, 5, 7), 4, P.PF_FP64, 13), ((9, 10, 11), 2, P.PF_FP64, 30),
-             # p = 2 on 64 or 128 columns of 64 or 128 rows: the row kernel
-             # (one wave per band of rows, x-neighbours by lane rotation)
+             # p = 2 on 64 or 128 columns and p = 4 on 128 columns, of 64 or
+             # 128 rows: the row kernel (one wave per band of rows,
+             # x-neighbours by lane rotation)
              ((1, 64, 128), 2, P.PF_FP64, 29), ((1, 128, 64), 2, P.PF_FP32, 33),
-             ((1, 64, 64), 2, P.PF_FP32, 8), ((1, 128, 64), 2, P.PF_FP64, 1)]
+             ((1, 64, 64), 2, P.PF_FP32, 8), ((1, 128, 64), 2, P.PF_FP64, 1),
+             ((1, 64, 128), 4, P.PF_FP64, 17), ((1, 128, 128), 4, P.PF_FP32, 9)]
 
 
 @pytest.mark.parametrize("shape,order,prec,steps", LDS_CASES,
