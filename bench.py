@@ -201,7 +201,8 @@ def run_ch_variant(P, n, prec, steps, warmup, direct, ndim, seed=202):
     per = kernel_ms / ksteps
     gbs = 2 * (8 if prec == P.PF_FP64 else 4) * sites / (per * 1e-3) / 1e9
     return {"value": sites * steps / wall, "ms_per_step": round(wall / steps * 1e3, 4),
-            "kernel_ms": round(per, 4), "achieved_gbs": round(gbs, 1),
+            "kernel_ms": round(per, 4), "kernel_ms_per_launch": round(kernel_ms / launches, 4),
+            "achieved_gbs": round(gbs, 1),
             "frac_of_peak": round(gbs / PEAK_GBS, 4), "mass_drift": drift,
             "chunk": chunk, "time_block": tb}
 
@@ -700,21 +701,28 @@ def main():
         log("Model C done")
     if want("next", args.skip_next):
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
-            extra["chd2d_%d_%s" % (args.n, tag)] = run_ch_variant(
-                P, args.n, prec, max(10, args.steps // 4), 4, direct=True, ndim=2)
-            extra["ch1d_%d_%s" % (args.n * args.n // 4, tag)] = run_ch_variant(
-                P, args.n * args.n // 4, prec, max(10, args.steps // 4), 4, direct=False, ndim=1)
-            extra["chd3d_512_%s" % tag] = run_ch_variant(P, 512, prec, max(10, args.steps // 4), 4,
-                                                         direct=True, ndim=3)
+            key = "chd2d_%d_%s" % (args.n, tag)
+            extra[key] = attach_traffic(run_ch_variant(
+                P, args.n, prec, max(10, args.steps // 4), 4, direct=True, ndim=2), key, src)
+            key = "ch1d_%d_%s" % (args.n * args.n // 4, tag)
+            extra[key] = attach_traffic(run_ch_variant(
+                P, args.n * args.n // 4, prec, max(10, args.steps // 4), 4, direct=False, ndim=1), key,
+                source_hash("1d"))
+            key = "chd3d_512_%s" % tag
+            extra[key] = attach_traffic(run_ch_variant(P, 512, prec, max(10, args.steps // 4), 4,
+                                                       direct=True, ndim=3), key, source_hash("chd3d"))
         log("direct biharmonic and 1D done")
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
             extra["spectral_ch2d_%d_%s" % (args.n // 2, tag)] = run_spectral(
                 P, args.n // 2, prec, max(10, args.steps // 10), 3)
         log("spectral done")
         for prec, tag in ((P.PF_FP64, "fp64"), (P.PF_FP32, "fp32")):
-            extra["mh2d_%d_%s" % (args.n // 4, tag)] = run_mh(P, args.n // 4, prec, max(10, args.steps // 10), 2)
-            extra["mh1d_%d_%s" % (args.n * args.n // 16, tag)] = run_mh(
-                P, args.n * args.n // 16, prec, max(10, args.steps // 10), 2, ndim=1)
+            key = "mh2d_%d_%s" % (args.n // 4, tag)
+            extra[key] = attach_traffic(run_mh(P, args.n // 4, prec, max(10, args.steps // 10), 2), key,
+                                        source_hash("mh2d"))
+            key = "mh1d_%d_%s" % (args.n * args.n // 16, tag)
+            extra[key] = attach_traffic(run_mh(
+                P, args.n * args.n // 16, prec, max(10, args.steps // 10), 2, ndim=1), key, source_hash("1d"))
             extra["mh3d_512_%s" % tag] = attach_traffic(
                 run_mh(P, 512, prec, max(10, args.steps // 10), 2, ndim=3), "mh3d_512_" + tag,
                 source_hash("mh3d"))
